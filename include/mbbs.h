@@ -1,0 +1,236 @@
+/*
+ * mbbs.h -- C ABI of an MI355X (gfx950) library that solves the Wilson-Dirac
+ * equation D X = B for a block of L right-hand sides with the QR-stabilised
+ * ("modified") block BiCGSTAB of Nakamura, Ishikawa, Kuramashi, Sakurai and
+ * Tadano, right-preconditioned by the Schwarz alternating procedure (SAP).
+ *
+ * Problem statement (Sec. 2.1): A X = B with A the N x N Wilson-Dirac matrix,
+ * N = Lx*Ly*Lz*Lt*3*4, and X, B complex N x L blocks.
+ *
+ * Conventions shared by every entry point
+ *  - Complex numbers are interleaved (re, im) pairs of the stated real type.
+ *  - Spinor block layout: row-major N x L with the right-hand side fastest
+ *    (Sec. 2.1 keeps the RHS index innermost): element (n, i) sits at
+ *    n*L + i, n = 12*site + 3*spin + colour, site = x + Lx*(y + Ly*(z + Lz*t)).
+ *  - Gauge layout: U[((site*4 + mu)*3 + a)*3 + b], mu = 0..3 = x,y,z,t;
+ *    U_{x,mu} is the link from x to x + mu.
+ *  - Gamma matrices: Euclidean chiral basis, gamma_k = [[0, -i s_k], [i s_k, 0]]
+ *    (k = 1,2,3 for mu = 0,1,2, s_k Pauli), gamma_4 = [[0, 1], [1, 0]].
+ *  - Boundary phases: a hop that wraps forward across x_mu = L_mu - 1 is
+ *    multiplied by phase[mu], a backward wrap by its conjugate.
+ *  - Pointers named *_dev are device memory (hipMalloc'd or torch tensors on
+ *    the current device); everything else is host memory.  `stream` is a
+ *    hipStream_t passed as void* (NULL = default stream).
+ *  - Return value: 0 = MBBS_OK, 1 = MBBS_NOT_CONVERGED (results valid, tolerance
+ *    not reached), < 0 = error; on error nothing was written unless stated,
+ *    and mbbs_last_error() holds a message for the calling thread.
+ *  - One lattice handle may be used by one stream at a time.
+ */
+#ifndef MBBS_H
+#define MBBS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mbbs_lattice_s* mbbs_lattice_t;
+
+typedef enum {
+  MBBS_FP64 = 0,   /* double storage, double arithmetic                         */
+  MBBS_FP32 = 1,   /* float storage, float arithmetic                           */
+  MBBS_FP16S = 2   /* half storage with one float scale per (site, column),
+                      half links, float arithmetic                              */
+} mbbs_prec;
+
+enum {
+  MBBS_OK = 0,
+  MBBS_NOT_CONVERGED = 1,
+  MBBS_EINVAL = -1,
+  MBBS_ENOMEM = -2,
+  MBBS_EHIP = -3,
+  MBBS_EBREAKDOWN = -4
+};
+
+/* ---------------------------------------------------------------- lattice */
+
+/* Create a lattice: extents dims[4] (all even), SAP domain block[4] (each
+ * extent divisible by its block, an even number >= 2 of domains per
+ * direction, Sec. 2.2 colours domains even/odd), links U_dev (FP64, layout
+ * above, caller keeps ownership; copied), hopping parameter kappa and
+ * boundary phases phase[8] = (re, im) per direction, each of modulus 1.
+ * The handle owns device copies of the links in FP64/FP32/FP16 in
+ * lexicographic and domain-major site order.  Synchronises `stream`.
+ * Errors: EINVAL (bad extents, blocks, phases, kappa), ENOMEM, EHIP. */
+int mbbs_lattice_create(const int dims[4], const int block[4], const double* U_dev,
+                        double kappa, const double phase[8], void* stream,
+                        mbbs_lattice_t* out);
+
+/* Release every device buffer of the handle.  NULL is accepted. */
+int mbbs_lattice_destroy(mbbs_lattice_t lat);
+
+/* Index tables (built on the GPU by the same index functions the kernels
+ * use), copied to host memory `out` of `count` int32 entries.
+ *  MBBS_TAB_COORD      V x 4   x, y, z, t of each site
+ *  MBBS_TAB_NEIGHBOUR  V x 8   column 2mu: site + mu, 2mu+1: site - mu (wrapped)
+ *  MBBS_TAB_BOUNDARY   V       bit 2mu+s set if hop (mu, s) wraps the lattice
+ *  MBBS_TAB_PARITY     V       (x+y+z+t) mod 2
+ *  MBBS_TAB_EO         V       parity*V/2 + site/2
+ *  MBBS_TAB_DOMAIN     V       SAP domain id (lexicographic over the domain grid)
+ *  MBBS_TAB_COLOUR     V       domain colour, parity of the domain coordinates
+ *  MBBS_TAB_LOCAL      V       lexicographic index inside the domain
+ *  MBBS_TAB_DM_INDEX   V       position of the site in domain-major order
+ *                              (colour-0 domains by id, then colour-1, local inside)
+ *  MBBS_TAB_DM_SITE    V       inverse of MBBS_TAB_DM_INDEX
+ *  MBBS_TAB_LOCAL_NB   Vb x 8  in-domain neighbour (local index) per hop, -1 if
+ *                              the hop leaves the domain
+ *  MBBS_TAB_DM_NEIGHBOUR V x 8 neighbours in domain-major positions: row i lists
+ *                              the positions of the 8 neighbours of the site at
+ *                              position i (what the SAP kernels compute)
+ * mbbs_lattice_table_size gives the entry count.  Errors: EINVAL. */
+enum {
+  MBBS_TAB_COORD = 0, MBBS_TAB_NEIGHBOUR, MBBS_TAB_BOUNDARY, MBBS_TAB_PARITY,
+  MBBS_TAB_EO, MBBS_TAB_DOMAIN, MBBS_TAB_COLOUR, MBBS_TAB_LOCAL,
+  MBBS_TAB_DM_INDEX, MBBS_TAB_DM_SITE, MBBS_TAB_LOCAL_NB, MBBS_TAB_DM_NEIGHBOUR, MBBS_TAB_COUNT
+};
+int mbbs_lattice_table_size(mbbs_lattice_t lat, int which, size_t* count);
+int mbbs_lattice_table(mbbs_lattice_t lat, int which, int32_t* out, size_t count);
+
+/* ---------------------------------------------------------------- operator */
+
+/* Y = A X with A = 1 - kappa*H, H the hopping term of Sec. 2.1 applied to
+ * every one of the L columns with the same links (block hopping-term
+ * equation).  X_dev, Y_dev: FP64 N x L blocks (layout above), distinct.
+ * prec selects the arithmetic: FP64 directly; FP32 / FP16S convert X to
+ * that storage, apply, and convert back (for accuracy checks).  Asynchronous
+ * on `stream`.  Errors: EINVAL (L < 1, aliasing, bad prec). */
+int mbbs_apply_dirac(mbbs_lattice_t lat, int L, const double* X_dev, double* Y_dev,
+                     int prec, void* stream);
+
+/* Same operator on fields already in a precision's own storage (what the
+ * solver's kernels see), for timing.  Layout as above with element types:
+ *   FP64: double pairs; FP32: float pairs; FP16S: half pairs (X_dev) plus
+ *   one float scale per (site, column) at scale[site*L + i] (Xs_dev, Ys_dev).
+ * Xs_dev / Ys_dev are ignored unless prec == FP16S. */
+int mbbs_apply_dirac_raw(mbbs_lattice_t lat, int L, int prec, const void* X_dev,
+                         const float* Xs_dev, void* Y_dev, float* Ys_dev, void* stream);
+
+/* Convert an FP64 N x L block to a precision's storage (RNE) and back. */
+int mbbs_convert_to(int prec, size_t nsites, int L, const double* X_dev, void* Y_dev,
+                    float* Ys_dev, void* stream);
+int mbbs_convert_from(int prec, size_t nsites, int L, const void* X_dev,
+                      const float* Xs_dev, double* Y_dev, void* stream);
+
+/* Domain-restricted (Dirichlet) operator, Sec. 2.2: Y = sum_D A_DD X, i.e.
+ * A with every hop between two different SAP domains removed, on FP64
+ * blocks in lexicographic order, computed in precision `prec`. */
+int mbbs_apply_blocked(mbbs_lattice_t lat, int L, const double* X_dev, double* Y_dev,
+                       int prec, void* stream);
+
+/* SAP preconditioner, Sec. 2.2: Y = M X with M = K sum_{j<ncy} (1 - A K)^j,
+ * K the even-then-odd domain sweep, each domain block approximately inverted
+ * by nmr minimal-residual steps from zero (one step size per domain and
+ * column).  X_dev, Y_dev: FP64 lexicographic blocks; the preconditioner runs
+ * in `prec` in domain-major order; Y is the FP64 image of the result.
+ * ws_dev must hold mbbs_sap_workspace_size bytes (caller-owned). */
+int mbbs_sap_workspace_size(mbbs_lattice_t lat, int L, int prec, size_t* bytes);
+int mbbs_sap_apply(mbbs_lattice_t lat, int L, const double* X_dev, double* Y_dev,
+                   int ncy, int nmr, int prec, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------ block linear algebra */
+
+/* G = X^H Y, the L x L Gram matrix G[i*L + j] = sum_n conj(X[n,i]) Y[n,j]
+ * (steps 4.4, 4.8, 4.11 of Alg. 1 need such products) for FP64 N x L blocks, deterministic fixed-order reduction; G_dev device
+ * memory.  ws_dev holds mbbs_gram_workspace_size bytes. */
+int mbbs_gram_workspace_size(size_t N, int L, size_t* bytes);
+int mbbs_gram(size_t N, int L, const double* X_dev, const double* Y_dev, double* G_dev,
+              void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Cholesky QR (step 4.1, QR of P): G = P^H P = gamma^H gamma, Q = P gamma^{-1},
+ * gamma upper triangular with positive real diagonal (the unique QR factor).
+ * passes = 2 repeats the factorisation on Q (CholQR2).  Q_dev may equal P_dev.
+ * gamma_dev (L x L, row-major) receives the combined factor.  Returns
+ * EBREAKDOWN if P^H P is not numerically positive definite. */
+int mbbs_cholqr(size_t N, int L, const double* P_dev, double* Q_dev, double* gamma_dev,
+                int passes, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Solve G X = R for L x L complex G and L x m right-hand sides R (row-major,
+ * host or device pointers as named), LU with partial pivoting on
+ * |Re|+|Im| (steps 4.4 and 4.11).  Returns EBREAKDOWN on a zero pivot. */
+int mbbs_lu_solve(int L, int m, const double* G_dev, const double* R_dev, double* X_dev,
+                  void* stream);
+
+/* ---------------------------------------------------------------- solver */
+
+typedef struct {
+  double tol;          /* stop when max_i ||r_i||/||b_i|| <= tol (true residual) */
+  int maxiter;         /* iteration cap (Alg. 1 loop)                             */
+  int max_restarts;    /* restarts from the true residual after a false stop      */
+  int ncy;             /* SAP cycles (applications of K)                          */
+  int nmr;             /* MR steps per domain                                     */
+  int sap_prec;        /* mbbs_prec of the preconditioner                         */
+  int x0_is_guess;     /* 1: X_dev holds an initial guess; 0: start from X = 0    */
+  int qr_passes;       /* 1 = Cholesky QR, 2 = CholQR2                            */
+  int graph_iters;     /* iterations per captured HIP graph (0/1: no graph)       */
+  int precond;         /* 1: SAP right preconditioner; 0: M = 1                   */
+  int memsave;         /* 1: memory-saving form (Alg. 2); 0: Alg. 1               */
+  int profile;         /* 1: time kernel classes with HIP events                  */
+} mbbs_solve_params;
+
+/* Kernel classes timed when params.profile = 1. */
+enum { MBBS_K_DSLASH64 = 0, MBBS_K_SAP_RES, MBBS_K_MR_DSLASH, MBBS_K_MR_UPDATE,
+       MBBS_K_CONVERT, MBBS_K_GRAM, MBBS_K_UPDATE, MBBS_K_SMALL, MBBS_K_COUNT };
+
+typedef struct {
+  int status;                   /* return value of the call                        */
+  int iterations;               /* Alg. 1 iterations performed                     */
+  int restarts;
+  long long n_dslash_outer;     /* full-lattice FP64 applications of A             */
+  long long n_sap;              /* applications of M                               */
+  double* true_res;             /* caller-owned host arrays of length L: final      */
+  double* rec_res;              /* ||b - A x||/||b|| and recursive ||r||/||b||      */
+  double seconds;               /* wall time of the call                           */
+  double kernel_ms[MBBS_K_COUNT];        /* summed kernel time per class (profile) */
+  long long kernel_launches[MBBS_K_COUNT];
+} mbbs_solve_info;
+
+void mbbs_solve_params_default(mbbs_solve_params* p);
+
+/* Workspace (device bytes) needed by mbbs_solve for this lattice, L, params. */
+int mbbs_solve_workspace_size(mbbs_lattice_t lat, int L, const mbbs_solve_params* params,
+                              size_t* bytes);
+
+/* Solve A X = B (Alg. 1, or Alg. 2 if params->memsave): B_dev, X_dev FP64
+ * N x L blocks; X_dev is read as the initial guess when x0_is_guess and
+ * always receives the result.  R~ = R_0.  The outer recurrences, Gram
+ * products, Cholesky QR, L x L solves and the true residual run in FP64;
+ * SAP runs in params->sap_prec.  Allocates nothing: ws_dev (caller-owned,
+ * mbbs_solve_workspace_size bytes) holds every intermediate.  Blocks until
+ * done.  Returns OK, NOT_CONVERGED (maxiter or restarts exhausted; X and
+ * residuals valid), EBREAKDOWN (singular R~^H V, non-positive P^H P or
+ * non-finite coefficient; X is the last consistent iterate), EINVAL (bad
+ * arguments, a zero column of B, workspace too small). */
+int mbbs_solve(mbbs_lattice_t lat, int L, const double* B_dev, double* X_dev,
+               const mbbs_solve_params* params, void* ws_dev, size_t ws_bytes,
+               mbbs_solve_info* info, void* stream);
+
+/* Solve nsys independent systems (each its own lattice, L, B, X, params and
+ * info) together: iterations of all unconverged systems are interleaved in
+ * one captured launch sequence per round; converged systems stop early on
+ * a device flag.  ws_dev holds mbbs_solve_batched_workspace_size bytes. */
+int mbbs_solve_batched_workspace_size(int nsys, const mbbs_lattice_t* lats, const int* Ls,
+                                      const mbbs_solve_params* params, size_t* bytes);
+int mbbs_solve_batched(int nsys, const mbbs_lattice_t* lats, const int* Ls,
+                       const double* const* B_dev, double* const* X_dev,
+                       const mbbs_solve_params* params, void* ws_dev, size_t ws_bytes,
+                       mbbs_solve_info* infos, void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* mbbs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MBBS_H */

@@ -1,0 +1,289 @@
+"""Thin ctypes binding of libmbbs.so: the C ABI's names, argument marshalling only.
+
+Device arrays are torch tensors on the current HIP device (complex128 for
+FP64 spinor blocks and links); host arrays are numpy arrays.  Every function
+raises MbbsError on a negative status.  The library must be built first
+(`python -m paper_1104_0737_amd.build`); nothing here falls back to any other
+implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmbbs.so")
+
+FP64, FP32, FP16S = 0, 1, 2
+OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, EBREAKDOWN = 0, 1, -1, -2, -3, -4
+TABLES = ("COORD", "NEIGHBOUR", "BOUNDARY", "PARITY", "EO", "DOMAIN", "COLOUR", "LOCAL",
+          "DM_INDEX", "DM_SITE", "LOCAL_NB", "DM_NEIGHBOUR")
+KERNEL_CLASSES = ("dslash64", "sap_resid", "mr_dslash", "mr_update", "convert", "gram", "update", "small")
+
+EXPORTS = (
+    "mbbs_lattice_create", "mbbs_lattice_destroy", "mbbs_lattice_table_size", "mbbs_lattice_table",
+    "mbbs_apply_dirac", "mbbs_apply_dirac_raw", "mbbs_convert_to", "mbbs_convert_from",
+    "mbbs_apply_blocked", "mbbs_sap_workspace_size", "mbbs_sap_apply", "mbbs_gram_workspace_size",
+    "mbbs_gram", "mbbs_cholqr", "mbbs_lu_solve", "mbbs_solve_params_default",
+    "mbbs_solve_workspace_size", "mbbs_solve", "mbbs_solve_batched_workspace_size",
+    "mbbs_solve_batched", "mbbs_last_error",
+)
+
+
+class MbbsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mbbs error {code}: {msg}")
+        self.code = code
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("max_restarts", ctypes.c_int),
+                ("ncy", ctypes.c_int), ("nmr", ctypes.c_int), ("sap_prec", ctypes.c_int),
+                ("x0_is_guess", ctypes.c_int), ("qr_passes", ctypes.c_int), ("graph_iters", ctypes.c_int),
+                ("precond", ctypes.c_int), ("memsave", ctypes.c_int), ("profile", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("n_dslash_outer", ctypes.c_longlong), ("n_sap", ctypes.c_longlong),
+                ("true_res", ctypes.POINTER(ctypes.c_double)), ("rec_res", ctypes.POINTER(ctypes.c_double)),
+                ("seconds", ctypes.c_double), ("kernel_ms", ctypes.c_double * 8),
+                ("kernel_launches", ctypes.c_longlong * 8)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmbbs.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1104_0737_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+        sig = {
+            "mbbs_lattice_create": (i, [ctypes.POINTER(i), ctypes.POINTER(i), vp, d, ctypes.POINTER(d), vp,
+                                        ctypes.POINTER(vp)]),
+            "mbbs_lattice_destroy": (i, [vp]),
+            "mbbs_lattice_table_size": (i, [vp, i, ctypes.POINTER(sz)]),
+            "mbbs_lattice_table": (i, [vp, i, vp, sz]),
+            "mbbs_apply_dirac": (i, [vp, i, vp, vp, i, vp]),
+            "mbbs_apply_dirac_raw": (i, [vp, i, i, vp, vp, vp, vp, vp]),
+            "mbbs_convert_to": (i, [i, sz, i, vp, vp, vp, vp]),
+            "mbbs_convert_from": (i, [i, sz, i, vp, vp, vp, vp]),
+            "mbbs_apply_blocked": (i, [vp, i, vp, vp, i, vp]),
+            "mbbs_sap_workspace_size": (i, [vp, i, i, ctypes.POINTER(sz)]),
+            "mbbs_sap_apply": (i, [vp, i, vp, vp, i, i, i, vp, sz, vp]),
+            "mbbs_gram_workspace_size": (i, [sz, i, ctypes.POINTER(sz)]),
+            "mbbs_gram": (i, [sz, i, vp, vp, vp, vp, sz, vp]),
+            "mbbs_cholqr": (i, [sz, i, vp, vp, vp, i, vp, sz, vp]),
+            "mbbs_lu_solve": (i, [i, i, vp, vp, vp, vp]),
+            "mbbs_solve_params_default": (None, [ctypes.POINTER(SolveParams)]),
+            "mbbs_solve_workspace_size": (i, [vp, i, ctypes.POINTER(SolveParams), ctypes.POINTER(sz)]),
+            "mbbs_solve": (i, [vp, i, vp, vp, ctypes.POINTER(SolveParams), vp, sz, ctypes.POINTER(SolveInfo), vp]),
+            "mbbs_solve_batched_workspace_size": (i, [i, ctypes.POINTER(vp), ctypes.POINTER(i),
+                                                      ctypes.POINTER(SolveParams), ctypes.POINTER(sz)]),
+            "mbbs_solve_batched": (i, [i, ctypes.POINTER(vp), ctypes.POINTER(i), ctypes.POINTER(vp),
+                                       ctypes.POINTER(vp), ctypes.POINTER(SolveParams), vp, sz,
+                                       ctypes.POINTER(SolveInfo), vp]),
+            "mbbs_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc < 0:
+        raise MbbsError(rc, lib().mbbs_last_error().decode())
+    return rc
+
+
+def _dev(t, dtype=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("device tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _opt(t):
+    return ctypes.c_void_p(0) if t is None else _dev(t)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _c128():
+    import torch
+    return torch.complex128
+
+
+# ----------------------------------------------------------------- lattice
+def mbbs_lattice_create(dims, block, U, kappa, phases, stream=None):
+    """U: complex128 device tensor (V, 4, 3, 3); phases: 4 (re, im) pairs."""
+    d = (ctypes.c_int * 4)(*dims)
+    b = (ctypes.c_int * 4)(*block)
+    ph = (ctypes.c_double * 8)(*[float(x) for p in phases for x in p])
+    out = ctypes.c_void_p()
+    _check(lib().mbbs_lattice_create(d, b, _dev(U, _c128()), float(kappa), ph, _stream(stream), ctypes.byref(out)))
+    return out
+
+
+def mbbs_lattice_destroy(lat):
+    return _check(lib().mbbs_lattice_destroy(lat))
+
+
+def mbbs_lattice_table(lat, which):
+    """Table `which` (int or name) as an int32 numpy array."""
+    if isinstance(which, str):
+        which = TABLES.index(which)
+    n = ctypes.c_size_t()
+    _check(lib().mbbs_lattice_table_size(lat, which, ctypes.byref(n)))
+    out = np.empty(n.value, dtype=np.int32)
+    _check(lib().mbbs_lattice_table(lat, which, out.ctypes.data_as(ctypes.c_void_p), n.value))
+    return out
+
+
+# ----------------------------------------------------------------- operator
+def mbbs_apply_dirac(lat, L, X, Y, prec=FP64, stream=None):
+    return _check(lib().mbbs_apply_dirac(lat, L, _dev(X, _c128()), _dev(Y, _c128()), prec, _stream(stream)))
+
+
+def mbbs_apply_dirac_raw(lat, L, prec, X, Xs, Y, Ys, stream=None):
+    return _check(lib().mbbs_apply_dirac_raw(lat, L, prec, _dev(X), _opt(Xs), _dev(Y), _opt(Ys), _stream(stream)))
+
+
+def mbbs_convert_to(prec, nsites, L, X, Y, Ys=None, stream=None):
+    return _check(lib().mbbs_convert_to(prec, nsites, L, _dev(X, _c128()), _dev(Y), _opt(Ys), _stream(stream)))
+
+
+def mbbs_convert_from(prec, nsites, L, X, Xs, Y, stream=None):
+    return _check(lib().mbbs_convert_from(prec, nsites, L, _dev(X), _opt(Xs), _dev(Y, _c128()), _stream(stream)))
+
+
+def mbbs_apply_blocked(lat, L, X, Y, prec=FP64, stream=None):
+    return _check(lib().mbbs_apply_blocked(lat, L, _dev(X, _c128()), _dev(Y, _c128()), prec, _stream(stream)))
+
+
+def mbbs_sap_workspace_size(lat, L, prec):
+    n = ctypes.c_size_t()
+    _check(lib().mbbs_sap_workspace_size(lat, L, prec, ctypes.byref(n)))
+    return n.value
+
+
+def mbbs_sap_apply(lat, L, X, Y, ncy, nmr, prec, ws, stream=None):
+    return _check(lib().mbbs_sap_apply(lat, L, _dev(X, _c128()), _dev(Y, _c128()), ncy, nmr, prec, _dev(ws),
+                                       ws.numel() * ws.element_size(), _stream(stream)))
+
+
+# ----------------------------------------------------------------- block LA
+def mbbs_gram_workspace_size(N, L):
+    n = ctypes.c_size_t()
+    _check(lib().mbbs_gram_workspace_size(N, L, ctypes.byref(n)))
+    return n.value
+
+
+def mbbs_gram(N, L, X, Y, G, ws, stream=None):
+    return _check(lib().mbbs_gram(N, L, _dev(X, _c128()), _dev(Y, _c128()), _dev(G, _c128()), _dev(ws),
+                                  ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def mbbs_cholqr(N, L, P, Q, gamma, passes, ws, stream=None):
+    return _check(lib().mbbs_cholqr(N, L, _dev(P, _c128()), _dev(Q, _c128()), _dev(gamma, _c128()), passes,
+                                    _dev(ws), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def mbbs_lu_solve(L, m, G, R, X, stream=None):
+    return _check(lib().mbbs_lu_solve(L, m, _dev(G, _c128()), _dev(R, _c128()), _dev(X, _c128()),
+                                      _stream(stream)))
+
+
+# ----------------------------------------------------------------- solver
+def mbbs_solve_params_default(**overrides):
+    p = SolveParams()
+    lib().mbbs_solve_params_default(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def mbbs_solve_workspace_size(lat, L, params):
+    n = ctypes.c_size_t()
+    _check(lib().mbbs_solve_workspace_size(lat, L, ctypes.byref(params), ctypes.byref(n)))
+    return n.value
+
+
+def _info(L):
+    info = SolveInfo()
+    tr = (ctypes.c_double * L)()
+    rr = (ctypes.c_double * L)()
+    info.true_res = ctypes.cast(tr, ctypes.POINTER(ctypes.c_double))
+    info.rec_res = ctypes.cast(rr, ctypes.POINTER(ctypes.c_double))
+    return info, tr, rr
+
+
+def _info_dict(info, tr, rr, rc):
+    return {"status": rc, "iterations": info.iterations, "restarts": info.restarts,
+            "n_dslash_outer": info.n_dslash_outer, "n_sap": info.n_sap,
+            "true_res": np.array(tr[:]), "rec_res": np.array(rr[:]), "seconds": info.seconds,
+            "kernel_ms": dict(zip(KERNEL_CLASSES, info.kernel_ms[:])),
+            "kernel_launches": dict(zip(KERNEL_CLASSES, info.kernel_launches[:]))}
+
+
+def mbbs_solve(lat, L, B, X, params, ws, stream=None):
+    """Returns a dict: status, iterations, restarts, residuals, timings."""
+    info, tr, rr = _info(L)
+    rc = _check(lib().mbbs_solve(lat, L, _dev(B, _c128()), _dev(X, _c128()), ctypes.byref(params), _dev(ws),
+                                 ws.numel() * ws.element_size(), ctypes.byref(info), _stream(stream)))
+    return _info_dict(info, tr, rr, rc)
+
+
+def mbbs_solve_batched_workspace_size(lats, Ls, params):
+    n = len(lats)
+    la = (ctypes.c_void_p * n)(*[x.value for x in lats])
+    Li = (ctypes.c_int * n)(*Ls)
+    pa = (SolveParams * n)(*params)
+    out = ctypes.c_size_t()
+    _check(lib().mbbs_solve_batched_workspace_size(n, la, Li, pa, ctypes.byref(out)))
+    return out.value
+
+
+def mbbs_solve_batched(lats, Ls, Bs, Xs, params, ws, stream=None):
+    n = len(lats)
+    la = (ctypes.c_void_p * n)(*[x.value for x in lats])
+    Li = (ctypes.c_int * n)(*Ls)
+    Bp = (ctypes.c_void_p * n)(*[_dev(b, _c128()).value for b in Bs])
+    Xp = (ctypes.c_void_p * n)(*[_dev(x, _c128()).value for x in Xs])
+    pa = (SolveParams * n)(*params)
+    infos = (SolveInfo * n)()
+    keep = []
+    for k in range(n):
+        tr = (ctypes.c_double * Ls[k])()
+        rr = (ctypes.c_double * Ls[k])()
+        infos[k].true_res = ctypes.cast(tr, ctypes.POINTER(ctypes.c_double))
+        infos[k].rec_res = ctypes.cast(rr, ctypes.POINTER(ctypes.c_double))
+        keep.append((tr, rr))
+    rc = _check(lib().mbbs_solve_batched(n, la, Li, Bp, Xp, pa, _dev(ws), ws.numel() * ws.element_size(), infos,
+                                         _stream(stream)))
+    return rc, [_info_dict(infos[k], keep[k][0], keep[k][1], infos[k].status) for k in range(n)]
+
+
+def mbbs_last_error():
+    return lib().mbbs_last_error().decode()

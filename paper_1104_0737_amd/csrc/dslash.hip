@@ -1,0 +1,686 @@
+// Multi-RHS Wilson hopping kernels (Sec. 2.1, block hopping-term equation):
+// one thread owns one site and C consecutive right-hand sides, loads each of
+// the 8 links once and applies it to all C columns (the link reuse across
+// right-hand sides the paper builds its cache tuning on), accumulating the
+// spin-projected hops in registers.  Variants: full operator, the
+// domain-restricted (Dirichlet) operator of Sec. 2.2, the SAP residual
+// eta - A psi, and the MR domain step with its per-domain reductions.
+#include "internal.h"
+#include "sitectx.h"
+
+namespace mbbs {
+
+template <typename R>
+struct Mat3 { cplx<R> m[3][3]; };
+
+template <int PL, typename R>
+__device__ __forceinline__ Mat3<R> load_link(const LinkElem<PL>* U, int site, int mu) {
+  Mat3<R> u;
+  const LinkElem<PL>* p = U + ((size_t)site * 4 + mu) * 9;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      auto v = Store<PL>::ld(p, a * 3 + b);
+      u.m[a][b] = cmake<R>((R)v.re, (R)v.im);
+    }
+  return u;
+}
+
+// Which hops a kernel sums: every hop, only hops inside the SAP domain
+// (Dirichlet operator A_DD), or only hops that leave it (coupling to the
+// neighbouring domains).
+enum Hops { ALL = 0, INSIDE = 1, OUTSIDE = 2 };
+
+// acc[spin][colour][k] += (1 -/+ gamma_mu) W psi_nb for the C columns.
+template <int PIN, int PL, int C, int ORDER, int HOPS, typename R>
+__device__ __forceinline__ void hop_sum(const GeomK& k, const SiteCtx& c,
+                                        const typename Store<PIN>::Elem* __restrict__ in,
+                                        const float* __restrict__ in_s,
+                                        const LinkElem<PL>* __restrict__ U, int L, int col0,
+                                        cplx<R> (&acc)[4][3][C]) {
+  R token = 0;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+    for (int fwd = 1; fwd >= 0; --fwd) {
+      const int dir = fwd ? 1 : -1;
+      if constexpr (HOPS != ALL) {
+        int r = (ORDER == DM) ? c.l[mu] : (c.x[mu] % k.g.b[mu]);
+        bool leaves = fwd ? (r == k.g.b[mu] - 1) : (r == 0);
+        if (HOPS == INSIDE && leaves) continue;
+        if (HOPS == OUTSIDE && !leaves) continue;
+      }
+      int sn = neighbour<ORDER>(k, c, mu, dir);
+      // Tie this hop's addresses to the previous hop's result so that its
+      // loads are not hoisted above it: one hop's data in flight per thread
+      // keeps register pressure low (other waves supply memory parallelism).
+      int ls = fwd ? c.s : sn;
+      asm volatile("" : "+v"(sn), "+v"(ls) : "v"(token));
+      bool wrap = fwd ? (c.x[mu] == k.g.d[mu] - 1) : (c.x[mu] == 0);
+      cplx<R> ph = cmake<R>((R)1, (R)0);
+      if (HOPS != INSIDE && wrap) ph = cmake<R>((R)k.g.ph[mu][0], (R)(fwd ? k.g.ph[mu][1] : -k.g.ph[mu][1]));
+      const Mat3<R> u = load_link<PL, R>(U, ls, mu);
+      const SpinRule sr = spin_rule(mu, fwd);
+#pragma unroll
+      for (int q = 0; q < C; ++q) {
+        const size_t base = (size_t)sn * 12 * L + col0 + q;
+        cplx<R> p[4][3];
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            auto v = Store<PIN>::ld(in, base + (size_t)(3 * sp + a) * L);
+            p[sp][a] = cmake<R>((R)v.re, (R)v.im);
+          }
+        if constexpr (Store<PIN>::scaled) {
+          R sc = (R)in_s[(size_t)sn * L + col0 + q];
+#pragma unroll
+          for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) p[sp][a] = sc * p[sp][a];
+        }
+        cplx<R> h0[3], h1[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          h0[a] = p[0][a] + umul(sr.A0, p[sr.P0][a]);
+          h1[a] = p[1][a] + umul(sr.A1, p[sr.P1][a]);
+        }
+        if (HOPS != INSIDE && wrap) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) { h0[a] = ph * h0[a]; h1[a] = ph * h1[a]; }
+        }
+        cplx<R> x0[3], x1[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          cplx<R> s0 = cmake<R>(0, 0), s1 = cmake<R>(0, 0);
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            if (fwd) {  // U h
+              s0 = s0 + u.m[a][b] * h0[b];
+              s1 = s1 + u.m[a][b] * h1[b];
+            } else {    // U^dagger h
+              s0 = s0 + cdot(u.m[b][a], h0[b]);
+              s1 = s1 + cdot(u.m[b][a], h1[b]);
+            }
+          }
+          x0[a] = s0; x1[a] = s1;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          acc[0][a][q] = acc[0][a][q] + x0[a];
+          acc[1][a][q] = acc[1][a][q] + x1[a];
+          acc[2][a][q] = acc[2][a][q] + umul(sr.B0, sr.Q0 ? x1[a] : x0[a]);
+          acc[3][a][q] = acc[3][a][q] + umul(sr.B1, sr.Q1 ? x1[a] : x0[a]);
+        }
+      }
+      // materialise the accumulators at every hop boundary (otherwise the
+      // additions are deferred and every hop's partial result stays live)
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int q = 0; q < C; ++q) asm volatile("" : "+v"(acc[sp][a][q].re), "+v"(acc[sp][a][q].im));
+      token = acc[0][0][0].re;
+    }
+  }
+}
+
+// Store one (site, column) spinor; P16 computes the per-(site, column) scale.
+template <int POUT, typename R>
+__device__ __forceinline__ void store_spinor(typename Store<POUT>::Elem* out, float* out_s,
+                                             size_t base, int L, size_t sidx, cplx<R> (&v)[4][3]) {
+  if constexpr (Store<POUT>::scaled) {
+    R m = 0;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) m = fmaxf(m, fmaxf(fabsf(v[sp][a].re), fabsf(v[sp][a].im)));
+    R inv = m > 0 ? (R)1 / m : (R)0;
+    out_s[sidx] = m;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) Store<POUT>::st(out, base + (size_t)(3 * sp + a) * L, inv * v[sp][a]);
+  } else {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        Store<POUT>::st(out, base + (size_t)(3 * sp + a) * L,
+                        cplx<typename Store<POUT>::Real>{(typename Store<POUT>::Real)v[sp][a].re,
+                                                         (typename Store<POUT>::Real)v[sp][a].im});
+  }
+}
+
+template <int PIN, typename R>
+__device__ __forceinline__ void load_spinor(const typename Store<PIN>::Elem* in, const float* in_s,
+                                            size_t base, int L, size_t sidx, cplx<R> (&v)[4][3]) {
+  R sc = 1;
+  if constexpr (Store<PIN>::scaled) sc = (R)in_s[sidx];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      auto e = Store<PIN>::ld(in, base + (size_t)(3 * sp + a) * L);
+      v[sp][a] = cmake<R>((R)e.re * sc, (R)e.im * sc);
+    }
+}
+
+// ---------------------------------------------------------------- kernels
+// Thread layout: threadIdx.x = column chunk (C columns each), threadIdx.y =
+// site within the block; blocks cover consecutive sites of the field order.
+template <int PIN, int POUT, int PL, int C, int ORDER, bool BLOCKED>
+__global__ void __launch_bounds__(256) k_dslash(GeomK k, double kappa, int L,
+                                                const typename Store<PIN>::Elem* __restrict__ in,
+                                                const float* __restrict__ in_s,
+                                                typename Store<POUT>::Elem* __restrict__ out,
+                                                float* __restrict__ out_s,
+                                                const LinkElem<PL>* __restrict__ U, int s0, int n,
+                                                const int* __restrict__ frozen) {
+  if (frozen && *frozen) return;
+  using R = typename Store<PL>::Real;
+  const int s = s0 + blockIdx.x * blockDim.y + threadIdx.y;
+  if (s >= s0 + n) return;
+  const int col0 = threadIdx.x * C;
+  const SiteCtx c = site_ctx<ORDER>(k, s);
+  cplx<R> acc[4][3][C];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int q = 0; q < C; ++q) acc[sp][a][q] = cmake<R>(0, 0);
+  hop_sum<PIN, PL, C, ORDER, BLOCKED ? INSIDE : ALL, R>(k, c, in, in_s, U, L, col0, acc);
+  const R kap = (R)kappa;
+#pragma unroll
+  for (int q = 0; q < C; ++q) {
+    const size_t base = (size_t)s * 12 * L + col0 + q;
+    cplx<R> v[4][3];
+    load_spinor<PIN, R>(in, in_s, base, L, (size_t)s * L + col0 + q, v);
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v[sp][a] = v[sp][a] - kap * acc[sp][a][q];
+    store_spinor<POUT, R>(out, out_s, base, L, (size_t)s * L + col0 + q, v);
+  }
+}
+
+// SAP residual on the sites of one colour: r = eta - (psi - kappa H psi).
+// mode 0: psi = 0 everywhere (first half-sweep): r = eta.
+// mode 1: psi = 0 on this colour (second half-sweep of the first cycle): only
+//         hops leaving the domain see a nonzero psi, r = eta + kappa H_out psi.
+// mode 2: general case.
+template <int PR, int PPSI, int PL, int C>
+__global__ void __launch_bounds__(256) k_sap_resid(GeomK k, double kappa, int L, int s0, int n, int mode,
+                                                   const typename Store<PR>::Elem* __restrict__ eta,
+                                                   const float* __restrict__ eta_s,
+                                                   const typename Store<PPSI>::Elem* __restrict__ psi,
+                                                   typename Store<PR>::Elem* __restrict__ r,
+                                                   float* __restrict__ r_s,
+                                                   const LinkElem<PL>* __restrict__ U,
+                                                   const int* __restrict__ frozen) {
+  if (frozen && *frozen) return;
+  using R = typename Store<PL>::Real;
+  const int s = s0 + blockIdx.x * blockDim.y + threadIdx.y;
+  if (s >= s0 + n) return;
+  const int col0 = threadIdx.x * C;
+  cplx<R> acc[4][3][C];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int q = 0; q < C; ++q) acc[sp][a][q] = cmake<R>(0, 0);
+  if (mode != 0) {
+    const SiteCtx c = site_ctx<DM>(k, s);
+    if (mode == 1) hop_sum<PPSI, PL, C, DM, OUTSIDE, R>(k, c, psi, nullptr, U, L, col0, acc);
+    else hop_sum<PPSI, PL, C, DM, ALL, R>(k, c, psi, nullptr, U, L, col0, acc);
+  }
+  const R kap = (R)kappa;
+#pragma unroll
+  for (int q = 0; q < C; ++q) {
+    const size_t base = (size_t)s * 12 * L + col0 + q;
+    const size_t sidx = (size_t)s * L + col0 + q;
+    cplx<R> e[4][3];
+    load_spinor<PR, R>(eta, eta_s, base, L, sidx, e);
+    if (mode != 0) {
+      cplx<R> p[4][3];
+      if (mode == 2) {
+        load_spinor<PPSI, R>(psi, nullptr, base, L, sidx, p);
+      } else {
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) p[sp][a] = cmake<R>(0, 0);
+      }
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) e[sp][a] = e[sp][a] - p[sp][a] + kap * acc[sp][a][q];
+    }
+    store_spinor<PR, R>(r, r_s, base, L, sidx, e);
+  }
+}
+
+// MR step, part 1: w = A_DD r on one colour's domains, plus per-block sums of
+// <w, r> and <w, w> per column; the last block of each domain to finish sums
+// the domain's block partials in fixed order and writes the step size
+// omega = <w, r> / <w, w> (0 when <w, w> = 0).
+template <int PR, int PL, int C>
+__global__ void __launch_bounds__(256) k_mr_dslash(GeomK k, double kappa, int L, int s0, int n,
+                                                   const typename Store<PR>::Elem* __restrict__ r,
+                                                   const float* __restrict__ r_s,
+                                                   typename Store<PR>::Elem* __restrict__ w,
+                                                   float* __restrict__ w_s,
+                                                   const LinkElem<PL>* __restrict__ U,
+                                                   double* __restrict__ partial,
+                                                   unsigned* __restrict__ counter,
+                                                   double* __restrict__ omega,
+                                                   const int* __restrict__ frozen) {
+  if (frozen && *frozen) return;
+  using R = typename Store<PL>::Real;
+  extern __shared__ double red[];  // [3][blockDim.y][blockDim.x*C]
+  const int s = s0 + blockIdx.x * blockDim.y + threadIdx.y;  // blocks never straddle domains
+  const int col0 = threadIdx.x * C;
+  const SiteCtx c = site_ctx<DM>(k, s);
+  cplx<R> acc[4][3][C];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int q = 0; q < C; ++q) acc[sp][a][q] = cmake<R>(0, 0);
+  hop_sum<PR, PL, C, DM, INSIDE, R>(k, c, r, r_s, U, L, col0, acc);
+  const R kap = (R)kappa;
+  const int ny = blockDim.y, nx = blockDim.x * C;
+#pragma unroll
+  for (int q = 0; q < C; ++q) {
+    const size_t base = (size_t)s * 12 * L + col0 + q;
+    const size_t sidx = (size_t)s * L + col0 + q;
+    cplx<R> v[4][3];
+    load_spinor<PR, R>(r, r_s, base, L, sidx, v);
+    double wr_re = 0, wr_im = 0, ww = 0;
+    cplx<R> wv[4][3];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        wv[sp][a] = v[sp][a] - kap * acc[sp][a][q];
+      }
+    store_spinor<PR, R>(w, w_s, base, L, sidx, wv);
+    if constexpr (Store<PR>::scaled) {
+      // use the stored (rounded) w so that the update sees the same vector
+      load_spinor<PR, R>(w, w_s, base, L, sidx, wv);
+    }
+    R a_re = 0, a_im = 0, a_ww = 0;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cplx<R> d = cdot(wv[sp][a], v[sp][a]);
+        a_re += d.re; a_im += d.im; a_ww += norm2(wv[sp][a]);
+      }
+    wr_re = a_re; wr_im = a_im; ww = a_ww;
+    const int col = col0 + q;
+    red[(0 * ny + threadIdx.y) * nx + col] = wr_re;
+    red[(1 * ny + threadIdx.y) * nx + col] = wr_im;
+    red[(2 * ny + threadIdx.y) * nx + col] = ww;
+  }
+  __syncthreads();
+  // tree over sites (fixed order), one thread per (quantity, column)
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int nthr = blockDim.x * blockDim.y;
+  for (int stride = 1; stride < ny; stride <<= 1) {
+    for (int e = tid; e < 3 * nx * ny; e += nthr) {
+      int qn = e / (nx * ny), rem = e % (nx * ny), y = rem / nx, col = rem % nx;
+      if ((y % (2 * stride)) == 0 && y + stride < ny)
+        red[(qn * ny + y) * nx + col] += red[(qn * ny + y + stride) * nx + col];
+    }
+    __syncthreads();
+  }
+  const int rel = blockIdx.x * ny;                        // first site of the block in its colour
+  const int dom = rel / k.g.Vb;                           // domain rank within the colour
+  const int nblk = k.g.Vb / ny;
+  const int bid = (rel % k.g.Vb) / ny;                    // block index inside the domain
+  for (int e = tid; e < 3 * nx; e += nthr) {
+    int qn = e / nx, col = e % nx;
+    partial[(((size_t)dom * nblk + bid) * L + col) * 3 + qn] = red[(qn * ny + 0) * nx + col];
+  }
+  __threadfence();
+  __syncthreads();
+  __shared__ unsigned last;
+  if (tid == 0) last = (atomicInc(&counter[dom], (unsigned)(nblk - 1)) == (unsigned)(nblk - 1));
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  for (int col = tid; col < L; col += nthr) {
+    double a_re = 0, a_im = 0, a_ww = 0;
+    const volatile double* pp = partial + ((size_t)dom * nblk) * L * 3;
+    for (int b = 0; b < nblk; ++b) {
+      a_re += pp[((size_t)b * L + col) * 3 + 0];
+      a_im += pp[((size_t)b * L + col) * 3 + 1];
+      a_ww += pp[((size_t)b * L + col) * 3 + 2];
+    }
+    double o_re = 0, o_im = 0;
+    if (a_ww > 0) { o_re = a_re / a_ww; o_im = a_im / a_ww; }
+    omega[((size_t)dom * L + col) * 2 + 0] = o_re;
+    omega[((size_t)dom * L + col) * 2 + 1] = o_im;
+  }
+}
+
+// MR step, part 2: psi += omega r ; r -= omega w  (per domain and column).
+template <int PR, int PPSI>
+__global__ void __launch_bounds__(256) k_mr_update(GeomK k, int L, int s0, int n,
+                                                   typename Store<PR>::Elem* __restrict__ r,
+                                                   float* __restrict__ r_s,
+                                                   const typename Store<PR>::Elem* __restrict__ w,
+                                                   const float* __restrict__ w_s,
+                                                   typename Store<PPSI>::Elem* __restrict__ psi,
+                                                   const double* __restrict__ omega, int update_r,
+                                                   int assign, const int* __restrict__ frozen) {
+  if (frozen && *frozen) return;
+  using R = typename Store<PR>::Real;
+  using RP = typename Store<PPSI>::Real;
+  const int s = s0 + blockIdx.x * blockDim.y + threadIdx.y;
+  if (s >= s0 + n) return;
+  const int col = threadIdx.x;
+  const int dom = (s - (s >= k.g.Vh ? k.g.Vh : 0)) / k.g.Vb;
+  const cplx<R> om = cmake<R>((R)omega[((size_t)dom * L + col) * 2], (R)omega[((size_t)dom * L + col) * 2 + 1]);
+  const size_t base = (size_t)s * 12 * L + col;
+  const size_t sidx = (size_t)s * L + col;
+  cplx<R> rv[4][3];
+  load_spinor<PR, R>(r, r_s, base, L, sidx, rv);
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const size_t i = base + (size_t)(3 * sp + a) * L;
+      cplx<R> d = om * rv[sp][a];
+      if (assign) {
+        Store<PPSI>::st(psi, i, cplx<RP>{(RP)d.re, (RP)d.im});
+      } else {
+        auto pv = Store<PPSI>::ld(psi, i);
+        Store<PPSI>::st(psi, i, cplx<RP>{(RP)(pv.re + (RP)d.re), (RP)(pv.im + (RP)d.im)});
+      }
+    }
+  if (!update_r) return;
+  cplx<R> wv[4][3];
+  load_spinor<PR, R>(w, w_s, base, L, sidx, wv);
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) rv[sp][a] = rv[sp][a] - om * wv[sp][a];
+  store_spinor<PR, R>(r, r_s, base, L, sidx, rv);
+}
+
+// ---------------------------------------------------------------- host side
+GeomK make_geomk(const Geom& g) {
+  GeomK k;
+  k.g = g;
+  for (int m = 0; m < 4; ++m) {
+    k.fd[m] = make_fastdiv(g.d[m]);
+    k.fb[m] = make_fastdiv(g.b[m]);
+  }
+  k.fnd0 = make_fastdiv(g.nd[0]);
+  k.fVb = make_fastdiv(g.Vb);
+  k.lstride[0] = 1;
+  k.stride[0] = 1;
+  for (int m = 1; m < 4; ++m) {
+    k.lstride[m] = k.lstride[m - 1] * g.b[m - 1];
+    k.stride[m] = k.stride[m - 1] * g.d[m - 1];
+  }
+  return k;
+}
+
+// Sites per block so that blockDim = (L/C, S) has about `target` threads and S
+// divides `vdiv` (so blocks never straddle SAP domains when vdiv = Vb).
+static int sites_per_block(int nchunk, int vdiv, int target = 256) {
+  int best = 1;
+  for (int s = 1; s * nchunk <= target; ++s)
+    if (vdiv % s == 0) best = s;
+  return best;
+}
+
+template <int PIN, int POUT, int PL, int C>
+static int dslash_dispatch_order(const mbbs_lattice_s* lat, int L, int order, bool blocked,
+                                 const void* in, const float* in_s, void* out, float* out_s,
+                                 int s0, int n, const int* frozen, hipStream_t st) {
+  const int nchunk = L / C;
+  const int S = sites_per_block(nchunk, lat->g.Vb);
+  dim3 blk(nchunk, S);
+  dim3 grd(ceil_div(n, S));
+  const void* U;
+  if (order == LEX) U = PL == P64 ? (const void*)lat->U64 : PL == P32 ? (const void*)lat->U32 : (const void*)lat->U16;
+  else U = PL == P64 ? (const void*)lat->U64dm : PL == P32 ? (const void*)lat->U32dm : (const void*)lat->U16dm;
+  using EI = typename Store<PIN>::Elem;
+  using EO = typename Store<POUT>::Elem;
+  using EL = LinkElem<PL>;
+#define MBBS_LAUNCH(ORD, BLK)                                                                   \
+  hipLaunchKernelGGL((k_dslash<PIN, POUT, PL, C, ORD, BLK>), grd, blk, 0, st, lat->gk, lat->kappa, L, \
+                     (const EI*)in, in_s, (EO*)out, out_s, (const EL*)U, s0, n, frozen)
+  if (order == LEX) {
+    if (blocked) MBBS_LAUNCH(LEX, true); else MBBS_LAUNCH(LEX, false);
+  } else {
+    if (blocked) MBBS_LAUNCH(DM, true); else MBBS_LAUNCH(DM, false);
+  }
+#undef MBBS_LAUNCH
+  MBBS_HIP(hipGetLastError());
+  return MBBS_OK;
+}
+
+template <int PIN, int POUT, int PL>
+static int dslash_dispatch_c(const mbbs_lattice_s* lat, int L, int order, bool blocked,
+                             const void* in, const float* in_s, void* out, float* out_s, int s0,
+                             int n, const int* frozen, hipStream_t st) {
+  switch (pick_chunk(L, PL)) {
+    case 4: return dslash_dispatch_order<PIN, POUT, PL, 4>(lat, L, order, blocked, in, in_s, out, out_s, s0, n, frozen, st);
+    case 3: return dslash_dispatch_order<PIN, POUT, PL, 3>(lat, L, order, blocked, in, in_s, out, out_s, s0, n, frozen, st);
+    case 2: return dslash_dispatch_order<PIN, POUT, PL, 2>(lat, L, order, blocked, in, in_s, out, out_s, s0, n, frozen, st);
+    default: return dslash_dispatch_order<PIN, POUT, PL, 1>(lat, L, order, blocked, in, in_s, out, out_s, s0, n, frozen, st);
+  }
+}
+
+int launch_dslash(const mbbs_lattice_s* lat, int L, int prec_in, int prec_out, int order,
+                  bool blocked, const void* in, const float* in_s, void* out, float* out_s,
+                  int s0, int n, const int* frozen, hipStream_t st) {
+  if (n <= 0) return MBBS_OK;
+  if (prec_in == P64 && prec_out == P64)
+    return dslash_dispatch_c<P64, P64, P64>(lat, L, order, blocked, in, in_s, out, out_s, s0, n, frozen, st);
+  if (prec_in == P32 && prec_out == P64)
+    return dslash_dispatch_c<P32, P64, P64>(lat, L, order, blocked, in, in_s, out, out_s, s0, n, frozen, st);
+  if (prec_in == P32 && prec_out == P32)
+    return dslash_dispatch_c<P32, P32, P32>(lat, L, order, blocked, in, in_s, out, out_s, s0, n, frozen, st);
+  if (prec_in == P16 && prec_out == P16)
+    return dslash_dispatch_c<P16, P16, P16>(lat, L, order, blocked, in, in_s, out, out_s, s0, n, frozen, st);
+  set_error("unsupported precision combination");
+  return MBBS_EINVAL;
+}
+
+// ---------------------------------------------------------------- SAP host
+size_t sap_buffer_bytes(const mbbs_lattice_s* lat, int L, int prec) {
+  const size_t V = lat->g.V;
+  const size_t elem = prec == P64 ? 16 : prec == P32 ? 8 : 4;
+  const size_t field = V * 12 * L * elem;
+  const size_t scales = prec == P16 ? V * L * sizeof(float) : 0;
+  const size_t psi = V * 12 * L * (prec == P64 ? 16 : 8);
+  const size_t ndc = lat->g.ndom / 2;             // domains per colour
+  const size_t nblk = lat->g.Vh;                  // upper bound on blocks per colour
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  return al(field) * 3 + al(scales) * 3 + al(psi) + al(nblk * L * 3 * sizeof(double)) +
+         al(ndc * sizeof(unsigned)) + al(ndc * L * 2 * sizeof(double));
+}
+
+int sap_bind(const mbbs_lattice_s* lat, int L, int prec, void* ws, size_t bytes, SapBuffers* b) {
+  const size_t need = sap_buffer_bytes(lat, L, prec);
+  MBBS_CHECK(ws != nullptr && bytes >= need, "SAP workspace too small");
+  const size_t V = lat->g.V;
+  const size_t elem = prec == P64 ? 16 : prec == P32 ? 8 : 4;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  char* p = (char*)ws;
+  const size_t field = al(V * 12 * L * elem);
+  const size_t scales = al(prec == P16 ? V * L * sizeof(float) : 0);
+  b->L = L;
+  b->prec = prec;
+  b->eta = p; p += field;
+  b->r = p; p += field;
+  b->w = p; p += field;
+  b->eta_s = prec == P16 ? (float*)p : nullptr; p += scales;
+  b->r_s = prec == P16 ? (float*)p : nullptr; p += scales;
+  b->w_s = prec == P16 ? (float*)p : nullptr; p += scales;
+  b->psi = p; p += al(V * 12 * L * (prec == P64 ? 16 : 8));
+  b->partial = (double*)p; p += al((size_t)lat->g.Vh * L * 3 * sizeof(double));
+  b->counter = (unsigned*)p; p += al((size_t)lat->g.ndom / 2 * sizeof(unsigned));
+  b->omega = (double*)p;
+  return MBBS_OK;
+}
+
+template <int PR, int PPSI, int PL>
+static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, int nmr,
+                      const int* frozen, hipStream_t st, Profiler* prof) {
+  using ER = typename Store<PR>::Elem;
+  using EP = typename Store<PPSI>::Elem;
+  using EL = LinkElem<PL>;
+  const int L = b.L;
+  const Geom& g = lat->g;
+  const EL* U = PL == P64 ? (const EL*)lat->U64dm : PL == P32 ? (const EL*)lat->U32dm : (const EL*)lat->U16dm;
+  const int C = pick_chunk(L, PL);
+  const int nchunk = L / C;
+  const int S = sites_per_block(nchunk, g.Vb);
+  const int Su = sites_per_block(L, g.Vb);
+  const size_t red_bytes = 3 * (size_t)S * nchunk * C * sizeof(double);
+  for (int cy = 0; cy < ncy; ++cy) {
+    for (int col = 0; col < 2; ++col) {
+      const int s0 = col * g.Vh, n = g.Vh;
+      if (prof) prof->begin(MBBS_K_SAP_RES);
+#define RES(CC)                                                                                      \
+  hipLaunchKernelGGL((k_sap_resid<PR, PPSI, PL, CC>), dim3(ceil_div(n, S)), dim3(nchunk, S), 0, st,   \
+                     lat->gk, lat->kappa, L, s0, n, cy > 0 ? 2 : col, (const ER*)b.eta,                \
+                     b.eta_s, (const EP*)b.psi, (ER*)b.r, b.r_s, U, frozen)
+      switch (C) { case 4: RES(4); break; case 3: RES(3); break; case 2: RES(2); break; default: RES(1); }
+#undef RES
+      if (prof) prof->end();
+      MBBS_HIP(hipGetLastError());
+      for (int it = 0; it < nmr; ++it) {
+        if (prof) prof->begin(MBBS_K_MR_DSLASH);
+#define MRD(CC)                                                                                       \
+  hipLaunchKernelGGL((k_mr_dslash<PR, PL, CC>), dim3(n / S), dim3(nchunk, S), red_bytes, st, lat->gk, \
+                     lat->kappa, L, s0, n, (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial,      \
+                     b.counter, b.omega, frozen)
+        switch (C) { case 4: MRD(4); break; case 3: MRD(3); break; case 2: MRD(2); break; default: MRD(1); }
+#undef MRD
+        if (prof) prof->end();
+        MBBS_HIP(hipGetLastError());
+        if (prof) prof->begin(MBBS_K_MR_UPDATE);
+        hipLaunchKernelGGL((k_mr_update<PR, PPSI>), dim3(ceil_div(n, Su)), dim3(L, Su), 0, st, lat->gk, L, s0,
+                           n, (ER*)b.r, b.r_s, (const ER*)b.w, b.w_s, (EP*)b.psi, b.omega,
+                           (int)(it + 1 < nmr), (int)(cy == 0 && it == 0), frozen);
+        if (prof) prof->end();
+        MBBS_HIP(hipGetLastError());
+      }
+    }
+  }
+  return MBBS_OK;
+}
+
+// Conversion kernels between the FP64 lexicographic block and the SAP
+// domain-major storage.  to_sap optionally right-multiplies by an L x L
+// matrix first (the Cholesky-QR factor gamma^{-1}, folded into the copy).
+template <int PR>
+__global__ void __launch_bounds__(256) k_to_sap(GeomK k, int L, const double2* __restrict__ in,
+                                                const double2* __restrict__ gam,
+                                                typename Store<PR>::Elem* __restrict__ out,
+                                                float* __restrict__ out_s, const int* __restrict__ frozen) {
+  if (frozen && *frozen) return;
+  using R = typename Store<PR>::Real;
+  extern __shared__ double2 gsh[];
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  if (gam) {
+    for (int e = tid; e < L * L; e += blockDim.x * blockDim.y) gsh[e] = gam[e];
+    __syncthreads();
+  }
+  const int s = blockIdx.x * blockDim.y + threadIdx.y;  // domain-major index
+  if (s >= k.g.V) return;
+  const int j = threadIdx.x;
+  const SiteCtx c = site_ctx<DM>(k, s);
+  Coord x;
+  for (int m = 0; m < 4; ++m) x.c[m] = c.x[m];
+  const int ls = lex_site(k.g, x);
+  cplx<double> v[4][3];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const size_t row = ((size_t)ls * 12 + 3 * sp + a) * L;
+      if (gam) {
+        cplx<double> acc = cmake(0.0, 0.0);
+        for (int m = 0; m < L; ++m) {
+          double2 e = in[row + m], gg = gsh[m * L + j];
+          acc = acc + cmake(e.x, e.y) * cmake(gg.x, gg.y);
+        }
+        v[sp][a] = acc;
+      } else {
+        double2 e = in[row + j];
+        v[sp][a] = cmake(e.x, e.y);
+      }
+    }
+  cplx<R> vr[4][3];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) vr[sp][a] = cmake<R>((R)v[sp][a].re, (R)v[sp][a].im);
+  store_spinor<PR, R>(out, out_s, (size_t)s * 12 * L + j, L, (size_t)s * L + j, vr);
+}
+
+template <int PPSI>
+__global__ void __launch_bounds__(256) k_from_sap(GeomK k, int L, const typename Store<PPSI>::Elem* __restrict__ in,
+                                                  double2* __restrict__ out, const int* __restrict__ frozen) {
+  if (frozen && *frozen) return;
+  const int s = blockIdx.x * blockDim.y + threadIdx.y;
+  if (s >= k.g.V) return;
+  const int j = threadIdx.x;
+  const SiteCtx c = site_ctx<DM>(k, s);
+  Coord x;
+  for (int m = 0; m < 4; ++m) x.c[m] = c.x[m];
+  const int ls = lex_site(k.g, x);
+#pragma unroll
+  for (int e = 0; e < 12; ++e) {
+    auto v = Store<PPSI>::ld(in, ((size_t)s * 12 + e) * L + j);
+    out[((size_t)ls * 12 + e) * L + j] = make_double2((double)v.re, (double)v.im);
+  }
+}
+
+int sap_apply(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, int nmr, const double2* in,
+              const double2* gam, double2* out, const int* frozen, hipStream_t st, Profiler* prof) {
+  const int L = b.L;
+  const Geom& g = lat->g;
+  const int S = sites_per_block(L, g.V);
+  if (prof) prof->begin(MBBS_K_CONVERT);
+  const size_t gsh = gam ? (size_t)L * L * sizeof(double2) : 0;
+  switch (b.prec) {
+    case P64: hipLaunchKernelGGL((k_to_sap<P64>), dim3(ceil_div(g.V, S)), dim3(L, S), gsh, st, lat->gk, L, in, gam, (double2*)b.eta, nullptr, frozen); break;
+    case P32: hipLaunchKernelGGL((k_to_sap<P32>), dim3(ceil_div(g.V, S)), dim3(L, S), gsh, st, lat->gk, L, in, gam, (float2*)b.eta, nullptr, frozen); break;
+    default: hipLaunchKernelGGL((k_to_sap<P16>), dim3(ceil_div(g.V, S)), dim3(L, S), gsh, st, lat->gk, L, in, gam, (__half2*)b.eta, b.eta_s, frozen); break;
+  }
+  if (prof) prof->end();
+  MBBS_HIP(hipGetLastError());
+  // psi needs no clearing: the first MR step of the first cycle assigns it.
+  int rc;
+  switch (b.prec) {
+    case P64: rc = sap_cycles<P64, P64, P64>(lat, b, ncy, nmr, frozen, st, prof); break;
+    case P32: rc = sap_cycles<P32, P32, P32>(lat, b, ncy, nmr, frozen, st, prof); break;
+    default: rc = sap_cycles<P16, P32, P16>(lat, b, ncy, nmr, frozen, st, prof); break;
+  }
+  if (rc < 0) return rc;
+  if (prof) prof->begin(MBBS_K_CONVERT);
+  if (b.prec == P64)
+    hipLaunchKernelGGL((k_from_sap<P64>), dim3(ceil_div(g.V, S)), dim3(L, S), 0, st, lat->gk, L, (const double2*)b.psi, out, frozen);
+  else
+    hipLaunchKernelGGL((k_from_sap<P32>), dim3(ceil_div(g.V, S)), dim3(L, S), 0, st, lat->gk, L, (const float2*)b.psi, out, frozen);
+  if (prof) prof->end();
+  MBBS_HIP(hipGetLastError());
+  return MBBS_OK;
+}
+
+}  // namespace mbbs

@@ -1,0 +1,152 @@
+// Internal host-side declarations shared by the library's translation units.
+#pragma once
+
+#include <string>
+
+#include "common.h"
+#include "../../include/mbbs.h"
+
+namespace mbbs {
+
+// Error reporting: a thread-local message plus a status code.
+void set_error(const std::string& msg);
+const char* last_error();
+
+#define MBBS_HIP(call)                                                            \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      ::mbbs::set_error(std::string(#call) + ": " + hipGetErrorString(e_));       \
+      return MBBS_EHIP;                                                           \
+    }                                                                             \
+  } while (0)
+
+#define MBBS_CHECK(cond, msg)                                                     \
+  do {                                                                            \
+    if (!(cond)) {                                                                \
+      ::mbbs::set_error(msg);                                                     \
+      return MBBS_EINVAL;                                                         \
+    }                                                                             \
+  } while (0)
+
+#define MBBS_TRY(call)                                                            \
+  do {                                                                            \
+    int r_ = (call);                                                              \
+    if (r_ < 0) return r_;                                                        \
+  } while (0)
+
+// Unsigned division by a runtime constant: q = umulhi(n, mul) >> shift
+// (Granlund-Montgomery round-up method), exact for 0 <= n < 2^31.
+struct FastDiv {
+  uint32_t d, mul, shift;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f{d, 0, 0};
+  if (d == 1) { f.mul = 0; f.shift = 0; return f; }
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  f.shift = l - 1;
+  f.mul = (uint32_t)((((1ull << 32) * ((1ull << l) - d)) / d) + 1);
+  return f;
+}
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+  if (f.d == 1) return n;
+  uint32_t t = __umulhi(n, f.mul);
+  return (t + ((n - t) >> 1)) >> f.shift;
+}
+
+// Geometry plus the fast dividers and strides the kernels need.
+struct GeomK {
+  Geom g;
+  FastDiv fd[4];     // extents
+  FastDiv fb[4];     // block sizes
+  FastDiv fnd0;      // domains along x
+  FastDiv fVb;       // block volume
+  int lstride[4];    // local strides inside a domain
+  int stride[4];     // lexicographic strides
+};
+GeomK make_geomk(const Geom& g);
+
+}  // namespace mbbs
+
+struct mbbs_lattice_s {
+  mbbs::Geom g;
+  mbbs::GeomK gk;
+  double kappa;
+  int device;
+  double2* U64 = nullptr;     // lexicographic links (FP64), [site][mu][a][b]
+  float2* U32 = nullptr;
+  __half2* U16 = nullptr;
+  double2* U64dm = nullptr;   // domain-major links
+  float2* U32dm = nullptr;
+  __half2* U16dm = nullptr;
+};
+
+namespace mbbs {
+
+// ---------------------------------------------------------------- launchers
+// Field order of a kernel's sites.
+enum Order { LEX = 0, DM = 1 };
+
+// out = in - kappa * H(in) on sites [s0, s0 + n) (order `order`), all hops
+// (blocked = false) or in-domain hops only (blocked = true).
+int launch_dslash(const mbbs_lattice_s* lat, int L, int prec_in, int prec_out, int order,
+                  bool blocked, const void* in, const float* in_s, void* out, float* out_s,
+                  int s0, int n, const int* frozen, hipStream_t st);
+
+// SAP pieces (domain-major order, colour c sites [c*Vh, (c+1)*Vh)).
+struct SapBuffers {
+  int L, prec;             // prec of r, w, eta; psi is FP64 for P64 else FP32
+  void* eta; float* eta_s;
+  void* r;   float* r_s;
+  void* w;   float* w_s;
+  void* psi;               // double2 or float2
+  double* partial;         // per block, per column: (wr.re, wr.im, ww)
+  unsigned* counter;       // per domain-of-colour arrival counters (zeroed)
+  double* omega;           // per domain-of-colour, per column: complex step
+};
+size_t sap_buffer_bytes(const mbbs_lattice_s* lat, int L, int prec);
+int sap_bind(const mbbs_lattice_s* lat, int L, int prec, void* ws, size_t bytes, SapBuffers* b);
+// Full preconditioner application.  `in` is an FP64 lexicographic block;
+// if gam != nullptr, in is right-multiplied by the L x L matrix gam (device,
+// row-major) first.  out (FP64 lexicographic) receives psi.  `frozen` (device
+// int, may be null) makes every kernel a no-op when nonzero.
+int sap_apply(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, int nmr,
+              const double2* in, const double2* gam, double2* out, const int* frozen,
+              hipStream_t st, struct Profiler* prof);
+
+// Conversions between the FP64 ABI block and the precision storages.
+int launch_convert_to(int prec, size_t nsites, int L, const double2* x, void* y, float* ys,
+                      hipStream_t st);
+int launch_convert_from(int prec, size_t nsites, int L, const void* x, const float* xs,
+                        double2* y, hipStream_t st);
+
+// Index tables.
+int build_table(const mbbs_lattice_s* lat, int which, int32_t* dev_out, hipStream_t st);
+size_t table_entries(const mbbs_lattice_s* lat, int which);
+
+// Kernel-class timing with HIP events (solver profile mode).
+struct Profiler {
+  static constexpr int CAP = 512;
+  bool on = false;
+  hipStream_t st = nullptr;
+  hipEvent_t ev[2 * CAP];
+  int cls[CAP];
+  int n = 0;
+  double ms[MBBS_K_COUNT] = {0};
+  long long launches[MBBS_K_COUNT] = {0};
+  void begin(int k);
+  void end();
+  void flush();
+};
+
+// Launch configuration helpers.
+inline int pick_chunk(int L, int prec) {
+  // columns per thread: amortise link loads and index work over columns
+  int cmax = prec == P64 ? 1 : 2;
+  for (int c = cmax; c > 1; --c)
+    if (L % c == 0) return c;
+  return 1;
+}
+
+}  // namespace mbbs

@@ -1,0 +1,238 @@
+// Lattice handle: geometry validation, device copies of the links in every
+// precision and site order the kernels read, index tables, error strings and
+// the kernel-class profiler.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+#include "sitectx.h"
+
+namespace mbbs {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+const char* last_error() { return g_err.c_str(); }
+
+// Link copies: lexicographic FP32/FP16 and domain-major FP64/FP32/FP16.
+__global__ void k_links(GeomK k, const double2* __restrict__ U, float2* __restrict__ U32, __half2* __restrict__ U16,
+                        double2* __restrict__ U64dm, float2* __restrict__ U32dm, __half2* __restrict__ U16dm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // domain-major position
+  if (i >= k.g.V) return;
+  const SiteCtx c = site_ctx<DM>(k, i);
+  Coord x;
+  for (int m = 0; m < 4; ++m) x.c[m] = c.x[m];
+  const int s = lex_site(k.g, x);
+  for (int e = 0; e < 36; ++e) {
+    const double2 v = U[(size_t)i * 36 + e];  // lexicographic site i
+    U32[(size_t)i * 36 + e] = make_float2((float)v.x, (float)v.y);
+    U16[(size_t)i * 36 + e] = __floats2half2_rn((float)v.x, (float)v.y);
+    const double2 w = U[(size_t)s * 36 + e];  // site at domain-major position i
+    U64dm[(size_t)i * 36 + e] = w;
+    U32dm[(size_t)i * 36 + e] = make_float2((float)w.x, (float)w.y);
+    U16dm[(size_t)i * 36 + e] = __floats2half2_rn((float)w.x, (float)w.y);
+  }
+}
+
+// All per-site tables, from the kernels' own index functions.
+__global__ void k_tables(GeomK k, int which, int32_t* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const Geom& g = k.g;
+  if (which == MBBS_TAB_LOCAL_NB) {
+    if (i >= g.Vb) return;
+    // local site i of the first colour-0 domain (domain id 0, position i)
+    const SiteCtx c = site_ctx<DM>(k, i);
+    for (int mu = 0; mu < 4; ++mu)
+      for (int s = 0; s < 2; ++s) {
+        const int dir = s ? -1 : 1;
+        const int lv = c.l[mu] + dir;
+        out[(size_t)i * 8 + 2 * mu + s] = (lv >= 0 && lv < g.b[mu]) ? neighbour<DM>(k, c, mu, dir) - (i - c.loc) : -1;
+      }
+    return;
+  }
+  if (i >= g.V) return;
+  if (which == MBBS_TAB_DM_NEIGHBOUR || which == MBBS_TAB_DM_SITE) {
+    const SiteCtx c = site_ctx<DM>(k, i);
+    if (which == MBBS_TAB_DM_SITE) {
+      Coord x;
+      for (int m = 0; m < 4; ++m) x.c[m] = c.x[m];
+      out[i] = lex_site(g, x);
+      return;
+    }
+    for (int mu = 0; mu < 4; ++mu) {
+      out[(size_t)i * 8 + 2 * mu] = neighbour<DM>(k, c, mu, 1);
+      out[(size_t)i * 8 + 2 * mu + 1] = neighbour<DM>(k, c, mu, -1);
+    }
+    return;
+  }
+  const SiteCtx c = site_ctx<LEX>(k, i);
+  Coord x;
+  for (int m = 0; m < 4; ++m) x.c[m] = c.x[m];
+  switch (which) {
+    case MBBS_TAB_COORD:
+      for (int m = 0; m < 4; ++m) out[(size_t)i * 4 + m] = c.x[m];
+      break;
+    case MBBS_TAB_NEIGHBOUR:
+      for (int mu = 0; mu < 4; ++mu) {
+        out[(size_t)i * 8 + 2 * mu] = neighbour<LEX>(k, c, mu, 1);
+        out[(size_t)i * 8 + 2 * mu + 1] = neighbour<LEX>(k, c, mu, -1);
+      }
+      break;
+    case MBBS_TAB_BOUNDARY: {
+      int f = 0;
+      for (int mu = 0; mu < 4; ++mu) {
+        if (c.x[mu] == g.d[mu] - 1) f |= 1 << (2 * mu);
+        if (c.x[mu] == 0) f |= 1 << (2 * mu + 1);
+      }
+      out[i] = f;
+      break;
+    }
+    case MBBS_TAB_PARITY: out[i] = (c.x[0] + c.x[1] + c.x[2] + c.x[3]) & 1; break;
+    case MBBS_TAB_EO: out[i] = ((c.x[0] + c.x[1] + c.x[2] + c.x[3]) & 1) * g.Vh + (i >> 1); break;
+    case MBBS_TAB_DOMAIN: out[i] = domain_id(g, x); break;
+    case MBBS_TAB_COLOUR: out[i] = domain_colour(g, x); break;
+    case MBBS_TAB_LOCAL: out[i] = local_index(g, x); break;
+    case MBBS_TAB_DM_INDEX: out[i] = dm_index(g, x); break;
+    default: break;
+  }
+}
+
+size_t table_entries(const mbbs_lattice_s* lat, int which) {
+  const size_t V = lat->g.V;
+  switch (which) {
+    case MBBS_TAB_COORD: return 4 * V;
+    case MBBS_TAB_NEIGHBOUR: case MBBS_TAB_DM_NEIGHBOUR: return 8 * V;
+    case MBBS_TAB_LOCAL_NB: return 8 * (size_t)lat->g.Vb;
+    default: return V;
+  }
+}
+
+int build_table(const mbbs_lattice_s* lat, int which, int32_t* dev_out, hipStream_t st) {
+  const int n = which == MBBS_TAB_LOCAL_NB ? lat->g.Vb : lat->g.V;
+  hipLaunchKernelGGL(k_tables, dim3(ceil_div(n, 256)), dim3(256), 0, st, lat->gk, which, dev_out);
+  MBBS_HIP(hipGetLastError());
+  return MBBS_OK;
+}
+
+// ---------------------------------------------------------------- profiler
+void Profiler::begin(int k) {
+  if (!on || n >= CAP) return;
+  cls[n] = k;
+  (void)hipEventRecord(ev[2 * n], st);
+}
+void Profiler::end() {
+  if (!on || n >= CAP) return;
+  (void)hipEventRecord(ev[2 * n + 1], st);
+  ++n;
+  if (n == CAP) flush();
+}
+void Profiler::flush() {
+  if (!on || n == 0) return;
+  (void)hipEventSynchronize(ev[2 * n - 1]);
+  for (int i = 0; i < n; ++i) {
+    float t = 0;
+    if (hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) == hipSuccess) ms[cls[i]] += t;
+    launches[cls[i]] += 1;
+  }
+  n = 0;
+}
+
+}  // namespace mbbs
+
+using namespace mbbs;
+
+static int lattice_create(const int dims[4], const int block[4], const double* U_dev, double kappa,
+                          const double phase[8], void* stream, mbbs_lattice_t* out) {
+  MBBS_CHECK(dims && block && U_dev && phase && out, "null argument");
+  Geom g;
+  long long V = 1;
+  for (int m = 0; m < 4; ++m) {
+    MBBS_CHECK(dims[m] >= 2 && dims[m] % 2 == 0, "every extent must be even and >= 2");
+    MBBS_CHECK(block[m] >= 1 && dims[m] % block[m] == 0, "extent not divisible by the SAP block");
+    MBBS_CHECK((dims[m] / block[m]) % 2 == 0, "the number of domains along each direction must be even");
+    const double a = phase[2 * m], b = phase[2 * m + 1];
+    MBBS_CHECK(std::fabs(std::sqrt(a * a + b * b) - 1.0) < 1e-12, "boundary phases must have modulus 1");
+    g.d[m] = dims[m];
+    g.b[m] = block[m];
+    g.nd[m] = dims[m] / block[m];
+    g.ph[m][0] = a;
+    g.ph[m][1] = b;
+    V *= dims[m];
+  }
+  MBBS_CHECK(V * 12 < (1ll << 31), "lattice too large for 32-bit site indexing");
+  MBBS_CHECK(std::isfinite(kappa), "kappa must be finite");
+  g.V = (int)V;
+  g.Vh = g.V / 2;
+  g.Vb = block[0] * block[1] * block[2] * block[3];
+  g.ndom = g.V / g.Vb;
+  auto* lat = new mbbs_lattice_s();
+  lat->g = g;
+  lat->gk = make_geomk(g);
+  lat->kappa = kappa;
+  (void)hipGetDevice(&lat->device);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t n = (size_t)V * 36;
+  auto fail = [&](int rc) { mbbs_lattice_destroy(lat); return rc; };
+  if (hipMalloc(&lat->U64, n * sizeof(double2)) != hipSuccess || hipMalloc(&lat->U32, n * sizeof(float2)) != hipSuccess ||
+      hipMalloc(&lat->U16, n * sizeof(__half2)) != hipSuccess ||
+      hipMalloc(&lat->U64dm, n * sizeof(double2)) != hipSuccess ||
+      hipMalloc(&lat->U32dm, n * sizeof(float2)) != hipSuccess ||
+      hipMalloc(&lat->U16dm, n * sizeof(__half2)) != hipSuccess) {
+    set_error("out of device memory for link copies");
+    return fail(MBBS_ENOMEM);
+  }
+  if (hipMemcpyAsync(lat->U64, U_dev, n * sizeof(double2), hipMemcpyDeviceToDevice, st) != hipSuccess) {
+    set_error("link copy failed");
+    return fail(MBBS_EHIP);
+  }
+  hipLaunchKernelGGL(k_links, dim3(ceil_div(V, 256)), dim3(256), 0, st, lat->gk, (const double2*)lat->U64, lat->U32,
+                     lat->U16, lat->U64dm, lat->U32dm, lat->U16dm);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+    set_error("link conversion failed");
+    return fail(MBBS_EHIP);
+  }
+  *out = lat;
+  return MBBS_OK;
+}
+
+extern "C" int mbbs_lattice_create(const int dims[4], const int block[4], const double* U_dev, double kappa,
+                                   const double phase[8], void* stream, mbbs_lattice_t* out) {
+  return lattice_create(dims, block, U_dev, kappa, phase, stream, out);
+}
+
+extern "C" int mbbs_lattice_destroy(mbbs_lattice_t lat) {
+  if (!lat) return MBBS_OK;
+  (void)hipFree(lat->U64);
+  (void)hipFree(lat->U32);
+  (void)hipFree(lat->U16);
+  (void)hipFree(lat->U64dm);
+  (void)hipFree(lat->U32dm);
+  (void)hipFree(lat->U16dm);
+  delete lat;
+  return MBBS_OK;
+}
+
+extern "C" int mbbs_lattice_table_size(mbbs_lattice_t lat, int which, size_t* count) {
+  MBBS_CHECK(lat && count, "null argument");
+  MBBS_CHECK(which >= 0 && which < MBBS_TAB_COUNT, "unknown table");
+  *count = table_entries(lat, which);
+  return MBBS_OK;
+}
+
+extern "C" int mbbs_lattice_table(mbbs_lattice_t lat, int which, int32_t* out, size_t count) {
+  MBBS_CHECK(lat && out, "null argument");
+  MBBS_CHECK(which >= 0 && which < MBBS_TAB_COUNT, "unknown table");
+  const size_t n = table_entries(lat, which);
+  MBBS_CHECK(count >= n, "output buffer too small for the table");
+  int32_t* d = nullptr;
+  MBBS_HIP(hipMalloc(&d, n * sizeof(int32_t)));
+  int rc = build_table(lat, which, d, nullptr);
+  if (rc == MBBS_OK && hipMemcpy(out, d, n * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) {
+    set_error("table copy failed");
+    rc = MBBS_EHIP;
+  }
+  (void)hipFree(d);
+  return rc;
+}
+
+extern "C" const char* mbbs_last_error(void) { return last_error(); }

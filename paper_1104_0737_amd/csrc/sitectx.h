@@ -1,0 +1,79 @@
+// Per-thread site context and neighbour arithmetic shared by the stencil
+// kernels and the index-table builder (so the exported tables certify the
+// very index computations the kernels perform).
+#pragma once
+
+#include "internal.h"
+
+namespace mbbs {
+
+// Per-thread site context: coordinates and, in domain-major order, the
+// domain coordinates and local coordinates (computed once, hops are then
+// incremental).
+struct SiteCtx {
+  int s;        // index in the field's order
+  int x[4];     // global coordinates
+  int l[4];     // local coordinates in the domain (DM order)
+  int dc[4];    // domain coordinates (DM order)
+  int colour;
+  int loc;      // local index (DM order)
+};
+
+template <int ORDER>
+__device__ __forceinline__ SiteCtx site_ctx(const GeomK& k, int s) {
+  SiteCtx c;
+  c.s = s;
+  if constexpr (ORDER == LEX) {
+    uint32_t q = s;
+    uint32_t q1 = fdiv(q, k.fd[0]); c.x[0] = q - q1 * k.g.d[0];
+    uint32_t q2 = fdiv(q1, k.fd[1]); c.x[1] = q1 - q2 * k.g.d[1];
+    uint32_t q3 = fdiv(q2, k.fd[2]); c.x[2] = q2 - q3 * k.g.d[2];
+    c.x[3] = q3;
+    c.colour = 0; c.loc = 0;
+    for (int m = 0; m < 4; ++m) { c.l[m] = 0; c.dc[m] = 0; }
+  } else {
+    c.colour = s >= k.g.Vh;
+    uint32_t rem = s - c.colour * k.g.Vh;
+    uint32_t kk = fdiv(rem, k.fVb);
+    uint32_t loc = rem - kk * k.g.Vb;
+    c.loc = loc;
+    uint32_t id = 2 * kk;
+    uint32_t t0 = fdiv(id, k.fnd0);
+    int d0 = id - t0 * k.g.nd[0];
+    int d1 = t0 % k.g.nd[1];
+    uint32_t t1 = t0 / k.g.nd[1];
+    int d2 = t1 % k.g.nd[2];
+    int d3 = t1 / k.g.nd[2];
+    if (((d0 + d1 + d2 + d3) & 1) != c.colour) d0 += 1;
+    c.dc[0] = d0; c.dc[1] = d1; c.dc[2] = d2; c.dc[3] = d3;
+    uint32_t q1 = fdiv(loc, k.fb[0]); c.l[0] = loc - q1 * k.g.b[0];
+    uint32_t q2 = fdiv(q1, k.fb[1]); c.l[1] = q1 - q2 * k.g.b[1];
+    uint32_t q3 = fdiv(q2, k.fb[2]); c.l[2] = q2 - q3 * k.g.b[2];
+    c.l[3] = q3;
+    for (int m = 0; m < 4; ++m) c.x[m] = c.dc[m] * k.g.b[m] + c.l[m];
+  }
+  return c;
+}
+
+// Neighbour index of the site along (mu, dir) in the field's order.
+template <int ORDER>
+__device__ __forceinline__ int neighbour(const GeomK& k, const SiteCtx& c, int mu, int dir) {
+  if constexpr (ORDER == LEX) {
+    int v = c.x[mu] + dir;
+    if (v == k.g.d[mu]) return c.s - (k.g.d[mu] - 1) * k.stride[mu];
+    if (v < 0) return c.s + (k.g.d[mu] - 1) * k.stride[mu];
+    return c.s + dir * k.stride[mu];
+  } else {
+    int lv = c.l[mu] + dir;
+    if (lv >= 0 && lv < k.g.b[mu]) return c.s + dir * k.lstride[mu];
+    int dc[4] = {c.dc[0], c.dc[1], c.dc[2], c.dc[3]};
+    int nv = dc[mu] + dir;
+    dc[mu] = nv < 0 ? k.g.nd[mu] - 1 : (nv == k.g.nd[mu] ? 0 : nv);
+    int nl = dir > 0 ? 0 : k.g.b[mu] - 1;
+    int loc = c.loc + (nl - c.l[mu]) * k.lstride[mu];
+    int id = dc[0] + k.g.nd[0] * (dc[1] + k.g.nd[1] * (dc[2] + k.g.nd[2] * dc[3]));
+    return (1 - c.colour) * k.g.Vh + (id >> 1) * k.g.Vb + loc;
+  }
+}
+
+}  // namespace mbbs

@@ -1,0 +1,637 @@
+// Modified block BiCGSTAB (Alg. 1, and the memory-saving Alg. 2) driven from
+// the host with every coefficient computed on the device: the host only
+// enqueues iterations (optionally captured in a HIP graph of k iterations)
+// and reads a small state record after each batch.  The loop test of Alg. 1
+// (continue while max_i ||r_i||/||b_i|| > tol) runs on the device at the
+// start of each iteration; once it fails, the device sets `frozen` and every
+// later kernel of the batch returns at once.  After the recursive residual
+// converges, the true residual B - A X is checked in FP64 and the iteration
+// restarts from it if needed.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "blas.h"
+
+namespace mbbs {
+
+namespace {
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Work {
+  // FP64 N x L blocks
+  double2 *R, *P, *Rt, *V, *T, *Z, *U, *S;
+  SapBuffers sap;
+  double2* partial;
+  SolverDev d;
+  double* trnorm2;   // true residual norms^2
+  double2* mone;     // constant -1
+};
+
+size_t small_bytes(int L) {
+  const size_t LL = (size_t)L * L * sizeof(double2);
+  return al(sizeof(SolverState)) + 3 * al(L * sizeof(double)) + 16 * al(LL) + al(L * sizeof(int)) +
+         4 * al(sizeof(double2));
+}
+
+size_t block_bytes(const mbbs_lattice_s* lat, int L) { return al((size_t)lat->g.V * 12 * L * sizeof(double2)); }
+
+int nblocks_needed(const mbbs_solve_params& p) {
+  // R, P, Rt, V, Z, U always; T unless memsave; S only with a preconditioner
+  int n = 6;
+  if (!p.memsave) n += 1;
+  if (p.precond) n += 1;
+  return n;
+}
+
+size_t workspace_bytes(const mbbs_lattice_s* lat, int L, const mbbs_solve_params& p) {
+  const size_t N = (size_t)lat->g.V * 12;
+  size_t b = nblocks_needed(p) * block_bytes(lat, L);
+  if (p.precond) b += al(sap_buffer_bytes(lat, L, p.sap_prec));
+  b += al(gram_partial_bytes(N, L));
+  b += small_bytes(L);
+  return b;
+}
+
+int bind(const mbbs_lattice_s* lat, int L, const mbbs_solve_params& p, void* ws, size_t bytes, Work& w) {
+  MBBS_CHECK(ws != nullptr && bytes >= workspace_bytes(lat, L, p), "solver workspace too small");
+  char* q = (char*)ws;
+  const size_t B = block_bytes(lat, L);
+  const size_t N = (size_t)lat->g.V * 12;
+  auto take = [&](size_t n) { char* r = q; q += al(n); return r; };
+  w.R = (double2*)take(B);
+  w.P = (double2*)take(B);
+  w.Rt = (double2*)take(B);
+  w.V = (double2*)take(B);
+  w.Z = (double2*)take(B);
+  w.U = (double2*)take(B);
+  w.T = p.memsave ? w.R : (double2*)take(B);
+  w.S = p.precond ? (double2*)take(B) : w.T;
+  if (p.precond) {
+    const size_t sb = sap_buffer_bytes(lat, L, p.sap_prec);
+    MBBS_TRY(sap_bind(lat, L, p.sap_prec, take(sb), sb, &w.sap));
+  }
+  w.partial = (double2*)take(gram_partial_bytes(N, L));
+  const size_t LL = (size_t)L * L * sizeof(double2);
+  SolverDev& d = w.d;
+  d.state = (SolverState*)take(sizeof(SolverState));
+  d.rnorm2 = (double*)take(L * sizeof(double));
+  d.bnorm2 = (double*)take(L * sizeof(double));
+  w.trnorm2 = (double*)take(L * sizeof(double));
+  d.Gpp = (double2*)take(LL);
+  d.Gpp2 = (double2*)take(LL);
+  d.ginv = (double2*)take(LL);
+  d.RtV = (double2*)take(LL);
+  d.RtR = (double2*)take(LL);
+  d.RtZ = (double2*)take(LL);
+  d.ZT = (double2*)take(LL);
+  d.ZZ = (double2*)take(LL);
+  d.lu = (double2*)take(LL);
+  d.alpha = (double2*)take(LL);
+  d.nalpha = (double2*)take(LL);
+  d.beta = (double2*)take(LL);
+  d.C1 = (double2*)take(LL);
+  d.C2 = (double2*)take(LL);
+  take(LL);
+  take(LL);
+  d.piv = (int*)take(L * sizeof(int));
+  d.zeta = (double2*)take(sizeof(double2));
+  d.nzeta = (double2*)take(sizeof(double2));
+  d.one = (double2*)take(sizeof(double2));
+  w.mone = (double2*)take(sizeof(double2));
+  d.qr_passes = p.qr_passes;
+  return MBBS_OK;
+}
+
+// Column norms^2 of a block through a diagonal Gram product into dst (L doubles
+// as the real parts of the diagonal, gathered by a tiny copy kernel).
+__global__ void k_diag_real(int L, const double2* __restrict__ G, double* __restrict__ out, const int* frozen) {
+  if (frozen && *frozen) return;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) out[i] = G[i * L + i].x;
+}
+
+struct Ctx {
+  const mbbs_lattice_s* lat;
+  int L;
+  size_t N;
+  mbbs_solve_params p;
+  Work w;
+  const double2* B;
+  double2* X;
+  hipStream_t st;
+  Profiler* prof;
+  const int* frozen;
+};
+
+int col_norms(Ctx& c, const double2* A, double* out, const int* frozen) {
+  GramArgs g{};
+  g.npair = 1;
+  g.diag[0] = 1;
+  g.X[0] = A;
+  g.Y[0] = A;
+  GramOut o{};
+  o.G[0] = c.w.d.Gpp2;  // scratch L x L
+  if (c.prof) c.prof->begin(MBBS_K_GRAM);
+  MBBS_TRY(launch_gram(c.L, c.N, g, o, c.w.partial, frozen, c.st));
+  hipLaunchKernelGGL(k_diag_real, dim3(1), dim3(64), 0, c.st, c.L, (const double2*)c.w.d.Gpp2, out, frozen);
+  if (c.prof) c.prof->end();
+  MBBS_HIP(hipGetLastError());
+  return MBBS_OK;
+}
+
+int dslash64(Ctx& c, const double2* in, double2* out) {
+  if (c.prof) c.prof->begin(MBBS_K_DSLASH64);
+  int rc = launch_dslash(c.lat, c.L, P64, P64, LEX, false, in, nullptr, out, nullptr, 0, c.lat->g.V, c.frozen, c.st);
+  if (c.prof) c.prof->end();
+  return rc;
+}
+
+int combo(Ctx& c, ComboArgs a, double2* out, int gm, double2* gout, const int* frozen) {
+  GramOut o{};
+  o.G[0] = gout;
+  if (c.prof) c.prof->begin(gm ? MBBS_K_GRAM : MBBS_K_UPDATE);
+  int rc = launch_combo(c.L, c.N, a, out, gm, &o, c.w.partial, frozen, c.st);
+  if (c.prof) c.prof->end();
+  return rc;
+}
+
+int precondition(Ctx& c, const double2* in, const double2* gam, double2* out) {
+  if (c.p.precond) return sap_apply(c.lat, c.w.sap, c.p.ncy, c.p.nmr, in, gam, out, c.frozen, c.st, c.prof);
+  // M = 1: out = in * gam (gam may be null only when out aliases in)
+  if (gam == nullptr) return MBBS_OK;
+  ComboArgs a{};
+  a.nin = 1;
+  a.mode[0] = 2; a.in[0] = in; a.coef[0] = gam;
+  return combo(c, a, out, 0, nullptr, c.frozen);
+}
+
+int coef(Ctx& c, int which) {
+  if (c.prof) c.prof->begin(MBBS_K_SMALL);
+  int rc = launch_coef(which, c.L, c.w.d, c.st);
+  if (c.prof) c.prof->end();
+  return rc;
+}
+
+// One iteration of Alg. 1 (or Alg. 2), every step on the device.
+int enqueue_iteration(Ctx& c) {
+  Work& w = c.w;
+  SolverDev& d = w.d;
+  const int* fz = c.frozen;
+  // loop test + 4.1 (Cholesky QR factor of P, folded into the consumers)
+  MBBS_TRY(coef(c, 0));
+  if (c.p.qr_passes == 2) {
+    ComboArgs a{};
+    a.nin = 1; a.mode[0] = 2; a.in[0] = w.P; a.coef[0] = d.ginv;
+    MBBS_TRY(combo(c, a, w.U, 2, d.Gpp2, fz));
+    MBBS_TRY(coef(c, 1));
+  }
+  // 4.2 U = M (P gamma^{-1});  4.3 V = A U
+  MBBS_TRY(precondition(c, w.P, d.ginv, w.U));
+  MBBS_TRY(dslash64(c, w.U, w.V));
+  // 4.4 alpha from R~^H V and R~^H R
+  {
+    GramArgs g{};
+    g.npair = 2;
+    g.X[0] = w.Rt; g.Y[0] = w.V;
+    g.X[1] = w.Rt; g.Y[1] = w.R;
+    GramOut o{};
+    o.G[0] = d.RtV; o.G[1] = d.RtR;
+    if (c.prof) c.prof->begin(MBBS_K_GRAM);
+    MBBS_TRY(launch_gram(c.L, c.N, g, o, w.partial, fz, c.st));
+    if (c.prof) c.prof->end();
+  }
+  MBBS_TRY(coef(c, 2));
+  // 4.5 T = R - V alpha   (Alg. 2: R <- R - V alpha, X <- X + U alpha)
+  {
+    ComboArgs a{};
+    a.nin = 2;
+    a.mode[0] = 0; a.in[0] = w.R;
+    a.mode[1] = 2; a.in[1] = w.V; a.coef[1] = d.nalpha;
+    MBBS_TRY(combo(c, a, w.T, 0, nullptr, fz));
+  }
+  if (c.p.memsave) {
+    ComboArgs a{};
+    a.nin = 2;
+    a.mode[0] = 0; a.in[0] = c.X;
+    a.mode[1] = 2; a.in[1] = w.U; a.coef[1] = d.alpha;
+    MBBS_TRY(combo(c, a, c.X, 0, nullptr, fz));
+  }
+  // 4.6 S = M T;  4.7 Z = A S
+  if (c.p.precond) MBBS_TRY(precondition(c, w.T, nullptr, w.S));
+  MBBS_TRY(dslash64(c, w.S, w.Z));
+  // 4.8 / 4.11: R~^H Z, Tr(Z^H T), Tr(Z^H Z)
+  {
+    GramArgs g{};
+    g.npair = 3;
+    g.X[0] = w.Rt; g.Y[0] = w.Z;
+    g.diag[1] = 1; g.X[1] = w.Z; g.Y[1] = w.T;
+    g.diag[2] = 1; g.X[2] = w.Z; g.Y[2] = w.Z;
+    GramOut o{};
+    o.G[0] = d.RtZ; o.G[1] = d.ZT; o.G[2] = d.ZZ;
+    if (c.prof) c.prof->begin(MBBS_K_GRAM);
+    MBBS_TRY(launch_gram(c.L, c.N, g, o, w.partial, fz, c.st));
+    if (c.prof) c.prof->end();
+  }
+  MBBS_TRY(coef(c, 3));
+  // 4.9 X <- X + U alpha + zeta S   (Alg. 2: X <- X + zeta S)
+  {
+    ComboArgs a{};
+    a.nin = c.p.memsave ? 2 : 3;
+    a.mode[0] = 0; a.in[0] = c.X;
+    a.mode[1] = 1; a.in[1] = w.S; a.coef[1] = d.zeta;
+    if (!c.p.memsave) { a.mode[2] = 2; a.in[2] = w.U; a.coef[2] = d.alpha; }
+    MBBS_TRY(combo(c, a, c.X, 0, nullptr, fz));
+  }
+  // 4.10 R = T - zeta Z, with ||r_i||^2 for the next loop test
+  {
+    ComboArgs a{};
+    a.nin = 2;
+    a.mode[0] = 0; a.in[0] = w.T;
+    a.mode[1] = 1; a.in[1] = w.Z; a.coef[1] = d.nzeta;
+    MBBS_TRY(combo(c, a, w.R, 1, d.Gpp2, fz));
+    if (c.prof) c.prof->begin(MBBS_K_SMALL);
+    hipLaunchKernelGGL(k_diag_real, dim3(1), dim3(64), 0, c.st, c.L, (const double2*)d.Gpp2, d.rnorm2, fz);
+    if (c.prof) c.prof->end();
+    MBBS_HIP(hipGetLastError());
+  }
+  // 4.12 P <- R + (Q - zeta V) beta = R + P (gamma^{-1} beta) - V (zeta beta), with P^H P
+  {
+    ComboArgs a{};
+    a.nin = 3;
+    a.mode[0] = 0; a.in[0] = w.R;
+    a.mode[1] = 2; a.in[1] = w.P; a.coef[1] = d.C1;
+    a.mode[2] = 2; a.in[2] = w.V; a.coef[2] = d.C2;
+    MBBS_TRY(combo(c, a, w.P, 2, d.Gpp, fz));
+  }
+  return MBBS_OK;
+}
+
+// R = B - A X (or B when X = 0), P = R, R~ = R, norms and P^H P.
+int start(Ctx& c, bool x_zero, bool set_rt) {
+  Work& w = c.w;
+  if (x_zero) {
+    MBBS_TRY(launch_copy(c.B, w.R, c.N * c.L, c.st));
+  } else {
+    MBBS_TRY(dslash64(c, c.X, w.V));
+    ComboArgs a{};
+    a.nin = 2;
+    a.mode[0] = 0; a.in[0] = c.B;
+    a.mode[1] = 1; a.in[1] = w.V; a.coef[1] = w.mone;
+    MBBS_TRY(combo(c, a, w.R, 0, nullptr, nullptr));
+  }
+  MBBS_TRY(launch_copy(w.R, w.P, c.N * c.L, c.st));
+  if (set_rt) MBBS_TRY(launch_copy(w.R, w.Rt, c.N * c.L, c.st));
+  MBBS_TRY(col_norms(c, w.R, w.d.rnorm2, nullptr));
+  {
+    GramArgs g{};
+    g.npair = 1;
+    g.X[0] = w.P; g.Y[0] = w.P;
+    GramOut o{};
+    o.G[0] = w.d.Gpp;
+    MBBS_TRY(launch_gram(c.L, c.N, g, o, w.partial, nullptr, c.st));
+  }
+  return MBBS_OK;
+}
+
+// True residual T = B - A X and its column norms.
+int true_residual(Ctx& c) {
+  Work& w = c.w;
+  MBBS_TRY(dslash64(c, c.X, w.V));
+  ComboArgs a{};
+  a.nin = 2;
+  a.mode[0] = 0; a.in[0] = c.B;
+  a.mode[1] = 1; a.in[1] = w.V; a.coef[1] = w.mone;
+  MBBS_TRY(combo(c, a, w.T == w.R ? w.Z : w.T, 0, nullptr, nullptr));
+  MBBS_TRY(col_norms(c, w.T == w.R ? w.Z : w.T, w.trnorm2, nullptr));
+  return MBBS_OK;
+}
+
+}  // namespace
+
+// Host-visible parts of one system's solve, shared with the batched driver.
+struct SolveJob {
+  Ctx c;
+  SolverState hs{};
+  int restarts = 0;
+  int rc = MBBS_OK;
+  bool done = false;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  long long n_outer = 0;
+};
+
+static int set_scalars(Ctx& c) {
+  const double2 h[2] = {make_double2(1, 0), make_double2(-1, 0)};
+  MBBS_HIP(hipMemcpyAsync(c.w.d.one, &h[0], sizeof(double2), hipMemcpyHostToDevice, c.st));
+  MBBS_HIP(hipMemcpyAsync(c.w.mone, &h[1], sizeof(double2), hipMemcpyHostToDevice, c.st));
+  MBBS_HIP(hipStreamSynchronize(c.st));
+  return MBBS_OK;
+}
+
+static int job_init(SolveJob& j) {
+  Ctx& c = j.c;
+  MBBS_TRY(set_scalars(c));
+  if (!c.p.x0_is_guess) MBBS_TRY(launch_fill(c.X, c.N * c.L, make_double2(0, 0), c.st));
+  // ||b_i||^2
+  MBBS_TRY(col_norms(c, c.B, c.w.d.bnorm2, nullptr));
+  std::vector<double> bn(c.L);
+  MBBS_HIP(hipMemcpyAsync(bn.data(), c.w.d.bnorm2, c.L * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  MBBS_HIP(hipStreamSynchronize(c.st));
+  for (int i = 0; i < c.L; ++i) {
+    if (!(bn[i] > 0) || !std::isfinite(bn[i])) {
+      set_error("right-hand side column " + std::to_string(i) + (bn[i] > 0 ? " is not finite" : " is zero"));
+      return MBBS_EINVAL;
+    }
+  }
+  if (c.p.precond)  // MR arrival counters start at zero and return to zero after every step
+    MBBS_HIP(hipMemsetAsync(c.w.sap.counter, 0, (size_t)c.lat->g.ndom / 2 * sizeof(unsigned), c.st));
+  MBBS_TRY(start(c, !c.p.x0_is_guess, true));
+  j.n_outer += c.p.x0_is_guess ? 1 : 0;
+  SolverState s{};
+  s.maxiter = c.p.maxiter;
+  s.tol2 = c.p.tol * c.p.tol;
+  MBBS_HIP(hipMemcpyAsync(c.w.d.state, &s, sizeof(s), hipMemcpyHostToDevice, c.st));
+  MBBS_HIP(hipStreamSynchronize(c.st));
+  return MBBS_OK;
+}
+
+// After a batch: read the state; on a stop, check the true residual and
+// restart if it disagrees with the recursive one.
+static int job_check(SolveJob& j) {
+  Ctx& c = j.c;
+  MBBS_HIP(hipMemcpy(&j.hs, c.w.d.state, sizeof(SolverState), hipMemcpyDeviceToHost));
+  if (!j.hs.frozen) return MBBS_OK;
+  MBBS_TRY(true_residual(c));
+  j.n_outer += 1;
+  std::vector<double> tn(c.L), bn(c.L);
+  MBBS_HIP(hipMemcpy(tn.data(), c.w.trnorm2, c.L * sizeof(double), hipMemcpyDeviceToHost));
+  MBBS_HIP(hipMemcpy(bn.data(), c.w.d.bnorm2, c.L * sizeof(double), hipMemcpyDeviceToHost));
+  double worst = 0;
+  bool finite = true;
+  for (int i = 0; i < c.L; ++i) {
+    double r = tn[i] / bn[i];
+    finite = finite && std::isfinite(r);
+    worst = std::max(worst, r);
+  }
+  const bool ok = finite && worst <= c.p.tol * c.p.tol;
+  if (j.hs.status == ST_BREAKDOWN) {
+    j.done = true;
+    j.rc = ok ? MBBS_OK : MBBS_EBREAKDOWN;
+    if (!ok) set_error("block BiCGSTAB breakdown (" +
+                       std::string(j.hs.reason == 1 ? "P^H P not positive definite" :
+                                   j.hs.reason == 2 ? "singular R~^H V" : "non-finite zeta") + ")");
+    return MBBS_OK;
+  }
+  if (ok) { j.done = true; j.rc = MBBS_OK; return MBBS_OK; }
+  if (j.hs.status == ST_MAXITER || j.restarts >= c.p.max_restarts || j.hs.iter >= c.p.maxiter) {
+    j.done = true;
+    j.rc = MBBS_NOT_CONVERGED;
+    return MBBS_OK;
+  }
+  // restart from the true residual: R = B - A X, P = R, keep R~
+  j.restarts += 1;
+  MBBS_TRY(start(j.c, false, false));
+  j.n_outer += 1;
+  SolverState s = j.hs;
+  s.frozen = 0;
+  s.status = ST_RUNNING;
+  MBBS_HIP(hipMemcpy(c.w.d.state, &s, sizeof(s), hipMemcpyHostToDevice));
+  return MBBS_OK;
+}
+
+static int job_enqueue(SolveJob& j, int k) {
+  for (int i = 0; i < k; ++i) MBBS_TRY(enqueue_iteration(j.c));
+  return MBBS_OK;
+}
+
+static void job_fill_info(SolveJob& j, mbbs_solve_info* info, double seconds) {
+  if (!info) return;
+  Ctx& c = j.c;
+  info->status = j.rc;
+  info->iterations = j.hs.iter;
+  info->restarts = j.restarts;
+  info->n_dslash_outer = 2ll * j.hs.iter + j.n_outer;
+  info->n_sap = c.p.precond ? 2ll * j.hs.iter : 0;
+  info->seconds = seconds;
+  std::vector<double> tn(c.L), rn(c.L), bn(c.L);
+  if (hipMemcpy(tn.data(), c.w.trnorm2, c.L * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess &&
+      hipMemcpy(rn.data(), c.w.d.rnorm2, c.L * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess &&
+      hipMemcpy(bn.data(), c.w.d.bnorm2, c.L * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess) {
+    for (int i = 0; i < c.L; ++i) {
+      if (info->true_res) info->true_res[i] = std::sqrt(tn[i] / bn[i]);
+      if (info->rec_res) info->rec_res[i] = std::sqrt(rn[i] / bn[i]);
+    }
+  }
+  if (c.prof) {
+    for (int k = 0; k < MBBS_K_COUNT; ++k) {
+      info->kernel_ms[k] = c.prof->ms[k];
+      info->kernel_launches[k] = c.prof->launches[k];
+    }
+  }
+}
+
+static int validate(const mbbs_lattice_s* lat, int L, const mbbs_solve_params* p) {
+  MBBS_CHECK(lat != nullptr && p != nullptr, "null argument");
+  MBBS_CHECK(L >= 1 && L <= LMAX_SOLVER, "L must be in 1..16 for the solver");
+  MBBS_CHECK(p->tol > 0 && std::isfinite(p->tol), "tol must be positive");
+  MBBS_CHECK(p->maxiter >= 0, "maxiter must be >= 0");
+  MBBS_CHECK(p->qr_passes == 1 || p->qr_passes == 2, "qr_passes must be 1 or 2");
+  MBBS_CHECK(p->sap_prec >= 0 && p->sap_prec <= 2, "bad sap_prec");
+  if (p->precond) MBBS_CHECK(p->ncy >= 1 && p->nmr >= 1, "SAP needs ncy >= 1 and nmr >= 1");
+  return MBBS_OK;
+}
+
+static int solve_impl(mbbs_lattice_t lat, int L, const double* B_dev, double* X_dev, const mbbs_solve_params* params,
+                      void* ws, size_t ws_bytes, mbbs_solve_info* info, void* stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  MBBS_TRY(validate(lat, L, params));
+  MBBS_CHECK(B_dev && X_dev && B_dev != X_dev, "B and X must be distinct device blocks");
+  SolveJob j;
+  Ctx& c = j.c;
+  c.lat = lat;
+  c.L = L;
+  c.N = (size_t)lat->g.V * 12;
+  c.p = *params;
+  c.B = (const double2*)B_dev;
+  c.X = (double2*)X_dev;
+  c.st = (hipStream_t)stream;
+  Profiler prof;
+  c.prof = nullptr;
+  MBBS_TRY(bind(lat, L, c.p, ws, ws_bytes, c.w));
+  c.frozen = &c.w.d.state->frozen;
+  if (c.p.profile) {
+    prof.on = true;
+    prof.st = c.st;
+    for (int i = 0; i < 2 * Profiler::CAP; ++i) (void)hipEventCreate(&prof.ev[i]);
+    c.prof = &prof;
+  }
+  int rc = job_init(j);
+  const int k = std::max(1, c.p.graph_iters);
+  const bool use_graph = c.p.graph_iters > 1 && c.st != nullptr && !c.p.profile;
+  while (rc == MBBS_OK && !j.done) {
+    if (use_graph) {
+      if (!j.exec) {
+        if (hipStreamBeginCapture(c.st, hipStreamCaptureModeThreadLocal) != hipSuccess) { rc = MBBS_EHIP; break; }
+        int erc = job_enqueue(j, k);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c.st, &g);
+        if (erc < 0 || e != hipSuccess) { rc = erc < 0 ? erc : MBBS_EHIP; set_error("graph capture failed"); break; }
+        j.graph = g;
+        if (hipGraphInstantiate(&j.exec, g, nullptr, nullptr, 0) != hipSuccess) {
+          set_error("graph instantiation failed");
+          rc = MBBS_EHIP;
+          break;
+        }
+      }
+      if (hipGraphLaunch(j.exec, c.st) != hipSuccess) { set_error("graph launch failed"); rc = MBBS_EHIP; break; }
+    } else {
+      rc = job_enqueue(j, k);
+      if (rc < 0) break;
+    }
+    if (prof.on) prof.flush();
+    rc = job_check(j);
+  }
+  if (j.exec) (void)hipGraphExecDestroy(j.exec);
+  if (j.graph) (void)hipGraphDestroy(j.graph);
+  if (prof.on) prof.flush();
+  (void)hipStreamSynchronize(c.st);
+  double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (rc < 0 && !j.done) {
+    if (info) info->status = rc;
+  } else {
+    job_fill_info(j, info, secs);
+    rc = j.rc;
+  }
+  if (prof.on)
+    for (int i = 0; i < 2 * Profiler::CAP; ++i) (void)hipEventDestroy(prof.ev[i]);
+  return rc;
+}
+
+// ---------------------------------------------------------------- batched
+static int batched_impl(int nsys, const mbbs_lattice_t* lats, const int* Ls, const double* const* B, double* const* X,
+                        const mbbs_solve_params* params, void* ws, size_t ws_bytes, mbbs_solve_info* infos,
+                        void* stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  MBBS_CHECK(nsys >= 1 && lats && Ls && B && X && params, "null argument");
+  std::vector<SolveJob> jobs(nsys);
+  char* q = (char*)ws;
+  size_t left = ws_bytes;
+  hipStream_t st = (hipStream_t)stream;
+  for (int i = 0; i < nsys; ++i) {
+    MBBS_TRY(validate(lats[i], Ls[i], &params[i]));
+    const size_t need = workspace_bytes(lats[i], Ls[i], params[i]);
+    MBBS_CHECK(q != nullptr && left >= need, "batched workspace too small");
+    Ctx& c = jobs[i].c;
+    c.lat = lats[i];
+    c.L = Ls[i];
+    c.N = (size_t)lats[i]->g.V * 12;
+    c.p = params[i];
+    c.p.profile = 0;
+    c.B = (const double2*)B[i];
+    c.X = (double2*)X[i];
+    c.st = st;
+    c.prof = nullptr;
+    MBBS_TRY(bind(lats[i], Ls[i], c.p, q, need, c.w));
+    c.frozen = &c.w.d.state->frozen;
+    q += al(need);
+    left -= std::min(left, al(need));
+    MBBS_TRY(job_init(jobs[i]));
+  }
+  int k = 1;
+  for (int i = 0; i < nsys; ++i) k = std::max(k, params[i].graph_iters);
+  const bool use_graph = k > 1 && st != nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int rc = MBBS_OK;
+  for (;;) {
+    bool any = false;
+    for (auto& j : jobs) any = any || !j.done;
+    if (!any) break;
+    if (use_graph) {
+      // one graph holds k iterations of every system; finished systems stay
+      // frozen on the device and their kernels return at once
+      if (!exec) {
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) { rc = MBBS_EHIP; break; }
+        int erc = MBBS_OK;
+        for (int it = 0; it < k && erc >= 0; ++it)
+          for (auto& j : jobs) { erc = enqueue_iteration(j.c); if (erc < 0) break; }
+        hipError_t e = hipStreamEndCapture(st, &graph);
+        if (erc < 0 || e != hipSuccess) { rc = erc < 0 ? erc : MBBS_EHIP; set_error("graph capture failed"); break; }
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) { rc = MBBS_EHIP; break; }
+      }
+      if (hipGraphLaunch(exec, st) != hipSuccess) { rc = MBBS_EHIP; break; }
+    } else {
+      for (int it = 0; it < k && rc >= 0; ++it)
+        for (auto& j : jobs)
+          if (!j.done) { rc = enqueue_iteration(j.c); if (rc < 0) break; }
+      if (rc < 0) break;
+    }
+    for (auto& j : jobs)
+      if (!j.done) { rc = job_check(j); if (rc < 0) break; }
+    if (rc < 0) break;
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamSynchronize(st);
+  double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = MBBS_OK;
+  for (int i = 0; i < nsys; ++i) {
+    job_fill_info(jobs[i], infos ? &infos[i] : nullptr, secs);
+    if (jobs[i].rc < 0) worst = std::min(worst, jobs[i].rc);
+    else if (worst == MBBS_OK && jobs[i].rc == MBBS_NOT_CONVERGED) worst = MBBS_NOT_CONVERGED;
+  }
+  return rc < 0 ? rc : worst;
+}
+
+}  // namespace mbbs
+
+using namespace mbbs;
+
+extern "C" void mbbs_solve_params_default(mbbs_solve_params* p) {
+  if (!p) return;
+  p->tol = 1e-10;
+  p->maxiter = 1000;
+  p->max_restarts = 3;
+  p->ncy = 4;
+  p->nmr = 4;
+  p->sap_prec = MBBS_FP32;
+  p->x0_is_guess = 0;
+  p->qr_passes = 1;
+  p->graph_iters = 1;
+  p->precond = 1;
+  p->memsave = 0;
+  p->profile = 0;
+}
+
+extern "C" int mbbs_solve_workspace_size(mbbs_lattice_t lat, int L, const mbbs_solve_params* params, size_t* bytes) {
+  MBBS_TRY(validate(lat, L, params));
+  MBBS_CHECK(bytes != nullptr, "null argument");
+  *bytes = workspace_bytes(lat, L, *params);
+  return MBBS_OK;
+}
+
+extern "C" int mbbs_solve(mbbs_lattice_t lat, int L, const double* B_dev, double* X_dev,
+                          const mbbs_solve_params* params, void* ws_dev, size_t ws_bytes, mbbs_solve_info* info,
+                          void* stream) {
+  return solve_impl(lat, L, B_dev, X_dev, params, ws_dev, ws_bytes, info, stream);
+}
+
+extern "C" int mbbs_solve_batched_workspace_size(int nsys, const mbbs_lattice_t* lats, const int* Ls,
+                                                 const mbbs_solve_params* params, size_t* bytes) {
+  MBBS_CHECK(nsys >= 1 && lats && Ls && params && bytes, "null argument");
+  size_t t = 0;
+  for (int i = 0; i < nsys; ++i) {
+    MBBS_TRY(validate(lats[i], Ls[i], &params[i]));
+    t += al(workspace_bytes(lats[i], Ls[i], params[i]));
+  }
+  *bytes = t;
+  return MBBS_OK;
+}
+
+extern "C" int mbbs_solve_batched(int nsys, const mbbs_lattice_t* lats, const int* Ls, const double* const* B_dev,
+                                  double* const* X_dev, const mbbs_solve_params* params, void* ws_dev,
+                                  size_t ws_bytes, mbbs_solve_info* infos, void* stream) {
+  return batched_impl(nsys, lats, Ls, B_dev, X_dev, params, ws_dev, ws_bytes, infos, stream);
+}

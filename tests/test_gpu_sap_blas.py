@@ -1,0 +1,118 @@
+"""GPU SAP preconditioner and block linear algebra against the oracle.
+
+SAP (Sec. 2.2): the GPU updates the residual with domain-major kernels and
+assigns psi on the first MR step; the oracle recomputes eta - A psi with the
+full operator every half-sweep.  Equal in exact arithmetic, so FP64 agrees to
+rounding; FP32 / FP16 storage within their precision.
+Block LA: Gram products, Cholesky QR (against modified Gram-Schmidt, Q and the
+triangular factor are unique with a positive diagonal) and LU solves.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import krylov, sap
+from paper_1104_0737_amd import inputs
+
+pytestmark = pytest.mark.gpu
+gu = pytest.importorskip("tests.gpu_util")
+torch = gu.torch
+B = gu.binding
+
+
+@pytest.mark.parametrize("dims,block,L,ncy,nmr", [((8, 8, 4, 4), (4, 4, 2, 2), 3, 2, 3),
+                                                  ((8, 8, 8, 8), (4, 4, 4, 4), 4, 4, 4),
+                                                  ((12, 12, 12, 12), (6, 6, 6, 6), 2, 1, 2),
+                                                  ((4, 4, 4, 6), (2, 2, 2, 3), 5, 3, 1)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 3e-5), (2, 1e-2)])
+def test_sap_parity(dims, block, L, ncy, nmr, prec, tol):
+    gu.flush(f"sap {dims} L={L} prec={prec}")
+    V = int(np.prod(dims))
+    U = inputs.gauge_field(dims, 0.3, 21)
+    kappa = 0.12
+    eta = inputs.gaussian_block(V, L, 22)
+    dom = sap.Domains(dims, block)
+    ref = sap.sap(U, kappa, gu.PH_AP, dom, eta, ncy, nmr).reshape(12 * V, L)
+    with gu.Lattice(dims, block, U, kappa) as lat:
+        ws = torch.empty(B.mbbs_sap_workspace_size(lat.h, L, prec), dtype=torch.uint8, device="cuda")
+        Yd = torch.empty((12 * V, L), dtype=torch.complex128, device="cuda")
+        B.mbbs_sap_apply(lat.h, L, gu.dev(eta), Yd, ncy, nmr, prec, ws)
+        err = gu.rel_col_err(gu.host(Yd), ref)
+    assert np.all(err <= tol), err
+
+
+def test_sap_point_source_fp16():
+    # point source: many domains hold an exactly zero residual (omega = 0 path)
+    dims, block, L = (8, 8, 8, 8), (4, 4, 4, 4), 4
+    V = 4096
+    U = inputs.gauge_field(dims, 0.3, 23)
+    eta = inputs.point_sources(V, L, 0, 0)
+    dom = sap.Domains(dims, block)
+    ref = sap.sap(U, 0.11, gu.PH_AP, dom, eta, 4, 4).reshape(12 * V, L)
+    with gu.Lattice(dims, block, U, 0.11) as lat:
+        for prec, tol in ((0, 1e-12), (1, 3e-5), (2, 1e-2)):
+            ws = torch.empty(B.mbbs_sap_workspace_size(lat.h, L, prec), dtype=torch.uint8, device="cuda")
+            Yd = torch.empty((12 * V, L), dtype=torch.complex128, device="cuda")
+            B.mbbs_sap_apply(lat.h, L, gu.dev(eta), Yd, 4, 4, prec, ws)
+            Y = gu.host(Yd)
+            assert np.all(np.isfinite(Y))
+            err = gu.rel_col_err(Y, ref)
+            assert np.all(err <= tol), (prec, err)
+
+
+@pytest.mark.parametrize("N,L", [(1000, 1), (12 * 4096, 4), (12 * 777, 12), (12 * 8192, 7), (300, 16)])
+def test_gram(N, L):
+    X = np.random.default_rng(1).standard_normal((N, L)) + 1j * np.random.default_rng(2).standard_normal((N, L))
+    Y = np.random.default_rng(3).standard_normal((N, L)) + 1j * np.random.default_rng(4).standard_normal((N, L))
+    ws = torch.empty(B.mbbs_gram_workspace_size(N, L), dtype=torch.uint8, device="cuda")
+    G = torch.empty((L, L), dtype=torch.complex128, device="cuda")
+    B.mbbs_gram(N, L, gu.dev(X), gu.dev(Y), G, ws)
+    ref = X.conj().T @ Y
+    np.testing.assert_allclose(gu.host(G), ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("passes", [1, 2])
+@pytest.mark.parametrize("N,L", [(12 * 512, 4), (12 * 4096, 12), (12 * 100, 3)])
+def test_cholqr_vs_mgs(N, L, passes):
+    rng = np.random.default_rng(5)
+    P = rng.standard_normal((N, L)) + 1j * rng.standard_normal((N, L))
+    P[:, -1] += 0.5 * P[:, 0]   # some correlation between columns
+    Qr, gr = krylov.mgs(P)
+    ws = torch.empty(B.mbbs_gram_workspace_size(N, L) + 5 * L * L * 16 + 256, dtype=torch.uint8, device="cuda")
+    Qd = torch.empty((N, L), dtype=torch.complex128, device="cuda")
+    gd = torch.empty((L, L), dtype=torch.complex128, device="cuda")
+    B.mbbs_cholqr(N, L, gu.dev(P), Qd, gd, passes, ws)
+    Q, g = gu.host(Qd), gu.host(gd)
+    np.testing.assert_allclose(Q, Qr, atol=1e-12)
+    np.testing.assert_allclose(g, gr, atol=1e-12 * np.abs(gr).max())
+    np.testing.assert_allclose(Q.conj().T @ Q, np.eye(L), atol=1e-12)
+
+
+def test_cholqr_breakdown():
+    N, L = 1200, 3
+    P = np.random.default_rng(6).standard_normal((N, L)) + 0j
+    P[:, 2] = P[:, 1]
+    ws = torch.empty(B.mbbs_gram_workspace_size(N, L) + 5 * L * L * 16 + 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.MbbsError) as e:
+        B.mbbs_cholqr(N, L, gu.dev(P), torch.empty((N, L), dtype=torch.complex128, device="cuda"),
+                      torch.empty((L, L), dtype=torch.complex128, device="cuda"), 1, ws)
+    assert e.value.code == B.EBREAKDOWN
+
+
+@pytest.mark.parametrize("L,m", [(1, 1), (4, 4), (12, 12), (7, 3)])
+def test_lu_solve(L, m):
+    rng = np.random.default_rng(L)
+    G = rng.standard_normal((L, L)) + 1j * rng.standard_normal((L, L))
+    R = rng.standard_normal((L, m)) + 1j * rng.standard_normal((L, m))
+    Xd = torch.empty((L, m), dtype=torch.complex128, device="cuda")
+    B.mbbs_lu_solve(L, m, gu.dev(G), gu.dev(R), Xd)
+    np.testing.assert_allclose(gu.host(Xd), np.linalg.solve(G, R), atol=1e-12 * np.linalg.cond(G))
+
+
+def test_lu_zero_pivot():
+    G = np.zeros((3, 3), complex)
+    G[0, 1] = G[1, 0] = 1.0
+    with pytest.raises(B.MbbsError) as e:
+        B.mbbs_lu_solve(3, 1, gu.dev(G), gu.dev(np.ones((3, 1), complex)),
+                        torch.empty((3, 1), dtype=torch.complex128, device="cuda"))
+    assert e.value.code == B.EBREAKDOWN

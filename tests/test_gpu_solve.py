@@ -1,0 +1,186 @@
+"""GPU modified block BiCGSTAB (Alg. 1 / Alg. 2) with SAP, against the oracle.
+
+* config 1 (8^4, L = 4, all FP64, tol 1e-12): every true residual <= tol,
+  X agrees with the oracle's solution, iteration count within 10 %;
+* config 3 (same system, FP32 and FP16-storage SAP, tol 1e-10): the true
+  residual of the GPU solution, recomputed by the oracle's own operator, is
+  <= 1e-10 on every column; the error against the oracle's FP64 solution is
+  reported;
+* config 2 (16^3 x 32, L = 12, all FP64): true residual by the oracle;
+* Alg. 2, no preconditioner, CholQR2, graph capture, restart from a guess;
+* failure handling: zero column, duplicate columns, iteration cap,
+  workspace too small;
+* batched solves equal independent solves.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import dirac, krylov, sap
+from paper_1104_0737_amd import configs, inputs
+
+pytestmark = pytest.mark.gpu
+gu = pytest.importorskip("tests.gpu_util")
+torch = gu.torch
+B = gu.binding
+
+
+def _oracle_true_res(cfg, U, Bh, X):
+    R = Bh - dirac.apply_D(U, cfg.kappa, cfg.phases, X, cfg.dims).reshape(Bh.shape)
+    return np.linalg.norm(R, axis=0) / np.linalg.norm(Bh, axis=0)
+
+
+def _solve(lat, L, Bh, stream=None, X0=None, ws_extra=0, **kw):
+    p = B.mbbs_solve_params_default(**kw)
+    ws = torch.empty(B.mbbs_solve_workspace_size(lat.h, L, p) + ws_extra, dtype=torch.uint8, device="cuda")
+    Bd = gu.dev(Bh)
+    Xd = gu.dev(X0) if X0 is not None else torch.empty_like(Bd)
+    info = B.mbbs_solve(lat.h, L, Bd, Xd, p, ws, stream=stream)
+    return gu.host(Xd), info
+
+
+@pytest.fixture(scope="module")
+def c1():
+    cfg = configs.c1()
+    U = cfg.gauge()
+    Bh = cfg.sources()
+    dom = sap.Domains(cfg.dims, cfg.block)
+    A = lambda X: dirac.apply_D(U, cfg.kappa, cfg.phases, X, cfg.dims).reshape(12 * cfg.V, -1)
+    M = lambda X: sap.sap(U, cfg.kappa, cfg.phases, dom, X, cfg.ncy, cfg.nmr).reshape(12 * cfg.V, -1)
+    ref = krylov.block_bicgstab(A, M, Bh, cfg.tol, maxiter=100)
+    lat = gu.Lattice(cfg.dims, cfg.block, U, cfg.kappa)
+    yield cfg, U, Bh, ref, lat
+    lat.close()
+
+
+def test_c1_fp64(c1):
+    cfg, U, Bh, ref, lat = c1
+    gu.flush("c1 fp64")
+    X, info = _solve(lat, cfg.L, Bh, tol=cfg.tol, sap_prec=B.FP64)
+    assert info["status"] == B.OK
+    assert np.all(info["true_res"] <= cfg.tol)
+    assert np.all(_oracle_true_res(cfg, U, Bh, X) <= cfg.tol * 1.01)
+    err = np.linalg.norm(X - ref.X, axis=0) / np.linalg.norm(ref.X, axis=0)
+    assert np.all(err <= 1e-8), err
+    assert abs(info["iterations"] - ref.iterations) <= max(1, 0.1 * ref.iterations)
+    assert info["n_dslash_outer"] >= 2 * info["iterations"] and info["n_sap"] == 2 * info["iterations"]
+
+
+@pytest.mark.parametrize("prec", [B.FP32, B.FP16S])
+def test_c3_mixed(c1, prec):
+    cfg, U, Bh, ref, lat = c1
+    gu.flush(f"c3 prec={prec}")
+    X, info = _solve(lat, cfg.L, Bh, tol=1e-10, sap_prec=prec)
+    assert info["status"] == B.OK
+    assert np.all(info["true_res"] <= 1e-10)
+    assert np.all(_oracle_true_res(cfg, U, Bh, X) <= 1e-10 * 1.01)
+    err = np.linalg.norm(X - ref.X, axis=0) / np.linalg.norm(ref.X, axis=0)
+    gu.flush(f"  iterations {info['iterations']} (FP64 oracle {ref.iterations}), error vs FP64 {err.max():.2e}")
+    assert np.all(err <= 1e-8)
+
+
+def test_memsave_matches_alg1(c1):
+    cfg, U, Bh, ref, lat = c1
+    X1, i1 = _solve(lat, cfg.L, Bh, tol=cfg.tol, sap_prec=B.FP64)
+    X2, i2 = _solve(lat, cfg.L, Bh, tol=cfg.tol, sap_prec=B.FP64, memsave=1)
+    assert i2["status"] == B.OK and i1["iterations"] == i2["iterations"]
+    np.testing.assert_allclose(X2, X1, atol=1e-9 * np.abs(X1).max())
+
+
+def test_graph_and_cholqr2(c1):
+    cfg, U, Bh, ref, lat = c1
+    s = torch.cuda.Stream()
+    X1, i1 = _solve(lat, cfg.L, Bh, tol=cfg.tol, sap_prec=B.FP64)
+    with torch.cuda.stream(s):
+        X2, i2 = _solve(lat, cfg.L, Bh, stream=s, tol=cfg.tol, sap_prec=B.FP64, graph_iters=4)
+    assert i2["status"] == B.OK and i2["iterations"] == i1["iterations"]
+    assert X1.tobytes() == X2.tobytes()          # same kernels, same order: bit-identical
+    X3, i3 = _solve(lat, cfg.L, Bh, tol=cfg.tol, sap_prec=B.FP64, qr_passes=2)
+    assert i3["status"] == B.OK and np.all(i3["true_res"] <= cfg.tol)
+
+
+def test_unpreconditioned_and_guess():
+    dims, block, L = (4, 4, 4, 4), (2, 2, 2, 2), 3
+    U = inputs.gauge_field(dims, 0.3, 41)
+    Bh = inputs.point_sources(256, L, 9, 1)
+    D = dirac.dense_D(U, 0.13, gu.PH_AP, dims)
+    ref = krylov.block_bicgstab(lambda X: D @ X, lambda X: X, Bh, 1e-12, maxiter=300)
+    with gu.Lattice(dims, block, U, 0.13) as lat:
+        X, info = _solve(lat, L, Bh, tol=1e-12, precond=0)
+        assert info["status"] == B.OK and np.all(info["true_res"] <= 1e-12)
+        assert abs(info["iterations"] - ref.iterations) <= max(1, 0.1 * ref.iterations)
+        np.testing.assert_allclose(X, np.linalg.solve(D, Bh), atol=1e-9)
+        # resume from the solution: no iteration needed
+        X2, i2 = _solve(lat, L, Bh, X0=X, tol=1e-12, precond=0, x0_is_guess=1)
+        assert i2["status"] == B.OK and i2["iterations"] == 0
+
+
+def test_failures():
+    dims, block, L = (4, 4, 4, 4), (2, 2, 2, 2), 3
+    U = inputs.gauge_field(dims, 0.3, 42)
+    with gu.Lattice(dims, block, U, 0.13) as lat:
+        Bh = inputs.point_sources(256, L, 3, 0)
+        Z = Bh.copy()
+        Z[:, 1] = 0
+        with pytest.raises(B.MbbsError) as e:
+            _solve(lat, L, Z)
+        assert e.value.code == B.EINVAL
+        D = Bh.copy()
+        D[:, 2] = D[:, 1]
+        with pytest.raises(B.MbbsError) as e:
+            _solve(lat, L, D, tol=1e-12)
+        assert e.value.code == B.EBREAKDOWN
+        X, info = _solve(lat, L, Bh, tol=1e-14, maxiter=1)
+        assert info["status"] == B.NOT_CONVERGED and info["iterations"] == 1
+        assert np.all(info["true_res"] > 1e-14) and np.all(np.isfinite(info["rec_res"]))
+        p = B.mbbs_solve_params_default()
+        need = B.mbbs_solve_workspace_size(lat.h, L, p)
+        ws = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+        Bd = gu.dev(Bh)
+        with pytest.raises(B.MbbsError) as e:
+            B.mbbs_solve(lat.h, L, Bd, torch.empty_like(Bd), p, ws)
+        assert e.value.code == B.EINVAL
+
+
+@pytest.mark.slow
+def test_c2_fp64():
+    cfg = configs.c2()
+    gu.flush("c2 fp64: links")
+    U = cfg.gauge()
+    Bh = cfg.sources()
+    with gu.Lattice(cfg.dims, cfg.block, U, cfg.kappa) as lat:
+        gu.flush("c2 fp64: solve")
+        X, info = _solve(lat, cfg.L, Bh, tol=cfg.tol, sap_prec=B.FP64)
+        gu.flush(f"  iterations {info['iterations']} restarts {info['restarts']} {info['seconds']:.2f}s")
+        assert info["status"] == B.OK and np.all(info["true_res"] <= cfg.tol)
+        gu.flush("c2 fp64: oracle true residual")
+        assert np.all(_oracle_true_res(cfg, U, Bh, X) <= cfg.tol * 1.01)
+
+
+def test_batched_equals_single():
+    systems = []
+    for k, (dims, block, L) in enumerate((((4, 4, 4, 4), (2, 2, 2, 2), 2), ((8, 8, 4, 4), (4, 4, 2, 2), 4),
+                                          ((6, 6, 6, 6), (3, 3, 3, 3), 3))):
+        U = inputs.gauge_field(dims, 0.25, 50 + k)
+        Bh = inputs.z2_sources(int(np.prod(dims)), L, 60 + k) if k % 2 else \
+            inputs.point_sources(int(np.prod(dims)), L, 5, 0)
+        systems.append((dims, block, L, U, Bh, 0.115 + 0.002 * k))
+    lats = [gu.Lattice(d, b, U, kap) for d, b, L, U, Bh, kap in systems]
+    try:
+        singles = [_solve(l, s[2], s[4], tol=1e-10) for l, s in zip(lats, systems)]
+        params = [B.mbbs_solve_params_default(tol=1e-10, graph_iters=3) for _ in systems]
+        Ls = [s[2] for s in systems]
+        ws = torch.empty(B.mbbs_solve_batched_workspace_size([l.h for l in lats], Ls, params),
+                         dtype=torch.uint8, device="cuda")
+        Bs = [gu.dev(s[4]) for s in systems]
+        Xs = [torch.empty_like(b) for b in Bs]
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            rc, infos = B.mbbs_solve_batched([l.h for l in lats], Ls, Bs, Xs, params, ws, stream=st)
+        assert rc == B.OK
+        for (Xs1, i1), Xb, ib in zip(singles, Xs, infos):
+            assert ib["status"] == B.OK and ib["iterations"] == i1["iterations"]
+            np.testing.assert_allclose(gu.host(Xb), Xs1, atol=1e-12 * np.abs(Xs1).max())
+    finally:
+        for l in lats:
+            l.close()
