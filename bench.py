@@ -1,0 +1,298 @@
+"""Benchmark: SAP-preconditioned modified block BiCGSTAB on a 32^3 x 64 lattice.
+
+One step is one mixed-precision solve (outer recurrences, Gram products,
+Cholesky QR, L x L solves and true residual in FP64; SAP with its MR domain
+solves in FP32) of D X = B for L = 12 point sources (all spin-colour
+components at one seeded site), tolerance 1e-10 on every column, with the
+inputs resident in HBM when the timed region starts.  Synthetic random SU(3)
+links (eps = 0.2, kappa = 0.1240) stand in for the paper's gauge
+configurations.  Reported beside it: the operator's stand-alone rate in FP64,
+FP32 and FP16 storage, the all-FP64 solve's time per right-hand side, the
+dominant kernel's roofline (event-timed inside the timed solves), and the CPU
+oracle's operator rate on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Dslash site·RHS/s (HBM GB/s) + time-to-solution/RHS, mixed vs FP64 @1e-10"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--L", type=int, default=12)
+    ap.add_argument("--dims", type=str, default="32,32,32,64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-solve", action="store_true")
+    ap.add_argument("--dslash-reps", type=int, default=20)
+    ap.add_argument("--only-dslash", action="store_true", help="stand-alone operator timing only")
+    ap.add_argument("--profile", type=int, default=1, help="event-time kernel classes in the timed solves")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a device-to-device copy of 4 GiB (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(cls, L, dims, block, ncy, nmr):
+    """Compulsory HBM bytes of one launch of a kernel class, averaged over the
+    launches of one SAP application where they differ (FP32 SAP storage:
+    8-byte complex, 72-byte link; FP64 outer: 16-byte complex, 144-byte link).
+
+    dslash64   whole lattice: read X, write Y, 4 links per site.
+    mr_dslash  one colour (V/2 sites): read r, write w, 4 links per site.
+    mr_update  one colour: read r and psi, write psi; while r is still
+               needed also read w and write r; the first step of the first
+               cycle assigns psi (no psi read).
+    sap_resid  one colour: read eta, write r; except on the first half-sweep
+               also read psi on the colour and on the other colour's sites
+               that touch it (a fraction f of them), and 4 links per site.
+    """
+    V = int(np.prod(dims))
+    Vh = V // 2
+    s = 12 * L * 8                         # one FP32 spinor row block per site
+    if cls == "dslash64":
+        return V * (48 * L + 72) * 8
+    if cls == "mr_dslash":
+        return Vh * (2 * s + 4 * 72)
+    if cls == "mr_update":
+        tot = 0
+        for cy in range(ncy):
+            for it in range(nmr):
+                streams = 2 + (0 if (cy == 0 and it == 0) else 1) + (2 if it + 1 < nmr else 0)
+                tot += 2 * streams * Vh * s      # both colours
+        return tot / (2 * ncy * nmr)
+    if cls == "sap_resid":
+        inner = int(np.prod([b - 2 for b in block]))
+        f = 1 - inner / int(np.prod(block))  # sites of a domain that touch another domain
+        tot = 2 * (2 * Vh * s)                           # first cycle, colour 0 and 1: eta, r
+        tot += Vh * (f * s + 4 * 72)                     # first cycle, colour 1: psi of colour 0
+        tot += 2 * (ncy - 1) * Vh * (2 * s + (1 + f) * s + 4 * 72)
+        return tot / (2 * ncy)
+    return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is a design described in DESIGN.md, not a measured path.", flush=True)
+        sys.exit(1)
+    import torch
+    from paper_1104_0737_amd import binding as B
+    from paper_1104_0737_amd import configs, model
+
+    if args.copy_calibration:
+        # a plain copy of known size: 4 GiB read, 4 GiB written per launch
+        a = torch.empty(1 << 29, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8}), flush=True)
+        return
+
+    dims = tuple(int(x) for x in args.dims.split(","))
+    cfg = configs.c4(L=args.L)
+    cfg.dims = dims
+    V = int(np.prod(dims))
+    L = args.L
+    N = 12 * V
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
+
+    log(f"generating links for {dims}")
+    t0 = time.time()
+    U = cfg.gauge()
+    log(f"links ready in {time.time() - t0:.1f}s")
+    Ud = torch.from_numpy(U).to(dev)
+    lat = B.mbbs_lattice_create(dims, cfg.block, Ud, cfg.kappa, cfg.phases, stream=stream)
+    del Ud
+
+    # ------------------------------------------------------------ operator alone
+    def time_dslash(prec):
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(7)
+        X = torch.randn((N, L), dtype=torch.complex128, device=dev, generator=gen)
+        if prec == B.FP64:
+            Xr, Yr, Xs, Ys = X, torch.empty_like(X), None, None
+        else:
+            dt = torch.float32 if prec == B.FP32 else torch.float16
+            Xr = torch.empty((N, L, 2), dtype=dt, device=dev)
+            Yr = torch.empty_like(Xr)
+            Xs = torch.empty((V, L), dtype=torch.float32, device=dev) if prec == B.FP16S else None
+            Ys = torch.empty_like(Xs) if Xs is not None else None
+            B.mbbs_convert_to(prec, V, L, X, Xr, Xs, stream=stream)
+        for _ in range(3):
+            B.mbbs_apply_dirac_raw(lat, L, prec, Xr, Xs, Yr, Ys, stream=stream)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.dslash_reps):
+            B.mbbs_apply_dirac_raw(lat, L, prec, Xr, Xs, Yr, Ys, stream=stream)
+        ev1.record(stream)
+        ev1.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.dslash_reps
+        name = {B.FP64: "fp64", B.FP32: "fp32", B.FP16S: "fp16s"}[prec]
+        by = model.dslash_bytes_per_site(L, name) * V
+        fl = model.dslash_flops_per_site(L) * V
+        del X, Xr, Yr, Xs, Ys
+        torch.cuda.empty_cache()
+        return {"ms": ms, "site_rhs_per_s": V * L / (ms * 1e-3), "algo_GBps": by / (ms * 1e-3) / 1e9,
+                "frac_hbm_peak": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "TFLOPs": fl / (ms * 1e-3) / 1e12,
+                "bytes_per_launch": by}
+
+    dslash = {}
+    for prec, name in ((B.FP64, "fp64"), (B.FP32, "fp32"), (B.FP16S, "fp16s")):
+        log(f"operator {name}")
+        dslash[name] = time_dslash(prec)
+        log(f"  {dslash[name]['ms']:.3f} ms, {dslash[name]['algo_GBps']:.0f} GB/s algorithmic")
+    if args.only_dslash:
+        print(json.dumps({"dslash": dslash}), flush=True)
+        B.mbbs_lattice_destroy(lat)
+        return
+
+    # ------------------------------------------------------------ solves
+    site = cfg.src_site()
+    Bd = torch.zeros((N, L), dtype=torch.complex128, device=dev)
+    for j in range(L):
+        Bd[12 * site + cfg.comp0 + j, j] = 1.0
+    Xd = torch.empty_like(Bd)
+
+    def run_solve(sap_prec, profile):
+        p = B.mbbs_solve_params_default(tol=cfg.tol, sap_prec=sap_prec, ncy=cfg.ncy, nmr=cfg.nmr,
+                                        profile=profile, graph_iters=1)
+        ws = torch.empty(B.mbbs_solve_workspace_size(lat, L, p), dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = B.mbbs_solve(lat, L, Bd, Xd, p, ws, stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        del ws
+        return dt, info
+
+    for w in range(args.warmup):
+        log(f"warmup solve {w}")
+        dt, info = run_solve(B.FP32, 0)
+        log(f"  {dt:.2f}s, {info['iterations']} iterations, status {info['status']}")
+    torch.cuda.synchronize()
+    times, infos = [], []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        dt, info = run_solve(B.FP32, args.profile)
+        times.append(dt)
+        infos.append(info)
+        log(f"step {k}: {dt:.3f}s, {info['iterations']} iterations, max true residual "
+            f"{info['true_res'].max():.2e}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ok = all(i["status"] == 0 and np.all(i["true_res"] <= cfg.tol) for i in infos)
+
+    fp64 = None
+    if not args.no_fp64_solve:
+        log("all-FP64 solve")
+        dt64, i64 = run_solve(B.FP64, 0)
+        fp64 = {"seconds": dt64, "tts_per_rhs_s": dt64 / L, "iterations": i64["iterations"],
+                "max_true_res": float(i64["true_res"].max()), "status": i64["status"]}
+        log(f"  {dt64:.2f}s, {i64['iterations']} iterations")
+
+    # ------------------------------------------------------------ accounting
+    it = infos[-1]["iterations"]
+    Vh = V // 2
+    n_outer = infos[-1]["n_dslash_outer"]
+    n_sap = infos[-1]["n_sap"]
+    # stencil site.RHS work per solve: outer operator, SAP residual (half
+    # lattice per colour) and MR domain operator (half lattice per step)
+    per_sap = cfg.ncy * 2 * (1 + cfg.nmr) * Vh * L
+    stencil_work = n_outer * V * L + n_sap * per_sap
+    step_s = wall / args.steps
+    value = stencil_work / step_s
+    km = infos[-1]["kernel_ms"]
+    kl = infos[-1]["kernel_launches"]
+    dominant = max(("dslash64", "mr_dslash", "mr_update", "sap_resid"), key=lambda c: km[c])
+    roof = None
+    if args.profile and kl[dominant] > 0:
+        byl = algorithmic_bytes(dominant, L, dims, cfg.block, cfg.ncy, cfg.nmr)
+        avg_ms = km[dominant] / kl[dominant]
+        ach = byl / (avg_ms * 1e-3) / 1e9
+        roof = {"kernel": dominant, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": byl, "avg_launch_ms": avg_ms, "launches": kl[dominant],
+                "class_ms": {k: round(v, 3) for k, v in km.items()}}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, L)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "site·RHS/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"{'x'.join(map(str, dims))} Wilson-Dirac, L={L} point sources, "
+                               f"SAP 8^4 domains ncy={cfg.ncy} nmr={cfg.nmr}, FP32 SAP, tol {cfg.tol:g}",
+                   "lattice": list(dims), "L": L, "kappa": cfg.kappa, "eps": cfg.eps,
+                   "parallelism": "single GPU"},
+        "converged": ok,
+        "iterations": it,
+        "tts_per_rhs_s": {"mixed": step_s / L, "fp64": fp64["tts_per_rhs_s"] if fp64 else None,
+                          "fp64_over_mixed": (fp64["tts_per_rhs_s"] / (step_s / L)) if fp64 else None},
+        "fp64_solve": fp64,
+        "max_true_res": float(max(i["true_res"].max() for i in infos)),
+        "dslash": dslash,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    B.mbbs_lattice_destroy(lat)
+
+
+def cpu_baseline(cfg, L):
+    """The oracle's operator on a bounded sample of the workload: a 32^3 x 4
+    slab of the lattice (same per-site work, periodic in its own t extent)."""
+    from oracle import dirac
+    from paper_1104_0737_amd import inputs
+    dims = (cfg.dims[0], cfg.dims[1], cfg.dims[2], 4)
+    V = int(np.prod(dims))
+    U = inputs.gauge_field(dims, cfg.eps, 99)
+    X = inputs.gaussian_block(V, L, 98)
+    t = time.perf_counter()
+    reps = 0
+    while True:
+        dirac.apply_D(U, cfg.kappa, cfg.phases, X, dims)
+        reps += 1
+        if time.perf_counter() - t > 10:
+            break
+    dt = (time.perf_counter() - t) / reps
+    return {"value": V * L / dt, "unit": "site·RHS/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle Wilson-Dirac (numpy, FP64) on a {'x'.join(map(str, dims))} slab, L={L}, "
+                      f"{reps} application(s), {dt:.2f}s each; {len(os.sched_getaffinity(0))} host cores "
+                      "visible, numpy ran single-threaded"}
+
+
+if __name__ == "__main__":
+    main()

@@ -141,9 +141,11 @@ int col_norms(Ctx& c, const double2* A, double* out, const int* frozen) {
   return MBBS_OK;
 }
 
-int dslash64(Ctx& c, const double2* in, double2* out) {
+// A applied in FP64; `frozen` is the iteration flag inside the loop and null
+// for the set-up, true-residual and restart steps (which run after a stop).
+int dslash64(Ctx& c, const double2* in, double2* out, const int* frozen) {
   if (c.prof) c.prof->begin(MBBS_K_DSLASH64);
-  int rc = launch_dslash(c.lat, c.L, P64, P64, LEX, false, in, nullptr, out, nullptr, 0, c.lat->g.V, c.frozen, c.st);
+  int rc = launch_dslash(c.lat, c.L, P64, P64, LEX, false, in, nullptr, out, nullptr, 0, c.lat->g.V, frozen, c.st);
   if (c.prof) c.prof->end();
   return rc;
 }
@@ -189,7 +191,7 @@ int enqueue_iteration(Ctx& c) {
   }
   // 4.2 U = M (P gamma^{-1});  4.3 V = A U
   MBBS_TRY(precondition(c, w.P, d.ginv, w.U));
-  MBBS_TRY(dslash64(c, w.U, w.V));
+  MBBS_TRY(dslash64(c, w.U, w.V, fz));
   // 4.4 alpha from R~^H V and R~^H R
   {
     GramArgs g{};
@@ -220,7 +222,7 @@ int enqueue_iteration(Ctx& c) {
   }
   // 4.6 S = M T;  4.7 Z = A S
   if (c.p.precond) MBBS_TRY(precondition(c, w.T, nullptr, w.S));
-  MBBS_TRY(dslash64(c, w.S, w.Z));
+  MBBS_TRY(dslash64(c, w.S, w.Z, fz));
   // 4.8 / 4.11: R~^H Z, Tr(Z^H T), Tr(Z^H Z)
   {
     GramArgs g{};
@@ -274,7 +276,7 @@ int start(Ctx& c, bool x_zero, bool set_rt) {
   if (x_zero) {
     MBBS_TRY(launch_copy(c.B, w.R, c.N * c.L, c.st));
   } else {
-    MBBS_TRY(dslash64(c, c.X, w.V));
+    MBBS_TRY(dslash64(c, c.X, w.V, nullptr));
     ComboArgs a{};
     a.nin = 2;
     a.mode[0] = 0; a.in[0] = c.B;
@@ -298,7 +300,7 @@ int start(Ctx& c, bool x_zero, bool set_rt) {
 // True residual T = B - A X and its column norms.
 int true_residual(Ctx& c) {
   Work& w = c.w;
-  MBBS_TRY(dslash64(c, c.X, w.V));
+  MBBS_TRY(dslash64(c, c.X, w.V, nullptr));
   ComboArgs a{};
   a.nin = 2;
   a.mode[0] = 0; a.in[0] = c.B;
@@ -359,15 +361,23 @@ static int job_init(SolveJob& j) {
 
 // After a batch: read the state; on a stop, check the true residual and
 // restart if it disagrees with the recursive one.
+// Copy device memory to the host in stream order (the caller's stream may be
+// non-blocking with respect to the legacy default stream).
+static int read_dev(Ctx& c, void* dst, const void* src, size_t n) {
+  MBBS_HIP(hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, c.st));
+  MBBS_HIP(hipStreamSynchronize(c.st));
+  return MBBS_OK;
+}
+
 static int job_check(SolveJob& j) {
   Ctx& c = j.c;
-  MBBS_HIP(hipMemcpy(&j.hs, c.w.d.state, sizeof(SolverState), hipMemcpyDeviceToHost));
+  MBBS_TRY(read_dev(c, &j.hs, c.w.d.state, sizeof(SolverState)));
   if (!j.hs.frozen) return MBBS_OK;
   MBBS_TRY(true_residual(c));
   j.n_outer += 1;
   std::vector<double> tn(c.L), bn(c.L);
-  MBBS_HIP(hipMemcpy(tn.data(), c.w.trnorm2, c.L * sizeof(double), hipMemcpyDeviceToHost));
-  MBBS_HIP(hipMemcpy(bn.data(), c.w.d.bnorm2, c.L * sizeof(double), hipMemcpyDeviceToHost));
+  MBBS_TRY(read_dev(c, tn.data(), c.w.trnorm2, c.L * sizeof(double)));
+  MBBS_TRY(read_dev(c, bn.data(), c.w.d.bnorm2, c.L * sizeof(double)));
   double worst = 0;
   bool finite = true;
   for (int i = 0; i < c.L; ++i) {
@@ -397,7 +407,8 @@ static int job_check(SolveJob& j) {
   SolverState s = j.hs;
   s.frozen = 0;
   s.status = ST_RUNNING;
-  MBBS_HIP(hipMemcpy(c.w.d.state, &s, sizeof(s), hipMemcpyHostToDevice));
+  MBBS_HIP(hipMemcpyAsync(c.w.d.state, &s, sizeof(s), hipMemcpyHostToDevice, c.st));
+  MBBS_HIP(hipStreamSynchronize(c.st));
   return MBBS_OK;
 }
 
@@ -416,9 +427,9 @@ static void job_fill_info(SolveJob& j, mbbs_solve_info* info, double seconds) {
   info->n_sap = c.p.precond ? 2ll * j.hs.iter : 0;
   info->seconds = seconds;
   std::vector<double> tn(c.L), rn(c.L), bn(c.L);
-  if (hipMemcpy(tn.data(), c.w.trnorm2, c.L * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess &&
-      hipMemcpy(rn.data(), c.w.d.rnorm2, c.L * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess &&
-      hipMemcpy(bn.data(), c.w.d.bnorm2, c.L * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess) {
+  if (read_dev(c, tn.data(), c.w.trnorm2, c.L * sizeof(double)) == MBBS_OK &&
+      read_dev(c, rn.data(), c.w.d.rnorm2, c.L * sizeof(double)) == MBBS_OK &&
+      read_dev(c, bn.data(), c.w.d.bnorm2, c.L * sizeof(double)) == MBBS_OK) {
     for (int i = 0; i < c.L; ++i) {
       if (info->true_res) info->true_res[i] = std::sqrt(tn[i] / bn[i]);
       if (info->rec_res) info->rec_res[i] = std::sqrt(rn[i] / bn[i]);

@@ -100,9 +100,11 @@ def test_graph_and_cholqr2(c1):
 
 
 def test_unpreconditioned_and_guess():
+    # Z2 sources: with point sources, R~ = R_0 and M = 1, R~^H V is singular
+    # in exact arithmetic at the second iteration (a true breakdown)
     dims, block, L = (4, 4, 4, 4), (2, 2, 2, 2), 3
     U = inputs.gauge_field(dims, 0.3, 41)
-    Bh = inputs.point_sources(256, L, 9, 1)
+    Bh = inputs.z2_sources(256, L, 9)
     D = dirac.dense_D(U, 0.13, gu.PH_AP, dims)
     ref = krylov.block_bicgstab(lambda X: D @ X, lambda X: X, Bh, 1e-12, maxiter=300)
     with gu.Lattice(dims, block, U, 0.13) as lat:
