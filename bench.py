@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-fp64-solve", action="store_true")
     ap.add_argument("--dslash-reps", type=int, default=20)
     ap.add_argument("--only-dslash", action="store_true", help="stand-alone operator timing only")
+    ap.add_argument("--skip-dslash", action="store_true", help="no stand-alone operator timing")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--profile", type=int, default=1, help="event-time kernel classes in the timed solves")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a device-to-device copy of 4 GiB (HBM counter calibration)")
@@ -126,6 +128,18 @@ def main():
     lat = B.mbbs_lattice_create(dims, cfg.block, Ud, cfg.kappa, cfg.phases, stream=stream)
     del Ud
 
+    # ------------------------------------------------------------ launch tuning
+    tuning = {}
+    if not args.no_tune:
+        from paper_1104_0737_amd import autotune
+        for prec, name in ((B.FP64, "fp64"), (B.FP32, "fp32"), (B.FP16S, "fp16s")):
+            best, times = autotune.tune_operator(lat, V, L, prec, stream=stream)
+            tuning[name] = {"group_cols": best[0], "block_threads": best[1], "ms": round(times[best], 4),
+                            "worst_ms": round(max(times.values()), 4)}
+            log(f"tuned {name}: group {best[0]} threads {best[1]} ({times[best]:.3f} ms; worst "
+                f"{max(times.values()):.3f} ms)")
+        torch.cuda.empty_cache()
+
     # ------------------------------------------------------------ operator alone
     def time_dslash(prec):
         gen = torch.Generator(device=dev)
@@ -159,12 +173,12 @@ def main():
                 "bytes_per_launch": by}
 
     dslash = {}
-    for prec, name in ((B.FP64, "fp64"), (B.FP32, "fp32"), (B.FP16S, "fp16s")):
+    for prec, name in () if args.skip_dslash else ((B.FP64, "fp64"), (B.FP32, "fp32"), (B.FP16S, "fp16s")):
         log(f"operator {name}")
         dslash[name] = time_dslash(prec)
         log(f"  {dslash[name]['ms']:.3f} ms, {dslash[name]['algo_GBps']:.0f} GB/s algorithmic")
     if args.only_dslash:
-        print(json.dumps({"dslash": dslash}), flush=True)
+        print(json.dumps({"dslash": dslash, "tuning": tuning}), flush=True)
         B.mbbs_lattice_destroy(lat)
         return
 
@@ -264,6 +278,7 @@ def main():
         "fp64_solve": fp64,
         "max_true_res": float(max(i["true_res"].max() for i in infos)),
         "dslash": dslash,
+        "tuning": tuning,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -24,7 +24,8 @@ TABLES = ("COORD", "NEIGHBOUR", "BOUNDARY", "PARITY", "EO", "DOMAIN", "COLOUR", 
 KERNEL_CLASSES = ("dslash64", "sap_resid", "mr_dslash", "mr_update", "convert", "gram", "update", "small")
 
 EXPORTS = (
-    "mbbs_lattice_create", "mbbs_lattice_destroy", "mbbs_lattice_table_size", "mbbs_lattice_table",
+    "mbbs_lattice_create", "mbbs_lattice_destroy", "mbbs_lattice_tune", "mbbs_lattice_table_size",
+    "mbbs_lattice_table",
     "mbbs_apply_dirac", "mbbs_apply_dirac_raw", "mbbs_convert_to", "mbbs_convert_from",
     "mbbs_apply_blocked", "mbbs_sap_workspace_size", "mbbs_sap_apply", "mbbs_gram_workspace_size",
     "mbbs_gram", "mbbs_cholqr", "mbbs_lu_solve", "mbbs_solve_params_default",
@@ -69,6 +70,7 @@ def lib():
             "mbbs_lattice_create": (i, [ctypes.POINTER(i), ctypes.POINTER(i), vp, d, ctypes.POINTER(d), vp,
                                         ctypes.POINTER(vp)]),
             "mbbs_lattice_destroy": (i, [vp]),
+            "mbbs_lattice_tune": (i, [vp, i, i]),
             "mbbs_lattice_table_size": (i, [vp, i, ctypes.POINTER(sz)]),
             "mbbs_lattice_table": (i, [vp, i, vp, sz]),
             "mbbs_apply_dirac": (i, [vp, i, vp, vp, i, vp]),
@@ -146,6 +148,15 @@ def mbbs_lattice_create(dims, block, U, kappa, phases, stream=None):
 
 def mbbs_lattice_destroy(lat):
     return _check(lib().mbbs_lattice_destroy(lat))
+
+
+TUNE_GROUP = {0: 0, 1: 1, 2: 2}      # precision -> knob
+TUNE_BLOCK_THREADS = 3
+TUNE_LDS_PAD_KB = 4
+
+
+def mbbs_lattice_tune(lat, knob, value):
+    return _check(lib().mbbs_lattice_tune(lat, knob, value))
 
 
 def mbbs_lattice_table(lat, which):

@@ -31,41 +31,48 @@ __device__ inline double2 block_reduce_y(double2* sh, cplx<double> v, int j, int
 // ---------------------------------------------------------------- Gram
 // Thread (j, y): column j of X, row y of the block's current row tile.  Each
 // block accumulates sum_n conj(X[n,j]) Y[n,:] over its rows (Y rows staged in
-// LDS), reduces over y in LDS and writes its partial Gram matrices.
-template <int LMAX>
+// LDS), reduces over y in LDS and writes its partial Gram matrices.  The pair
+// count NP and the column bound LMAX are compile-time so that the
+// accumulators stay in registers.
+template <int LMAX, int NF, int ND>
 __global__ void __launch_bounds__(256) k_gram(int L, size_t N, GramArgs a, double2* __restrict__ partial,
                                               const int* __restrict__ frozen) {
+  // pairs 0..NF-1 are full products, NF..NF+ND-1 diagonal-only
+  constexpr int NP = NF + ND;
   if (frozen && *frozen) return;
-  extern __shared__ double2 sh[];  // [npair][S][L] Y rows, reused for the reduction
+  extern __shared__ double2 sh[];  // [NP][S][L] Y rows, reused for the reduction
   const int j = threadIdx.x, y = threadIdx.y, S = blockDim.y;
-  const int np = a.npair;
-  cplx<double> acc[GRAM_MAXPAIR][LMAX];
+  cplx<double> acc[NF > 0 ? NF : 1][LMAX];
+  cplx<double> dacc[ND > 0 ? ND : 1];
 #pragma unroll
-  for (int p = 0; p < GRAM_MAXPAIR; ++p)
+  for (int p = 0; p < (NF > 0 ? NF : 1); ++p)
 #pragma unroll
     for (int q = 0; q < LMAX; ++q) acc[p][q] = cmake(0.0, 0.0);
+#pragma unroll
+  for (int p = 0; p < (ND > 0 ? ND : 1); ++p) dacc[p] = cmake(0.0, 0.0);
   const size_t stride = (size_t)gridDim.x * S;
   for (size_t n0 = (size_t)blockIdx.x * S; n0 < N; n0 += stride) {
     const size_t n = n0 + y;
-    cplx<double> xv[GRAM_MAXPAIR];
+    cplx<double> xv[NP];
+    double2 yv[NP];
     __syncthreads();
-    for (int p = 0; p < np; ++p) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
       double2 xe = make_double2(0, 0), ye = make_double2(0, 0);
       if (n < N) {
         xe = a.X[p][n * L + j];
         ye = a.Y[p][n * L + j];
       }
       xv[p] = cmake(xe.x, xe.y);
-      sh[((size_t)p * S + y) * L + j] = ye;
+      yv[p] = ye;
+      if (p < NF) sh[((size_t)p * S + y) * L + j] = ye;
     }
-    __syncthreads();
 #pragma unroll
-    for (int p = 0; p < GRAM_MAXPAIR; ++p) {
-      if (p >= np) break;
-      if (a.diag[p]) {
-        double2 ye = sh[((size_t)p * S + y) * L + j];
-        acc[p][0] = acc[p][0] + cdot(xv[p], cmake(ye.x, ye.y));
-      } else {
+    for (int p = NF; p < NP; ++p) dacc[p - NF] = dacc[p - NF] + cdot(xv[p], cmake(yv[p].x, yv[p].y));
+    if constexpr (NF > 0) {
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < NF; ++p)
 #pragma unroll
         for (int q = 0; q < LMAX; ++q) {
           if (q < L) {
@@ -73,27 +80,26 @@ __global__ void __launch_bounds__(256) k_gram(int L, size_t N, GramArgs a, doubl
             acc[p][q] = acc[p][q] + cdot(xv[p], cmake(ye.x, ye.y));
           }
         }
+    }
+  }
+  // reduce over y one output column at a time: sh reused as [S][L]
+#pragma unroll
+  for (int p = 0; p < NF; ++p) {
+    double2* out = partial + ((size_t)blockIdx.x * GRAM_MAXPAIR + p) * L * L;
+#pragma unroll
+    for (int q = 0; q < LMAX; ++q) {
+      if (q < L) {
+        double2 r = block_reduce_y(sh, acc[p][q], j, y, L, S);
+        if (y == 0) out[j * L + q] = r;
       }
     }
   }
-  // reduce over y one output column q at a time: sh reused as [S][L]
-  for (int p = 0; p < np; ++p) {
-    const int nq = a.diag[p] ? 1 : L;
-    double2* out = partial + ((size_t)blockIdx.x * GRAM_MAXPAIR + p) * L * L;
-    for (int q = 0; q < nq; ++q) {
-      cplx<double> v = acc[p][0];
 #pragma unroll
-      for (int qq = 0; qq < LMAX; ++qq)
-        if (qq == q) v = acc[p][qq];
-      double2 r = block_reduce_y(sh, v, j, y, L, S);
-      if (y == 0) {
-        if (a.diag[p]) {
-          for (int qq = 0; qq < L; ++qq) out[j * L + qq] = qq == j ? r : make_double2(0, 0);
-        } else {
-          out[j * L + q] = r;
-        }
-      }
-    }
+  for (int p = 0; p < ND; ++p) {
+    double2* out = partial + ((size_t)blockIdx.x * GRAM_MAXPAIR + NF + p) * L * L;
+    double2 r = block_reduce_y(sh, dacc[p], j, y, L, S);
+    if (y == 0)
+      for (int qq = 0; qq < L; ++qq) out[j * L + qq] = qq == j ? r : make_double2(0, 0);
   }
 }
 
@@ -181,17 +187,16 @@ __global__ void __launch_bounds__(256) k_combo(int L, size_t N, ComboArgs a, dou
   if constexpr (GM != 0) {
     const int nq = GM == 1 ? 1 : L;
     double2* o = partial + (size_t)blockIdx.x * GRAM_MAXPAIR * L * L;
-    for (int q = 0; q < nq; ++q) {
-      cplx<double> v = g[0];
 #pragma unroll
-      for (int qq = 0; qq < LMAX; ++qq)
-        if (qq == q) v = g[qq];
-      double2 r = block_reduce_y(sh, v, j, y, L, S);
-      if (y == 0) {
-        if (GM == 1) {
-          for (int qq = 0; qq < L; ++qq) o[j * L + qq] = qq == j ? r : make_double2(0, 0);
-        } else {
-          o[j * L + q] = r;
+    for (int q = 0; q < LMAX; ++q) {
+      if (q < nq) {
+        double2 r = block_reduce_y(sh, g[q], j, y, L, S);
+        if (y == 0) {
+          if (GM == 1) {
+            for (int qq = 0; qq < L; ++qq) o[j * L + qq] = qq == j ? r : make_double2(0, 0);
+          } else {
+            o[j * L + q] = r;
+          }
         }
       }
     }
@@ -491,13 +496,27 @@ static void launch_gram_l(int L, size_t N, const GramArgs& a, double2* partial, 
   const int S = gram_rows_per_block(L);
   const int nb = gram_blocks(N, L);
   const size_t shb = (size_t)GRAM_MAXPAIR * S * L * sizeof(double2);
-  hipLaunchKernelGGL((k_gram<LMAX>), dim3(nb), dim3(L, S), shb, st, L, N, a, partial, frozen);
+  int nf = 0;
+  while (nf < a.npair && !a.diag[nf]) ++nf;
+  const int nd = a.npair - nf;
+#define GL(F, D) hipLaunchKernelGGL((k_gram<LMAX, F, D>), dim3(nb), dim3(L, S), shb, st, L, N, a, partial, frozen)
+  if (nf == 1 && nd == 0) GL(1, 0);
+  else if (nf == 2 && nd == 0) GL(2, 0);
+  else if (nf == 1 && nd == 2) GL(1, 2);
+  else if (nf == 0 && nd == 1) GL(0, 1);
+  else if (nf == 3 && nd == 0) GL(3, 0);
+  else if (nf == 1 && nd == 1) GL(1, 1);
+  else if (nf == 0 && nd == 2) GL(0, 2);
+  else GL(0, 3);
+#undef GL
 }
 
 int launch_gram(int L, size_t N, const GramArgs& a, const GramOut& o, double2* partial, const int* frozen,
                 hipStream_t st) {
   MBBS_CHECK(L >= 1 && L <= LMAX_SOLVER, "L out of range for block linear algebra");
   MBBS_CHECK(a.npair >= 1 && a.npair <= GRAM_MAXPAIR, "bad Gram pair count");
+  for (int p = 1; p < a.npair; ++p)
+    MBBS_CHECK(!(a.diag[p - 1] && !a.diag[p]), "full Gram pairs must precede diagonal ones");
   if (L <= 4) launch_gram_l<4>(L, N, a, partial, frozen, st);
   else if (L <= 8) launch_gram_l<8>(L, N, a, partial, frozen, st);
   else if (L <= 12) launch_gram_l<12>(L, N, a, partial, frozen, st);

@@ -95,8 +95,6 @@ extern "C" int mbbs_sap_apply(mbbs_lattice_t lat, int L, const double* X, double
   MBBS_CHECK(prec_ok(prec), "bad precision");
   SapBuffers b;
   MBBS_TRY(sap_bind(lat, L, prec, ws, ws_bytes, &b));
-  // counters start at zero; every completed MR step returns them to zero
-  MBBS_HIP(hipMemsetAsync(b.counter, 0, (size_t)lat->g.ndom / 2 * sizeof(unsigned), (hipStream_t)stream));
   return sap_apply(lat, b, ncy, nmr, (const double2*)X, nullptr, (double2*)Y, nullptr, (hipStream_t)stream, nullptr);
 }
 

@@ -178,13 +178,16 @@ __global__ void __launch_bounds__(256) k_dslash(GeomK k, double kappa, int L,
                                                 typename Store<POUT>::Elem* __restrict__ out,
                                                 float* __restrict__ out_s,
                                                 const LinkElem<PL>* __restrict__ U, int s0, int n,
-                                                const int* __restrict__ frozen) {
+                                                int bpt, int ngroups, const int* __restrict__ frozen) {
   if (frozen && *frozen) return;
   using R = typename Store<PL>::Real;
-  const int s = s0 + blockIdx.x * blockDim.y + threadIdx.y;
-  if (s >= s0 + n) return;
-  const int col0 = threadIdx.x * C;
-  const SiteCtx c = site_ctx<ORDER>(k, s);
+  int i, grp;
+  decompose(xcd_block(blockIdx.x, gridDim.x), bpt, ngroups, blockDim.y, i, grp);
+  if (i >= n) return;
+  const int col0 = (grp * blockDim.x + threadIdx.x) * C;
+  // lexicographic fields are walked tile by tile (whole lattice, s0 = 0)
+  const SiteCtx c = ORDER == LEX ? site_ctx_tiled(k, i) : site_ctx<DM>(k, s0 + i);
+  const int s = c.s;
   cplx<R> acc[4][3][C];
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
@@ -219,13 +222,15 @@ __global__ void __launch_bounds__(256) k_sap_resid(GeomK k, double kappa, int L,
                                                    const typename Store<PPSI>::Elem* __restrict__ psi,
                                                    typename Store<PR>::Elem* __restrict__ r,
                                                    float* __restrict__ r_s,
-                                                   const LinkElem<PL>* __restrict__ U,
-                                                   const int* __restrict__ frozen) {
+                                                   const LinkElem<PL>* __restrict__ U, int bpt,
+                                                   int ngroups, const int* __restrict__ frozen) {
   if (frozen && *frozen) return;
   using R = typename Store<PL>::Real;
-  const int s = s0 + blockIdx.x * blockDim.y + threadIdx.y;
-  if (s >= s0 + n) return;
-  const int col0 = threadIdx.x * C;
+  int i, grp;
+  decompose(xcd_block(blockIdx.x, gridDim.x), bpt, ngroups, blockDim.y, i, grp);
+  if (i >= n) return;
+  const int s = s0 + i;
+  const int col0 = (grp * blockDim.x + threadIdx.x) * C;
   cplx<R> acc[4][3][C];
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
@@ -265,9 +270,7 @@ __global__ void __launch_bounds__(256) k_sap_resid(GeomK k, double kappa, int L,
 }
 
 // MR step, part 1: w = A_DD r on one colour's domains, plus per-block sums of
-// <w, r> and <w, w> per column; the last block of each domain to finish sums
-// the domain's block partials in fixed order and writes the step size
-// omega = <w, r> / <w, w> (0 when <w, w> = 0).
+// <w, r> and <w, w> per column.
 template <int PR, int PL, int C>
 __global__ void __launch_bounds__(256) k_mr_dslash(GeomK k, double kappa, int L, int s0, int n,
                                                    const typename Store<PR>::Elem* __restrict__ r,
@@ -275,15 +278,16 @@ __global__ void __launch_bounds__(256) k_mr_dslash(GeomK k, double kappa, int L,
                                                    typename Store<PR>::Elem* __restrict__ w,
                                                    float* __restrict__ w_s,
                                                    const LinkElem<PL>* __restrict__ U,
-                                                   double* __restrict__ partial,
-                                                   unsigned* __restrict__ counter,
-                                                   double* __restrict__ omega,
+                                                   double* __restrict__ partial, int bpt, int ngroups,
                                                    const int* __restrict__ frozen) {
   if (frozen && *frozen) return;
   using R = typename Store<PL>::Real;
   extern __shared__ double red[];  // [3][blockDim.y][blockDim.x*C]
-  const int s = s0 + blockIdx.x * blockDim.y + threadIdx.y;  // blocks never straddle domains
-  const int col0 = threadIdx.x * C;
+  int i, grp;
+  decompose(xcd_block(blockIdx.x, gridDim.x), bpt, ngroups, blockDim.y, i, grp);
+  const int s = s0 + i;  // blocks never straddle domains
+  const int colg = grp * blockDim.x * C;           // first column of the group
+  const int col0 = colg + threadIdx.x * C;
   const SiteCtx c = site_ctx<DM>(k, s);
   cplx<R> acc[4][3][C];
 #pragma unroll
@@ -323,48 +327,67 @@ __global__ void __launch_bounds__(256) k_mr_dslash(GeomK k, double kappa, int L,
         a_re += d.re; a_im += d.im; a_ww += norm2(wv[sp][a]);
       }
     wr_re = a_re; wr_im = a_im; ww = a_ww;
-    const int col = col0 + q;
+    const int col = threadIdx.x * C + q;             // column within the group
     red[(0 * ny + threadIdx.y) * nx + col] = wr_re;
     red[(1 * ny + threadIdx.y) * nx + col] = wr_im;
     red[(2 * ny + threadIdx.y) * nx + col] = ww;
   }
   __syncthreads();
-  // tree over sites (fixed order), one thread per (quantity, column)
-  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-  const int nthr = blockDim.x * blockDim.y;
-  for (int stride = 1; stride < ny; stride <<= 1) {
-    for (int e = tid; e < 3 * nx * ny; e += nthr) {
-      int qn = e / (nx * ny), rem = e % (nx * ny), y = rem / nx, col = rem % nx;
-      if ((y % (2 * stride)) == 0 && y + stride < ny)
-        red[(qn * ny + y) * nx + col] += red[(qn * ny + y + stride) * nx + col];
-    }
-    __syncthreads();
-  }
-  const int rel = blockIdx.x * ny;                        // first site of the block in its colour
+  // sum over the block's sites in fixed order, one thread per column chunk
+  const int rel = i - threadIdx.y;                        // first site of the block in its colour
   const int dom = rel / k.g.Vb;                           // domain rank within the colour
   const int nblk = k.g.Vb / ny;
   const int bid = (rel % k.g.Vb) / ny;                    // block index inside the domain
-  for (int e = tid; e < 3 * nx; e += nthr) {
-    int qn = e / nx, col = e % nx;
-    partial[(((size_t)dom * nblk + bid) * L + col) * 3 + qn] = red[(qn * ny + 0) * nx + col];
+  if (threadIdx.y == 0) {
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const int col = threadIdx.x * C + q;
+      double a0 = 0, a1 = 0, a2 = 0;
+      for (int y = 0; y < ny; ++y) {
+        a0 += red[(0 * ny + y) * nx + col];
+        a1 += red[(1 * ny + y) * nx + col];
+        a2 += red[(2 * ny + y) * nx + col];
+      }
+      double* pp = partial + (((size_t)dom * nblk + bid) * L + colg + col) * 3;
+      pp[0] = a0; pp[1] = a1; pp[2] = a2;
+    }
   }
-  __threadfence();
+}
+
+// MR step, part 1b: per domain of the colour (one block each), sum the block
+// partials in fixed order and form omega = <w, r> / <w, w> (0 if <w, w> = 0).
+// A separate launch: the kernel boundary makes every block's partial visible
+// without device-wide fences (which on this chip write back and invalidate the
+// per-XCD L2 caches).
+__global__ void __launch_bounds__(256) k_mr_omega(int L, int nblk, const double* __restrict__ partial,
+                                                  double* __restrict__ omega, const int* __restrict__ frozen) {
+  if (frozen && *frozen) return;
+  __shared__ double red[3 * 256];
+  const int dom = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
+  const int G = nthr / L > 0 ? nthr / L : 1;
+  const double* pp = partial + ((size_t)dom * nblk) * L * 3;
+  for (int e = tid; e < G * L; e += nthr) {
+    const int g = e / L, col = e % L;
+    double a0 = 0, a1 = 0, a2 = 0;
+    for (int bb = g; bb < nblk; bb += G) {
+      a0 += pp[((size_t)bb * L + col) * 3 + 0];
+      a1 += pp[((size_t)bb * L + col) * 3 + 1];
+      a2 += pp[((size_t)bb * L + col) * 3 + 2];
+    }
+    red[(0 * G + g) * L + col] = a0;
+    red[(1 * G + g) * L + col] = a1;
+    red[(2 * G + g) * L + col] = a2;
+  }
   __syncthreads();
-  __shared__ unsigned last;
-  if (tid == 0) last = (atomicInc(&counter[dom], (unsigned)(nblk - 1)) == (unsigned)(nblk - 1));
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
   for (int col = tid; col < L; col += nthr) {
-    double a_re = 0, a_im = 0, a_ww = 0;
-    const volatile double* pp = partial + ((size_t)dom * nblk) * L * 3;
-    for (int b = 0; b < nblk; ++b) {
-      a_re += pp[((size_t)b * L + col) * 3 + 0];
-      a_im += pp[((size_t)b * L + col) * 3 + 1];
-      a_ww += pp[((size_t)b * L + col) * 3 + 2];
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int gg = 0; gg < G; ++gg) {
+      s0 += red[(0 * G + gg) * L + col];
+      s1 += red[(1 * G + gg) * L + col];
+      s2 += red[(2 * G + gg) * L + col];
     }
     double o_re = 0, o_im = 0;
-    if (a_ww > 0) { o_re = a_re / a_ww; o_im = a_im / a_ww; }
+    if (s2 > 0) { o_re = s0 / s2; o_im = s1 / s2; }
     omega[((size_t)dom * L + col) * 2 + 0] = o_re;
     omega[((size_t)dom * L + col) * 2 + 1] = o_im;
   }
@@ -383,7 +406,7 @@ __global__ void __launch_bounds__(256) k_mr_update(GeomK k, int L, int s0, int n
   if (frozen && *frozen) return;
   using R = typename Store<PR>::Real;
   using RP = typename Store<PPSI>::Real;
-  const int s = s0 + blockIdx.x * blockDim.y + threadIdx.y;
+  const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * blockDim.y + threadIdx.y;
   if (s >= s0 + n) return;
   const int col = threadIdx.x;
   const int dom = (s - (s >= k.g.Vh ? k.g.Vh : 0)) / k.g.Vb;
@@ -424,6 +447,7 @@ GeomK make_geomk(const Geom& g) {
     k.fb[m] = make_fastdiv(g.b[m]);
   }
   k.fnd0 = make_fastdiv(g.nd[0]);
+  for (int m = 0; m < 4; ++m) k.fnd[m] = make_fastdiv(g.nd[m]);
   k.fVb = make_fastdiv(g.Vb);
   k.lstride[0] = 1;
   k.stride[0] = 1;
@@ -443,14 +467,32 @@ static int sites_per_block(int nchunk, int vdiv, int target = 256) {
   return best;
 }
 
+// Launch plan of a stencil kernel over `nsites` sites (a multiple of the
+// SAP block volume): C columns per thread, column groups of gw columns,
+// S sites per block, bpt blocks per tile.
+struct Plan {
+  int C, gw, nchunk, ngroups, S, bpt, nblocks;
+};
+static Plan make_plan(const mbbs_lattice_s* lat, int L, int prec, int nsites) {
+  Plan p;
+  p.C = pick_chunk(L, prec);
+  p.gw = lat->group_cols[prec];
+  if (p.gw <= 0 || p.gw % p.C || L % p.gw) p.gw = L;
+  p.nchunk = p.gw / p.C;
+  p.ngroups = L / p.gw;
+  p.S = sites_per_block(p.nchunk, lat->g.Vb, lat->block_threads);
+  p.bpt = lat->g.Vb / p.S;
+  p.nblocks = (nsites / lat->g.Vb) * p.ngroups * p.bpt;
+  return p;
+}
+
 template <int PIN, int POUT, int PL, int C>
 static int dslash_dispatch_order(const mbbs_lattice_s* lat, int L, int order, bool blocked,
                                  const void* in, const float* in_s, void* out, float* out_s,
                                  int s0, int n, const int* frozen, hipStream_t st) {
-  const int nchunk = L / C;
-  const int S = sites_per_block(nchunk, lat->g.Vb);
-  dim3 blk(nchunk, S);
-  dim3 grd(ceil_div(n, S));
+  const Plan pl = make_plan(lat, L, PL, n);
+  dim3 blk(pl.nchunk, pl.S);
+  dim3 grd(pl.nblocks);
   const void* U;
   if (order == LEX) U = PL == P64 ? (const void*)lat->U64 : PL == P32 ? (const void*)lat->U32 : (const void*)lat->U16;
   else U = PL == P64 ? (const void*)lat->U64dm : PL == P32 ? (const void*)lat->U32dm : (const void*)lat->U16dm;
@@ -458,8 +500,9 @@ static int dslash_dispatch_order(const mbbs_lattice_s* lat, int L, int order, bo
   using EO = typename Store<POUT>::Elem;
   using EL = LinkElem<PL>;
 #define MBBS_LAUNCH(ORD, BLK)                                                                   \
-  hipLaunchKernelGGL((k_dslash<PIN, POUT, PL, C, ORD, BLK>), grd, blk, 0, st, lat->gk, lat->kappa, L, \
-                     (const EI*)in, in_s, (EO*)out, out_s, (const EL*)U, s0, n, frozen)
+  hipLaunchKernelGGL((k_dslash<PIN, POUT, PL, C, ORD, BLK>), grd, blk, (size_t)lat->lds_pad_kb * 1024, st,     \
+                     lat->gk, lat->kappa, L,                                                                \
+                     (const EI*)in, in_s, (EO*)out, out_s, (const EL*)U, s0, n, pl.bpt, pl.ngroups, frozen)
   if (order == LEX) {
     if (blocked) MBBS_LAUNCH(LEX, true); else MBBS_LAUNCH(LEX, false);
   } else {
@@ -509,7 +552,7 @@ size_t sap_buffer_bytes(const mbbs_lattice_s* lat, int L, int prec) {
   const size_t nblk = lat->g.Vh;                  // upper bound on blocks per colour
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   return al(field) * 3 + al(scales) * 3 + al(psi) + al(nblk * L * 3 * sizeof(double)) +
-         al(ndc * sizeof(unsigned)) + al(ndc * L * 2 * sizeof(double));
+         al(ndc * L * 2 * sizeof(double));
 }
 
 int sap_bind(const mbbs_lattice_s* lat, int L, int prec, void* ws, size_t bytes, SapBuffers* b) {
@@ -531,7 +574,6 @@ int sap_bind(const mbbs_lattice_s* lat, int L, int prec, void* ws, size_t bytes,
   b->w_s = prec == P16 ? (float*)p : nullptr; p += scales;
   b->psi = p; p += al(V * 12 * L * (prec == P64 ? 16 : 8));
   b->partial = (double*)p; p += al((size_t)lat->g.Vh * L * 3 * sizeof(double));
-  b->counter = (unsigned*)p; p += al((size_t)lat->g.ndom / 2 * sizeof(unsigned));
   b->omega = (double*)p;
   return MBBS_OK;
 }
@@ -545,19 +587,19 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
   const int L = b.L;
   const Geom& g = lat->g;
   const EL* U = PL == P64 ? (const EL*)lat->U64dm : PL == P32 ? (const EL*)lat->U32dm : (const EL*)lat->U16dm;
-  const int C = pick_chunk(L, PL);
-  const int nchunk = L / C;
-  const int S = sites_per_block(nchunk, g.Vb);
+  const Plan pl = make_plan(lat, L, PL, g.Vh);
+  const int C = pl.C, S = pl.S;
   const int Su = sites_per_block(L, g.Vb);
-  const size_t red_bytes = 3 * (size_t)S * nchunk * C * sizeof(double);
+  const size_t red_bytes = 3 * (size_t)S * pl.gw * sizeof(double);
   for (int cy = 0; cy < ncy; ++cy) {
     for (int col = 0; col < 2; ++col) {
       const int s0 = col * g.Vh, n = g.Vh;
       if (prof) prof->begin(MBBS_K_SAP_RES);
 #define RES(CC)                                                                                      \
-  hipLaunchKernelGGL((k_sap_resid<PR, PPSI, PL, CC>), dim3(ceil_div(n, S)), dim3(nchunk, S), 0, st,   \
+  hipLaunchKernelGGL((k_sap_resid<PR, PPSI, PL, CC>), dim3(pl.nblocks), dim3(pl.nchunk, S),                  \
+                     (size_t)lat->lds_pad_kb * 1024, st,                                                     \
                      lat->gk, lat->kappa, L, s0, n, cy > 0 ? 2 : col, (const ER*)b.eta,                \
-                     b.eta_s, (const EP*)b.psi, (ER*)b.r, b.r_s, U, frozen)
+                     b.eta_s, (const EP*)b.psi, (ER*)b.r, b.r_s, U, pl.bpt, pl.ngroups, frozen)
       switch (C) { case 4: RES(4); break; case 3: RES(3); break; case 2: RES(2); break; default: RES(1); }
 #undef RES
       if (prof) prof->end();
@@ -565,11 +607,15 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
       for (int it = 0; it < nmr; ++it) {
         if (prof) prof->begin(MBBS_K_MR_DSLASH);
 #define MRD(CC)                                                                                       \
-  hipLaunchKernelGGL((k_mr_dslash<PR, PL, CC>), dim3(n / S), dim3(nchunk, S), red_bytes, st, lat->gk, \
-                     lat->kappa, L, s0, n, (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial,      \
-                     b.counter, b.omega, frozen)
+  hipLaunchKernelGGL((k_mr_dslash<PR, PL, CC>), dim3(pl.nblocks), dim3(pl.nchunk, S),                       \
+                     red_bytes + (size_t)lat->lds_pad_kb * 1024, st, lat->gk,                                \
+                     lat->kappa, L, s0, n, (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial, pl.bpt,   \
+                     pl.ngroups, frozen)
         switch (C) { case 4: MRD(4); break; case 3: MRD(3); break; case 2: MRD(2); break; default: MRD(1); }
 #undef MRD
+        MBBS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_mr_omega, dim3(g.ndom / 2), dim3(256), 0, st, L, g.Vb / S, (const double*)b.partial,
+                           b.omega, frozen);
         if (prof) prof->end();
         MBBS_HIP(hipGetLastError());
         if (prof) prof->begin(MBBS_K_MR_UPDATE);

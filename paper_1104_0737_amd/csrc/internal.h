@@ -61,11 +61,21 @@ struct GeomK {
   FastDiv fd[4];     // extents
   FastDiv fb[4];     // block sizes
   FastDiv fnd0;      // domains along x
+  FastDiv fnd[4];    // domains along each direction
   FastDiv fVb;       // block volume
   int lstride[4];    // local strides inside a domain
   int stride[4];     // lexicographic strides
 };
 GeomK make_geomk(const Geom& g);
+
+// Workgroups are dealt to the 8 XCDs of the chip in turn (block b runs on XCD
+// b mod 8).  Remap so that XCD x processes one contiguous run of logical
+// blocks, in order: spatial neighbours then share that XCD's L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int per = nb >> 3;
+  if (b >= per * 8) return b;
+  return (b & 7) * per + (b >> 3);
+}
 
 }  // namespace mbbs
 
@@ -80,6 +90,12 @@ struct mbbs_lattice_s {
   double2* U64dm = nullptr;   // domain-major links
   float2* U32dm = nullptr;
   __half2* U16dm = nullptr;
+  // launch tuning (set through mbbs_lattice_tune): columns per column group
+  // of the stencil kernels per precision (0: all columns in one group) and
+  // the target number of threads per block
+  int group_cols[3] = {0, 0, 0};
+  int block_threads = 256;
+  int lds_pad_kb = 0;   // extra LDS per stencil block: caps resident blocks per CU
 };
 
 namespace mbbs {
@@ -102,7 +118,6 @@ struct SapBuffers {
   void* w;   float* w_s;
   void* psi;               // double2 or float2
   double* partial;         // per block, per column: (wr.re, wr.im, ww)
-  unsigned* counter;       // per domain-of-colour arrival counters (zeroed)
   double* omega;           // per domain-of-colour, per column: complex step
 };
 size_t sap_buffer_bytes(const mbbs_lattice_s* lat, int L, int prec);
@@ -147,6 +162,19 @@ inline int pick_chunk(int L, int prec) {
   for (int c = cmax; c > 1; --c)
     if (L % c == 0) return c;
   return 1;
+}
+
+// Decomposition of a stencil launch into (tile, column group, site block):
+// logical block lb covers sites [t*Vb + b*S, +S) of the traversal and the
+// column group g; blocks of one tile's column group are consecutive so that
+// they run together on one XCD.
+__device__ __forceinline__ void decompose(int lb, int bpt, int ngroups, int S, int& site, int& g) {
+  const int per_tile = ngroups * bpt;
+  const int t = lb / per_tile;
+  const int rem = lb - t * per_tile;
+  g = rem / bpt;
+  const int b = rem - g * bpt;
+  site = (t * bpt + b) * S + (int)threadIdx.y;
 }
 
 }  // namespace mbbs

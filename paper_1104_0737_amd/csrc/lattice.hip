@@ -212,6 +212,29 @@ extern "C" int mbbs_lattice_destroy(mbbs_lattice_t lat) {
   return MBBS_OK;
 }
 
+extern "C" int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value) {
+  MBBS_CHECK(lat != nullptr, "null lattice");
+  switch (knob) {
+    case MBBS_TUNE_GROUP_FP64:
+    case MBBS_TUNE_GROUP_FP32:
+    case MBBS_TUNE_GROUP_FP16S:
+      MBBS_CHECK(value >= 0 && value <= 64, "column group out of range");
+      lat->group_cols[knob] = value;
+      return MBBS_OK;
+    case MBBS_TUNE_BLOCK_THREADS:
+      MBBS_CHECK(value >= 32 && value <= 256, "threads per block must be in 32..256");
+      lat->block_threads = value;
+      return MBBS_OK;
+    case MBBS_TUNE_LDS_PAD_KB:
+      MBBS_CHECK(value >= 0 && value <= 64, "LDS pad must be in 0..64 KiB");
+      lat->lds_pad_kb = value;
+      return MBBS_OK;
+    default:
+      set_error("unknown tuning knob");
+      return MBBS_EINVAL;
+  }
+}
+
 extern "C" int mbbs_lattice_table_size(mbbs_lattice_t lat, int which, size_t* count) {
   MBBS_CHECK(lat && count, "null argument");
   MBBS_CHECK(which >= 0 && which < MBBS_TAB_COUNT, "unknown table");

@@ -55,6 +55,34 @@ __device__ __forceinline__ SiteCtx site_ctx(const GeomK& k, int s) {
   return c;
 }
 
+// Lexicographic context of the i-th site of a tiled traversal: tiles are the
+// SAP blocks in lexicographic order of the domain grid, sites inside a tile
+// in local lexicographic order.  Used to walk lexicographic fields tile by
+// tile so that a tile's neighbour data stays in one XCD's L2.
+__device__ __forceinline__ SiteCtx site_ctx_tiled(const GeomK& k, int i) {
+  SiteCtx c;
+  const uint32_t tile = fdiv(i, k.fVb);
+  const uint32_t loc = i - tile * k.g.Vb;
+  uint32_t q = tile, r;
+  int tc[4], lc[4];
+  r = fdiv(q, k.fnd[0]); tc[0] = q - r * k.g.nd[0]; q = r;
+  r = fdiv(q, k.fnd[1]); tc[1] = q - r * k.g.nd[1]; q = r;
+  r = fdiv(q, k.fnd[2]); tc[2] = q - r * k.g.nd[2]; tc[3] = r;
+  q = loc;
+  r = fdiv(q, k.fb[0]); lc[0] = q - r * k.g.b[0]; q = r;
+  r = fdiv(q, k.fb[1]); lc[1] = q - r * k.g.b[1]; q = r;
+  r = fdiv(q, k.fb[2]); lc[2] = q - r * k.g.b[2]; lc[3] = r;
+  for (int m = 0; m < 4; ++m) {
+    c.x[m] = tc[m] * k.g.b[m] + lc[m];
+    c.l[m] = lc[m];
+    c.dc[m] = tc[m];
+  }
+  c.s = c.x[0] + k.stride[1] * c.x[1] + k.stride[2] * c.x[2] + k.stride[3] * c.x[3];
+  c.colour = 0;
+  c.loc = loc;
+  return c;
+}
+
 // Neighbour index of the site along (mu, dir) in the field's order.
 template <int ORDER>
 __device__ __forceinline__ int neighbour(const GeomK& k, const SiteCtx& c, int mu, int dir) {

@@ -347,8 +347,6 @@ static int job_init(SolveJob& j) {
       return MBBS_EINVAL;
     }
   }
-  if (c.p.precond)  // MR arrival counters start at zero and return to zero after every step
-    MBBS_HIP(hipMemsetAsync(c.w.sap.counter, 0, (size_t)c.lat->g.ndom / 2 * sizeof(unsigned), c.st));
   MBBS_TRY(start(c, !c.p.x0_is_guess, true));
   j.n_outer += c.p.x0_is_guess ? 1 : 0;
   SolverState s{};

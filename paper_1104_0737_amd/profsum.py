@@ -1,0 +1,59 @@
+"""Summarise rocprofv3 SQLite output (kernel trace and PMC counters) as text.
+
+usage: python -m paper_1104_0737_amd.profsum DB [DB ...] [--match SUBSTR]
+Kernel-trace databases print calls and average/total duration per kernel;
+counter databases print the average counter value per dispatch per kernel.
+"""
+
+from __future__ import annotations
+
+import argparse
+import re
+import sqlite3
+from collections import defaultdict
+
+
+def short(name: str) -> str:
+    name = re.sub(r"\(.*$", "", name)
+    name = name.replace("mbbs::", "").replace("void ", "")
+    return name if len(name) < 90 else name[:87] + "..."
+
+
+def kernel_stats(db):
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, total_calls, total_duration, average from top_kernels").fetchall()
+    # top_kernels reports durations in microseconds
+    return [(short(n), k, tot / 1e3, avg) for n, k, tot, avg in rows]
+
+
+def counters(db):
+    c = sqlite3.connect(db)
+    acc = defaultdict(list)
+    for name, cname, val in c.execute("select kernel_name, counter_name, value from counters_collection"):
+        acc[(short(name), cname)].append(val)
+    return [(k[0], k[1], len(v), sum(v) / len(v)) for k, v in acc.items()]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("db", nargs="+")
+    ap.add_argument("--match", default="")
+    a = ap.parse_args()
+    for db in a.db:
+        c = sqlite3.connect(db)
+        has_pmc = c.execute("select count(*) from counters_collection").fetchone()[0] > 0
+        print(f"# {db}")
+        if has_pmc:
+            print(f"{'kernel':90s} {'counter':12s} {'n':>4s} {'avg/dispatch':>16s}")
+            for k, cn, n, v in counters(db):
+                if a.match in k:
+                    print(f"{k:90s} {cn:12s} {n:4d} {v:16.1f}")
+        else:
+            print(f"{'kernel':90s} {'calls':>6s} {'total ms':>10s} {'avg us':>10s}")
+            for k, n, tot, avg in kernel_stats(db):
+                if a.match in k:
+                    print(f"{k:90s} {n:6d} {tot:10.3f} {avg:10.1f}")
+
+
+if __name__ == "__main__":
+    main()

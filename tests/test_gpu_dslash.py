@@ -127,3 +127,24 @@ def test_dslash_full_size_sampled():
         got = gu.host(Yd.index_select(0, idx))
         err = gu.rel_col_err(got, ref.reshape(-1, L))
         assert np.all(err <= 1e-6), err
+
+
+def test_tuning_is_bit_identical():
+    """Launch shapes chosen by the autotuner never change results."""
+    from paper_1104_0737_amd import autotune
+    dims, L = (8, 8, 8, 8), 12
+    V = 4096
+    U = inputs.gauge_field(dims, 0.3, 18)
+    X = gu.dev(inputs.gaussian_block(V, L, 19))
+    with gu.Lattice(dims, (4, 4, 4, 4), U, 0.11) as lat:
+        for prec in (0, 1, 2):
+            ref = None
+            for g, t in autotune.candidates(L, prec):
+                B.mbbs_lattice_tune(lat.h, B.TUNE_GROUP[prec], g)
+                B.mbbs_lattice_tune(lat.h, B.TUNE_BLOCK_THREADS, t)
+                Y = torch.empty_like(X)
+                B.mbbs_apply_dirac(lat.h, L, X, Y, prec)
+                out = gu.host(Y)
+                if ref is None:
+                    ref = out
+                assert out.tobytes() == ref.tobytes(), (prec, g, t)
