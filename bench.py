@@ -134,10 +134,11 @@ def main():
         from paper_1104_0737_amd import autotune
         for prec, name in ((B.FP64, "fp64"), (B.FP32, "fp32"), (B.FP16S, "fp16s")):
             best, times = autotune.tune_operator(lat, V, L, prec, stream=stream)
-            tuning[name] = {"group_cols": best[0], "block_threads": best[1], "ms": round(times[best], 4),
-                            "worst_ms": round(max(times.values()), 4)}
-            log(f"tuned {name}: group {best[0]} threads {best[1]} ({times[best]:.3f} ms; worst "
-                f"{max(times.values()):.3f} ms)")
+            tuning[name] = {"group_cols": best[0], "block_threads": best[1], "split": best[2],
+                            "ms": round(times[best], 4), "worst_ms": round(max(times.values()), 4),
+                            "classic_best_ms": round(min(v for k, v in times.items() if k[2] == 0), 4)}
+            log(f"tuned {name}: group {best[0]} threads {best[1]} split {best[2]} ({times[best]:.3f} ms; "
+                f"best classic {tuning[name]['classic_best_ms']:.3f} ms; worst {max(times.values()):.3f} ms)")
         torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ operator alone

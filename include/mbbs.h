@@ -99,20 +99,25 @@ int mbbs_lattice_table_size(mbbs_lattice_t lat, int which, size_t* count);
 int mbbs_lattice_table(mbbs_lattice_t lat, int which, int32_t* out, size_t count);
 
 /* Launch tuning of the stencil kernels (what an autotuner varies).  The
- * operator's output is bit-identical under every setting; the SAP domain
- * sums are accumulated per block, so changing the threads per block changes
- * their rounding order (results stay deterministic for a fixed setting).
+ * operator's output is bit-identical under the group, thread and LDS knobs;
+ * the split knob changes the order in which the eight hops are summed, and
+ * the SAP domain sums follow the block shape, so those change rounding only
+ * (results stay deterministic for a fixed setting).
  * Knobs:
  *  MBBS_TUNE_GROUP_FP64/FP32/FP16S  columns processed per column group by one
  *      pass of blocks over a tile (0 = all L columns; must divide L and be a
  *      multiple of the kernel's columns per thread, else all columns are used)
  *  MBBS_TUNE_BLOCK_THREADS          target threads per block (32..256)
+ *  MBBS_TUNE_SPLIT_FP64/FP32/FP16S  hop groups per site (0 or 1: one thread applies
+ *      all 8 hops; 2 or 4: the hops are split over wave-uniform groups that
+ *      combine through LDS; falls back to 1 where no launch shape fits)
  *  MBBS_TUNE_LDS_PAD_KB             extra LDS (KiB, 0..64) reserved per stencil
  *      block, which caps the blocks resident on a CU (fewer sites in flight
  *      per XCD, so more of their neighbour data stays in its L2)
  * Errors: EINVAL for an unknown knob or out-of-range value. */
 enum { MBBS_TUNE_GROUP_FP64 = 0, MBBS_TUNE_GROUP_FP32 = 1, MBBS_TUNE_GROUP_FP16S = 2,
-       MBBS_TUNE_BLOCK_THREADS = 3, MBBS_TUNE_LDS_PAD_KB = 4 };
+       MBBS_TUNE_BLOCK_THREADS = 3, MBBS_TUNE_LDS_PAD_KB = 4, MBBS_TUNE_SPLIT_FP64 = 5,
+       MBBS_TUNE_SPLIT_FP32 = 6, MBBS_TUNE_SPLIT_FP16S = 7 };
 int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value);
 
 /* ---------------------------------------------------------------- operator */

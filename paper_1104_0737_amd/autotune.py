@@ -18,14 +18,17 @@ def _cmax(prec):
 
 
 def candidates(L, prec):
+    """(group columns, threads per block, split) settings: the classic kernel
+    over column groups and block sizes, then the split-wave kernels."""
     c = next(c for c in range(_cmax(prec), 0, -1) if L % c == 0)
     groups = [g for g in range(c, L + 1, c) if L % g == 0]
     threads = (64, 128, 192, 256)
-    return list(itertools.product(groups, threads))
+    classic = [(g, t, 0) for g, t in itertools.product(groups, threads)]
+    return classic + [(L, 256, 2), (L, 256, 4)]
 
 
 def tune_operator(lat, V, L, prec, stream=None, reps=3):
-    """Return (best (group, threads), {setting: ms}) and apply the best."""
+    """Return (best (group, threads, split), {setting: ms}) and apply the best."""
     import torch
     dev = torch.device("cuda")
     N = 12 * V
@@ -40,9 +43,10 @@ def tune_operator(lat, V, L, prec, stream=None, reps=3):
     Y = torch.empty_like(X)
     s = stream or torch.cuda.current_stream()
     times = {}
-    for g, t in candidates(L, prec):
+    for g, t, sp in candidates(L, prec):
         B.mbbs_lattice_tune(lat, B.TUNE_GROUP[prec], g)
         B.mbbs_lattice_tune(lat, B.TUNE_BLOCK_THREADS, t)
+        B.mbbs_lattice_tune(lat, B.TUNE_SPLIT[prec], sp)
         B.mbbs_apply_dirac_raw(lat, L, prec, X, Xs, Y, Ys, stream=s)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s)
@@ -50,9 +54,10 @@ def tune_operator(lat, V, L, prec, stream=None, reps=3):
             B.mbbs_apply_dirac_raw(lat, L, prec, X, Xs, Y, Ys, stream=s)
         e1.record(s)
         e1.synchronize()
-        times[(g, t)] = e0.elapsed_time(e1) / reps
+        times[(g, t, sp)] = e0.elapsed_time(e1) / reps
     best = min(times, key=times.get)
     B.mbbs_lattice_tune(lat, B.TUNE_GROUP[prec], best[0])
     B.mbbs_lattice_tune(lat, B.TUNE_BLOCK_THREADS, best[1])
+    B.mbbs_lattice_tune(lat, B.TUNE_SPLIT[prec], best[2])
     del X, Y, Xs, Ys
     return best, times

@@ -32,7 +32,105 @@ __device__ __forceinline__ Mat3<R> load_link(const LinkElem<PL>* U, int site, in
 // neighbouring domains).
 enum Hops { ALL = 0, INSIDE = 1, OUTSIDE = 2 };
 
-// acc[spin][colour][k] += (1 -/+ gamma_mu) W psi_nb for the C columns.
+// One hop (MU, FWD) of the hopping term for the C columns of a thread:
+// acc[spin][colour][k] += (1 -/+ gamma_mu) W psi_nb (W = U or U^dagger).
+// `token` chains consecutive hops: each hop's addresses depend on the
+// previous hop's accumulator (an empty asm), so its loads are not hoisted
+// above it; one hop's data in flight per thread keeps register pressure low.
+template <int PIN, int PL, int C, int ORDER, int HOPS, int MU, int FWD, typename R>
+__device__ __forceinline__ void hop_one(const GeomK& k, const SiteCtx& c,
+                                        const typename Store<PIN>::Elem* __restrict__ in,
+                                        const float* __restrict__ in_s,
+                                        const LinkElem<PL>* __restrict__ U, int L, int col0,
+                                        cplx<R> (&acc)[4][3][C], R& token) {
+  constexpr int dir = FWD ? 1 : -1;
+  if constexpr (HOPS != ALL) {
+    int r = (ORDER == DM) ? c.l[MU] : (c.x[MU] % k.g.b[MU]);
+    bool leaves = FWD ? (r == k.g.b[MU] - 1) : (r == 0);
+    if (HOPS == INSIDE && leaves) return;
+    if (HOPS == OUTSIDE && !leaves) return;
+  }
+  int sn = neighbour<ORDER>(k, c, MU, dir);
+  int ls = FWD ? c.s : sn;
+  asm volatile("" : "+v"(sn), "+v"(ls) : "v"(token));
+  const bool wrap = FWD ? (c.x[MU] == k.g.d[MU] - 1) : (c.x[MU] == 0);
+  cplx<R> ph = cmake<R>((R)1, (R)0);
+  if (HOPS != INSIDE && wrap) ph = cmake<R>((R)k.g.ph[MU][0], (R)(FWD ? k.g.ph[MU][1] : -k.g.ph[MU][1]));
+  const Mat3<R> u = load_link<PL, R>(U, ls, MU);
+  constexpr SpinRule sr = spin_rule(MU, FWD);
+#pragma unroll
+  for (int q = 0; q < C; ++q) {
+    const size_t base = (size_t)sn * 12 * L + col0 + q;
+    cplx<R> p[4][3];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        auto v = Store<PIN>::ld(in, base + (size_t)(3 * sp + a) * L);
+        p[sp][a] = cmake<R>((R)v.re, (R)v.im);
+      }
+    if constexpr (Store<PIN>::scaled) {
+      R sc = (R)in_s[(size_t)sn * L + col0 + q];
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) p[sp][a] = sc * p[sp][a];
+    }
+    cplx<R> h0[3], h1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      h0[a] = p[0][a] + unit_mul<sr.A0>(p[sr.P0][a]);
+      h1[a] = p[1][a] + unit_mul<sr.A1>(p[sr.P1][a]);
+    }
+    if (HOPS != INSIDE && wrap) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) { h0[a] = ph * h0[a]; h1[a] = ph * h1[a]; }
+    }
+    cplx<R> x0[3], x1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cplx<R> s0 = cmake<R>(0, 0), s1 = cmake<R>(0, 0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if constexpr (FWD) {  // U h
+          s0 = s0 + u.m[a][b] * h0[b];
+          s1 = s1 + u.m[a][b] * h1[b];
+        } else {              // U^dagger h
+          s0 = s0 + cdot(u.m[b][a], h0[b]);
+          s1 = s1 + cdot(u.m[b][a], h1[b]);
+        }
+      }
+      x0[a] = s0; x1[a] = s1;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      acc[0][a][q] = acc[0][a][q] + x0[a];
+      acc[1][a][q] = acc[1][a][q] + x1[a];
+      acc[2][a][q] = acc[2][a][q] + unit_mul<sr.B0>(sr.Q0 ? x1[a] : x0[a]);
+      acc[3][a][q] = acc[3][a][q] + unit_mul<sr.B1>(sr.Q1 ? x1[a] : x0[a]);
+    }
+  }
+  // materialise the accumulators at the hop boundary (otherwise the additions
+  // are deferred and every hop's partial result stays live)
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int q = 0; q < C; ++q) asm volatile("" : "+v"(acc[sp][a][q].re), "+v"(acc[sp][a][q].im));
+  token = acc[0][0][0].re;
+}
+
+// Both hops of direction MU.
+template <int PIN, int PL, int C, int ORDER, int HOPS, int MU, typename R>
+__device__ __forceinline__ void hop_dir(const GeomK& k, const SiteCtx& c, const typename Store<PIN>::Elem* in,
+                                        const float* in_s, const LinkElem<PL>* U, int L, int col0,
+                                        cplx<R> (&acc)[4][3][C], R& token) {
+  hop_one<PIN, PL, C, ORDER, HOPS, MU, 1, R>(k, c, in, in_s, U, L, col0, acc, token);
+  hop_one<PIN, PL, C, ORDER, HOPS, MU, 0, R>(k, c, in, in_s, U, L, col0, acc, token);
+}
+
+// All eight hops.
 template <int PIN, int PL, int C, int ORDER, int HOPS, typename R>
 __device__ __forceinline__ void hop_sum(const GeomK& k, const SiteCtx& c,
                                         const typename Store<PIN>::Elem* __restrict__ in,
@@ -40,90 +138,36 @@ __device__ __forceinline__ void hop_sum(const GeomK& k, const SiteCtx& c,
                                         const LinkElem<PL>* __restrict__ U, int L, int col0,
                                         cplx<R> (&acc)[4][3][C]) {
   R token = 0;
-#pragma unroll
-  for (int mu = 0; mu < 4; ++mu) {
-#pragma unroll
-    for (int fwd = 1; fwd >= 0; --fwd) {
-      const int dir = fwd ? 1 : -1;
-      if constexpr (HOPS != ALL) {
-        int r = (ORDER == DM) ? c.l[mu] : (c.x[mu] % k.g.b[mu]);
-        bool leaves = fwd ? (r == k.g.b[mu] - 1) : (r == 0);
-        if (HOPS == INSIDE && leaves) continue;
-        if (HOPS == OUTSIDE && !leaves) continue;
-      }
-      int sn = neighbour<ORDER>(k, c, mu, dir);
-      // Tie this hop's addresses to the previous hop's result so that its
-      // loads are not hoisted above it: one hop's data in flight per thread
-      // keeps register pressure low (other waves supply memory parallelism).
-      int ls = fwd ? c.s : sn;
-      asm volatile("" : "+v"(sn), "+v"(ls) : "v"(token));
-      bool wrap = fwd ? (c.x[mu] == k.g.d[mu] - 1) : (c.x[mu] == 0);
-      cplx<R> ph = cmake<R>((R)1, (R)0);
-      if (HOPS != INSIDE && wrap) ph = cmake<R>((R)k.g.ph[mu][0], (R)(fwd ? k.g.ph[mu][1] : -k.g.ph[mu][1]));
-      const Mat3<R> u = load_link<PL, R>(U, ls, mu);
-      const SpinRule sr = spin_rule(mu, fwd);
-#pragma unroll
-      for (int q = 0; q < C; ++q) {
-        const size_t base = (size_t)sn * 12 * L + col0 + q;
-        cplx<R> p[4][3];
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            auto v = Store<PIN>::ld(in, base + (size_t)(3 * sp + a) * L);
-            p[sp][a] = cmake<R>((R)v.re, (R)v.im);
-          }
-        if constexpr (Store<PIN>::scaled) {
-          R sc = (R)in_s[(size_t)sn * L + col0 + q];
-#pragma unroll
-          for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) p[sp][a] = sc * p[sp][a];
-        }
-        cplx<R> h0[3], h1[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          h0[a] = p[0][a] + umul(sr.A0, p[sr.P0][a]);
-          h1[a] = p[1][a] + umul(sr.A1, p[sr.P1][a]);
-        }
-        if (HOPS != INSIDE && wrap) {
-#pragma unroll
-          for (int a = 0; a < 3; ++a) { h0[a] = ph * h0[a]; h1[a] = ph * h1[a]; }
-        }
-        cplx<R> x0[3], x1[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          cplx<R> s0 = cmake<R>(0, 0), s1 = cmake<R>(0, 0);
-#pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            if (fwd) {  // U h
-              s0 = s0 + u.m[a][b] * h0[b];
-              s1 = s1 + u.m[a][b] * h1[b];
-            } else {    // U^dagger h
-              s0 = s0 + cdot(u.m[b][a], h0[b]);
-              s1 = s1 + cdot(u.m[b][a], h1[b]);
-            }
-          }
-          x0[a] = s0; x1[a] = s1;
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          acc[0][a][q] = acc[0][a][q] + x0[a];
-          acc[1][a][q] = acc[1][a][q] + x1[a];
-          acc[2][a][q] = acc[2][a][q] + umul(sr.B0, sr.Q0 ? x1[a] : x0[a]);
-          acc[3][a][q] = acc[3][a][q] + umul(sr.B1, sr.Q1 ? x1[a] : x0[a]);
-        }
-      }
-      // materialise the accumulators at every hop boundary (otherwise the
-      // additions are deferred and every hop's partial result stays live)
-#pragma unroll
-      for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int q = 0; q < C; ++q) asm volatile("" : "+v"(acc[sp][a][q].re), "+v"(acc[sp][a][q].im));
-      token = acc[0][0][0].re;
+  hop_dir<PIN, PL, C, ORDER, HOPS, 0, R>(k, c, in, in_s, U, L, col0, acc, token);
+  hop_dir<PIN, PL, C, ORDER, HOPS, 1, R>(k, c, in, in_s, U, L, col0, acc, token);
+  hop_dir<PIN, PL, C, ORDER, HOPS, 2, R>(k, c, in, in_s, U, L, col0, acc, token);
+  hop_dir<PIN, PL, C, ORDER, HOPS, 3, R>(k, c, in, in_s, U, L, col0, acc, token);
+}
+
+// The hops of group h when the eight hops are split over P wave-uniform
+// groups (P = 4: direction h; P = 2: directions 2h and 2h+1).
+template <int PIN, int PL, int ORDER, int HOPS, int P, typename R>
+__device__ __forceinline__ void hop_group(int h, const GeomK& k, const SiteCtx& c,
+                                          const typename Store<PIN>::Elem* in, const float* in_s,
+                                          const LinkElem<PL>* U, int L, int col, cplx<R> (&acc)[4][3][1]) {
+  R token = 0;
+  if constexpr (P == 4) {
+    switch (h) {
+      case 0: hop_dir<PIN, PL, 1, ORDER, HOPS, 0, R>(k, c, in, in_s, U, L, col, acc, token); break;
+      case 1: hop_dir<PIN, PL, 1, ORDER, HOPS, 1, R>(k, c, in, in_s, U, L, col, acc, token); break;
+      case 2: hop_dir<PIN, PL, 1, ORDER, HOPS, 2, R>(k, c, in, in_s, U, L, col, acc, token); break;
+      default: hop_dir<PIN, PL, 1, ORDER, HOPS, 3, R>(k, c, in, in_s, U, L, col, acc, token); break;
     }
+  } else if constexpr (P == 2) {
+    if (h == 0) {
+      hop_dir<PIN, PL, 1, ORDER, HOPS, 0, R>(k, c, in, in_s, U, L, col, acc, token);
+      hop_dir<PIN, PL, 1, ORDER, HOPS, 1, R>(k, c, in, in_s, U, L, col, acc, token);
+    } else {
+      hop_dir<PIN, PL, 1, ORDER, HOPS, 2, R>(k, c, in, in_s, U, L, col, acc, token);
+      hop_dir<PIN, PL, 1, ORDER, HOPS, 3, R>(k, c, in, in_s, U, L, col, acc, token);
+    }
+  } else {
+    hop_sum<PIN, PL, 1, ORDER, HOPS, R>(k, c, in, in_s, U, L, col, acc);
   }
 }
 
@@ -438,6 +482,262 @@ __global__ void __launch_bounds__(256) k_mr_update(GeomK k, int L, int s0, int n
   store_spinor<PR, R>(r, r_s, base, L, sidx, rv);
 }
 
+// ---------------------------------------------------------------- split-wave kernels
+// Block = (IPB items) x (P hop groups); item = (site, column), IPB = S * L is a
+// multiple of the wave size so every wave belongs to one hop group.  Group h
+// sums its hops (hop_group), the P partial sums meet in LDS, and group h then
+// finishes spins h*(4/P) .. h*(4/P)+4/P-1 of every item.  Compared with one
+// thread per site doing all eight hops, a site has P times more loads in
+// flight and P times fewer sites are resident per CU, so the neighbour data
+// of the resident sites fits the XCD's L2 better.
+template <typename R>
+struct SplitSmem {
+  cplx<R>* xs;    // [P][IPB][12] partial hop sums
+  R* mx;          // [P][IPB] partial maxima (FP16 storage scale)
+};
+template <typename R>
+__device__ __forceinline__ SplitSmem<R> split_smem(int P, int IPB) {
+  extern __shared__ unsigned char smem_raw[];
+  SplitSmem<R> m;
+  m.xs = (cplx<R>*)smem_raw;
+  m.mx = (R*)(smem_raw + (size_t)P * IPB * 12 * sizeof(cplx<R>));
+  return m;
+}
+
+// Final value of this group's spins: v = base + coef * (sum over groups).
+template <int P, typename R>
+__device__ __forceinline__ void split_total(const SplitSmem<R>& m, int h, int item, int IPB,
+                                            cplx<R> (&tot)[4 / P][3]) {
+  constexpr int NS = 4 / P;
+#pragma unroll
+  for (int t = 0; t < NS; ++t)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cplx<R> sum = cmake<R>(0, 0);
+#pragma unroll
+      for (int g = 0; g < P; ++g) sum = sum + m.xs[((size_t)g * IPB + item) * 12 + 3 * (h * NS + t) + a];
+      tot[t][a] = sum;
+    }
+}
+
+template <int P, typename R>
+__device__ __forceinline__ void split_publish(const SplitSmem<R>& m, int h, int item, int IPB,
+                                              const cplx<R> (&acc)[4][3][1]) {
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) m.xs[((size_t)h * IPB + item) * 12 + 3 * sp + a] = acc[sp][a][0];
+}
+
+// Store this group's spins of one (site, column); FP16 storage exchanges the
+// groups' maxima first so that all of them use the same scale.
+template <int POUT, int P, typename R>
+__device__ __forceinline__ void split_store(const SplitSmem<R>& m, int h, int item, int IPB, bool active,
+                                            typename Store<POUT>::Elem* out, float* out_s, size_t base, int L,
+                                            size_t sidx, cplx<R> (&v)[4 / P][3]) {
+  constexpr int NS = 4 / P;
+  if constexpr (Store<POUT>::scaled) {
+    R mloc = 0;
+#pragma unroll
+    for (int t = 0; t < NS; ++t)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) mloc = fmaxf(mloc, fmaxf(fabsf(v[t][a].re), fabsf(v[t][a].im)));
+    m.mx[(size_t)h * IPB + item] = mloc;
+    __syncthreads();
+    R mx = 0;
+#pragma unroll
+    for (int g = 0; g < P; ++g) mx = fmaxf(mx, m.mx[(size_t)g * IPB + item]);
+    if (!active) return;
+    if (h == 0) out_s[sidx] = mx;
+    const R inv = mx > 0 ? (R)1 / mx : (R)0;
+#pragma unroll
+    for (int t = 0; t < NS; ++t)
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        Store<POUT>::st(out, base + (size_t)(3 * (h * NS + t) + a) * L, inv * v[t][a]);
+  } else {
+    if (!active) return;
+    using RO = typename Store<POUT>::Real;
+#pragma unroll
+    for (int t = 0; t < NS; ++t)
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        Store<POUT>::st(out, base + (size_t)(3 * (h * NS + t) + a) * L, cplx<RO>{(RO)v[t][a].re, (RO)v[t][a].im});
+  }
+}
+
+// This group's spins of one stored (site, column) spinor.
+template <int PIN, int P, typename R>
+__device__ __forceinline__ void split_load(const typename Store<PIN>::Elem* in, const float* in_s, size_t base,
+                                           int L, size_t sidx, int h, cplx<R> (&v)[4 / P][3]) {
+  constexpr int NS = 4 / P;
+  R sc = 1;
+  if constexpr (Store<PIN>::scaled) sc = (R)in_s[sidx];
+#pragma unroll
+  for (int t = 0; t < NS; ++t)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      auto e = Store<PIN>::ld(in, base + (size_t)(3 * (h * NS + t) + a) * L);
+      v[t][a] = cmake<R>((R)e.re * sc, (R)e.im * sc);
+    }
+}
+
+template <int PIN, int POUT, int PL, int ORDER, bool BLOCKED, int P>
+__global__ void __launch_bounds__(768) k_dslash_split(GeomK k, double kappa, int L,
+                                                       const typename Store<PIN>::Elem* __restrict__ in,
+                                                       const float* __restrict__ in_s,
+                                                       typename Store<POUT>::Elem* __restrict__ out,
+                                                       float* __restrict__ out_s,
+                                                       const LinkElem<PL>* __restrict__ U, int s0, int n, int S,
+                                                       const int* __restrict__ frozen) {
+  if (frozen && *frozen) return;
+  using R = typename Store<PL>::Real;
+  const int IPB = blockDim.x, h = threadIdx.y, item = threadIdx.x;
+  const int lsite = item / L, col = item - lsite * L;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * S + lsite;
+  const bool active = i < n;
+  const SiteCtx c = ORDER == LEX ? site_ctx_tiled(k, active ? i : 0) : site_ctx<DM>(k, s0 + (active ? i : 0));
+  const SplitSmem<R> m = split_smem<R>(P, IPB);
+  cplx<R> acc[4][3][1];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc[sp][a][0] = cmake<R>(0, 0);
+  if (active) hop_group<PIN, PL, ORDER, BLOCKED ? INSIDE : ALL, P, R>(h, k, c, in, in_s, U, L, col, acc);
+  split_publish<P, R>(m, h, item, IPB, acc);
+  __syncthreads();
+  cplx<R> tot[4 / P][3], v[4 / P][3];
+  split_total<P, R>(m, h, item, IPB, tot);
+  const size_t base = (size_t)c.s * 12 * L + col, sidx = (size_t)c.s * L + col;
+  if (active) split_load<PIN, P, R>(in, in_s, base, L, sidx, h, v);
+  const R kap = (R)kappa;
+#pragma unroll
+  for (int t = 0; t < 4 / P; ++t)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[t][a] = v[t][a] - kap * tot[t][a];
+  split_store<POUT, P, R>(m, h, item, IPB, active, out, out_s, base, L, sidx, v);
+}
+
+// Split-wave SAP residual on one colour (modes as in k_sap_resid).
+template <int PR, int PPSI, int PL, int P>
+__global__ void __launch_bounds__(768) k_sap_resid_split(GeomK k, double kappa, int L, int s0, int n, int mode,
+                                                          const typename Store<PR>::Elem* __restrict__ eta,
+                                                          const float* __restrict__ eta_s,
+                                                          const typename Store<PPSI>::Elem* __restrict__ psi,
+                                                          typename Store<PR>::Elem* __restrict__ r,
+                                                          float* __restrict__ r_s,
+                                                          const LinkElem<PL>* __restrict__ U, int S,
+                                                          const int* __restrict__ frozen) {
+  if (frozen && *frozen) return;
+  using R = typename Store<PL>::Real;
+  const int IPB = blockDim.x, h = threadIdx.y, item = threadIdx.x;
+  const int lsite = item / L, col = item - lsite * L;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * S + lsite;
+  const bool active = i < n;
+  const int s = s0 + (active ? i : 0);
+  const SplitSmem<R> m = split_smem<R>(P, IPB);
+  cplx<R> acc[4][3][1];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc[sp][a][0] = cmake<R>(0, 0);
+  if (active && mode != 0) {
+    const SiteCtx c = site_ctx<DM>(k, s);
+    if (mode == 1) hop_group<PPSI, PL, DM, OUTSIDE, P, R>(h, k, c, psi, nullptr, U, L, col, acc);
+    else hop_group<PPSI, PL, DM, ALL, P, R>(h, k, c, psi, nullptr, U, L, col, acc);
+  }
+  split_publish<P, R>(m, h, item, IPB, acc);
+  __syncthreads();
+  cplx<R> tot[4 / P][3], e[4 / P][3], pv[4 / P][3];
+  split_total<P, R>(m, h, item, IPB, tot);
+  const size_t base = (size_t)s * 12 * L + col, sidx = (size_t)s * L + col;
+  if (active) {
+    split_load<PR, P, R>(eta, eta_s, base, L, sidx, h, e);
+    if (mode == 2) split_load<PPSI, P, R>(psi, nullptr, base, L, sidx, h, pv);
+  }
+  const R kap = (R)kappa;
+#pragma unroll
+  for (int t = 0; t < 4 / P; ++t)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (mode == 2) e[t][a] = e[t][a] - pv[t][a];
+      if (mode != 0) e[t][a] = e[t][a] + kap * tot[t][a];
+    }
+  split_store<PR, P, R>(m, h, item, IPB, active, r, r_s, base, L, sidx, e);
+}
+
+// Split-wave MR step, part 1: w = A_DD r on one colour plus per-block sums of
+// <w, r> and <w, w> per column.  S divides the block volume, so a block never
+// straddles two domains.
+template <int PR, int PL, int P>
+__global__ void __launch_bounds__(768) k_mr_dslash_split(GeomK k, double kappa, int L, int s0, int n,
+                                                          const typename Store<PR>::Elem* __restrict__ r,
+                                                          const float* __restrict__ r_s,
+                                                          typename Store<PR>::Elem* __restrict__ w,
+                                                          float* __restrict__ w_s,
+                                                          const LinkElem<PL>* __restrict__ U,
+                                                          double* __restrict__ partial, int S,
+                                                          const int* __restrict__ frozen) {
+  if (frozen && *frozen) return;
+  using R = typename Store<PL>::Real;
+  const int IPB = blockDim.x, h = threadIdx.y, item = threadIdx.x;
+  const int lsite = item / L, col = item - lsite * L;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int i = lb * S + lsite;
+  const int s = s0 + i;
+  const SplitSmem<R> m = split_smem<R>(P, IPB);
+  const SiteCtx c = site_ctx<DM>(k, s);
+  cplx<R> acc[4][3][1];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc[sp][a][0] = cmake<R>(0, 0);
+  hop_group<PR, PL, DM, INSIDE, P, R>(h, k, c, r, r_s, U, L, col, acc);
+  split_publish<P, R>(m, h, item, IPB, acc);
+  __syncthreads();
+  cplx<R> tot[4 / P][3], rv[4 / P][3], wv[4 / P][3];
+  split_total<P, R>(m, h, item, IPB, tot);
+  const size_t base = (size_t)s * 12 * L + col, sidx = (size_t)s * L + col;
+  split_load<PR, P, R>(r, r_s, base, L, sidx, h, rv);
+  const R kap = (R)kappa;
+#pragma unroll
+  for (int t = 0; t < 4 / P; ++t)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) wv[t][a] = rv[t][a] - kap * tot[t][a];
+  split_store<PR, P, R>(m, h, item, IPB, true, w, w_s, base, L, sidx, wv);
+  if constexpr (Store<PR>::scaled) {
+    __syncthreads();   // make the stored halves visible to this thread's reload
+    split_load<PR, P, R>(w, w_s, base, L, sidx, h, wv);
+  }
+  double a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+  for (int t = 0; t < 4 / P; ++t)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cplx<R> d = cdot(wv[t][a], rv[t][a]);
+      a0 += d.re; a1 += d.im; a2 += norm2(wv[t][a]);
+    }
+  // reduce over (group, site) per column in fixed order, reusing the exchange area
+  __syncthreads();
+  double* red = (double*)m.xs;   // [3][P][IPB]
+  red[(0 * P + h) * IPB + item] = a0;
+  red[(1 * P + h) * IPB + item] = a1;
+  red[(2 * P + h) * IPB + item] = a2;
+  __syncthreads();
+  if (h == 0 && lsite == 0) {
+    double s0v = 0, s1v = 0, s2v = 0;
+    for (int g = 0; g < P; ++g)
+      for (int y = 0; y < S; ++y) {
+        s0v += red[(0 * P + g) * IPB + y * L + col];
+        s1v += red[(1 * P + g) * IPB + y * L + col];
+        s2v += red[(2 * P + g) * IPB + y * L + col];
+      }
+    const int dom = i / k.g.Vb, nblk = k.g.Vb / S, bid = (i % k.g.Vb) / S;
+    double* pp = partial + (((size_t)dom * nblk + bid) * L + col) * 3;
+    pp[0] = s0v; pp[1] = s1v; pp[2] = s2v;
+  }
+}
+
 // ---------------------------------------------------------------- host side
 GeomK make_geomk(const Geom& g) {
   GeomK k;
@@ -486,6 +786,60 @@ static Plan make_plan(const mbbs_lattice_s* lat, int L, int prec, int nsites) {
   return p;
 }
 
+// Sites per block of a split-wave launch: S divides the block volume, S*L is
+// a multiple of the wave size and at most 256, P*S*L <= 768 threads, and the
+// exchange area fits the 160 KiB LDS.  0 if no such S exists.
+static int split_sites(const mbbs_lattice_s* lat, int L, int prec, int P) {
+  const size_t rb = prec == P64 ? 8 : 4;
+  int best = 0;
+  for (int S = 1; S * L <= 256; ++S) {
+    if (lat->g.Vb % S || (S * L) % 64 || P * S * L > 768) continue;
+    const size_t smem = (size_t)P * S * L * (24 * rb + rb);
+    if (smem > 160 * 1024) continue;
+    best = S;
+  }
+  return best;
+}
+static size_t split_smem_bytes(int prec, int P, int S, int L) {
+  const size_t rb = prec == P64 ? 8 : 4;
+  return (size_t)P * S * L * (24 * rb + rb);
+}
+// Allow dynamic LDS above the 64 KiB default for a kernel (once per kernel).
+static void allow_lds(const void* fn) {
+  static const void* seen[64];
+  static int nseen = 0;
+  for (int i = 0; i < nseen; ++i)
+    if (seen[i] == fn) return;
+  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (nseen < 64) seen[nseen++] = fn;
+}
+
+template <int PIN, int POUT, int PL, int P>
+static int dslash_split_launch(const mbbs_lattice_s* lat, int L, int order, bool blocked, const void* in,
+                               const float* in_s, void* out, float* out_s, int s0, int n, int S, const int* frozen,
+                               hipStream_t st) {
+  const void* U;
+  if (order == LEX) U = PL == P64 ? (const void*)lat->U64 : PL == P32 ? (const void*)lat->U32 : (const void*)lat->U16;
+  else U = PL == P64 ? (const void*)lat->U64dm : PL == P32 ? (const void*)lat->U32dm : (const void*)lat->U16dm;
+  using EI = typename Store<PIN>::Elem;
+  using EO = typename Store<POUT>::Elem;
+  using EL = LinkElem<PL>;
+  const size_t smem = split_smem_bytes(PL, P, S, L);
+  dim3 blk(S * L, P), grd(ceil_div(n, S));
+#define SL(ORD, BLK)                                                                                    \
+  do {                                                                                                  \
+    auto fn = k_dslash_split<PIN, POUT, PL, ORD, BLK, P>;                                               \
+    allow_lds((const void*)fn);                                                                         \
+    hipLaunchKernelGGL(fn, grd, blk, smem, st, lat->gk, lat->kappa, L, (const EI*)in, in_s, (EO*)out,   \
+                       out_s, (const EL*)U, s0, n, S, frozen);                                          \
+  } while (0)
+  if (order == LEX) { if (blocked) SL(LEX, true); else SL(LEX, false); }
+  else { if (blocked) SL(DM, true); else SL(DM, false); }
+#undef SL
+  MBBS_HIP(hipGetLastError());
+  return MBBS_OK;
+}
+
 template <int PIN, int POUT, int PL, int C>
 static int dslash_dispatch_order(const mbbs_lattice_s* lat, int L, int order, bool blocked,
                                  const void* in, const float* in_s, void* out, float* out_s,
@@ -517,6 +871,14 @@ template <int PIN, int POUT, int PL>
 static int dslash_dispatch_c(const mbbs_lattice_s* lat, int L, int order, bool blocked,
                              const void* in, const float* in_s, void* out, float* out_s, int s0,
                              int n, const int* frozen, hipStream_t st) {
+  const int P = lat->split[PL];
+  if (P == 2 || P == 4) {
+    const int S = split_sites(lat, L, PL, P);
+    if (S > 0) {
+      if (P == 4) return dslash_split_launch<PIN, POUT, PL, 4>(lat, L, order, blocked, in, in_s, out, out_s, s0, n, S, frozen, st);
+      return dslash_split_launch<PIN, POUT, PL, 2>(lat, L, order, blocked, in, in_s, out, out_s, s0, n, S, frozen, st);
+    }
+  }
   switch (pick_chunk(L, PL)) {
     case 4: return dslash_dispatch_order<PIN, POUT, PL, 4>(lat, L, order, blocked, in, in_s, out, out_s, s0, n, frozen, st);
     case 3: return dslash_dispatch_order<PIN, POUT, PL, 3>(lat, L, order, blocked, in, in_s, out, out_s, s0, n, frozen, st);
@@ -594,7 +956,24 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
   for (int cy = 0; cy < ncy; ++cy) {
     for (int col = 0; col < 2; ++col) {
       const int s0 = col * g.Vh, n = g.Vh;
+      const int P = lat->split[PL];
+      const int SS = (P == 2 || P == 4) ? split_sites(lat, L, PL, P) : 0;
       if (prof) prof->begin(MBBS_K_SAP_RES);
+      if (SS > 0) {
+        const size_t smem = split_smem_bytes(PL, P, SS, L);
+        const int mode = cy > 0 ? 2 : col;
+        if (P == 4) {
+          auto fn = k_sap_resid_split<PR, PPSI, PL, 4>;
+          allow_lds((const void*)fn);
+          hipLaunchKernelGGL(fn, dim3(ceil_div(n, SS)), dim3(SS * L, 4), smem, st, lat->gk, lat->kappa, L, s0, n,
+                             mode, (const ER*)b.eta, b.eta_s, (const EP*)b.psi, (ER*)b.r, b.r_s, U, SS, frozen);
+        } else {
+          auto fn = k_sap_resid_split<PR, PPSI, PL, 2>;
+          allow_lds((const void*)fn);
+          hipLaunchKernelGGL(fn, dim3(ceil_div(n, SS)), dim3(SS * L, 2), smem, st, lat->gk, lat->kappa, L, s0, n,
+                             mode, (const ER*)b.eta, b.eta_s, (const EP*)b.psi, (ER*)b.r, b.r_s, U, SS, frozen);
+        }
+      } else {
 #define RES(CC)                                                                                      \
   hipLaunchKernelGGL((k_sap_resid<PR, PPSI, PL, CC>), dim3(pl.nblocks), dim3(pl.nchunk, S),                  \
                      (size_t)lat->lds_pad_kb * 1024, st,                                                     \
@@ -602,10 +981,27 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
                      b.eta_s, (const EP*)b.psi, (ER*)b.r, b.r_s, U, pl.bpt, pl.ngroups, frozen)
       switch (C) { case 4: RES(4); break; case 3: RES(3); break; case 2: RES(2); break; default: RES(1); }
 #undef RES
+      }
       if (prof) prof->end();
       MBBS_HIP(hipGetLastError());
       for (int it = 0; it < nmr; ++it) {
         if (prof) prof->begin(MBBS_K_MR_DSLASH);
+        int nblk_dom = g.Vb / S;
+        if (SS > 0) {
+          nblk_dom = g.Vb / SS;
+          const size_t smem = split_smem_bytes(PL, P, SS, L);
+          if (P == 4) {
+            auto fn = k_mr_dslash_split<PR, PL, 4>;
+            allow_lds((const void*)fn);
+            hipLaunchKernelGGL(fn, dim3(n / SS), dim3(SS * L, 4), smem, st, lat->gk, lat->kappa, L, s0, n,
+                               (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial, SS, frozen);
+          } else {
+            auto fn = k_mr_dslash_split<PR, PL, 2>;
+            allow_lds((const void*)fn);
+            hipLaunchKernelGGL(fn, dim3(n / SS), dim3(SS * L, 2), smem, st, lat->gk, lat->kappa, L, s0, n,
+                               (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial, SS, frozen);
+          }
+        } else {
 #define MRD(CC)                                                                                       \
   hipLaunchKernelGGL((k_mr_dslash<PR, PL, CC>), dim3(pl.nblocks), dim3(pl.nchunk, S),                       \
                      red_bytes + (size_t)lat->lds_pad_kb * 1024, st, lat->gk,                                \
@@ -613,8 +1009,9 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
                      pl.ngroups, frozen)
         switch (C) { case 4: MRD(4); break; case 3: MRD(3); break; case 2: MRD(2); break; default: MRD(1); }
 #undef MRD
+        }
         MBBS_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_mr_omega, dim3(g.ndom / 2), dim3(256), 0, st, L, g.Vb / S, (const double*)b.partial,
+        hipLaunchKernelGGL(k_mr_omega, dim3(g.ndom / 2), dim3(256), 0, st, L, nblk_dom, (const double*)b.partial,
                            b.omega, frozen);
         if (prof) prof->end();
         MBBS_HIP(hipGetLastError());

@@ -96,6 +96,7 @@ struct mbbs_lattice_s {
   int group_cols[3] = {0, 0, 0};
   int block_threads = 256;
   int lds_pad_kb = 0;   // extra LDS per stencil block: caps resident blocks per CU
+  int split[3] = {0, 0, 0};  // hop groups per site (0/1: one thread does all 8 hops)
 };
 
 namespace mbbs {

@@ -225,6 +225,12 @@ extern "C" int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value) {
       MBBS_CHECK(value >= 32 && value <= 256, "threads per block must be in 32..256");
       lat->block_threads = value;
       return MBBS_OK;
+    case MBBS_TUNE_SPLIT_FP64:
+    case MBBS_TUNE_SPLIT_FP32:
+    case MBBS_TUNE_SPLIT_FP16S:
+      MBBS_CHECK(value == 0 || value == 1 || value == 2 || value == 4, "split must be 0, 1, 2 or 4");
+      lat->split[knob - MBBS_TUNE_SPLIT_FP64] = value;
+      return MBBS_OK;
     case MBBS_TUNE_LDS_PAD_KB:
       MBBS_CHECK(value >= 0 && value <= 64, "LDS pad must be in 0..64 KiB");
       lat->lds_pad_kb = value;

@@ -116,3 +116,22 @@ def test_lu_zero_pivot():
         B.mbbs_lu_solve(3, 1, gu.dev(G), gu.dev(np.ones((3, 1), complex)),
                         torch.empty((3, 1), dtype=torch.complex128, device="cuda"))
     assert e.value.code == B.EBREAKDOWN
+
+
+@pytest.mark.parametrize("split", [2, 4])
+@pytest.mark.parametrize("L", [4, 12])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 3e-5), (2, 1e-2)])
+def test_sap_split_wave_parity(split, L, prec, tol):
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    V = 4096
+    U = inputs.gauge_field(dims, 0.3, 24)
+    eta = inputs.gaussian_block(V, L, 25)
+    dom = sap.Domains(dims, block)
+    ref = sap.sap(U, 0.12, gu.PH_AP, dom, eta, 3, 4).reshape(12 * V, L)
+    with gu.Lattice(dims, block, U, 0.12) as lat:
+        B.mbbs_lattice_tune(lat.h, B.TUNE_SPLIT[prec], split)
+        ws = torch.empty(B.mbbs_sap_workspace_size(lat.h, L, prec), dtype=torch.uint8, device="cuda")
+        Yd = torch.empty((12 * V, L), dtype=torch.complex128, device="cuda")
+        B.mbbs_sap_apply(lat.h, L, gu.dev(eta), Yd, 3, 4, prec, ws)
+        err = gu.rel_col_err(gu.host(Yd), ref)
+    assert np.all(err <= tol), err
