@@ -111,13 +111,15 @@ int mbbs_lattice_table(mbbs_lattice_t lat, int which, int32_t* out, size_t count
  *  MBBS_TUNE_SPLIT_FP64/FP32/FP16S  hop groups per site (0 or 1: one thread applies
  *      all 8 hops; 2 or 4: the hops are split over wave-uniform groups that
  *      combine through LDS; falls back to 1 where no launch shape fits)
+ *  MBBS_TUNE_PERSIST_BLOCKS         0: one split-wave block per logical block;
+ *      1..16: that many resident blocks per CU loop over their XCD's range
  *  MBBS_TUNE_LDS_PAD_KB             extra LDS (KiB, 0..64) reserved per stencil
  *      block, which caps the blocks resident on a CU (fewer sites in flight
  *      per XCD, so more of their neighbour data stays in its L2)
  * Errors: EINVAL for an unknown knob or out-of-range value. */
 enum { MBBS_TUNE_GROUP_FP64 = 0, MBBS_TUNE_GROUP_FP32 = 1, MBBS_TUNE_GROUP_FP16S = 2,
        MBBS_TUNE_BLOCK_THREADS = 3, MBBS_TUNE_LDS_PAD_KB = 4, MBBS_TUNE_SPLIT_FP64 = 5,
-       MBBS_TUNE_SPLIT_FP32 = 6, MBBS_TUNE_SPLIT_FP16S = 7 };
+       MBBS_TUNE_SPLIT_FP32 = 6, MBBS_TUNE_SPLIT_FP16S = 7, MBBS_TUNE_PERSIST_BLOCKS = 8 };
 int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value);
 
 /* ---------------------------------------------------------------- operator */

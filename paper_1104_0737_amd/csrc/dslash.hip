@@ -594,10 +594,12 @@ __global__ void __launch_bounds__(768) k_dslash_split(GeomK k, double kappa, int
   using R = typename Store<PL>::Real;
   const int IPB = blockDim.x, h = threadIdx.y, item = threadIdx.x;
   const int lsite = item / L, col = item - lsite * L;
-  const int i = xcd_block(blockIdx.x, gridDim.x) * S + lsite;
+  const SplitSmem<R> m = split_smem<R>(P, IPB);
+  const PersistRange pr = persist_range((n + S - 1) / S);
+  for (int lb = pr.first; lb < pr.end; lb += pr.step) {
+  const int i = lb * S + lsite;
   const bool active = i < n;
   const SiteCtx c = ORDER == LEX ? site_ctx_tiled(k, active ? i : 0) : site_ctx<DM>(k, s0 + (active ? i : 0));
-  const SplitSmem<R> m = split_smem<R>(P, IPB);
   cplx<R> acc[4][3][1];
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
@@ -616,6 +618,8 @@ __global__ void __launch_bounds__(768) k_dslash_split(GeomK k, double kappa, int
 #pragma unroll
     for (int a = 0; a < 3; ++a) v[t][a] = v[t][a] - kap * tot[t][a];
   split_store<POUT, P, R>(m, h, item, IPB, active, out, out_s, base, L, sidx, v);
+  __syncthreads();   // the exchange area is reused by the next logical block
+  }
 }
 
 // Split-wave SAP residual on one colour (modes as in k_sap_resid).
@@ -632,10 +636,12 @@ __global__ void __launch_bounds__(768) k_sap_resid_split(GeomK k, double kappa, 
   using R = typename Store<PL>::Real;
   const int IPB = blockDim.x, h = threadIdx.y, item = threadIdx.x;
   const int lsite = item / L, col = item - lsite * L;
-  const int i = xcd_block(blockIdx.x, gridDim.x) * S + lsite;
+  const SplitSmem<R> m = split_smem<R>(P, IPB);
+  const PersistRange pr = persist_range((n + S - 1) / S);
+  for (int lb = pr.first; lb < pr.end; lb += pr.step) {
+  const int i = lb * S + lsite;
   const bool active = i < n;
   const int s = s0 + (active ? i : 0);
-  const SplitSmem<R> m = split_smem<R>(P, IPB);
   cplx<R> acc[4][3][1];
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
@@ -664,6 +670,8 @@ __global__ void __launch_bounds__(768) k_sap_resid_split(GeomK k, double kappa, 
       if (mode != 0) e[t][a] = e[t][a] + kap * tot[t][a];
     }
   split_store<PR, P, R>(m, h, item, IPB, active, r, r_s, base, L, sidx, e);
+  __syncthreads();
+  }
 }
 
 // Split-wave MR step, part 1: w = A_DD r on one colour plus per-block sums of
@@ -682,10 +690,11 @@ __global__ void __launch_bounds__(768) k_mr_dslash_split(GeomK k, double kappa, 
   using R = typename Store<PL>::Real;
   const int IPB = blockDim.x, h = threadIdx.y, item = threadIdx.x;
   const int lsite = item / L, col = item - lsite * L;
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const SplitSmem<R> m = split_smem<R>(P, IPB);
+  const PersistRange pr = persist_range(n / S);
+  for (int lb = pr.first; lb < pr.end; lb += pr.step) {
   const int i = lb * S + lsite;
   const int s = s0 + i;
-  const SplitSmem<R> m = split_smem<R>(P, IPB);
   const SiteCtx c = site_ctx<DM>(k, s);
   cplx<R> acc[4][3][1];
 #pragma unroll
@@ -735,6 +744,8 @@ __global__ void __launch_bounds__(768) k_mr_dslash_split(GeomK k, double kappa, 
     const int dom = i / k.g.Vb, nblk = k.g.Vb / S, bid = (i % k.g.Vb) / S;
     double* pp = partial + (((size_t)dom * nblk + bid) * L + col) * 3;
     pp[0] = s0v; pp[1] = s1v; pp[2] = s2v;
+  }
+  __syncthreads();
   }
 }
 
@@ -804,6 +815,16 @@ static size_t split_smem_bytes(int prec, int P, int S, int L) {
   const size_t rb = prec == P64 ? 8 : 4;
   return (size_t)P * S * L * (24 * rb + rb);
 }
+// Grid of a split-wave launch: one block per logical block (rounded up to a
+// multiple of 8 for the XCD mapping), or, with the persistent-blocks knob, a
+// fixed number of resident blocks per CU that loop over their XCD's range.
+static int split_grid(const mbbs_lattice_s* lat, int prec, int P, int S, int L, int nlb) {
+  (void)prec; (void)P; (void)S; (void)L;
+  int g = ((nlb + 7) / 8) * 8;
+  if (lat->persist_blocks > 0 && 256 * lat->persist_blocks < g) g = 256 * lat->persist_blocks;
+  return g < 8 ? 8 : g;
+}
+
 // Allow dynamic LDS above the 64 KiB default for a kernel (once per kernel).
 static void allow_lds(const void* fn) {
   static const void* seen[64];
@@ -825,7 +846,7 @@ static int dslash_split_launch(const mbbs_lattice_s* lat, int L, int order, bool
   using EO = typename Store<POUT>::Elem;
   using EL = LinkElem<PL>;
   const size_t smem = split_smem_bytes(PL, P, S, L);
-  dim3 blk(S * L, P), grd(ceil_div(n, S));
+  dim3 blk(S * L, P), grd(split_grid(lat, PL, P, S, L, ceil_div(n, S)));
 #define SL(ORD, BLK)                                                                                    \
   do {                                                                                                  \
     auto fn = k_dslash_split<PIN, POUT, PL, ORD, BLK, P>;                                               \
@@ -965,13 +986,13 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
         if (P == 4) {
           auto fn = k_sap_resid_split<PR, PPSI, PL, 4>;
           allow_lds((const void*)fn);
-          hipLaunchKernelGGL(fn, dim3(ceil_div(n, SS)), dim3(SS * L, 4), smem, st, lat->gk, lat->kappa, L, s0, n,
-                             mode, (const ER*)b.eta, b.eta_s, (const EP*)b.psi, (ER*)b.r, b.r_s, U, SS, frozen);
+          hipLaunchKernelGGL(fn, dim3(split_grid(lat, PL, 4, SS, L, ceil_div(n, SS))), dim3(SS * L, 4), smem, st,
+                             lat->gk, lat->kappa, L, s0, n, mode, (const ER*)b.eta, b.eta_s, (const EP*)b.psi, (ER*)b.r, b.r_s, U, SS, frozen);
         } else {
           auto fn = k_sap_resid_split<PR, PPSI, PL, 2>;
           allow_lds((const void*)fn);
-          hipLaunchKernelGGL(fn, dim3(ceil_div(n, SS)), dim3(SS * L, 2), smem, st, lat->gk, lat->kappa, L, s0, n,
-                             mode, (const ER*)b.eta, b.eta_s, (const EP*)b.psi, (ER*)b.r, b.r_s, U, SS, frozen);
+          hipLaunchKernelGGL(fn, dim3(split_grid(lat, PL, 2, SS, L, ceil_div(n, SS))), dim3(SS * L, 2), smem, st,
+                             lat->gk, lat->kappa, L, s0, n, mode, (const ER*)b.eta, b.eta_s, (const EP*)b.psi, (ER*)b.r, b.r_s, U, SS, frozen);
         }
       } else {
 #define RES(CC)                                                                                      \
@@ -993,12 +1014,14 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
           if (P == 4) {
             auto fn = k_mr_dslash_split<PR, PL, 4>;
             allow_lds((const void*)fn);
-            hipLaunchKernelGGL(fn, dim3(n / SS), dim3(SS * L, 4), smem, st, lat->gk, lat->kappa, L, s0, n,
+            hipLaunchKernelGGL(fn, dim3(split_grid(lat, PL, 4, SS, L, n / SS)), dim3(SS * L, 4), smem, st, lat->gk,
+                               lat->kappa, L, s0, n,
                                (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial, SS, frozen);
           } else {
             auto fn = k_mr_dslash_split<PR, PL, 2>;
             allow_lds((const void*)fn);
-            hipLaunchKernelGGL(fn, dim3(n / SS), dim3(SS * L, 2), smem, st, lat->gk, lat->kappa, L, s0, n,
+            hipLaunchKernelGGL(fn, dim3(split_grid(lat, PL, 2, SS, L, n / SS)), dim3(SS * L, 2), smem, st, lat->gk,
+                               lat->kappa, L, s0, n,
                                (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial, SS, frozen);
           }
         } else {

@@ -97,6 +97,7 @@ struct mbbs_lattice_s {
   int block_threads = 256;
   int lds_pad_kb = 0;   // extra LDS per stencil block: caps resident blocks per CU
   int split[3] = {0, 0, 0};  // hop groups per site (0/1: one thread does all 8 hops)
+  int persist_blocks = 0;    // resident blocks per CU of persistent split kernels (0: not persistent)
 };
 
 namespace mbbs {
@@ -163,6 +164,22 @@ inline int pick_chunk(int L, int prec) {
   for (int c = cmax; c > 1; --c)
     if (L % c == 0) return c;
   return 1;
+}
+
+// Persistent launches: gridDim.x blocks (a multiple of 8) walk `nlb` logical
+// blocks.  Block b runs on XCD x = b mod 8 and takes the logical blocks of
+// that XCD's contiguous range [x*nlb/8, (x+1)*nlb/8) with stride gridDim.x/8,
+// so the blocks resident on one XCD always work on neighbouring sites.
+struct PersistRange {
+  int first, end, step;
+};
+__device__ __forceinline__ PersistRange persist_range(int nlb) {
+  const int x = blockIdx.x & 7, j = blockIdx.x >> 3, per = gridDim.x >> 3;
+  PersistRange r;
+  r.first = (int)(((long long)x * nlb) / 8) + j;
+  r.end = (int)(((long long)(x + 1) * nlb) / 8);
+  r.step = per;
+  return r;
 }
 
 // Decomposition of a stencil launch into (tile, column group, site block):

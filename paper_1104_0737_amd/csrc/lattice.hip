@@ -231,6 +231,10 @@ extern "C" int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value) {
       MBBS_CHECK(value == 0 || value == 1 || value == 2 || value == 4, "split must be 0, 1, 2 or 4");
       lat->split[knob - MBBS_TUNE_SPLIT_FP64] = value;
       return MBBS_OK;
+    case MBBS_TUNE_PERSIST_BLOCKS:
+      MBBS_CHECK(value >= 0 && value <= 16, "persistent blocks per CU must be in 0..16");
+      lat->persist_blocks = value;
+      return MBBS_OK;
     case MBBS_TUNE_LDS_PAD_KB:
       MBBS_CHECK(value >= 0 && value <= 64, "LDS pad must be in 0..64 KiB");
       lat->lds_pad_kb = value;
