@@ -113,13 +113,19 @@ int mbbs_lattice_table(mbbs_lattice_t lat, int which, int32_t* out, size_t count
  *      combine through LDS; falls back to 1 where no launch shape fits)
  *  MBBS_TUNE_PERSIST_BLOCKS         0: one split-wave block per logical block;
  *      1..16: that many resident blocks per CU loop over their XCD's range
+ *  MBBS_TUNE_MR_FUSED               SAP domain solver: 1 runs all MR steps of a
+ *      colour in one launch, one workgroup per domain (domain-wide sums inside
+ *      the workgroup); 0 uses three launches per MR step spread over the whole
+ *      chip; -1 (default) picks 1 when a domain holds at most 2048 (site,
+ *      column) pairs
  *  MBBS_TUNE_LDS_PAD_KB             extra LDS (KiB, 0..64) reserved per stencil
  *      block, which caps the blocks resident on a CU (fewer sites in flight
  *      per XCD, so more of their neighbour data stays in its L2)
  * Errors: EINVAL for an unknown knob or out-of-range value. */
 enum { MBBS_TUNE_GROUP_FP64 = 0, MBBS_TUNE_GROUP_FP32 = 1, MBBS_TUNE_GROUP_FP16S = 2,
        MBBS_TUNE_BLOCK_THREADS = 3, MBBS_TUNE_LDS_PAD_KB = 4, MBBS_TUNE_SPLIT_FP64 = 5,
-       MBBS_TUNE_SPLIT_FP32 = 6, MBBS_TUNE_SPLIT_FP16S = 7, MBBS_TUNE_PERSIST_BLOCKS = 8 };
+       MBBS_TUNE_SPLIT_FP32 = 6, MBBS_TUNE_SPLIT_FP16S = 7, MBBS_TUNE_PERSIST_BLOCKS = 8,
+       MBBS_TUNE_MR_FUSED = 9 };
 int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value);
 
 /* ---------------------------------------------------------------- operator */
@@ -241,9 +247,19 @@ int mbbs_solve(mbbs_lattice_t lat, int L, const double* B_dev, double* X_dev,
                mbbs_solve_info* info, void* stream);
 
 /* Solve nsys independent systems (each its own lattice, L, B, X, params and
- * info) together: iterations of all unconverged systems are interleaved in
- * one captured launch sequence per round; converged systems stop early on
- * a device flag.  ws_dev holds mbbs_solve_batched_workspace_size bytes. */
+ * info) together.  The systems are spread over up to 4 internal streams
+ * (created and destroyed by the call, default priority; the first waits for
+ * the work already on `stream`), largest first onto the least loaded one, so
+ * the launches of small systems run concurrently.  Each system advances in
+ * batches of graph_iters iterations (captured once in a per-system HIP graph
+ * and replayed when graph_iters > 1); the host polls one event per system and
+ * enqueues its next batch, true-residual check or restart as soon as its
+ * previous batch has drained, without waiting for the other systems.  A
+ * system that converges inside a batch stops on a device flag.  ws_dev holds
+ * mbbs_solve_batched_workspace_size bytes (device); the call also takes a
+ * small pinned host buffer for the state records.  Blocks until every system
+ * is done; infos[i] and the return value are as for mbbs_solve (the worst
+ * status over the systems). */
 int mbbs_solve_batched_workspace_size(int nsys, const mbbs_lattice_t* lats, const int* Ls,
                                       const mbbs_solve_params* params, size_t* bytes);
 int mbbs_solve_batched(int nsys, const mbbs_lattice_t* lats, const int* Ls,

@@ -155,6 +155,7 @@ TUNE_BLOCK_THREADS = 3
 TUNE_LDS_PAD_KB = 4
 TUNE_SPLIT = {0: 5, 1: 6, 2: 7}      # precision -> knob
 TUNE_PERSIST_BLOCKS = 8
+TUNE_MR_FUSED = 9
 
 
 def mbbs_lattice_tune(lat, knob, value):

@@ -482,6 +482,117 @@ __global__ void __launch_bounds__(256) k_mr_update(GeomK k, int L, int s0, int n
   store_spinor<PR, R>(r, r_s, base, L, sidx, rv);
 }
 
+// The whole MR domain solve of one colour in one launch: one workgroup per
+// domain runs the nmr steps (w = A_DD r, omega = <w, r> / <w, w>,
+// psi += omega r, r -= omega w) with the domain-wide sums and the step-to-step
+// dependence handled inside the workgroup (barriers only).  Thread t owns
+// column t % L of the sites t / L, t / L + SPB, ... of its domain, so its
+// per-column sums need no atomics and are combined in fixed order.
+// r, w and psi are read and written by other threads of the workgroup
+// between barriers, so they carry no restrict / const qualifiers here.
+template <int PR> constexpr int mr_fused_threads() { return PR == P64 ? 512 : 1024; }
+
+template <int PR, int PPSI, int PL>
+__global__ void __launch_bounds__(mr_fused_threads<PR>()) k_mr_fused(GeomK k, double kappa, int L, int s0, int spb, int nmr,
+                                                   int assign_first, typename Store<PR>::Elem* r, float* r_s,
+                                                   typename Store<PR>::Elem* w, float* w_s,
+                                                   typename Store<PPSI>::Elem* psi,
+                                                   const LinkElem<PL>* __restrict__ U,
+                                                   const int* __restrict__ frozen) {
+  if (frozen && *frozen) return;
+  using R = typename Store<PR>::Real;
+  using RP = typename Store<PPSI>::Real;
+  __shared__ double red[3][1024];
+  __shared__ double om_sh[2 * 16];
+  const int t = threadIdx.x;
+  const int T = spb * L;
+  const bool active = t < T;
+  const int col = t % L, j = t / L;
+  const int base_site = s0 + blockIdx.x * k.g.Vb;
+  const R kap = (R)kappa;
+  for (int it = 0; it < nmr; ++it) {
+    double sr = 0, si = 0, sw = 0;
+    if (active) {
+      for (int loc = j; loc < k.g.Vb; loc += spb) {
+        const int s = base_site + loc;
+        const SiteCtx c = site_ctx<DM>(k, s);
+        cplx<R> acc[4][3][1];
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) acc[sp][a][0] = cmake<R>(0, 0);
+        hop_sum<PR, PL, 1, DM, INSIDE, R>(k, c, r, r_s, U, L, col, acc);
+        const size_t base = (size_t)s * 12 * L + col;
+        const size_t sidx = (size_t)s * L + col;
+        cplx<R> v[4][3], wv[4][3];
+        load_spinor<PR, R>(r, r_s, base, L, sidx, v);
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) wv[sp][a] = v[sp][a] - kap * acc[sp][a][0];
+        store_spinor<PR, R>(w, w_s, base, L, sidx, wv);
+        if constexpr (Store<PR>::scaled) load_spinor<PR, R>(w, w_s, base, L, sidx, wv);
+        R a_re = 0, a_im = 0, a_ww = 0;
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            cplx<R> d = cdot(wv[sp][a], v[sp][a]);
+            a_re += d.re; a_im += d.im; a_ww += norm2(wv[sp][a]);
+          }
+        sr += a_re; si += a_im; sw += a_ww;
+      }
+    }
+    red[0][t] = sr; red[1][t] = si; red[2][t] = sw;
+    __syncthreads();
+    if (t < L) {
+      double a0 = 0, a1 = 0, a2 = 0;
+      for (int jj = 0; jj < spb; ++jj) {
+        a0 += red[0][jj * L + t];
+        a1 += red[1][jj * L + t];
+        a2 += red[2][jj * L + t];
+      }
+      om_sh[2 * t] = a2 > 0 ? a0 / a2 : 0.0;
+      om_sh[2 * t + 1] = a2 > 0 ? a1 / a2 : 0.0;
+    }
+    __syncthreads();
+    if (active) {
+      const cplx<R> om = cmake<R>((R)om_sh[2 * col], (R)om_sh[2 * col + 1]);
+      const bool assign = assign_first && it == 0, update_r = it + 1 < nmr;
+      for (int loc = j; loc < k.g.Vb; loc += spb) {
+        const int s = base_site + loc;
+        const size_t base = (size_t)s * 12 * L + col;
+        const size_t sidx = (size_t)s * L + col;
+        cplx<R> rv[4][3];
+        load_spinor<PR, R>(r, r_s, base, L, sidx, rv);
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const size_t i = base + (size_t)(3 * sp + a) * L;
+            cplx<R> d = om * rv[sp][a];
+            if (assign) {
+              Store<PPSI>::st(psi, i, cplx<RP>{(RP)d.re, (RP)d.im});
+            } else {
+              auto pv = Store<PPSI>::ld(psi, i);
+              Store<PPSI>::st(psi, i, cplx<RP>{(RP)(pv.re + (RP)d.re), (RP)(pv.im + (RP)d.im)});
+            }
+          }
+        if (update_r) {
+          cplx<R> wv[4][3];
+          load_spinor<PR, R>(w, w_s, base, L, sidx, wv);
+#pragma unroll
+          for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) rv[sp][a] = rv[sp][a] - om * wv[sp][a];
+          store_spinor<PR, R>(r, r_s, base, L, sidx, rv);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- split-wave kernels
 // Block = (IPB items) x (P hop groups); item = (site, column), IPB = S * L is a
 // multiple of the wave size so every wave belongs to one hop group.  Group h
@@ -961,6 +1072,25 @@ int sap_bind(const mbbs_lattice_s* lat, int L, int prec, void* ws, size_t bytes,
   return MBBS_OK;
 }
 
+// Sites per pass of the fused MR kernel: the largest divisor of the block
+// volume with at most `tmax` threads (one per site and column), preferring
+// whole waves.
+static int mr_fused_spb(int Vb, int L, int tmax) {
+  int best = 0, best_w = 0;
+  for (int s = 1; s <= Vb && s * L <= tmax; ++s) {
+    if (Vb % s) continue;
+    best = s;
+    if ((s * L) % 64 == 0) best_w = s;
+  }
+  // whole waves unless that halves the threads or more
+  return (best_w > 0 && 2 * best_w > best) ? best_w : best;
+}
+static bool use_mr_fused(const mbbs_lattice_s* lat, int L) {
+  if (L > 16) return false;   // omega of at most 16 columns in LDS
+  if (lat->mr_fused >= 0) return lat->mr_fused == 1;
+  return (size_t)lat->g.Vb * L <= 2048;
+}
+
 template <int PR, int PPSI, int PL>
 static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, int nmr,
                       const int* frozen, hipStream_t st, Profiler* prof) {
@@ -1005,6 +1135,16 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
       }
       if (prof) prof->end();
       MBBS_HIP(hipGetLastError());
+      if (use_mr_fused(lat, L)) {
+        const int spb = mr_fused_spb(g.Vb, L, mr_fused_threads<PR>());
+        if (prof) prof->begin(MBBS_K_MR_DSLASH);
+        hipLaunchKernelGGL((k_mr_fused<PR, PPSI, PL>), dim3(g.ndom / 2), dim3(spb * L), 0, st, lat->gk, lat->kappa,
+                           L, s0, spb, nmr, (int)(cy == 0), (ER*)b.r, b.r_s, (ER*)b.w, b.w_s, (EP*)b.psi, U,
+                           frozen);
+        if (prof) prof->end();
+        MBBS_HIP(hipGetLastError());
+        continue;
+      }
       for (int it = 0; it < nmr; ++it) {
         if (prof) prof->begin(MBBS_K_MR_DSLASH);
         int nblk_dom = g.Vb / S;

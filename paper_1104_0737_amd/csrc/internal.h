@@ -98,6 +98,7 @@ struct mbbs_lattice_s {
   int lds_pad_kb = 0;   // extra LDS per stencil block: caps resident blocks per CU
   int split[3] = {0, 0, 0};  // hop groups per site (0/1: one thread does all 8 hops)
   int persist_blocks = 0;    // resident blocks per CU of persistent split kernels (0: not persistent)
+  int mr_fused = -1;         // SAP domain solve in one launch per colour: -1 auto, 0 off, 1 on
 };
 
 namespace mbbs {

@@ -235,6 +235,10 @@ extern "C" int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value) {
       MBBS_CHECK(value >= 0 && value <= 16, "persistent blocks per CU must be in 0..16");
       lat->persist_blocks = value;
       return MBBS_OK;
+    case MBBS_TUNE_MR_FUSED:
+      MBBS_CHECK(value >= -1 && value <= 1, "fused MR must be -1 (auto), 0 or 1");
+      lat->mr_fused = value;
+      return MBBS_OK;
     case MBBS_TUNE_LDS_PAD_KB:
       MBBS_CHECK(value >= 0 && value <= 64, "LDS pad must be in 0..64 KiB");
       lat->lds_pad_kb = value;

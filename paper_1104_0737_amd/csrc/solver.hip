@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <thread>
 #include <vector>
 
 #include "blas.h"
@@ -519,20 +520,174 @@ static int solve_impl(mbbs_lattice_t lat, int L, const double* B_dev, double* X_
 }
 
 // ---------------------------------------------------------------- batched
+// Batched driver.  Systems are spread over up to BATCH_LANES internal streams
+// (largest first, each to the least loaded lane); each lane is an independent
+// chain on its own hardware queue, so the latency-bound launches of small
+// systems overlap.  The host never waits for a whole round: it polls one event
+// per system and, as soon as a system's previous batch of k iterations (and
+// the copy of its state record) has drained, decides on the host what that
+// system does next (more iterations, a true-residual check, a restart, stop)
+// and enqueues it behind whatever its lane still holds.
+constexpr int BATCH_LANES = 4;
+
+// Host-side mirror of the small device records one system reports back
+// (pinned memory, written by asynchronous copies).
+struct HostRec {
+  SolverState st;
+  double tn[LMAX_SOLVER];
+  double bn[LMAX_SOLVER];
+};
+
+enum BatchPhase { PH_INIT = 0, PH_ITER = 1, PH_TRUE = 2 };
+
+struct BatchJob {
+  SolveJob j;
+  int lane = 0;
+  int phase = PH_INIT;
+  bool pending = false;
+  hipEvent_t ev = nullptr;
+  HostRec* h = nullptr;
+};
+
+static int batch_record(BatchJob& b) {
+  MBBS_HIP(hipEventRecord(b.ev, b.j.c.st));
+  b.pending = true;
+  return MBBS_OK;
+}
+
+// Set-up without host synchronisation: constants, X = 0, ||b_i||^2, R, P, R~,
+// the state record; ||b_i||^2 comes back for the host's check.
+static int batch_init(BatchJob& b) {
+  Ctx& c = b.j.c;
+  MBBS_TRY(launch_fill(c.w.d.one, 1, make_double2(1, 0), c.st));
+  MBBS_TRY(launch_fill(c.w.mone, 1, make_double2(-1, 0), c.st));
+  if (!c.p.x0_is_guess) MBBS_TRY(launch_fill(c.X, c.N * c.L, make_double2(0, 0), c.st));
+  MBBS_TRY(col_norms(c, c.B, c.w.d.bnorm2, nullptr));
+  MBBS_TRY(start(c, !c.p.x0_is_guess, true));
+  b.j.n_outer += c.p.x0_is_guess ? 1 : 0;
+  SolverState s{};
+  s.maxiter = c.p.maxiter;
+  s.tol2 = c.p.tol * c.p.tol;
+  b.h->st = s;
+  MBBS_HIP(hipMemcpyAsync(c.w.d.state, &b.h->st, sizeof(SolverState), hipMemcpyHostToDevice, c.st));
+  MBBS_HIP(hipMemcpyAsync(b.h->bn, c.w.d.bnorm2, c.L * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  b.phase = PH_INIT;
+  return batch_record(b);
+}
+
+// k iterations (replayed from a per-system graph when graph_iters > 1), then
+// the state record back to the host.
+static int batch_iterate(BatchJob& b, int k) {
+  SolveJob& j = b.j;
+  Ctx& c = j.c;
+  if (k > 1) {
+    if (!j.exec) {
+      MBBS_HIP(hipStreamBeginCapture(c.st, hipStreamCaptureModeThreadLocal));
+      int erc = job_enqueue(j, k);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(c.st, &g);
+      if (erc < 0) return erc;
+      MBBS_CHECK(e == hipSuccess, "graph capture failed");
+      j.graph = g;
+      MBBS_CHECK(hipGraphInstantiate(&j.exec, g, nullptr, nullptr, 0) == hipSuccess, "graph instantiation failed");
+    }
+    MBBS_HIP(hipGraphLaunch(j.exec, c.st));
+  } else {
+    MBBS_TRY(job_enqueue(j, 1));
+  }
+  MBBS_HIP(hipMemcpyAsync(&b.h->st, c.w.d.state, sizeof(SolverState), hipMemcpyDeviceToHost, c.st));
+  b.phase = PH_ITER;
+  return batch_record(b);
+}
+
+static int batch_true(BatchJob& b) {
+  Ctx& c = b.j.c;
+  MBBS_TRY(true_residual(c));
+  b.j.n_outer += 1;
+  MBBS_HIP(hipMemcpyAsync(b.h->tn, c.w.trnorm2, c.L * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  b.phase = PH_TRUE;
+  return batch_record(b);
+}
+
+// The host's decision once a system's pending work has drained.
+static int batch_step(BatchJob& b, int k) {
+  SolveJob& j = b.j;
+  Ctx& c = j.c;
+  if (b.phase == PH_INIT) {
+    for (int i = 0; i < c.L; ++i) {
+      const double bn = b.h->bn[i];
+      if (!(bn > 0) || !std::isfinite(bn)) {
+        set_error("right-hand side column " + std::to_string(i) + (bn > 0 ? " is not finite" : " is zero"));
+        j.rc = MBBS_EINVAL;
+        j.done = true;
+        return MBBS_OK;
+      }
+    }
+    return batch_iterate(b, k);
+  }
+  if (b.phase == PH_ITER) {
+    j.hs = b.h->st;
+    if (!j.hs.frozen) return batch_iterate(b, k);
+    return batch_true(b);
+  }
+  // PH_TRUE: same decisions as the single-system driver
+  double worst = 0;
+  bool finite = true;
+  for (int i = 0; i < c.L; ++i) {
+    const double r = b.h->tn[i] / b.h->bn[i];
+    finite = finite && std::isfinite(r);
+    worst = std::max(worst, r);
+  }
+  const bool ok = finite && worst <= c.p.tol * c.p.tol;
+  if (j.hs.status == ST_BREAKDOWN) {
+    j.done = true;
+    j.rc = ok ? MBBS_OK : MBBS_EBREAKDOWN;
+    if (!ok) set_error("block BiCGSTAB breakdown in a batched system");
+    return MBBS_OK;
+  }
+  if (ok) { j.done = true; j.rc = MBBS_OK; return MBBS_OK; }
+  if (j.hs.status == ST_MAXITER || j.restarts >= c.p.max_restarts || j.hs.iter >= c.p.maxiter) {
+    j.done = true;
+    j.rc = MBBS_NOT_CONVERGED;
+    return MBBS_OK;
+  }
+  j.restarts += 1;
+  MBBS_TRY(start(c, false, false));
+  j.n_outer += 1;
+  b.h->st = j.hs;
+  b.h->st.frozen = 0;
+  b.h->st.status = ST_RUNNING;
+  MBBS_HIP(hipMemcpyAsync(c.w.d.state, &b.h->st, sizeof(SolverState), hipMemcpyHostToDevice, c.st));
+  return batch_iterate(b, k);
+}
+
 static int batched_impl(int nsys, const mbbs_lattice_t* lats, const int* Ls, const double* const* B, double* const* X,
                         const mbbs_solve_params* params, void* ws, size_t ws_bytes, mbbs_solve_info* infos,
                         void* stream) {
   auto t0 = std::chrono::steady_clock::now();
   MBBS_CHECK(nsys >= 1 && lats && Ls && B && X && params, "null argument");
-  std::vector<SolveJob> jobs(nsys);
+  hipStream_t caller = (hipStream_t)stream;
+  std::vector<BatchJob> jobs(nsys);
+  // lanes: largest systems first, each to the least loaded lane
+  const int nl = std::min(nsys, BATCH_LANES);
+  std::vector<int> order(nsys);
+  for (int i = 0; i < nsys; ++i) order[i] = i;
+  for (int i = 0; i < nsys; ++i) MBBS_TRY(validate(lats[i], Ls[i], &params[i]));
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (double)lats[a]->g.V * Ls[a] > (double)lats[b]->g.V * Ls[b];
+  });
+  std::vector<double> load(nl, 0.0);
+  for (int i : order) {
+    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    jobs[i].lane = l;
+    load[l] += (double)lats[i]->g.V * Ls[i];
+  }
   char* q = (char*)ws;
   size_t left = ws_bytes;
-  hipStream_t st = (hipStream_t)stream;
   for (int i = 0; i < nsys; ++i) {
-    MBBS_TRY(validate(lats[i], Ls[i], &params[i]));
     const size_t need = workspace_bytes(lats[i], Ls[i], params[i]);
     MBBS_CHECK(q != nullptr && left >= need, "batched workspace too small");
-    Ctx& c = jobs[i].c;
+    Ctx& c = jobs[i].j.c;
     c.lat = lats[i];
     c.L = Ls[i];
     c.N = (size_t)lats[i]->g.V * 12;
@@ -540,57 +695,76 @@ static int batched_impl(int nsys, const mbbs_lattice_t* lats, const int* Ls, con
     c.p.profile = 0;
     c.B = (const double2*)B[i];
     c.X = (double2*)X[i];
-    c.st = st;
     c.prof = nullptr;
+    MBBS_CHECK(B[i] && X[i] && B[i] != X[i], "B and X must be distinct device blocks");
     MBBS_TRY(bind(lats[i], Ls[i], c.p, q, need, c.w));
     c.frozen = &c.w.d.state->frozen;
     q += al(need);
     left -= std::min(left, al(need));
-    MBBS_TRY(job_init(jobs[i]));
   }
-  int k = 1;
-  for (int i = 0; i < nsys; ++i) k = std::max(k, params[i].graph_iters);
-  const bool use_graph = k > 1 && st != nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // resources, released on every exit path below
+  std::vector<hipStream_t> lanes(nl, nullptr);
+  HostRec* host = nullptr;
+  hipEvent_t fork = nullptr;
   int rc = MBBS_OK;
-  for (;;) {
-    bool any = false;
-    for (auto& j : jobs) any = any || !j.done;
-    if (!any) break;
-    if (use_graph) {
-      // one graph holds k iterations of every system; finished systems stay
-      // frozen on the device and their kernels return at once
-      if (!exec) {
-        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) { rc = MBBS_EHIP; break; }
-        int erc = MBBS_OK;
-        for (int it = 0; it < k && erc >= 0; ++it)
-          for (auto& j : jobs) { erc = enqueue_iteration(j.c); if (erc < 0) break; }
-        hipError_t e = hipStreamEndCapture(st, &graph);
-        if (erc < 0 || e != hipSuccess) { rc = erc < 0 ? erc : MBBS_EHIP; set_error("graph capture failed"); break; }
-        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) { rc = MBBS_EHIP; break; }
-      }
-      if (hipGraphLaunch(exec, st) != hipSuccess) { rc = MBBS_EHIP; break; }
-    } else {
-      for (int it = 0; it < k && rc >= 0; ++it)
-        for (auto& j : jobs)
-          if (!j.done) { rc = enqueue_iteration(j.c); if (rc < 0) break; }
-      if (rc < 0) break;
-    }
-    for (auto& j : jobs)
-      if (!j.done) { rc = job_check(j); if (rc < 0) break; }
-    if (rc < 0) break;
+  auto fail = [&](int code, const char* msg) { if (rc >= 0) { rc = code; set_error(msg); } };
+  if (hipHostMalloc((void**)&host, sizeof(HostRec) * nsys, hipHostMallocDefault) != hipSuccess)
+    fail(MBBS_ENOMEM, "pinned host memory for the batched state records");
+  for (int l = 0; l < nl && rc >= 0; ++l)
+    if (hipStreamCreateWithFlags(&lanes[l], hipStreamNonBlocking) != hipSuccess) fail(MBBS_EHIP, "stream creation");
+  if (rc >= 0 && (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+                  hipEventRecord(fork, caller) != hipSuccess))
+    fail(MBBS_EHIP, "event creation");
+  for (int l = 0; l < nl && rc >= 0; ++l)
+    if (hipStreamWaitEvent(lanes[l], fork, 0) != hipSuccess) fail(MBBS_EHIP, "stream wait");
+  for (int i = 0; i < nsys && rc >= 0; ++i) {
+    BatchJob& b = jobs[i];
+    b.j.c.st = lanes[b.lane];
+    b.h = host + i;
+    if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) fail(MBBS_EHIP, "event creation");
   }
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
-  (void)hipStreamSynchronize(st);
+  // set-up of every system, then the polling loop
+  for (int i = 0; i < nsys && rc >= 0; ++i) {
+    const int e = batch_init(jobs[i]);
+    if (e < 0) rc = e;
+  }
+  int remaining = nsys;
+  while (rc >= 0 && remaining > 0) {
+    bool progress = false;
+    for (int i = 0; i < nsys && rc >= 0; ++i) {
+      BatchJob& b = jobs[i];
+      if (b.j.done || !b.pending) continue;
+      const hipError_t e = hipEventQuery(b.ev);
+      if (e == hipErrorNotReady) continue;
+      if (e != hipSuccess) { fail(MBBS_EHIP, "batched solve: device error"); break; }
+      b.pending = false;
+      progress = true;
+      const int k = std::max(1, b.j.c.p.graph_iters);
+      const int s = batch_step(b, k);
+      if (s < 0) { rc = s; break; }
+      if (b.j.done) --remaining;
+    }
+    if (!progress) std::this_thread::yield();
+  }
+  for (int l = 0; l < nl; ++l)
+    if (lanes[l]) (void)hipStreamSynchronize(lanes[l]);
   double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   int worst = MBBS_OK;
   for (int i = 0; i < nsys; ++i) {
-    job_fill_info(jobs[i], infos ? &infos[i] : nullptr, secs);
-    if (jobs[i].rc < 0) worst = std::min(worst, jobs[i].rc);
-    else if (worst == MBBS_OK && jobs[i].rc == MBBS_NOT_CONVERGED) worst = MBBS_NOT_CONVERGED;
+    SolveJob& j = jobs[i].j;
+    if (rc >= 0) job_fill_info(j, infos ? &infos[i] : nullptr, secs);
+    else if (infos) infos[i].status = j.done ? j.rc : rc;
+    if (j.rc < 0) worst = std::min(worst, j.rc);
+    else if (worst == MBBS_OK && j.rc == MBBS_NOT_CONVERGED) worst = MBBS_NOT_CONVERGED;
+    if (j.exec) (void)hipGraphExecDestroy(j.exec);
+    if (j.graph) (void)hipGraphDestroy(j.graph);
+    if (jobs[i].ev) (void)hipEventDestroy(jobs[i].ev);
   }
+  // the caller's stream sees every lane's work as complete
+  for (int l = 0; l < nl; ++l)
+    if (lanes[l]) (void)hipStreamDestroy(lanes[l]);
+  if (fork) (void)hipEventDestroy(fork);
+  if (host) (void)hipHostFree(host);
   return rc < 0 ? rc : worst;
 }
 

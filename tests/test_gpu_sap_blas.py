@@ -130,8 +130,32 @@ def test_sap_split_wave_parity(split, L, prec, tol):
     ref = sap.sap(U, 0.12, gu.PH_AP, dom, eta, 3, 4).reshape(12 * V, L)
     with gu.Lattice(dims, block, U, 0.12) as lat:
         B.mbbs_lattice_tune(lat.h, B.TUNE_SPLIT[prec], split)
+        B.mbbs_lattice_tune(lat.h, B.TUNE_MR_FUSED, 0)   # the split MR kernels, not the fused one
         ws = torch.empty(B.mbbs_sap_workspace_size(lat.h, L, prec), dtype=torch.uint8, device="cuda")
         Yd = torch.empty((12 * V, L), dtype=torch.complex128, device="cuda")
         B.mbbs_sap_apply(lat.h, L, gu.dev(eta), Yd, 3, 4, prec, ws)
         err = gu.rel_col_err(gu.host(Yd), ref)
     assert np.all(err <= tol), err
+
+
+@pytest.mark.parametrize("dims,block,L", [((8, 8, 8, 8), (4, 4, 4, 4), 4), ((12, 12, 12, 12), (6, 6, 6, 6), 6),
+                                          ((4, 4, 4, 6), (2, 2, 2, 3), 5), ((8, 8, 8, 8), (4, 4, 4, 4), 16),
+                                          ((16, 8, 8, 8), (8, 4, 4, 4), 12)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 3e-5), (2, 1e-2)])
+def test_sap_mr_fused_parity(dims, block, L, prec, tol):
+    """Domain solve in one launch per colour (one workgroup per domain) and
+    in three launches per MR step: both against the oracle."""
+    gu.flush(f"sap fused {dims} L={L} prec={prec}")
+    V = int(np.prod(dims))
+    U = inputs.gauge_field(dims, 0.3, 26)
+    eta = inputs.gaussian_block(V, L, 27)
+    dom = sap.Domains(dims, block)
+    ref = sap.sap(U, 0.12, gu.PH_AP, dom, eta, 3, 4).reshape(12 * V, L)
+    with gu.Lattice(dims, block, U, 0.12) as lat:
+        ws = torch.empty(B.mbbs_sap_workspace_size(lat.h, L, prec), dtype=torch.uint8, device="cuda")
+        for fused in (1, 0):
+            B.mbbs_lattice_tune(lat.h, B.TUNE_MR_FUSED, fused)
+            Yd = torch.empty((12 * V, L), dtype=torch.complex128, device="cuda")
+            B.mbbs_sap_apply(lat.h, L, gu.dev(eta), Yd, 3, 4, prec, ws)
+            err = gu.rel_col_err(gu.host(Yd), ref)
+            assert np.all(err <= tol), (fused, err)
