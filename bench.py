@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--skip-dslash", action="store_true", help="no stand-alone operator timing")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--profile", type=int, default=1, help="event-time kernel classes in the timed solves")
+    ap.add_argument("--sap-prec", choices=("fp32", "fp16s"), default="fp32",
+                    help="storage precision of the SAP preconditioner in the mixed solve")
     ap.add_argument("--batched", action="store_true",
                     help="48 independent systems of uneven size solved together (batched form)")
     ap.add_argument("--graph-iters", type=int, default=4)
@@ -134,19 +136,6 @@ def main():
     lat = B.mbbs_lattice_create(dims, cfg.block, Ud, cfg.kappa, cfg.phases, stream=stream)
     del Ud
 
-    # ------------------------------------------------------------ launch tuning
-    tuning = {}
-    if not args.no_tune:
-        from paper_1104_0737_amd import autotune
-        for prec, name in ((B.FP64, "fp64"), (B.FP32, "fp32"), (B.FP16S, "fp16s")):
-            best, times = autotune.tune_operator(lat, V, L, prec, stream=stream)
-            tuning[name] = {"group_cols": best[0], "block_threads": best[1], "split": best[2],
-                            "ms": round(times[best], 4), "worst_ms": round(max(times.values()), 4),
-                            "classic_best_ms": round(min(v for k, v in times.items() if k[2] == 0), 4)}
-            log(f"tuned {name}: group {best[0]} threads {best[1]} split {best[2]} ({times[best]:.3f} ms; "
-                f"best classic {tuning[name]['classic_best_ms']:.3f} ms; worst {max(times.values()):.3f} ms)")
-        torch.cuda.empty_cache()
-
     # ------------------------------------------------------------ operator alone
     def time_dslash(prec):
         gen = torch.Generator(device=dev)
@@ -179,8 +168,33 @@ def main():
                 "frac_hbm_peak": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "TFLOPs": fl / (ms * 1e-3) / 1e12,
                 "bytes_per_launch": by}
 
+    # ------------------------------------------------------------ launch tuning
+    tuning = {}
     dslash = {}
-    for prec, name in () if args.skip_dslash else ((B.FP64, "fp64"), (B.FP32, "fp32"), (B.FP16S, "fp16s")):
+    if not args.no_tune:
+        from paper_1104_0737_amd import autotune
+        for prec, name in ((B.FP64, "fp64"), (B.FP32, "fp32"), (B.FP16S, "fp16s")):
+            best, times = autotune.tune_operator(lat, V, L, prec, stream=stream)
+            tuning[name] = {"group_cols": best[0], "block_threads": best[1], "split": best[2],
+                            "hop_pair": best[3], "nt_store": best[4],
+                            "ms": round(times[best], 4), "worst_ms": round(max(times.values()), 4),
+                            "classic_best_ms": round(min(v for k, v in times.items() if k[2] == 0), 4)}
+            log(f"tuned {name}: {best} ({times[best]:.3f} ms; "
+                f"best classic {tuning[name]['classic_best_ms']:.3f} ms; worst {max(times.values()):.3f} ms)")
+            if not args.skip_dslash:
+                # the operator alone, in its fastest setting
+                dslash[name] = time_dslash(prec)
+                dslash[name]["setting"] = list(best)
+                log(f"  operator {name}: {dslash[name]['ms']:.3f} ms, {dslash[name]['algo_GBps']:.0f} GB/s algorithmic")
+            if prec != B.FP64:
+                # the SAP kernels of this precision: split or one thread per site
+                sbest, stimes = autotune.tune_sap(lat, V, L, prec, times, stream=stream)
+                tuning[name]["sap"] = {"setting": list(sbest), "ms": {str(k): round(v, 3) for k, v in stimes.items()}}
+                log(f"  SAP shape {sbest}: " + ", ".join(f"{k}: {v:.2f} ms" for k, v in stimes.items()))
+        torch.cuda.empty_cache()
+
+    for prec, name in () if args.skip_dslash or not args.no_tune else ((B.FP64, "fp64"), (B.FP32, "fp32"),
+                                                                        (B.FP16S, "fp16s")):
         log(f"operator {name}")
         dslash[name] = time_dslash(prec)
         log(f"  {dslash[name]['ms']:.3f} ms, {dslash[name]['algo_GBps']:.0f} GB/s algorithmic")
@@ -196,6 +210,8 @@ def main():
         Bd[12 * site + cfg.comp0 + j, j] = 1.0
     Xd = torch.empty_like(Bd)
 
+    sap_prec = {"fp32": B.FP32, "fp16s": B.FP16S}[args.sap_prec]
+
     def run_solve(sap_prec, profile):
         p = B.mbbs_solve_params_default(tol=cfg.tol, sap_prec=sap_prec, ncy=cfg.ncy, nmr=cfg.nmr,
                                         profile=profile, graph_iters=1)
@@ -210,13 +226,13 @@ def main():
 
     for w in range(args.warmup):
         log(f"warmup solve {w}")
-        dt, info = run_solve(B.FP32, 0)
+        dt, info = run_solve(sap_prec, 0)
         log(f"  {dt:.2f}s, {info['iterations']} iterations, status {info['status']}")
     torch.cuda.synchronize()
     times, infos = [], []
     t_start = time.perf_counter()
     for k in range(args.steps):
-        dt, info = run_solve(B.FP32, args.profile)
+        dt, info = run_solve(sap_prec, args.profile)
         times.append(dt)
         infos.append(info)
         log(f"step {k}: {dt:.3f}s, {info['iterations']} iterations, max true residual "
@@ -224,6 +240,17 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     ok = all(i["status"] == 0 and np.all(i["true_res"] <= cfg.tol) for i in infos)
+
+    # the other SAP storage precision, once, for comparison
+    other = None
+    if not args.no_fp64_solve:
+        oprec = B.FP16S if sap_prec == B.FP32 else B.FP32
+        oname = "fp16s" if oprec == B.FP16S else "fp32"
+        log(f"{oname}-SAP solve")
+        dto, io = run_solve(oprec, 0)
+        other = {"sap_prec": oname, "seconds": dto, "tts_per_rhs_s": dto / L, "iterations": io["iterations"],
+                 "max_true_res": float(io["true_res"].max()), "status": io["status"]}
+        log(f"  {dto:.2f}s, {io['iterations']} iterations, max true residual {io['true_res'].max():.2e}")
 
     fp64 = None
     if not args.no_fp64_solve:
@@ -272,10 +299,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32",
+        "dtype": "f64+f32" if args.sap_prec == "fp32" else "f64+f32 (fp16 storage)",
         "data": "synthetic",
         "config": {"workload": f"{'x'.join(map(str, dims))} Wilson-Dirac, L={L} point sources, "
-                               f"SAP 8^4 domains ncy={cfg.ncy} nmr={cfg.nmr}, FP32 SAP, tol {cfg.tol:g}",
+                               f"SAP 8^4 domains ncy={cfg.ncy} nmr={cfg.nmr}, {args.sap_prec.upper()} SAP, "
+                               f"tol {cfg.tol:g}",
                    "lattice": list(dims), "L": L, "kappa": cfg.kappa, "eps": cfg.eps,
                    "parallelism": "single GPU"},
         "converged": ok,
@@ -283,6 +311,7 @@ def main():
         "tts_per_rhs_s": {"mixed": step_s / L, "fp64": fp64["tts_per_rhs_s"] if fp64 else None,
                           "fp64_over_mixed": (fp64["tts_per_rhs_s"] / (step_s / L)) if fp64 else None},
         "fp64_solve": fp64,
+        "other_sap_prec_solve": other,
         "max_true_res": float(max(i["true_res"].max() for i in infos)),
         "dslash": dslash,
         "tuning": tuning,

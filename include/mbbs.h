@@ -118,6 +118,12 @@ int mbbs_lattice_table(mbbs_lattice_t lat, int which, int32_t* out, size_t count
  *      the workgroup); 0 uses three launches per MR step spread over the whole
  *      chip; -1 (default) picks 1 when a domain holds at most 2048 (site,
  *      column) pairs
+ *  MBBS_TUNE_NT_STORE_FP64/FP32/FP16S  1: the operator writes its output with
+ *      nontemporal stores (the output is not re-read by the same launch, so it
+ *      need not displace neighbour data in L2)
+ *  MBBS_TUNE_HOP_PAIR_FP64/FP32/FP16S  1: the one-thread-per-site operator keeps
+ *      both hops of a direction in flight (more loads in flight per thread,
+ *      more registers)
  *  MBBS_TUNE_LDS_PAD_KB             extra LDS (KiB, 0..64) reserved per stencil
  *      block, which caps the blocks resident on a CU (fewer sites in flight
  *      per XCD, so more of their neighbour data stays in its L2)
@@ -125,7 +131,9 @@ int mbbs_lattice_table(mbbs_lattice_t lat, int which, int32_t* out, size_t count
 enum { MBBS_TUNE_GROUP_FP64 = 0, MBBS_TUNE_GROUP_FP32 = 1, MBBS_TUNE_GROUP_FP16S = 2,
        MBBS_TUNE_BLOCK_THREADS = 3, MBBS_TUNE_LDS_PAD_KB = 4, MBBS_TUNE_SPLIT_FP64 = 5,
        MBBS_TUNE_SPLIT_FP32 = 6, MBBS_TUNE_SPLIT_FP16S = 7, MBBS_TUNE_PERSIST_BLOCKS = 8,
-       MBBS_TUNE_MR_FUSED = 9 };
+       MBBS_TUNE_MR_FUSED = 9, MBBS_TUNE_HOP_PAIR_FP64 = 11, MBBS_TUNE_HOP_PAIR_FP32 = 12,
+       MBBS_TUNE_HOP_PAIR_FP16S = 13, MBBS_TUNE_NT_STORE_FP64 = 14, MBBS_TUNE_NT_STORE_FP32 = 15,
+       MBBS_TUNE_NT_STORE_FP16S = 16 };
 int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value);
 
 /* ---------------------------------------------------------------- operator */

@@ -1,9 +1,13 @@
 """Autotuner for the stencil kernels' launch shape.
 
-For a lattice handle, L and a precision, time the operator (what the SAP
-kernels of that precision share: column-group width and threads per block)
-over the candidate settings and keep the fastest on the handle.  Every
-setting produces bit-identical results, so the choice only affects speed.
+For a lattice handle, L and a precision, time the operator over the
+candidate settings (column-group width, threads per block, split-wave hop
+groups, paired hops, nontemporal output stores) and keep the fastest on the
+handle.  The SAP kernels of a precision share the width, block and split
+settings; `tune_sap` then picks between the best split and the best
+one-thread-per-site shape by timing the preconditioner itself.  Settings
+other than the split change no result bit; split shapes sum the hops in
+another order.
 """
 
 from __future__ import annotations
@@ -27,8 +31,27 @@ def candidates(L, prec):
     return classic + [(L, 256, 2), (L, 256, 4)]
 
 
+def operator_candidates(L, prec):
+    """(group, threads, split, pair, nt) settings tried by tune_operator: all
+    L columns or half of them per group, three block sizes, paired hops and
+    nontemporal stores on or off, and the split-wave kernels."""
+    c = next(c for c in range(_cmax(prec), 0, -1) if L % c == 0)
+    groups = [L] + ([L // 2] if L % 2 == 0 and (L // 2) % c == 0 else [])
+    out = [(g, t, 0, pr, nt) for g in groups for t in (128, 192, 256) for pr in (0, 1) for nt in (0, 1)]
+    return out + [(L, 256, sp, 0, nt) for sp in (2, 4) for nt in (0, 1)]
+
+
+def apply(lat, prec, setting):
+    g, t, sp, pr, nt = setting
+    B.mbbs_lattice_tune(lat, B.TUNE_GROUP[prec], g)
+    B.mbbs_lattice_tune(lat, B.TUNE_BLOCK_THREADS, t)
+    B.mbbs_lattice_tune(lat, B.TUNE_SPLIT[prec], sp)
+    B.mbbs_lattice_tune(lat, B.TUNE_HOP_PAIR[prec], pr)
+    B.mbbs_lattice_tune(lat, B.TUNE_NT_STORE[prec], nt)
+
+
 def tune_operator(lat, V, L, prec, stream=None, reps=3):
-    """Return (best (group, threads, split), {setting: ms}) and apply the best."""
+    """Return (best (group, threads, split, pair, nt), {setting: ms}) and apply the best."""
     import torch
     dev = torch.device("cuda")
     N = 12 * V
@@ -43,10 +66,8 @@ def tune_operator(lat, V, L, prec, stream=None, reps=3):
     Y = torch.empty_like(X)
     s = stream or torch.cuda.current_stream()
     times = {}
-    for g, t, sp in candidates(L, prec):
-        B.mbbs_lattice_tune(lat, B.TUNE_GROUP[prec], g)
-        B.mbbs_lattice_tune(lat, B.TUNE_BLOCK_THREADS, t)
-        B.mbbs_lattice_tune(lat, B.TUNE_SPLIT[prec], sp)
+    for setting in operator_candidates(L, prec):
+        apply(lat, prec, setting)
         B.mbbs_apply_dirac_raw(lat, L, prec, X, Xs, Y, Ys, stream=s)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s)
@@ -54,10 +75,39 @@ def tune_operator(lat, V, L, prec, stream=None, reps=3):
             B.mbbs_apply_dirac_raw(lat, L, prec, X, Xs, Y, Ys, stream=s)
         e1.record(s)
         e1.synchronize()
-        times[(g, t, sp)] = e0.elapsed_time(e1) / reps
+        times[setting] = e0.elapsed_time(e1) / reps
     best = min(times, key=times.get)
-    B.mbbs_lattice_tune(lat, B.TUNE_GROUP[prec], best[0])
-    B.mbbs_lattice_tune(lat, B.TUNE_BLOCK_THREADS, best[1])
-    B.mbbs_lattice_tune(lat, B.TUNE_SPLIT[prec], best[2])
+    apply(lat, prec, best)
     del X, Y, Xs, Ys
+    return best, times
+
+
+def tune_sap(lat, V, L, prec, op_times, stream=None, ncy=4, nmr=4, reps=2):
+    """Between the fastest split and the fastest one-thread-per-site operator
+    settings (from tune_operator's timings), keep the one under which the SAP
+    preconditioner itself runs faster.  Returns (setting, {setting: ms})."""
+    import torch
+    split = [k for k in op_times if k[2] in (2, 4)]
+    classic = [k for k in op_times if k[2] not in (2, 4)]
+    cands = [min(c, key=op_times.get) for c in (split, classic) if c]
+    dev = torch.device("cuda")
+    s = stream or torch.cuda.current_stream()
+    X = torch.zeros((12 * V, L), dtype=torch.complex128, device=dev)
+    X[::7] = 1.0
+    Y = torch.empty_like(X)
+    ws = torch.empty(B.mbbs_sap_workspace_size(lat, L, prec), dtype=torch.uint8, device=dev)
+    times = {}
+    for setting in cands:
+        apply(lat, prec, setting)
+        B.mbbs_sap_apply(lat, L, X, Y, ncy, nmr, prec, ws, stream=s)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            B.mbbs_sap_apply(lat, L, X, Y, ncy, nmr, prec, ws, stream=s)
+        e1.record(s)
+        e1.synchronize()
+        times[setting] = e0.elapsed_time(e1) / reps
+    best = min(times, key=times.get)
+    apply(lat, prec, best)
+    del X, Y, ws
     return best, times

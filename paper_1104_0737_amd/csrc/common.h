@@ -62,6 +62,11 @@ template <> struct Store<P64> {
     return {v.x, v.y};
   }
   __device__ __forceinline__ static void st(Elem* p, size_t i, cplx<double> v) { p[i] = make_double2(v.re, v.im); }
+  __device__ __forceinline__ static void st_nt(Elem* p, size_t i, cplx<double> v) {
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    v2 x = {v.re, v.im};
+    __builtin_nontemporal_store(x, (v2*)(p + i));
+  }
 };
 template <> struct Store<P32> {
   using Real = float;
@@ -72,6 +77,11 @@ template <> struct Store<P32> {
     return {v.x, v.y};
   }
   __device__ __forceinline__ static void st(Elem* p, size_t i, cplx<float> v) { p[i] = make_float2(v.re, v.im); }
+  __device__ __forceinline__ static void st_nt(Elem* p, size_t i, cplx<float> v) {
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    v2 x = {v.re, v.im};
+    __builtin_nontemporal_store(x, (v2*)(p + i));
+  }
 };
 template <> struct Store<P16> {
   using Real = float;
@@ -83,6 +93,12 @@ template <> struct Store<P16> {
   }
   __device__ __forceinline__ static void st(Elem* p, size_t i, cplx<float> v) {
     p[i] = __floats2half2_rn(v.re, v.im);
+  }
+  __device__ __forceinline__ static void st_nt(Elem* p, size_t i, cplx<float> v) {
+    __half2 h = __floats2half2_rn(v.re, v.im);
+    unsigned u;
+    __builtin_memcpy(&u, &h, sizeof(u));
+    __builtin_nontemporal_store(u, (unsigned*)(p + i));
   }
 };
 

@@ -37,40 +37,170 @@ enum Hops { ALL = 0, INSIDE = 1, OUTSIDE = 2 };
 // `token` chains consecutive hops: each hop's addresses depend on the
 // previous hop's accumulator (an empty asm), so its loads are not hoisted
 // above it; one hop's data in flight per thread keeps register pressure low.
+// Whether hop (MU, FWD) is excluded by the HOPS selection.
+template <int ORDER, int HOPS, int MU, int FWD>
+__device__ __forceinline__ bool hop_skipped(const GeomK& k, const SiteCtx& c) {
+  if constexpr (HOPS == ALL) {
+    return false;
+  } else {
+    int r = (ORDER == DM) ? c.l[MU] : (c.x[MU] % k.g.b[MU]);
+    bool leaves = FWD ? (r == k.g.b[MU] - 1) : (r == 0);
+    return HOPS == INSIDE ? leaves : !leaves;
+  }
+}
+
+template <int PIN, int PL, int C, int ORDER, int HOPS, int MU, int FWD, typename R>
+__device__ __forceinline__ void hop_body(const GeomK& k, const SiteCtx& c, int sn, int ls,
+                                         const typename Store<PIN>::Elem* __restrict__ in,
+                                         const float* __restrict__ in_s,
+                                         const LinkElem<PL>* __restrict__ U, int L, int col0,
+                                         cplx<R> (&acc)[4][3][C], R& token);
+
 template <int PIN, int PL, int C, int ORDER, int HOPS, int MU, int FWD, typename R>
 __device__ __forceinline__ void hop_one(const GeomK& k, const SiteCtx& c,
                                         const typename Store<PIN>::Elem* __restrict__ in,
                                         const float* __restrict__ in_s,
                                         const LinkElem<PL>* __restrict__ U, int L, int col0,
                                         cplx<R> (&acc)[4][3][C], R& token) {
-  constexpr int dir = FWD ? 1 : -1;
-  if constexpr (HOPS != ALL) {
-    int r = (ORDER == DM) ? c.l[MU] : (c.x[MU] % k.g.b[MU]);
-    bool leaves = FWD ? (r == k.g.b[MU] - 1) : (r == 0);
-    if (HOPS == INSIDE && leaves) return;
-    if (HOPS == OUTSIDE && !leaves) return;
-  }
-  int sn = neighbour<ORDER>(k, c, MU, dir);
+  if (hop_skipped<ORDER, HOPS, MU, FWD>(k, c)) return;
+  int sn = neighbour<ORDER>(k, c, MU, FWD ? 1 : -1);
   int ls = FWD ? c.s : sn;
   asm volatile("" : "+v"(sn), "+v"(ls) : "v"(token));
-  const bool wrap = FWD ? (c.x[MU] == k.g.d[MU] - 1) : (c.x[MU] == 0);
-  cplx<R> ph = cmake<R>((R)1, (R)0);
-  if (HOPS != INSIDE && wrap) ph = cmake<R>((R)k.g.ph[MU][0], (R)(FWD ? k.g.ph[MU][1] : -k.g.ph[MU][1]));
-  const Mat3<R> u = load_link<PL, R>(U, ls, MU);
-  constexpr SpinRule sr = spin_rule(MU, FWD);
+  hop_body<PIN, PL, C, ORDER, HOPS, MU, FWD, R>(k, c, sn, ls, in, in_s, U, L, col0, acc, token);
+}
+
+// Raw register image of the data one hop reads: C columns of the neighbour's
+// spinor and the link, kept in storage format until every load of the hop
+// has been issued.
+template <int P> struct RawT;
+template <> struct RawT<P64> { using T = double; static constexpr int per = 2; };
+template <> struct RawT<P32> { using T = float; static constexpr int per = 2; };
+template <> struct RawT<P16> { using T = unsigned; static constexpr int per = 1; };
+
+template <int P>
+__device__ __forceinline__ void raw_split(typename Store<P>::Elem e, typename RawT<P>::T* r) {
+  if constexpr (P == P16) {
+    __builtin_memcpy(r, &e, sizeof(unsigned));
+  } else {
+    r[0] = e.x; r[1] = e.y;
+  }
+}
+template <int P, typename R>
+__device__ __forceinline__ cplx<R> raw_join(const typename RawT<P>::T* r) {
+  if constexpr (P == P16) {
+    __half2 h;
+    __builtin_memcpy(&h, r, sizeof(unsigned));
+    float2 f = __half22float2(h);
+    return cmake<R>((R)f.x, (R)f.y);
+  } else {
+    return cmake<R>((R)r[0], (R)r[1]);
+  }
+}
+
+// One asm consuming every value a hop loads: all of the hop's loads are
+// issued before its first wait (left alone, the compiler sinks each column's
+// loads to just before their use: one memory round trip per column).
+template <typename T, int NS, typename U, int NL>
+__device__ __forceinline__ void pin_regs(T (&s)[NS], U (&l)[NL]) {
+  if constexpr (NS == 12 && NL == 9) {
+    asm volatile("" : "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3]), "+v"(s[4]), "+v"(s[5]), "+v"(s[6]), "+v"(s[7]), "+v"(s[8]), "+v"(s[9]), "+v"(s[10]), "+v"(s[11]),
+                 "+v"(l[0]), "+v"(l[1]), "+v"(l[2]), "+v"(l[3]), "+v"(l[4]), "+v"(l[5]), "+v"(l[6]), "+v"(l[7]), "+v"(l[8]));
+  } else if constexpr (NS == 12 && NL == 18) {
+    asm volatile("" : "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3]), "+v"(s[4]), "+v"(s[5]), "+v"(s[6]), "+v"(s[7]), "+v"(s[8]), "+v"(s[9]), "+v"(s[10]), "+v"(s[11]),
+                 "+v"(l[0]), "+v"(l[1]), "+v"(l[2]), "+v"(l[3]), "+v"(l[4]), "+v"(l[5]), "+v"(l[6]), "+v"(l[7]), "+v"(l[8]), "+v"(l[9]), "+v"(l[10]), "+v"(l[11]), "+v"(l[12]), "+v"(l[13]), "+v"(l[14]), "+v"(l[15]), "+v"(l[16]), "+v"(l[17]));
+  } else if constexpr (NS == 24 && NL == 9) {
+    asm volatile("" : "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3]), "+v"(s[4]), "+v"(s[5]), "+v"(s[6]), "+v"(s[7]), "+v"(s[8]), "+v"(s[9]), "+v"(s[10]), "+v"(s[11]), "+v"(s[12]), "+v"(s[13]), "+v"(s[14]), "+v"(s[15]), "+v"(s[16]), "+v"(s[17]), "+v"(s[18]), "+v"(s[19]), "+v"(s[20]), "+v"(s[21]), "+v"(s[22]), "+v"(s[23]),
+                 "+v"(l[0]), "+v"(l[1]), "+v"(l[2]), "+v"(l[3]), "+v"(l[4]), "+v"(l[5]), "+v"(l[6]), "+v"(l[7]), "+v"(l[8]));
+  } else if constexpr (NS == 24 && NL == 18) {
+    asm volatile("" : "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3]), "+v"(s[4]), "+v"(s[5]), "+v"(s[6]), "+v"(s[7]), "+v"(s[8]), "+v"(s[9]), "+v"(s[10]), "+v"(s[11]), "+v"(s[12]), "+v"(s[13]), "+v"(s[14]), "+v"(s[15]), "+v"(s[16]), "+v"(s[17]), "+v"(s[18]), "+v"(s[19]), "+v"(s[20]), "+v"(s[21]), "+v"(s[22]), "+v"(s[23]),
+                 "+v"(l[0]), "+v"(l[1]), "+v"(l[2]), "+v"(l[3]), "+v"(l[4]), "+v"(l[5]), "+v"(l[6]), "+v"(l[7]), "+v"(l[8]), "+v"(l[9]), "+v"(l[10]), "+v"(l[11]), "+v"(l[12]), "+v"(l[13]), "+v"(l[14]), "+v"(l[15]), "+v"(l[16]), "+v"(l[17]));
+  } else if constexpr (NS == 36 && NL == 9) {
+    asm volatile("" : "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3]), "+v"(s[4]), "+v"(s[5]), "+v"(s[6]), "+v"(s[7]), "+v"(s[8]), "+v"(s[9]), "+v"(s[10]), "+v"(s[11]), "+v"(s[12]), "+v"(s[13]), "+v"(s[14]), "+v"(s[15]), "+v"(s[16]), "+v"(s[17]), "+v"(s[18]), "+v"(s[19]), "+v"(s[20]), "+v"(s[21]), "+v"(s[22]), "+v"(s[23]), "+v"(s[24]), "+v"(s[25]), "+v"(s[26]), "+v"(s[27]), "+v"(s[28]), "+v"(s[29]), "+v"(s[30]), "+v"(s[31]), "+v"(s[32]), "+v"(s[33]), "+v"(s[34]), "+v"(s[35]),
+                 "+v"(l[0]), "+v"(l[1]), "+v"(l[2]), "+v"(l[3]), "+v"(l[4]), "+v"(l[5]), "+v"(l[6]), "+v"(l[7]), "+v"(l[8]));
+  } else if constexpr (NS == 36 && NL == 18) {
+    asm volatile("" : "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3]), "+v"(s[4]), "+v"(s[5]), "+v"(s[6]), "+v"(s[7]), "+v"(s[8]), "+v"(s[9]), "+v"(s[10]), "+v"(s[11]), "+v"(s[12]), "+v"(s[13]), "+v"(s[14]), "+v"(s[15]), "+v"(s[16]), "+v"(s[17]), "+v"(s[18]), "+v"(s[19]), "+v"(s[20]), "+v"(s[21]), "+v"(s[22]), "+v"(s[23]), "+v"(s[24]), "+v"(s[25]), "+v"(s[26]), "+v"(s[27]), "+v"(s[28]), "+v"(s[29]), "+v"(s[30]), "+v"(s[31]), "+v"(s[32]), "+v"(s[33]), "+v"(s[34]), "+v"(s[35]),
+                 "+v"(l[0]), "+v"(l[1]), "+v"(l[2]), "+v"(l[3]), "+v"(l[4]), "+v"(l[5]), "+v"(l[6]), "+v"(l[7]), "+v"(l[8]), "+v"(l[9]), "+v"(l[10]), "+v"(l[11]), "+v"(l[12]), "+v"(l[13]), "+v"(l[14]), "+v"(l[15]), "+v"(l[16]), "+v"(l[17]));
+  } else if constexpr (NS == 48 && NL == 9) {
+    asm volatile("" : "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3]), "+v"(s[4]), "+v"(s[5]), "+v"(s[6]), "+v"(s[7]), "+v"(s[8]), "+v"(s[9]), "+v"(s[10]), "+v"(s[11]), "+v"(s[12]), "+v"(s[13]), "+v"(s[14]), "+v"(s[15]), "+v"(s[16]), "+v"(s[17]), "+v"(s[18]), "+v"(s[19]), "+v"(s[20]), "+v"(s[21]), "+v"(s[22]), "+v"(s[23]), "+v"(s[24]), "+v"(s[25]), "+v"(s[26]), "+v"(s[27]), "+v"(s[28]), "+v"(s[29]), "+v"(s[30]), "+v"(s[31]), "+v"(s[32]), "+v"(s[33]), "+v"(s[34]), "+v"(s[35]), "+v"(s[36]), "+v"(s[37]), "+v"(s[38]), "+v"(s[39]), "+v"(s[40]), "+v"(s[41]), "+v"(s[42]), "+v"(s[43]), "+v"(s[44]), "+v"(s[45]), "+v"(s[46]), "+v"(s[47]),
+                 "+v"(l[0]), "+v"(l[1]), "+v"(l[2]), "+v"(l[3]), "+v"(l[4]), "+v"(l[5]), "+v"(l[6]), "+v"(l[7]), "+v"(l[8]));
+  } else if constexpr (NS == 48 && NL == 18) {
+    asm volatile("" : "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3]), "+v"(s[4]), "+v"(s[5]), "+v"(s[6]), "+v"(s[7]), "+v"(s[8]), "+v"(s[9]), "+v"(s[10]), "+v"(s[11]), "+v"(s[12]), "+v"(s[13]), "+v"(s[14]), "+v"(s[15]), "+v"(s[16]), "+v"(s[17]), "+v"(s[18]), "+v"(s[19]), "+v"(s[20]), "+v"(s[21]), "+v"(s[22]), "+v"(s[23]), "+v"(s[24]), "+v"(s[25]), "+v"(s[26]), "+v"(s[27]), "+v"(s[28]), "+v"(s[29]), "+v"(s[30]), "+v"(s[31]), "+v"(s[32]), "+v"(s[33]), "+v"(s[34]), "+v"(s[35]), "+v"(s[36]), "+v"(s[37]), "+v"(s[38]), "+v"(s[39]), "+v"(s[40]), "+v"(s[41]), "+v"(s[42]), "+v"(s[43]), "+v"(s[44]), "+v"(s[45]), "+v"(s[46]), "+v"(s[47]),
+                 "+v"(l[0]), "+v"(l[1]), "+v"(l[2]), "+v"(l[3]), "+v"(l[4]), "+v"(l[5]), "+v"(l[6]), "+v"(l[7]), "+v"(l[8]), "+v"(l[9]), "+v"(l[10]), "+v"(l[11]), "+v"(l[12]), "+v"(l[13]), "+v"(l[14]), "+v"(l[15]), "+v"(l[16]), "+v"(l[17]));
+  } else if constexpr (NS == 72 && NL == 9) {
+    asm volatile("" : "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3]), "+v"(s[4]), "+v"(s[5]), "+v"(s[6]), "+v"(s[7]), "+v"(s[8]), "+v"(s[9]), "+v"(s[10]), "+v"(s[11]), "+v"(s[12]), "+v"(s[13]), "+v"(s[14]), "+v"(s[15]), "+v"(s[16]), "+v"(s[17]), "+v"(s[18]), "+v"(s[19]), "+v"(s[20]), "+v"(s[21]), "+v"(s[22]), "+v"(s[23]), "+v"(s[24]), "+v"(s[25]), "+v"(s[26]), "+v"(s[27]), "+v"(s[28]), "+v"(s[29]), "+v"(s[30]), "+v"(s[31]), "+v"(s[32]), "+v"(s[33]), "+v"(s[34]), "+v"(s[35]), "+v"(s[36]), "+v"(s[37]), "+v"(s[38]), "+v"(s[39]), "+v"(s[40]), "+v"(s[41]), "+v"(s[42]), "+v"(s[43]), "+v"(s[44]), "+v"(s[45]), "+v"(s[46]), "+v"(s[47]), "+v"(s[48]), "+v"(s[49]), "+v"(s[50]), "+v"(s[51]), "+v"(s[52]), "+v"(s[53]), "+v"(s[54]), "+v"(s[55]), "+v"(s[56]), "+v"(s[57]), "+v"(s[58]), "+v"(s[59]), "+v"(s[60]), "+v"(s[61]), "+v"(s[62]), "+v"(s[63]), "+v"(s[64]), "+v"(s[65]), "+v"(s[66]), "+v"(s[67]), "+v"(s[68]), "+v"(s[69]), "+v"(s[70]), "+v"(s[71]),
+                 "+v"(l[0]), "+v"(l[1]), "+v"(l[2]), "+v"(l[3]), "+v"(l[4]), "+v"(l[5]), "+v"(l[6]), "+v"(l[7]), "+v"(l[8]));
+  } else if constexpr (NS == 72 && NL == 18) {
+    asm volatile("" : "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3]), "+v"(s[4]), "+v"(s[5]), "+v"(s[6]), "+v"(s[7]), "+v"(s[8]), "+v"(s[9]), "+v"(s[10]), "+v"(s[11]), "+v"(s[12]), "+v"(s[13]), "+v"(s[14]), "+v"(s[15]), "+v"(s[16]), "+v"(s[17]), "+v"(s[18]), "+v"(s[19]), "+v"(s[20]), "+v"(s[21]), "+v"(s[22]), "+v"(s[23]), "+v"(s[24]), "+v"(s[25]), "+v"(s[26]), "+v"(s[27]), "+v"(s[28]), "+v"(s[29]), "+v"(s[30]), "+v"(s[31]), "+v"(s[32]), "+v"(s[33]), "+v"(s[34]), "+v"(s[35]), "+v"(s[36]), "+v"(s[37]), "+v"(s[38]), "+v"(s[39]), "+v"(s[40]), "+v"(s[41]), "+v"(s[42]), "+v"(s[43]), "+v"(s[44]), "+v"(s[45]), "+v"(s[46]), "+v"(s[47]), "+v"(s[48]), "+v"(s[49]), "+v"(s[50]), "+v"(s[51]), "+v"(s[52]), "+v"(s[53]), "+v"(s[54]), "+v"(s[55]), "+v"(s[56]), "+v"(s[57]), "+v"(s[58]), "+v"(s[59]), "+v"(s[60]), "+v"(s[61]), "+v"(s[62]), "+v"(s[63]), "+v"(s[64]), "+v"(s[65]), "+v"(s[66]), "+v"(s[67]), "+v"(s[68]), "+v"(s[69]), "+v"(s[70]), "+v"(s[71]),
+                 "+v"(l[0]), "+v"(l[1]), "+v"(l[2]), "+v"(l[3]), "+v"(l[4]), "+v"(l[5]), "+v"(l[6]), "+v"(l[7]), "+v"(l[8]), "+v"(l[9]), "+v"(l[10]), "+v"(l[11]), "+v"(l[12]), "+v"(l[13]), "+v"(l[14]), "+v"(l[15]), "+v"(l[16]), "+v"(l[17]));
+  } else if constexpr (NS == 96 && NL == 9) {
+    asm volatile("" : "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3]), "+v"(s[4]), "+v"(s[5]), "+v"(s[6]), "+v"(s[7]), "+v"(s[8]), "+v"(s[9]), "+v"(s[10]), "+v"(s[11]), "+v"(s[12]), "+v"(s[13]), "+v"(s[14]), "+v"(s[15]), "+v"(s[16]), "+v"(s[17]), "+v"(s[18]), "+v"(s[19]), "+v"(s[20]), "+v"(s[21]), "+v"(s[22]), "+v"(s[23]), "+v"(s[24]), "+v"(s[25]), "+v"(s[26]), "+v"(s[27]), "+v"(s[28]), "+v"(s[29]), "+v"(s[30]), "+v"(s[31]), "+v"(s[32]), "+v"(s[33]), "+v"(s[34]), "+v"(s[35]), "+v"(s[36]), "+v"(s[37]), "+v"(s[38]), "+v"(s[39]), "+v"(s[40]), "+v"(s[41]), "+v"(s[42]), "+v"(s[43]), "+v"(s[44]), "+v"(s[45]), "+v"(s[46]), "+v"(s[47]), "+v"(s[48]), "+v"(s[49]), "+v"(s[50]), "+v"(s[51]), "+v"(s[52]), "+v"(s[53]), "+v"(s[54]), "+v"(s[55]), "+v"(s[56]), "+v"(s[57]), "+v"(s[58]), "+v"(s[59]), "+v"(s[60]), "+v"(s[61]), "+v"(s[62]), "+v"(s[63]), "+v"(s[64]), "+v"(s[65]), "+v"(s[66]), "+v"(s[67]), "+v"(s[68]), "+v"(s[69]), "+v"(s[70]), "+v"(s[71]), "+v"(s[72]), "+v"(s[73]), "+v"(s[74]), "+v"(s[75]), "+v"(s[76]), "+v"(s[77]), "+v"(s[78]), "+v"(s[79]), "+v"(s[80]), "+v"(s[81]), "+v"(s[82]), "+v"(s[83]), "+v"(s[84]), "+v"(s[85]), "+v"(s[86]), "+v"(s[87]), "+v"(s[88]), "+v"(s[89]), "+v"(s[90]), "+v"(s[91]), "+v"(s[92]), "+v"(s[93]), "+v"(s[94]), "+v"(s[95]),
+                 "+v"(l[0]), "+v"(l[1]), "+v"(l[2]), "+v"(l[3]), "+v"(l[4]), "+v"(l[5]), "+v"(l[6]), "+v"(l[7]), "+v"(l[8]));
+  } else if constexpr (NS == 96 && NL == 18) {
+    asm volatile("" : "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3]), "+v"(s[4]), "+v"(s[5]), "+v"(s[6]), "+v"(s[7]), "+v"(s[8]), "+v"(s[9]), "+v"(s[10]), "+v"(s[11]), "+v"(s[12]), "+v"(s[13]), "+v"(s[14]), "+v"(s[15]), "+v"(s[16]), "+v"(s[17]), "+v"(s[18]), "+v"(s[19]), "+v"(s[20]), "+v"(s[21]), "+v"(s[22]), "+v"(s[23]), "+v"(s[24]), "+v"(s[25]), "+v"(s[26]), "+v"(s[27]), "+v"(s[28]), "+v"(s[29]), "+v"(s[30]), "+v"(s[31]), "+v"(s[32]), "+v"(s[33]), "+v"(s[34]), "+v"(s[35]), "+v"(s[36]), "+v"(s[37]), "+v"(s[38]), "+v"(s[39]), "+v"(s[40]), "+v"(s[41]), "+v"(s[42]), "+v"(s[43]), "+v"(s[44]), "+v"(s[45]), "+v"(s[46]), "+v"(s[47]), "+v"(s[48]), "+v"(s[49]), "+v"(s[50]), "+v"(s[51]), "+v"(s[52]), "+v"(s[53]), "+v"(s[54]), "+v"(s[55]), "+v"(s[56]), "+v"(s[57]), "+v"(s[58]), "+v"(s[59]), "+v"(s[60]), "+v"(s[61]), "+v"(s[62]), "+v"(s[63]), "+v"(s[64]), "+v"(s[65]), "+v"(s[66]), "+v"(s[67]), "+v"(s[68]), "+v"(s[69]), "+v"(s[70]), "+v"(s[71]), "+v"(s[72]), "+v"(s[73]), "+v"(s[74]), "+v"(s[75]), "+v"(s[76]), "+v"(s[77]), "+v"(s[78]), "+v"(s[79]), "+v"(s[80]), "+v"(s[81]), "+v"(s[82]), "+v"(s[83]), "+v"(s[84]), "+v"(s[85]), "+v"(s[86]), "+v"(s[87]), "+v"(s[88]), "+v"(s[89]), "+v"(s[90]), "+v"(s[91]), "+v"(s[92]), "+v"(s[93]), "+v"(s[94]), "+v"(s[95]),
+                 "+v"(l[0]), "+v"(l[1]), "+v"(l[2]), "+v"(l[3]), "+v"(l[4]), "+v"(l[5]), "+v"(l[6]), "+v"(l[7]), "+v"(l[8]), "+v"(l[9]), "+v"(l[10]), "+v"(l[11]), "+v"(l[12]), "+v"(l[13]), "+v"(l[14]), "+v"(l[15]), "+v"(l[16]), "+v"(l[17]));
+  } else {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) asm volatile("" : "+v"(s[i]));
+#pragma unroll
+    for (int i = 0; i < NL; ++i) asm volatile("" : "+v"(l[i]));
+  }
+}
+
+template <int PIN, int PL, int C>
+struct HopData {
+  typename RawT<PIN>::T sp[C * 12 * RawT<PIN>::per];   // column-major: column q at q * 12 * per
+  typename RawT<PL>::T lk[9 * RawT<PL>::per];
+  float sc[C];
+};
+
+template <int PIN, int PL, int C, int MU>
+__device__ __forceinline__ void hop_load(int sn, int ls, const typename Store<PIN>::Elem* __restrict__ in,
+                                         const float* __restrict__ in_s, const LinkElem<PL>* __restrict__ U,
+                                         int L, int col0, HopData<PIN, PL, C>& d) {
+  // the link first: loads complete in order, and the arithmetic on the first
+  // spinor elements needs the link
+  const LinkElem<PL>* lp = U + ((size_t)ls * 4 + MU) * 9;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) raw_split<PL>(lp[e], &d.lk[e * RawT<PL>::per]);
 #pragma unroll
   for (int q = 0; q < C; ++q) {
     const size_t base = (size_t)sn * 12 * L + col0 + q;
+#pragma unroll
+    for (int e = 0; e < 12; ++e) raw_split<PIN>(in[base + (size_t)e * L], &d.sp[(q * 12 + e) * RawT<PIN>::per]);
+    if constexpr (Store<PIN>::scaled) d.sc[q] = in_s[(size_t)sn * L + col0 + q];
+  }
+}
+
+// With one column per thread the loads of a hop are issued together anyway,
+// and consuming each value as it arrives overlaps the tail of the loads with
+// arithmetic: pin only from two columns on.
+template <int PIN, int PL, int C>
+__device__ __forceinline__ void hop_pin(HopData<PIN, PL, C>& d) {
+  if constexpr (C > 1) pin_regs(d.sp, d.lk);
+}
+
+// The hop's arithmetic on loaded data.
+template <int PIN, int PL, int C, int HOPS, int MU, int FWD, typename R>
+__device__ __forceinline__ void hop_compute(const GeomK& k, const SiteCtx& c, const HopData<PIN, PL, C>& d,
+                                            cplx<R> (&acc)[4][3][C]) {
+  const bool wrap = FWD ? (c.x[MU] == k.g.d[MU] - 1) : (c.x[MU] == 0);
+  cplx<R> ph = cmake<R>((R)1, (R)0);
+  if (HOPS != INSIDE && wrap) ph = cmake<R>((R)k.g.ph[MU][0], (R)(FWD ? k.g.ph[MU][1] : -k.g.ph[MU][1]));
+  Mat3<R> u;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) u.m[a][b] = raw_join<PL, R>(&d.lk[(a * 3 + b) * RawT<PL>::per]);
+  constexpr SpinRule sr = spin_rule(MU, FWD);
+#pragma unroll
+  for (int q = 0; q < C; ++q) {
     cplx<R> p[4][3];
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        auto v = Store<PIN>::ld(in, base + (size_t)(3 * sp + a) * L);
-        p[sp][a] = cmake<R>((R)v.re, (R)v.im);
-      }
+      for (int a = 0; a < 3; ++a) p[sp][a] = raw_join<PIN, R>(&d.sp[(q * 12 + 3 * sp + a) * RawT<PIN>::per]);
     if constexpr (Store<PIN>::scaled) {
-      R sc = (R)in_s[(size_t)sn * L + col0 + q];
+      const R sc = (R)d.sc[q];
 #pragma unroll
       for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -110,8 +240,12 @@ __device__ __forceinline__ void hop_one(const GeomK& k, const SiteCtx& c,
       acc[3][a][q] = acc[3][a][q] + unit_mul<sr.B1>(sr.Q1 ? x1[a] : x0[a]);
     }
   }
-  // materialise the accumulators at the hop boundary (otherwise the additions
-  // are deferred and every hop's partial result stays live)
+}
+
+// Materialise the accumulators at a hop boundary (otherwise the additions are
+// deferred and every hop's partial result stays live) and pass the token on.
+template <int C, typename R>
+__device__ __forceinline__ void hop_settle(cplx<R> (&acc)[4][3][C], R& token) {
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -121,27 +255,56 @@ __device__ __forceinline__ void hop_one(const GeomK& k, const SiteCtx& c,
   token = acc[0][0][0].re;
 }
 
-// Both hops of direction MU.
-template <int PIN, int PL, int C, int ORDER, int HOPS, int MU, typename R>
+template <int PIN, int PL, int C, int ORDER, int HOPS, int MU, int FWD, typename R>
+__device__ __forceinline__ void hop_body(const GeomK& k, const SiteCtx& c, int sn, int ls,
+                                         const typename Store<PIN>::Elem* __restrict__ in,
+                                         const float* __restrict__ in_s,
+                                         const LinkElem<PL>* __restrict__ U, int L, int col0,
+                                         cplx<R> (&acc)[4][3][C], R& token) {
+  HopData<PIN, PL, C> d;
+  hop_load<PIN, PL, C, MU>(sn, ls, in, in_s, U, L, col0, d);
+  hop_pin(d);
+  hop_compute<PIN, PL, C, HOPS, MU, FWD, R>(k, c, d, acc);
+  hop_settle(acc, token);
+}
+
+// Both hops of direction MU.  PAIR: the backward hop's addresses do not wait
+// for the forward hop, so both hops' loads can be in flight together.
+template <int PIN, int PL, int C, int ORDER, int HOPS, int MU, typename R, bool PAIR = false>
 __device__ __forceinline__ void hop_dir(const GeomK& k, const SiteCtx& c, const typename Store<PIN>::Elem* in,
                                         const float* in_s, const LinkElem<PL>* U, int L, int col0,
                                         cplx<R> (&acc)[4][3][C], R& token) {
-  hop_one<PIN, PL, C, ORDER, HOPS, MU, 1, R>(k, c, in, in_s, U, L, col0, acc, token);
-  hop_one<PIN, PL, C, ORDER, HOPS, MU, 0, R>(k, c, in, in_s, U, L, col0, acc, token);
+  if constexpr (PAIR) {
+    const bool sf = hop_skipped<ORDER, HOPS, MU, 1>(k, c), sb = hop_skipped<ORDER, HOPS, MU, 0>(k, c);
+    int snf = neighbour<ORDER>(k, c, MU, 1), snb = neighbour<ORDER>(k, c, MU, -1);
+    int lsf = c.s, lsb = snb;
+    asm volatile("" : "+v"(snf), "+v"(lsf), "+v"(snb), "+v"(lsb) : "v"(token));
+    HopData<PIN, PL, C> df, db;
+    if (!sf) hop_load<PIN, PL, C, MU>(snf, lsf, in, in_s, U, L, col0, df);
+    if (!sb) hop_load<PIN, PL, C, MU>(snb, lsb, in, in_s, U, L, col0, db);
+    if (!sf) hop_pin(df);
+    if (!sb) hop_pin(db);
+    if (!sf) hop_compute<PIN, PL, C, HOPS, MU, 1, R>(k, c, df, acc);
+    if (!sb) hop_compute<PIN, PL, C, HOPS, MU, 0, R>(k, c, db, acc);
+    hop_settle(acc, token);
+  } else {
+    hop_one<PIN, PL, C, ORDER, HOPS, MU, 1, R>(k, c, in, in_s, U, L, col0, acc, token);
+    hop_one<PIN, PL, C, ORDER, HOPS, MU, 0, R>(k, c, in, in_s, U, L, col0, acc, token);
+  }
 }
 
 // All eight hops.
-template <int PIN, int PL, int C, int ORDER, int HOPS, typename R>
+template <int PIN, int PL, int C, int ORDER, int HOPS, typename R, bool PAIR = false>
 __device__ __forceinline__ void hop_sum(const GeomK& k, const SiteCtx& c,
                                         const typename Store<PIN>::Elem* __restrict__ in,
                                         const float* __restrict__ in_s,
                                         const LinkElem<PL>* __restrict__ U, int L, int col0,
                                         cplx<R> (&acc)[4][3][C]) {
   R token = 0;
-  hop_dir<PIN, PL, C, ORDER, HOPS, 0, R>(k, c, in, in_s, U, L, col0, acc, token);
-  hop_dir<PIN, PL, C, ORDER, HOPS, 1, R>(k, c, in, in_s, U, L, col0, acc, token);
-  hop_dir<PIN, PL, C, ORDER, HOPS, 2, R>(k, c, in, in_s, U, L, col0, acc, token);
-  hop_dir<PIN, PL, C, ORDER, HOPS, 3, R>(k, c, in, in_s, U, L, col0, acc, token);
+  hop_dir<PIN, PL, C, ORDER, HOPS, 0, R, PAIR>(k, c, in, in_s, U, L, col0, acc, token);
+  hop_dir<PIN, PL, C, ORDER, HOPS, 1, R, PAIR>(k, c, in, in_s, U, L, col0, acc, token);
+  hop_dir<PIN, PL, C, ORDER, HOPS, 2, R, PAIR>(k, c, in, in_s, U, L, col0, acc, token);
+  hop_dir<PIN, PL, C, ORDER, HOPS, 3, R, PAIR>(k, c, in, in_s, U, L, col0, acc, token);
 }
 
 // The hops of group h when the eight hops are split over P wave-uniform
@@ -172,7 +335,7 @@ __device__ __forceinline__ void hop_group(int h, const GeomK& k, const SiteCtx& 
 }
 
 // Store one (site, column) spinor; P16 computes the per-(site, column) scale.
-template <int POUT, typename R>
+template <int POUT, typename R, bool NT = false>
 __device__ __forceinline__ void store_spinor(typename Store<POUT>::Elem* out, float* out_s,
                                              size_t base, int L, size_t sidx, cplx<R> (&v)[4][3]) {
   if constexpr (Store<POUT>::scaled) {
@@ -186,15 +349,20 @@ __device__ __forceinline__ void store_spinor(typename Store<POUT>::Elem* out, fl
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-      for (int a = 0; a < 3; ++a) Store<POUT>::st(out, base + (size_t)(3 * sp + a) * L, inv * v[sp][a]);
+      for (int a = 0; a < 3; ++a) {
+        if constexpr (NT) Store<POUT>::st_nt(out, base + (size_t)(3 * sp + a) * L, inv * v[sp][a]);
+        else Store<POUT>::st(out, base + (size_t)(3 * sp + a) * L, inv * v[sp][a]);
+      }
   } else {
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
-        Store<POUT>::st(out, base + (size_t)(3 * sp + a) * L,
-                        cplx<typename Store<POUT>::Real>{(typename Store<POUT>::Real)v[sp][a].re,
-                                                         (typename Store<POUT>::Real)v[sp][a].im});
+      for (int a = 0; a < 3; ++a) {
+        const cplx<typename Store<POUT>::Real> o{(typename Store<POUT>::Real)v[sp][a].re,
+                                                 (typename Store<POUT>::Real)v[sp][a].im};
+        if constexpr (NT) Store<POUT>::st_nt(out, base + (size_t)(3 * sp + a) * L, o);
+        else Store<POUT>::st(out, base + (size_t)(3 * sp + a) * L, o);
+      }
   }
 }
 
@@ -215,7 +383,7 @@ __device__ __forceinline__ void load_spinor(const typename Store<PIN>::Elem* in,
 // ---------------------------------------------------------------- kernels
 // Thread layout: threadIdx.x = column chunk (C columns each), threadIdx.y =
 // site within the block; blocks cover consecutive sites of the field order.
-template <int PIN, int POUT, int PL, int C, int ORDER, bool BLOCKED>
+template <int PIN, int POUT, int PL, int C, int ORDER, bool BLOCKED, bool PAIR = false>
 __global__ void __launch_bounds__(256) k_dslash(GeomK k, double kappa, int L,
                                                 const typename Store<PIN>::Elem* __restrict__ in,
                                                 const float* __restrict__ in_s,
@@ -239,7 +407,7 @@ __global__ void __launch_bounds__(256) k_dslash(GeomK k, double kappa, int L,
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int q = 0; q < C; ++q) acc[sp][a][q] = cmake<R>(0, 0);
-  hop_sum<PIN, PL, C, ORDER, BLOCKED ? INSIDE : ALL, R>(k, c, in, in_s, U, L, col0, acc);
+  hop_sum<PIN, PL, C, ORDER, BLOCKED ? INSIDE : ALL, R, PAIR>(k, c, in, in_s, U, L, col0, acc);
   const R kap = (R)kappa;
 #pragma unroll
   for (int q = 0; q < C; ++q) {
@@ -250,7 +418,8 @@ __global__ void __launch_bounds__(256) k_dslash(GeomK k, double kappa, int L,
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
       for (int a = 0; a < 3; ++a) v[sp][a] = v[sp][a] - kap * acc[sp][a][q];
-    store_spinor<POUT, R>(out, out_s, base, L, (size_t)s * L + col0 + q, v);
+    if (k.nt_store) store_spinor<POUT, R, true>(out, out_s, base, L, (size_t)s * L + col0 + q, v);
+    else store_spinor<POUT, R>(out, out_s, base, L, (size_t)s * L + col0 + q, v);
   }
 }
 
@@ -642,7 +811,7 @@ __device__ __forceinline__ void split_publish(const SplitSmem<R>& m, int h, int 
 
 // Store this group's spins of one (site, column); FP16 storage exchanges the
 // groups' maxima first so that all of them use the same scale.
-template <int POUT, int P, typename R>
+template <int POUT, int P, typename R, bool NT = false>
 __device__ __forceinline__ void split_store(const SplitSmem<R>& m, int h, int item, int IPB, bool active,
                                             typename Store<POUT>::Elem* out, float* out_s, size_t base, int L,
                                             size_t sidx, cplx<R> (&v)[4 / P][3]) {
@@ -664,16 +833,20 @@ __device__ __forceinline__ void split_store(const SplitSmem<R>& m, int h, int it
 #pragma unroll
     for (int t = 0; t < NS; ++t)
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
-        Store<POUT>::st(out, base + (size_t)(3 * (h * NS + t) + a) * L, inv * v[t][a]);
+      for (int a = 0; a < 3; ++a) {
+        if constexpr (NT) Store<POUT>::st_nt(out, base + (size_t)(3 * (h * NS + t) + a) * L, inv * v[t][a]);
+        else Store<POUT>::st(out, base + (size_t)(3 * (h * NS + t) + a) * L, inv * v[t][a]);
+      }
   } else {
     if (!active) return;
     using RO = typename Store<POUT>::Real;
 #pragma unroll
     for (int t = 0; t < NS; ++t)
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
-        Store<POUT>::st(out, base + (size_t)(3 * (h * NS + t) + a) * L, cplx<RO>{(RO)v[t][a].re, (RO)v[t][a].im});
+      for (int a = 0; a < 3; ++a) {
+        if constexpr (NT) Store<POUT>::st_nt(out, base + (size_t)(3 * (h * NS + t) + a) * L, cplx<RO>{(RO)v[t][a].re, (RO)v[t][a].im});
+        else Store<POUT>::st(out, base + (size_t)(3 * (h * NS + t) + a) * L, cplx<RO>{(RO)v[t][a].re, (RO)v[t][a].im});
+      }
   }
 }
 
@@ -728,7 +901,8 @@ __global__ void __launch_bounds__(768) k_dslash_split(GeomK k, double kappa, int
   for (int t = 0; t < 4 / P; ++t)
 #pragma unroll
     for (int a = 0; a < 3; ++a) v[t][a] = v[t][a] - kap * tot[t][a];
-  split_store<POUT, P, R>(m, h, item, IPB, active, out, out_s, base, L, sidx, v);
+  if (k.nt_store) split_store<POUT, P, R, true>(m, h, item, IPB, active, out, out_s, base, L, sidx, v);
+  else split_store<POUT, P, R>(m, h, item, IPB, active, out, out_s, base, L, sidx, v);
   __syncthreads();   // the exchange area is reused by the next logical block
   }
 }
@@ -871,6 +1045,7 @@ GeomK make_geomk(const Geom& g) {
   k.fnd0 = make_fastdiv(g.nd[0]);
   for (int m = 0; m < 4; ++m) k.fnd[m] = make_fastdiv(g.nd[m]);
   k.fVb = make_fastdiv(g.Vb);
+  k.nt_store = 0;
   k.lstride[0] = 1;
   k.stride[0] = 1;
   for (int m = 1; m < 4; ++m) {
@@ -958,11 +1133,13 @@ static int dslash_split_launch(const mbbs_lattice_s* lat, int L, int order, bool
   using EL = LinkElem<PL>;
   const size_t smem = split_smem_bytes(PL, P, S, L);
   dim3 blk(S * L, P), grd(split_grid(lat, PL, P, S, L, ceil_div(n, S)));
+  GeomK gk = lat->gk;
+  gk.nt_store = lat->nt_store[PL];
 #define SL(ORD, BLK)                                                                                    \
   do {                                                                                                  \
     auto fn = k_dslash_split<PIN, POUT, PL, ORD, BLK, P>;                                               \
     allow_lds((const void*)fn);                                                                         \
-    hipLaunchKernelGGL(fn, grd, blk, smem, st, lat->gk, lat->kappa, L, (const EI*)in, in_s, (EO*)out,   \
+    hipLaunchKernelGGL(fn, grd, blk, smem, st, gk, lat->kappa, L, (const EI*)in, in_s, (EO*)out,        \
                        out_s, (const EL*)U, s0, n, S, frozen);                                          \
   } while (0)
   if (order == LEX) { if (blocked) SL(LEX, true); else SL(LEX, false); }
@@ -985,12 +1162,19 @@ static int dslash_dispatch_order(const mbbs_lattice_s* lat, int L, int order, bo
   using EI = typename Store<PIN>::Elem;
   using EO = typename Store<POUT>::Elem;
   using EL = LinkElem<PL>;
+  GeomK gk = lat->gk;
+  gk.nt_store = lat->nt_store[PL];
 #define MBBS_LAUNCH(ORD, BLK)                                                                   \
   hipLaunchKernelGGL((k_dslash<PIN, POUT, PL, C, ORD, BLK>), grd, blk, (size_t)lat->lds_pad_kb * 1024, st,     \
-                     lat->gk, lat->kappa, L,                                                                \
+                     gk, lat->kappa, L,                                                                     \
                      (const EI*)in, in_s, (EO*)out, out_s, (const EL*)U, s0, n, pl.bpt, pl.ngroups, frozen)
   if (order == LEX) {
-    if (blocked) MBBS_LAUNCH(LEX, true); else MBBS_LAUNCH(LEX, false);
+    if (blocked) MBBS_LAUNCH(LEX, true);
+    else if (lat->hop_pair[PL])
+      hipLaunchKernelGGL((k_dslash<PIN, POUT, PL, C, LEX, false, true>), grd, blk, (size_t)lat->lds_pad_kb * 1024, st,
+                         gk, lat->kappa, L, (const EI*)in, in_s, (EO*)out, out_s, (const EL*)U, s0, n, pl.bpt,
+                         pl.ngroups, frozen);
+    else MBBS_LAUNCH(LEX, false);
   } else {
     if (blocked) MBBS_LAUNCH(DM, true); else MBBS_LAUNCH(DM, false);
   }

@@ -65,6 +65,7 @@ struct GeomK {
   FastDiv fVb;       // block volume
   int lstride[4];    // local strides inside a domain
   int stride[4];     // lexicographic strides
+  int nt_store;      // operator output written with nontemporal stores
 };
 GeomK make_geomk(const Geom& g);
 
@@ -99,6 +100,8 @@ struct mbbs_lattice_s {
   int split[3] = {0, 0, 0};  // hop groups per site (0/1: one thread does all 8 hops)
   int persist_blocks = 0;    // resident blocks per CU of persistent split kernels (0: not persistent)
   int mr_fused = -1;         // SAP domain solve in one launch per colour: -1 auto, 0 off, 1 on
+  int hop_pair[3] = {0, 0, 0};  // operator: both hops of a direction in flight at once
+  int nt_store[3] = {0, 0, 0};  // operator: nontemporal output stores
 };
 
 namespace mbbs {

@@ -130,7 +130,8 @@ def test_dslash_full_size_sampled():
 
 
 def test_tuning_is_bit_identical():
-    """Launch shapes chosen by the autotuner never change results."""
+    """Launch shapes, paired hops and nontemporal stores chosen by the
+    autotuner never change results."""
     from paper_1104_0737_amd import autotune
     dims, L = (8, 8, 8, 8), 12
     V = 4096
@@ -139,17 +140,17 @@ def test_tuning_is_bit_identical():
     with gu.Lattice(dims, (4, 4, 4, 4), U, 0.11) as lat:
         for prec in (0, 1, 2):
             ref = None
-            for g, t, sp in autotune.candidates(L, prec):
-                if sp:
+            settings = [c + (0, 0) for c in autotune.candidates(L, prec)] + autotune.operator_candidates(L, prec)
+            for setting in settings:
+                if setting[2]:
                     continue          # the split kernels sum the hops in another order
-                B.mbbs_lattice_tune(lat.h, B.TUNE_GROUP[prec], g)
-                B.mbbs_lattice_tune(lat.h, B.TUNE_BLOCK_THREADS, t)
+                autotune.apply(lat.h, prec, setting)
                 Y = torch.empty_like(X)
                 B.mbbs_apply_dirac(lat.h, L, X, Y, prec)
                 out = gu.host(Y)
                 if ref is None:
                     ref = out
-                assert out.tobytes() == ref.tobytes(), (prec, g, t)
+                assert out.tobytes() == ref.tobytes(), (prec, setting)
 
 
 @pytest.mark.parametrize("split", [2, 4])
