@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--profile", type=int, default=1, help="event-time kernel classes in the timed solves")
     ap.add_argument("--sap-prec", choices=("fp32", "fp16s"), default="fp32",
                     help="storage precision of the SAP preconditioner in the mixed solve")
+    ap.add_argument("--domain-solver", choices=("mr", "ssor"), default="mr",
+                    help="SAP domain solver: nmr MR steps, or SSOR (N_SSOR, omega) as in the paper")
+    ap.add_argument("--nssor", type=int, default=1)
+    ap.add_argument("--ssor-omega", type=float, default=1.26)
     ap.add_argument("--batched", action="store_true",
                     help="48 independent systems of uneven size solved together (batched form)")
     ap.add_argument("--graph-iters", type=int, default=4)
@@ -57,10 +61,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(cls, L, dims, block, ncy, nmr):
+def algorithmic_bytes(cls, L, dims, block, ncy, nmr, sap_prec="fp32", nssor=1):
     """Compulsory HBM bytes of one launch of a kernel class, averaged over the
-    launches of one SAP application where they differ (FP32 SAP storage:
-    8-byte complex, 72-byte link; FP64 outer: 16-byte complex, 144-byte link).
+    launches of one SAP application where they differ.  SAP storage: FP32
+    8-byte complex and 72-byte link, or FP16 storage 4-byte complex plus one
+    4-byte scale per site and column and 36-byte link; psi is FP32; the outer
+    operator is FP64 (16-byte complex, 144-byte link).
 
     dslash64   whole lattice: read X, write Y, 4 links per site.
     mr_dslash  one colour (V/2 sites): read r, write w, 4 links per site.
@@ -70,27 +76,38 @@ def algorithmic_bytes(cls, L, dims, block, ncy, nmr):
     sap_resid  one colour: read eta, write r; except on the first half-sweep
                also read psi on the colour and on the other colour's sites
                that touch it (a fraction f of them), and 4 links per site.
+    ssor       one colour, all sweeps: N_SSOR = 1 moves 11 storage fields
+               (r->a, a->b, a,b->r, a,b,r->b) and psi, 4 links per site and
+               sweep; N_SSOR = 0 moves 4 (r->a, a->b) and psi, 2 sweeps.
     """
     V = int(np.prod(dims))
     Vh = V // 2
-    s = 12 * L * 8                         # one FP32 spinor row block per site
+    sp = 12 * L * 8 if sap_prec == "fp32" else 12 * L * 4 + 4 * L   # storage spinor row block
+    ps = 12 * L * 8                                                  # psi (FP32)
+    lk = 72 if sap_prec == "fp32" else 36
     if cls == "dslash64":
         return V * (48 * L + 72) * 8
     if cls == "mr_dslash":
-        return Vh * (2 * s + 4 * 72)
+        return Vh * (2 * sp + 4 * lk)
     if cls == "mr_update":
         tot = 0
         for cy in range(ncy):
             for it in range(nmr):
-                streams = 2 + (0 if (cy == 0 and it == 0) else 1) + (2 if it + 1 < nmr else 0)
-                tot += 2 * streams * Vh * s      # both colours
+                b = sp + ps + (0 if (cy == 0 and it == 0) else ps) + (2 * sp if it + 1 < nmr else 0)
+                tot += 2 * Vh * b      # both colours
         return tot / (2 * ncy * nmr)
     if cls == "sap_resid":
         inner = int(np.prod([b - 2 for b in block]))
         f = 1 - inner / int(np.prod(block))  # sites of a domain that touch another domain
-        tot = 2 * (2 * Vh * s)                           # first cycle, colour 0 and 1: eta, r
-        tot += Vh * (f * s + 4 * 72)                     # first cycle, colour 1: psi of colour 0
-        tot += 2 * (ncy - 1) * Vh * (2 * s + (1 + f) * s + 4 * 72)
+        tot = 2 * (2 * Vh * sp)                          # first cycle, colour 0 and 1: eta, r
+        tot += Vh * (f * ps + 4 * lk)                    # first cycle, colour 1: psi of colour 0
+        tot += 2 * (ncy - 1) * Vh * (2 * sp + (1 + f) * ps + 4 * lk)
+        return tot / (2 * ncy)
+    if cls == "ssor":
+        fields, sweeps = (11, 4) if nssor == 1 else (4, 2)
+        tot = 0
+        for cy in range(ncy):
+            tot += 2 * Vh * (fields * sp + (1 if cy == 0 else 2) * ps + sweeps * 4 * lk)
         return tot / (2 * ncy)
     return None
 
@@ -214,7 +231,9 @@ def main():
 
     def run_solve(sap_prec, profile):
         p = B.mbbs_solve_params_default(tol=cfg.tol, sap_prec=sap_prec, ncy=cfg.ncy, nmr=cfg.nmr,
-                                        profile=profile, graph_iters=1)
+                                        profile=profile, graph_iters=1,
+                                        domain_solver=1 if args.domain_solver == "ssor" else 0,
+                                        nssor=args.nssor, ssor_omega=args.ssor_omega)
         ws = torch.empty(B.mbbs_solve_workspace_size(lat, L, p), dtype=torch.uint8, device=dev)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -260,6 +279,18 @@ def main():
                 "max_true_res": float(i64["true_res"].max()), "status": i64["status"]}
         log(f"  {dt64:.2f}s, {i64['iterations']} iterations")
 
+    # the paper's own domain solver (SSOR, N_SSOR = 1, omega = 1.26), once, for comparison
+    ssor_alt = None
+    if not args.no_fp64_solve and args.domain_solver == "mr":
+        log("SSOR-domain SAP solve")
+        args.domain_solver = "ssor"
+        dts, isr = run_solve(sap_prec, 0)
+        args.domain_solver = "mr"
+        ssor_alt = {"seconds": dts, "tts_per_rhs_s": dts / L, "iterations": isr["iterations"],
+                    "max_true_res": float(isr["true_res"].max()), "status": isr["status"],
+                    "nssor": args.nssor, "omega": args.ssor_omega}
+        log(f"  {dts:.2f}s, {isr['iterations']} iterations, max true residual {isr['true_res'].max():.2e}")
+
     # ------------------------------------------------------------ accounting
     it = infos[-1]["iterations"]
     Vh = V // 2
@@ -267,16 +298,19 @@ def main():
     n_sap = infos[-1]["n_sap"]
     # stencil site.RHS work per solve: outer operator, SAP residual (half
     # lattice per colour) and MR domain operator (half lattice per step)
-    per_sap = cfg.ncy * 2 * (1 + cfg.nmr) * Vh * L
+    if args.domain_solver == "ssor":
+        per_sap = cfg.ncy * 2 * (1 + (2 + 2 * args.nssor) / 2) * Vh * L   # a sweep applies 4 of the 8 hops
+    else:
+        per_sap = cfg.ncy * 2 * (1 + cfg.nmr) * Vh * L
     stencil_work = n_outer * V * L + n_sap * per_sap
     step_s = wall / args.steps
     value = stencil_work / step_s
     km = infos[-1]["kernel_ms"]
     kl = infos[-1]["kernel_launches"]
-    dominant = max(("dslash64", "mr_dslash", "mr_update", "sap_resid"), key=lambda c: km[c])
+    dominant = max(("dslash64", "mr_dslash", "mr_update", "sap_resid", "ssor"), key=lambda c: km[c])
     roof = None
     if args.profile and kl[dominant] > 0:
-        byl = algorithmic_bytes(dominant, L, dims, cfg.block, cfg.ncy, cfg.nmr)
+        byl = algorithmic_bytes(dominant, L, dims, cfg.block, cfg.ncy, cfg.nmr, args.sap_prec, args.nssor)
         avg_ms = km[dominant] / kl[dominant]
         ach = byl / (avg_ms * 1e-3) / 1e9
         roof = {"kernel": dominant, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
@@ -302,7 +336,10 @@ def main():
         "dtype": "f64+f32" if args.sap_prec == "fp32" else "f64+f32 (fp16 storage)",
         "data": "synthetic",
         "config": {"workload": f"{'x'.join(map(str, dims))} Wilson-Dirac, L={L} point sources, "
-                               f"SAP 8^4 domains ncy={cfg.ncy} nmr={cfg.nmr}, {args.sap_prec.upper()} SAP, "
+                               f"SAP 8^4 domains ncy={cfg.ncy} "
+                               + (f"nmr={cfg.nmr}" if args.domain_solver == "mr" else
+                                  f"SSOR N_SSOR={args.nssor} omega={args.ssor_omega}")
+                               + f", {args.sap_prec.upper()} SAP, "
                                f"tol {cfg.tol:g}",
                    "lattice": list(dims), "L": L, "kappa": cfg.kappa, "eps": cfg.eps,
                    "parallelism": "single GPU"},
@@ -312,6 +349,7 @@ def main():
                           "fp64_over_mixed": (fp64["tts_per_rhs_s"] / (step_s / L)) if fp64 else None},
         "fp64_solve": fp64,
         "other_sap_prec_solve": other,
+        "ssor_domain_solve": ssor_alt,
         "max_true_res": float(max(i["true_res"].max() for i in infos)),
         "dslash": dslash,
         "tuning": tuning,

@@ -89,11 +89,16 @@ int mbbs_lattice_destroy(mbbs_lattice_t lat);
  *  MBBS_TAB_DM_NEIGHBOUR V x 8 neighbours in domain-major positions: row i lists
  *                              the positions of the 8 neighbours of the site at
  *                              position i (what the SAP kernels compute)
+ *  MBBS_TAB_HYPERPLANE Vb + nh + 1  SSOR wavefront order: the Vb local indices
+ *                              sorted by h = l_0+l_1+l_2+l_3 (ties by local
+ *                              index), then the nh + 1 offsets of the
+ *                              hyperplanes h = 0 .. nh-1, nh = sum_mu (b_mu - 1) + 1
  * mbbs_lattice_table_size gives the entry count.  Errors: EINVAL. */
 enum {
   MBBS_TAB_COORD = 0, MBBS_TAB_NEIGHBOUR, MBBS_TAB_BOUNDARY, MBBS_TAB_PARITY,
   MBBS_TAB_EO, MBBS_TAB_DOMAIN, MBBS_TAB_COLOUR, MBBS_TAB_LOCAL,
-  MBBS_TAB_DM_INDEX, MBBS_TAB_DM_SITE, MBBS_TAB_LOCAL_NB, MBBS_TAB_DM_NEIGHBOUR, MBBS_TAB_COUNT
+  MBBS_TAB_DM_INDEX, MBBS_TAB_DM_SITE, MBBS_TAB_LOCAL_NB, MBBS_TAB_DM_NEIGHBOUR, MBBS_TAB_HYPERPLANE,
+  MBBS_TAB_COUNT
 };
 int mbbs_lattice_table_size(mbbs_lattice_t lat, int which, size_t* count);
 int mbbs_lattice_table(mbbs_lattice_t lat, int which, int32_t* out, size_t count);
@@ -177,6 +182,26 @@ int mbbs_sap_workspace_size(mbbs_lattice_t lat, int L, int prec, size_t* bytes);
 int mbbs_sap_apply(mbbs_lattice_t lat, int L, const double* X_dev, double* Y_dev,
                    int ncy, int nmr, int prec, void* ws_dev, size_t ws_bytes, void* stream);
 
+/* SAP with the SSOR domain inverse of Sec. 2.2 (SSOR equations) in place of
+ * MR: on each domain A_DD = 1 - Lf - Ub (Lf forward, Ub backward in-domain
+ * hops, the paper's L_EE and U_EE) and
+ *   B_DD = (1 - w Ub)^{-1} [sum_{j=0}^{nssor} (1 - A^S)^j] (1 - w Lf)^{-1},
+ *   A^S = (1/w)[(1 - w Lf)^{-1} + (1 - w Ub)^{-1} + (w - 2)(1 - w Lf)^{-1}(1 - w Ub)^{-1}].
+ * The triangular solves run as wavefronts over the hyperplanes
+ * l_0+l_1+l_2+l_3 = const of each domain (MBBS_TAB_HYPERPLANE), one
+ * workgroup per domain.  nssor is 0 or 1 (the paper uses 1), 0 < omega < 2.
+ * mbbs_ssor_workspace_size: device bytes for both calls below.
+ * mbbs_sap_apply_ssor: Y = M_SAP X with ncy cycles, as mbbs_sap_apply.
+ * mbbs_apply_ssor_blocked: Y = B X with B the block-diagonal SSOR inverse
+ * over all domains (both colours).  X, Y: FP64 N x L device blocks, not
+ * aliased; prec: storage precision of the sweeps (FP16 storage keeps psi
+ * in FP32).  Errors: EINVAL (arguments, workspace), EHIP. */
+int mbbs_ssor_workspace_size(mbbs_lattice_t lat, int L, int prec, size_t* bytes);
+int mbbs_sap_apply_ssor(mbbs_lattice_t lat, int L, const double* X, double* Y, int ncy, int nssor,
+                        double omega, int prec, void* ws, size_t ws_bytes, void* stream);
+int mbbs_apply_ssor_blocked(mbbs_lattice_t lat, int L, const double* X, double* Y, int nssor,
+                            double omega, int prec, void* ws, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------ block linear algebra */
 
 /* G = X^H Y, the L x L Gram matrix G[i*L + j] = sum_n conj(X[n,i]) Y[n,j]
@@ -215,11 +240,14 @@ typedef struct {
   int precond;         /* 1: SAP right preconditioner; 0: M = 1                   */
   int memsave;         /* 1: memory-saving form (Alg. 2); 0: Alg. 1               */
   int profile;         /* 1: time kernel classes with HIP events                  */
+  int domain_solver;   /* SAP domain solver: 0 = nmr MR steps, 1 = SSOR           */
+  int nssor;           /* SSOR correction terms N_SSOR (0 or 1)                   */
+  double ssor_omega;   /* SSOR relaxation, 0 < omega < 2                          */
 } mbbs_solve_params;
 
 /* Kernel classes timed when params.profile = 1. */
 enum { MBBS_K_DSLASH64 = 0, MBBS_K_SAP_RES, MBBS_K_MR_DSLASH, MBBS_K_MR_UPDATE,
-       MBBS_K_CONVERT, MBBS_K_GRAM, MBBS_K_UPDATE, MBBS_K_SMALL, MBBS_K_COUNT };
+       MBBS_K_CONVERT, MBBS_K_GRAM, MBBS_K_UPDATE, MBBS_K_SMALL, MBBS_K_SSOR, MBBS_K_COUNT };
 
 typedef struct {
   int status;                   /* return value of the call                        */

@@ -135,6 +135,22 @@ def local_neighbours(block) -> np.ndarray:
     return out
 
 
+def hyperplane_order(block):
+    """SSOR wavefront order inside a domain: local indices sorted by the
+    hyperplane h = l_0 + l_1 + l_2 + l_3 (ties by local index), and the
+    offsets of h = 0 .. H (H = sum_mu (b_mu - 1)).  A forward hop raises h by
+    one, so sites of one hyperplane never depend on each other in a
+    triangular sweep."""
+    bx, by, bz, bt = block
+    Vb = bx * by * bz * bt
+    l = np.arange(Vb)
+    h = l % bx + (l // bx) % by + (l // (bx * by)) % bz + l // (bx * by * bz)
+    order = np.argsort(h, kind="stable")
+    nh = sum(b - 1 for b in block) + 1
+    off = np.concatenate([[0], np.cumsum(np.bincount(h, minlength=nh))])
+    return order, off
+
+
 def check_domains(dims, block) -> None:
     """Raise ValueError unless every extent is even and 2-colourable by domains."""
     for d, b in zip(dims, block):

@@ -20,14 +20,15 @@ LIB_PATH = os.path.join(_HERE, "libmbbs.so")
 FP64, FP32, FP16S = 0, 1, 2
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, EBREAKDOWN = 0, 1, -1, -2, -3, -4
 TABLES = ("COORD", "NEIGHBOUR", "BOUNDARY", "PARITY", "EO", "DOMAIN", "COLOUR", "LOCAL",
-          "DM_INDEX", "DM_SITE", "LOCAL_NB", "DM_NEIGHBOUR")
-KERNEL_CLASSES = ("dslash64", "sap_resid", "mr_dslash", "mr_update", "convert", "gram", "update", "small")
+          "DM_INDEX", "DM_SITE", "LOCAL_NB", "DM_NEIGHBOUR", "HYPERPLANE")
+KERNEL_CLASSES = ("dslash64", "sap_resid", "mr_dslash", "mr_update", "convert", "gram", "update", "small", "ssor")
 
 EXPORTS = (
     "mbbs_lattice_create", "mbbs_lattice_destroy", "mbbs_lattice_tune", "mbbs_lattice_table_size",
     "mbbs_lattice_table",
     "mbbs_apply_dirac", "mbbs_apply_dirac_raw", "mbbs_convert_to", "mbbs_convert_from",
-    "mbbs_apply_blocked", "mbbs_sap_workspace_size", "mbbs_sap_apply", "mbbs_gram_workspace_size",
+    "mbbs_apply_blocked", "mbbs_sap_workspace_size", "mbbs_sap_apply", "mbbs_ssor_workspace_size",
+    "mbbs_sap_apply_ssor", "mbbs_apply_ssor_blocked", "mbbs_gram_workspace_size",
     "mbbs_gram", "mbbs_cholqr", "mbbs_lu_solve", "mbbs_solve_params_default",
     "mbbs_solve_workspace_size", "mbbs_solve", "mbbs_solve_batched_workspace_size",
     "mbbs_solve_batched", "mbbs_last_error",
@@ -44,15 +45,16 @@ class SolveParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("max_restarts", ctypes.c_int),
                 ("ncy", ctypes.c_int), ("nmr", ctypes.c_int), ("sap_prec", ctypes.c_int),
                 ("x0_is_guess", ctypes.c_int), ("qr_passes", ctypes.c_int), ("graph_iters", ctypes.c_int),
-                ("precond", ctypes.c_int), ("memsave", ctypes.c_int), ("profile", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("memsave", ctypes.c_int), ("profile", ctypes.c_int),
+                ("domain_solver", ctypes.c_int), ("nssor", ctypes.c_int), ("ssor_omega", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("n_dslash_outer", ctypes.c_longlong), ("n_sap", ctypes.c_longlong),
                 ("true_res", ctypes.POINTER(ctypes.c_double)), ("rec_res", ctypes.POINTER(ctypes.c_double)),
-                ("seconds", ctypes.c_double), ("kernel_ms", ctypes.c_double * 8),
-                ("kernel_launches", ctypes.c_longlong * 8)]
+                ("seconds", ctypes.c_double), ("kernel_ms", ctypes.c_double * len(KERNEL_CLASSES)),
+                ("kernel_launches", ctypes.c_longlong * len(KERNEL_CLASSES))]
 
 
 _lib = None
@@ -80,6 +82,9 @@ def lib():
             "mbbs_apply_blocked": (i, [vp, i, vp, vp, i, vp]),
             "mbbs_sap_workspace_size": (i, [vp, i, i, ctypes.POINTER(sz)]),
             "mbbs_sap_apply": (i, [vp, i, vp, vp, i, i, i, vp, sz, vp]),
+            "mbbs_ssor_workspace_size": (i, [vp, i, i, ctypes.POINTER(sz)]),
+            "mbbs_sap_apply_ssor": (i, [vp, i, vp, vp, i, i, d, i, vp, sz, vp]),
+            "mbbs_apply_ssor_blocked": (i, [vp, i, vp, vp, i, d, i, vp, sz, vp]),
             "mbbs_gram_workspace_size": (i, [sz, i, ctypes.POINTER(sz)]),
             "mbbs_gram": (i, [sz, i, vp, vp, vp, vp, sz, vp]),
             "mbbs_cholqr": (i, [sz, i, vp, vp, vp, i, vp, sz, vp]),
@@ -208,6 +213,24 @@ def mbbs_sap_apply(lat, L, X, Y, ncy, nmr, prec, ws, stream=None):
 
 
 # ----------------------------------------------------------------- block LA
+def mbbs_ssor_workspace_size(lat, L, prec):
+    n = ctypes.c_size_t()
+    _check(lib().mbbs_ssor_workspace_size(lat, L, prec, ctypes.byref(n)))
+    return n.value
+
+
+def mbbs_sap_apply_ssor(lat, L, X, Y, ncy, nssor, omega, prec, ws, stream=None):
+    return _check(lib().mbbs_sap_apply_ssor(lat, L, _dev(X, _c128()), _dev(Y, _c128()), ncy, nssor,
+                                            ctypes.c_double(omega), prec, _dev(ws), ws.numel() * ws.element_size(),
+                                            _stream(stream)))
+
+
+def mbbs_apply_ssor_blocked(lat, L, X, Y, nssor, omega, prec, ws, stream=None):
+    return _check(lib().mbbs_apply_ssor_blocked(lat, L, _dev(X, _c128()), _dev(Y, _c128()), nssor,
+                                                ctypes.c_double(omega), prec, _dev(ws),
+                                                ws.numel() * ws.element_size(), _stream(stream)))
+
+
 def mbbs_gram_workspace_size(N, L):
     n = ctypes.c_size_t()
     _check(lib().mbbs_gram_workspace_size(N, L, ctypes.byref(n)))

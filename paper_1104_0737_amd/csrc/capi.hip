@@ -1,5 +1,6 @@
 // C-ABI entry points for the operator, the SAP preconditioner and the block
 // linear algebra (the solver's own entry points live with the solver).
+#include <cmath>
 #include <vector>
 
 #include "blas.h"
@@ -96,6 +97,46 @@ extern "C" int mbbs_sap_apply(mbbs_lattice_t lat, int L, const double* X, double
   SapBuffers b;
   MBBS_TRY(sap_bind(lat, L, prec, ws, ws_bytes, &b));
   return sap_apply(lat, b, ncy, nmr, (const double2*)X, nullptr, (double2*)Y, nullptr, (hipStream_t)stream, nullptr);
+}
+
+static int ssor_args(mbbs_lattice_t lat, int L, int nssor, double omega, int prec) {
+  MBBS_CHECK(lat != nullptr, "null lattice");
+  MBBS_CHECK(L >= 1 && L <= 64, "L must be in 1..64");
+  MBBS_CHECK(nssor == 0 || nssor == 1, "N_SSOR must be 0 or 1");
+  MBBS_CHECK(std::isfinite(omega) && omega > 0 && omega < 2, "SSOR omega must lie in (0, 2)");
+  MBBS_CHECK(prec_ok(prec), "bad precision");
+  return MBBS_OK;
+}
+
+extern "C" int mbbs_ssor_workspace_size(mbbs_lattice_t lat, int L, int prec, size_t* bytes) {
+  MBBS_CHECK(lat && bytes, "null argument");
+  MBBS_CHECK(L >= 1 && L <= 64, "L must be in 1..64");
+  MBBS_CHECK(prec_ok(prec), "bad precision");
+  *bytes = sap_buffer_bytes(lat, L, prec, true);
+  return MBBS_OK;
+}
+
+extern "C" int mbbs_sap_apply_ssor(mbbs_lattice_t lat, int L, const double* X, double* Y, int ncy, int nssor,
+                                   double omega, int prec, void* ws, size_t ws_bytes, void* stream) {
+  MBBS_TRY(ssor_args(lat, L, nssor, omega, prec));
+  MBBS_CHECK(X && Y && X != Y, "null or aliased arguments");
+  MBBS_CHECK(ncy >= 1, "ncy must be >= 1");
+  SapBuffers b;
+  MBBS_TRY(sap_bind(lat, L, prec, ws, ws_bytes, &b, true));
+  b.nssor = nssor;
+  b.ssor_omega = omega;
+  return sap_apply(lat, b, ncy, 0, (const double2*)X, nullptr, (double2*)Y, nullptr, (hipStream_t)stream, nullptr);
+}
+
+extern "C" int mbbs_apply_ssor_blocked(mbbs_lattice_t lat, int L, const double* X, double* Y, int nssor,
+                                       double omega, int prec, void* ws, size_t ws_bytes, void* stream) {
+  MBBS_TRY(ssor_args(lat, L, nssor, omega, prec));
+  MBBS_CHECK(X && Y && X != Y, "null or aliased arguments");
+  SapBuffers b;
+  MBBS_TRY(sap_bind(lat, L, prec, ws, ws_bytes, &b, true));
+  b.nssor = nssor;
+  b.ssor_omega = omega;
+  return ssor_blocked_apply(lat, b, (const double2*)X, (double2*)Y, (hipStream_t)stream);
 }
 
 extern "C" int mbbs_gram_workspace_size(size_t N, int L, size_t* bytes) {

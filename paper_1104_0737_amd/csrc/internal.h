@@ -102,6 +102,13 @@ struct mbbs_lattice_s {
   int mr_fused = -1;         // SAP domain solve in one launch per colour: -1 auto, 0 off, 1 on
   int hop_pair[3] = {0, 0, 0};  // operator: both hops of a direction in flight at once
   int nt_store[3] = {0, 0, 0};  // operator: nontemporal output stores
+  // SSOR wavefront order inside a domain: local indices sorted by the
+  // hyperplane h = l_0 + l_1 + l_2 + l_3 (then by local index); hyperplane h
+  // holds entries hp_off[h] .. hp_off[h+1]-1 (device arrays)
+  int* hp_loc = nullptr;
+  int* hp_off = nullptr;
+  int nh = 0;          // number of hyperplanes, sum_mu (b_mu - 1) + 1
+  int hp_max = 0;      // sites in the largest hyperplane
 };
 
 namespace mbbs {
@@ -125,9 +132,26 @@ struct SapBuffers {
   void* psi;               // double2 or float2
   double* partial;         // per block, per column: (wr.re, wr.im, ww)
   double* omega;           // per domain-of-colour, per column: complex step
+  // domain solver: MR (ssor = 0) or SSOR with nssor correction terms and
+  // relaxation ssor_omega; SSOR needs one more field x2
+  int ssor = 0, nssor = 1;
+  double ssor_omega = 1.0;
+  void* x2 = nullptr; float* x2_s = nullptr;
 };
-size_t sap_buffer_bytes(const mbbs_lattice_s* lat, int L, int prec);
-int sap_bind(const mbbs_lattice_s* lat, int L, int prec, void* ws, size_t bytes, SapBuffers* b);
+size_t sap_buffer_bytes(const mbbs_lattice_s* lat, int L, int prec, bool ssor = false);
+int sap_bind(const mbbs_lattice_s* lat, int L, int prec, void* ws, size_t bytes, SapBuffers* b, bool ssor = false);
+// FP64 lexicographic block -> SAP storage of b.prec (dst, dst_s), optionally
+// right-multiplied by gam; SAP psi -> FP64 lexicographic block.
+int sap_to(const mbbs_lattice_s* lat, const SapBuffers& b, const double2* in, const double2* gam, void* dst,
+           float* dst_s, const int* frozen, hipStream_t st);
+int sap_from(const mbbs_lattice_s* lat, const SapBuffers& b, double2* out, const int* frozen, hipStream_t st);
+// SSOR domain inverse B on every domain of one colour: psi (+)= B r on those
+// domains (assign: psi = B r); r and w are overwritten.
+int ssor_colour(const mbbs_lattice_s* lat, const SapBuffers& b, int colour, bool assign, const int* frozen,
+                hipStream_t st);
+// out = B in on every domain (both colours), FP64 lexicographic blocks.
+int ssor_blocked_apply(const mbbs_lattice_s* lat, const SapBuffers& b, const double2* in, double2* out,
+                       hipStream_t st);
 // Full preconditioner application.  `in` is an FP64 lexicographic block;
 // if gam != nullptr, in is right-multiplied by the L x L matrix gam (device,
 // row-major) first.  out (FP64 lexicographic) receives psi.  `frozen` (device

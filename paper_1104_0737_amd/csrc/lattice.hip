@@ -5,6 +5,9 @@
 #include <cstring>
 #include <string>
 
+#include <algorithm>
+#include <vector>
+
 #include "internal.h"
 #include "sitectx.h"
 
@@ -103,11 +106,18 @@ size_t table_entries(const mbbs_lattice_s* lat, int which) {
     case MBBS_TAB_COORD: return 4 * V;
     case MBBS_TAB_NEIGHBOUR: case MBBS_TAB_DM_NEIGHBOUR: return 8 * V;
     case MBBS_TAB_LOCAL_NB: return 8 * (size_t)lat->g.Vb;
+    case MBBS_TAB_HYPERPLANE: return (size_t)lat->g.Vb + lat->nh + 1;
     default: return V;
   }
 }
 
 int build_table(const mbbs_lattice_s* lat, int which, int32_t* dev_out, hipStream_t st) {
+  if (which == MBBS_TAB_HYPERPLANE) {   // the arrays the SSOR kernels read
+    MBBS_HIP(hipMemcpyAsync(dev_out, lat->hp_loc, lat->g.Vb * sizeof(int), hipMemcpyDeviceToDevice, st));
+    MBBS_HIP(hipMemcpyAsync(dev_out + lat->g.Vb, lat->hp_off, (lat->nh + 1) * sizeof(int), hipMemcpyDeviceToDevice,
+                            st));
+    return MBBS_OK;
+  }
   const int n = which == MBBS_TAB_LOCAL_NB ? lat->g.Vb : lat->g.V;
   hipLaunchKernelGGL(k_tables, dim3(ceil_div(n, 256)), dim3(256), 0, st, lat->gk, which, dev_out);
   MBBS_HIP(hipGetLastError());
@@ -191,6 +201,34 @@ static int lattice_create(const int dims[4], const int block[4], const double* U
     set_error("link conversion failed");
     return fail(MBBS_EHIP);
   }
+  // SSOR wavefront order (counting sort of the local sites by hyperplane)
+  {
+    const int nh = (g.b[0] - 1) + (g.b[1] - 1) + (g.b[2] - 1) + (g.b[3] - 1) + 1;
+    std::vector<int> cnt(nh + 1, 0), loc(g.Vb), hsite(g.Vb);
+    for (int l = 0; l < g.Vb; ++l) {
+      const int l0 = l % g.b[0], l1 = (l / g.b[0]) % g.b[1], l2 = (l / (g.b[0] * g.b[1])) % g.b[2],
+                l3 = l / (g.b[0] * g.b[1] * g.b[2]);
+      hsite[l] = l0 + l1 + l2 + l3;
+      cnt[hsite[l] + 1] += 1;
+    }
+    for (int h = 0; h < nh; ++h) {
+      lat->hp_max = std::max(lat->hp_max, cnt[h + 1]);
+      cnt[h + 1] += cnt[h];
+    }
+    std::vector<int> off(cnt), pos(cnt.begin(), cnt.end() - 1);
+    for (int l = 0; l < g.Vb; ++l) loc[pos[hsite[l]]++] = l;
+    lat->nh = nh;
+    if (hipMalloc(&lat->hp_loc, g.Vb * sizeof(int)) != hipSuccess ||
+        hipMalloc(&lat->hp_off, (nh + 1) * sizeof(int)) != hipSuccess) {
+      set_error("out of device memory for the wavefront tables");
+      return fail(MBBS_ENOMEM);
+    }
+    if (hipMemcpy(lat->hp_loc, loc.data(), g.Vb * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(lat->hp_off, off.data(), (nh + 1) * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("wavefront table copy failed");
+      return fail(MBBS_EHIP);
+    }
+  }
   *out = lat;
   return MBBS_OK;
 }
@@ -208,6 +246,8 @@ extern "C" int mbbs_lattice_destroy(mbbs_lattice_t lat) {
   (void)hipFree(lat->U64dm);
   (void)hipFree(lat->U32dm);
   (void)hipFree(lat->U16dm);
+  (void)hipFree(lat->hp_loc);
+  (void)hipFree(lat->hp_off);
   delete lat;
   return MBBS_OK;
 }

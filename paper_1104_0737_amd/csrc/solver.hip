@@ -50,7 +50,7 @@ int nblocks_needed(const mbbs_solve_params& p) {
 size_t workspace_bytes(const mbbs_lattice_s* lat, int L, const mbbs_solve_params& p) {
   const size_t N = (size_t)lat->g.V * 12;
   size_t b = nblocks_needed(p) * block_bytes(lat, L);
-  if (p.precond) b += al(sap_buffer_bytes(lat, L, p.sap_prec));
+  if (p.precond) b += al(sap_buffer_bytes(lat, L, p.sap_prec, p.domain_solver == 1));
   b += al(gram_partial_bytes(N, L));
   b += small_bytes(L);
   return b;
@@ -71,8 +71,11 @@ int bind(const mbbs_lattice_s* lat, int L, const mbbs_solve_params& p, void* ws,
   w.T = p.memsave ? w.R : (double2*)take(B);
   w.S = p.precond ? (double2*)take(B) : w.T;
   if (p.precond) {
-    const size_t sb = sap_buffer_bytes(lat, L, p.sap_prec);
-    MBBS_TRY(sap_bind(lat, L, p.sap_prec, take(sb), sb, &w.sap));
+    const bool ssor = p.domain_solver == 1;
+    const size_t sb = sap_buffer_bytes(lat, L, p.sap_prec, ssor);
+    MBBS_TRY(sap_bind(lat, L, p.sap_prec, take(sb), sb, &w.sap, ssor));
+    w.sap.nssor = p.nssor;
+    w.sap.ssor_omega = p.ssor_omega;
   }
   w.partial = (double2*)take(gram_partial_bytes(N, L));
   const size_t LL = (size_t)L * L * sizeof(double2);
@@ -449,7 +452,16 @@ static int validate(const mbbs_lattice_s* lat, int L, const mbbs_solve_params* p
   MBBS_CHECK(p->maxiter >= 0, "maxiter must be >= 0");
   MBBS_CHECK(p->qr_passes == 1 || p->qr_passes == 2, "qr_passes must be 1 or 2");
   MBBS_CHECK(p->sap_prec >= 0 && p->sap_prec <= 2, "bad sap_prec");
-  if (p->precond) MBBS_CHECK(p->ncy >= 1 && p->nmr >= 1, "SAP needs ncy >= 1 and nmr >= 1");
+  if (p->precond) {
+    MBBS_CHECK(p->domain_solver == 0 || p->domain_solver == 1, "domain_solver must be 0 (MR) or 1 (SSOR)");
+    MBBS_CHECK(p->ncy >= 1, "SAP needs ncy >= 1");
+    if (p->domain_solver == 0) MBBS_CHECK(p->nmr >= 1, "MR domain solves need nmr >= 1");
+    else {
+      MBBS_CHECK(p->nssor == 0 || p->nssor == 1, "N_SSOR must be 0 or 1");
+      MBBS_CHECK(std::isfinite(p->ssor_omega) && p->ssor_omega > 0 && p->ssor_omega < 2,
+                 "SSOR omega must lie in (0, 2)");
+    }
+  }
   return MBBS_OK;
 }
 
@@ -786,6 +798,9 @@ extern "C" void mbbs_solve_params_default(mbbs_solve_params* p) {
   p->precond = 1;
   p->memsave = 0;
   p->profile = 0;
+  p->domain_solver = 0;
+  p->nssor = 1;
+  p->ssor_omega = 1.26;
 }
 
 extern "C" int mbbs_solve_workspace_size(mbbs_lattice_t lat, int L, const mbbs_solve_params* params, size_t* bytes) {

@@ -35,6 +35,8 @@ def test_tables_bit_exact(dims, block):
         # neighbours in domain-major positions: dmnb[dmi[s]] = dmi[nb[s]]
         dmnb = t("DM_NEIGHBOUR").reshape(V, 8)
         np.testing.assert_array_equal(dmnb[dmi], dmi[nb])
+        order, off = geometry.hyperplane_order(block)
+        np.testing.assert_array_equal(t("HYPERPLANE"), np.concatenate([order, off]))
 
 
 def test_create_rejects_bad_geometry():

@@ -152,3 +152,21 @@ def test_sap_with_ssor_domains_is_linear_and_preconditions(setup):
     np.testing.assert_allclose(M(P + 2j * Q), M(P) + 2j * M(Q), atol=1e-12)
     r = dirac.as_field(P, V) - dirac.apply_D(U, 0.12, PH, M(P), DIMS)
     assert np.linalg.norm(r) < 0.2 * np.linalg.norm(P)
+
+
+@pytest.mark.parametrize("block", [(2, 2, 2, 2), (4, 4, 4, 4), (2, 3, 2, 4), (8, 4, 4, 4)])
+def test_hyperplane_order(block):
+    """Every in-domain forward hop goes from hyperplane h to h + 1, the order
+    is a permutation, and the offsets count the sites of each hyperplane."""
+    order, off = geometry.hyperplane_order(block)
+    Vb = int(np.prod(block))
+    assert sorted(order.tolist()) == list(range(Vb))
+    h = np.empty(Vb, int)
+    for k in range(len(off) - 1):
+        h[order[off[k]:off[k + 1]]] = k
+    nb = geometry.local_neighbours(block)
+    for mu in range(4):
+        f = nb[:, 2 * mu]
+        inside = f >= 0
+        assert np.all(h[f[inside]] == h[inside] + 1)
+    assert off[0] == 0 and off[-1] == Vb and len(off) == sum(b - 1 for b in block) + 2
