@@ -22,6 +22,7 @@ import time
 
 import numpy as np
 
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -45,6 +46,8 @@ def parse():
     ap.add_argument("--profile", type=int, default=1, help="event-time kernel classes in the timed solves")
     ap.add_argument("--sap-prec", choices=("fp32", "fp16s"), default="fp32",
                     help="storage precision of the SAP preconditioner in the mixed solve")
+    ap.add_argument("--apply-tuning", default=None,
+                    help="apply the launch settings of an earlier run's JSON line instead of tuning")
     ap.add_argument("--domain-solver", choices=("mr", "ssor"), default="mr",
                     help="SAP domain solver: nmr MR steps, or SSOR (N_SSOR, omega) as in the paper")
     ap.add_argument("--nssor", type=int, default=1)
@@ -110,6 +113,21 @@ def algorithmic_bytes(cls, L, dims, block, ncy, nmr, sap_prec="fp32", nssor=1):
             tot += 2 * Vh * (fields * sp + (1 if cy == 0 else 2) * ps + sweeps * 4 * lk)
         return tot / (2 * ncy)
     return None
+
+
+def measured_traffic(cls, dims, L, sap_prec):
+    """HBM bytes per launch of a kernel class from the committed counter
+    summary (FETCH_SIZE / WRITE_SIZE, copy-calibrated) for this workload; None
+    if there is none or the library's sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_32x32x32x64_L12.json")
+    if tuple(dims) != (32, 32, 32, 64) or L != 12 or sap_prec != "fp32" or not os.path.exists(path):
+        return None
+    from paper_1104_0737_amd.build import source_hash
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_hash") != source_hash() or cls not in t["classes"]:
+        return None
+    return t["classes"][cls]["bytes"]
 
 
 def main():
@@ -188,7 +206,25 @@ def main():
     # ------------------------------------------------------------ launch tuning
     tuning = {}
     dslash = {}
-    if not args.no_tune:
+    if args.apply_tuning:
+        # settings chosen by an earlier run (its JSON line), applied without
+        # timing candidates: profiler runs then see only the kernels that run
+        from paper_1104_0737_amd import autotune
+        with open(args.apply_tuning) as f:
+            prev = json.loads(f.read().strip().splitlines()[-1])["tuning"]
+        for prec, name in ((B.FP64, "fp64"), (B.FP32, "fp32"), (B.FP16S, "fp16s")):
+            t = prev[name]
+            op = (t["group_cols"], t["block_threads"], t["split"], t["hop_pair"], t["nt_store"])
+            autotune.apply(lat, prec, op)
+            if not args.skip_dslash:
+                dslash[name] = time_dslash(prec)
+                dslash[name]["setting"] = list(op)
+                log(f"  operator {name}: {dslash[name]['ms']:.3f} ms")
+            if "sap" in t:
+                autotune.apply(lat, prec, tuple(t["sap"]["setting"]))
+            tuning[name] = t
+        log(f"applied tuning from {args.apply_tuning}")
+    elif not args.no_tune:
         from paper_1104_0737_amd import autotune
         for prec, name in ((B.FP64, "fp64"), (B.FP32, "fp32"), (B.FP16S, "fp16s")):
             best, times = autotune.tune_operator(lat, V, L, prec, stream=stream)
@@ -210,7 +246,7 @@ def main():
                 log(f"  SAP shape {sbest}: " + ", ".join(f"{k}: {v:.2f} ms" for k, v in stimes.items()))
         torch.cuda.empty_cache()
 
-    for prec, name in () if args.skip_dslash or not args.no_tune else ((B.FP64, "fp64"), (B.FP32, "fp32"),
+    for prec, name in () if args.skip_dslash or not args.no_tune or args.apply_tuning else ((B.FP64, "fp64"), (B.FP32, "fp32"),
                                                                         (B.FP16S, "fp16s")):
         log(f"operator {name}")
         dslash[name] = time_dslash(prec)
@@ -313,8 +349,10 @@ def main():
         byl = algorithmic_bytes(dominant, L, dims, cfg.block, cfg.ncy, cfg.nmr, args.sap_prec, args.nssor)
         avg_ms = km[dominant] / kl[dominant]
         ach = byl / (avg_ms * 1e-3) / 1e9
+        traffic = measured_traffic(dominant, dims, L, args.sap_prec)
         roof = {"kernel": dominant, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_over_algorithmic": round(traffic / byl, 3) if traffic else None,
                 "bytes_per_launch": byl, "avg_launch_ms": avg_ms, "launches": kl[dominant],
                 "class_ms": {k: round(v, 3) for k, v in km.items()}}
 

@@ -23,6 +23,20 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-u
          "-I", os.path.join(HERE, "..", "include")]
 
 
+def source_hash() -> str:
+    """SHA-256 over the library's sources and public header (the kernels as
+    built): counter summaries record it, so stale ones can be recognised."""
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(SRC) if f.endswith((".hip", ".h")))
+    for f in files:
+        with open(os.path.join(SRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    with open(os.path.join(HERE, "..", "include", "mbbs.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
+
+
 def _compile(unit: str) -> str:
     obj = os.path.join(BUILD, unit.replace(".hip", ".o"))
     cmd = [HIPCC, *FLAGS, "-c", os.path.join(SRC, unit), "-o", obj]

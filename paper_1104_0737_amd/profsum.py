@@ -34,11 +34,43 @@ def counters(db):
     return [(k[0], k[1], len(v), sum(v) / len(v)) for k, v in acc.items()]
 
 
+def traffic(fetch_db, write_db, cfetch_db, cwrite_db, classes, copy_bytes=4 << 30):
+    """HBM bytes per launch of the named kernels from a FETCH_SIZE and a
+    WRITE_SIZE run (KiB per dispatch), each scaled by what the same counter
+    reads for a plain device copy of `copy_bytes` bytes.  classes maps a
+    kernel class to its kernel name.  Returns a JSON-ready dict that also
+    records the hash of the sources the counters were taken with."""
+    from .build import source_hash
+
+    def avg(db, cname, kname):
+        vals = [v for k, c, n, v in counters(db) if c == cname and k == kname]
+        return vals[0] if vals else None
+    copy = "__amd_rocclr_copyBuffer"
+    rs = copy_bytes / 1024 / avg(cfetch_db, "FETCH_SIZE", copy)
+    ws = copy_bytes / 1024 / avg(cwrite_db, "WRITE_SIZE", copy)
+    out = {"source_hash": source_hash(), "read_scale": rs, "write_scale": ws, "classes": {}}
+    for cls, kname in classes.items():
+        f, w = avg(fetch_db, "FETCH_SIZE", kname), avg(write_db, "WRITE_SIZE", kname)
+        if f is None or w is None:
+            continue
+        out["classes"][cls] = {"kernel": kname, "fetch_kib": f, "write_kib": w,
+                               "bytes": f * 1024 * rs + w * 1024 * ws}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("db", nargs="+")
+    ap.add_argument("db", nargs="*")
     ap.add_argument("--match", default="")
+    ap.add_argument("--traffic", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
+                    help="print per-launch HBM traffic of --kernel CLASS=NAME pairs as JSON")
+    ap.add_argument("--kernel", action="append", default=[])
     a = ap.parse_args()
+    if a.traffic:
+        import json
+        classes = dict(kv.split("=", 1) for kv in a.kernel)
+        print(json.dumps(traffic(*a.traffic, classes), indent=1))
+        return
     for db in a.db:
         c = sqlite3.connect(db)
         has_pmc = c.execute("select count(*) from counters_collection").fetchone()[0] > 0
