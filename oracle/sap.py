@@ -22,7 +22,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import dirac, geometry
+from . import clover, dirac, geometry
 
 
 class Domains:
@@ -47,18 +47,30 @@ class Domains:
         return (self.colour == colour)[:, None, None, None]
 
 
-def apply_blocked(U, kappa, phases, dom: Domains, phi):
+def apply_blocked(U, kappa, phases, dom: Domains, phi, cinv=None):
+    """A_DD phi on every domain; with cinv = (1 + T)^{-1} per site (clover,
+    Jacobi preconditioned) A_DD = 1 - kappa (1 + T)^{-1} H_DD."""
     V = dom.V
     phi = dirac.as_field(phi, V)
-    return phi - kappa * dirac.hopping(U, phases, phi, dom.dims, keep=dom.keep)
+    h = dirac.hopping(U, phases, phi, dom.dims, keep=dom.keep)
+    if cinv is not None:
+        h = clover.site_mul(cinv, h)
+    return phi - kappa * h
 
 
-def mr_domains(U, kappa, phases, dom: Domains, rho, colour: int, nmr: int):
+def apply_A(U, kappa, phases, dims, phi, cinv=None):
+    """The full operator: Wilson, or Jacobi-preconditioned clover if cinv is given."""
+    if cinv is None:
+        return dirac.apply_D(U, kappa, phases, phi, dims)
+    return clover.apply_A(U, kappa, phases, cinv, phi, dims)
+
+
+def mr_domains(U, kappa, phases, dom: Domains, rho, colour: int, nmr: int, cinv=None):
     """MR approximation of A_DD^{-1} rho_D on every domain of one colour."""
     r = dirac.as_field(rho, dom.V) * dom.mask(colour)
     x = np.zeros_like(r)
     for _ in range(nmr):
-        w = apply_blocked(U, kappa, phases, dom, r)
+        w = apply_blocked(U, kappa, phases, dom, r, cinv)
         wr = dom.per_domain_sum(np.sum(np.conj(w) * r, axis=(1, 2)))
         ww = dom.per_domain_sum(np.sum(np.abs(w) ** 2, axis=(1, 2)))
         omega = np.zeros_like(wr)
@@ -88,23 +100,31 @@ def mr_trace(U, kappa, phases, dom: Domains, rho, colour: int, nmr: int):
     return x, norms, orth
 
 
-def sap(U, kappa, phases, dom: Domains, eta, ncy: int, nmr: int, domain_solve=None):
-    """psi = M_SAP eta with ncy cycles; domain_solve(rho, colour) -> increment."""
+def sap(U, kappa, phases, dom: Domains, eta, ncy: int, nmr: int, domain_solve=None, cinv=None):
+    """psi = M_SAP eta with ncy cycles; domain_solve(rho, colour) -> increment.
+    cinv: (1 + T)^{-1} per site for the Jacobi-preconditioned clover operator."""
     if domain_solve is None:
         def domain_solve(rho, colour):
-            return mr_domains(U, kappa, phases, dom, rho, colour, nmr)
+            return mr_domains(U, kappa, phases, dom, rho, colour, nmr, cinv)
     eta = dirac.as_field(eta, dom.V)
     psi = np.zeros_like(eta)
     for _ in range(ncy):
         for colour in (0, 1):
-            rho = eta - dirac.apply_D(U, kappa, phases, psi, dom.dims)
+            rho = eta - apply_A(U, kappa, phases, dom.dims, psi, cinv)
             psi = psi + domain_solve(rho * dom.mask(colour), colour)
     return psi
 
 
-def exact_domain_solver(U, kappa, phases, dom: Domains):
+def exact_domain_solver(U, kappa, phases, dom: Domains, cinv=None):
     """domain_solve using dense LU of every A_DD (tiny lattices only)."""
     D = dirac.dense_D(U, kappa, phases, dom.dims)
+    if cinv is not None:
+        # A = 1 + (1 + T)^{-1} (D_wilson - 1), block-diagonal (1 + T)^{-1}
+        N = D.shape[0]
+        Cb = np.zeros_like(D)
+        for x in range(dom.V):
+            Cb[12 * x:12 * x + 12, 12 * x:12 * x + 12] = cinv[x]
+        D = np.eye(N) + Cb @ (D - np.eye(N))
     blocks = []
     for d in range(dom.ndom):
         sites = np.nonzero(dom.did == d)[0]

@@ -33,7 +33,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import dirac
+from . import clover, dirac
 
 
 def _keep(dom, forward: bool):
@@ -43,16 +43,18 @@ def _keep(dom, forward: bool):
     return [k if ((d % 2 == 0) == forward) else off for d, k in enumerate(keep)]
 
 
-def forward_inside(U, kappa, phases, dom, phi):
-    """Lf phi: the forward in-domain hops, times kappa."""
+def forward_inside(U, kappa, phases, dom, phi, cinv=None):
+    """Lf phi: the forward in-domain hops, times kappa (and (1 + T)^{-1} with clover)."""
     phi = dirac.as_field(phi, dom.V)
-    return kappa * dirac.hopping(U, phases, phi, dom.dims, keep=_keep(dom, True))
+    h = dirac.hopping(U, phases, phi, dom.dims, keep=_keep(dom, True))
+    return kappa * (clover.site_mul(cinv, h) if cinv is not None else h)
 
 
-def backward_inside(U, kappa, phases, dom, phi):
-    """Ub phi: the backward in-domain hops, times kappa."""
+def backward_inside(U, kappa, phases, dom, phi, cinv=None):
+    """Ub phi: the backward in-domain hops, times kappa (and (1 + T)^{-1} with clover)."""
     phi = dirac.as_field(phi, dom.V)
-    return kappa * dirac.hopping(U, phases, phi, dom.dims, keep=_keep(dom, False))
+    h = dirac.hopping(U, phases, phi, dom.dims, keep=_keep(dom, False))
+    return kappa * (clover.site_mul(cinv, h) if cinv is not None else h)
 
 
 def nilpotency_order(block) -> int:
@@ -69,16 +71,18 @@ def inv_one_minus(apply, omega, v, K):
     return out
 
 
-def ssor_blocked(U, kappa, phases, dom, v, omega: float, nssor: int):
-    """B v with B the SSOR inverse of every domain block (N_SSOR = nssor)."""
+def ssor_blocked(U, kappa, phases, dom, v, omega: float, nssor: int, cinv=None):
+    """B v with B the SSOR inverse of every domain block (N_SSOR = nssor).
+    With cinv (clover, Jacobi preconditioned) Lf and Ub carry (1 + T)^{-1},
+    which is site-diagonal, so they stay nilpotent."""
     v = dirac.as_field(v, dom.V)
     K = nilpotency_order(dom.block)
 
     def Finv(x):
-        return inv_one_minus(lambda y: forward_inside(U, kappa, phases, dom, y), omega, x, K)
+        return inv_one_minus(lambda y: forward_inside(U, kappa, phases, dom, y, cinv), omega, x, K)
 
     def Binv(x):
-        return inv_one_minus(lambda y: backward_inside(U, kappa, phases, dom, y), omega, x, K)
+        return inv_one_minus(lambda y: backward_inside(U, kappa, phases, dom, y, cinv), omega, x, K)
 
     def A_S(c):
         # the paper's three-term expression
@@ -93,8 +97,8 @@ def ssor_blocked(U, kappa, phases, dom, v, omega: float, nssor: int):
     return Binv(s)
 
 
-def ssor_domain_solver(U, kappa, phases, dom, omega: float, nssor: int):
+def ssor_domain_solver(U, kappa, phases, dom, omega: float, nssor: int, cinv=None):
     """domain_solve(rho, colour) for `sap.sap`: B_DD on the domains of one colour."""
     def solve(rho, colour):
-        return ssor_blocked(U, kappa, phases, dom, rho * dom.mask(colour), omega, nssor)
+        return ssor_blocked(U, kappa, phases, dom, rho * dom.mask(colour), omega, nssor, cinv)
     return solve
