@@ -141,6 +141,27 @@ enum { MBBS_TUNE_GROUP_FP64 = 0, MBBS_TUNE_GROUP_FP32 = 1, MBBS_TUNE_GROUP_FP16S
        MBBS_TUNE_NT_STORE_FP16S = 16 };
 int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value);
 
+/* O(a)-improved (clover) Wilson operator with Jacobi preconditioning (Sec. 2.2:
+ * the matrix is divided by I + clover term before the domain decomposition).
+ * The clover term, built on the device from the lattice's links and kappa, is
+ *   T(x) = i c_sw kappa sum_{mu<nu} sigma_{mu nu} F_{mu nu}(x),
+ *   F_{mu nu} = (Q_{mu nu} - Q_{mu nu}^dagger) / 8 (Q: the four plaquettes of
+ *   the (mu, nu) plane at x, each traversed mu first), sigma = (i/2)[gamma, gamma];
+ * the boundary phases do not enter it.  Once set, every operator of this
+ * lattice is A = (1 + T)^{-1} (1 + T - kappa H) = 1 - kappa (1 + T)^{-1} H
+ * (mbbs_apply_dirac, the Dirichlet blocks, SAP and SSOR), and mbbs_solve /
+ * mbbs_solve_batched solve A X = (1 + T)^{-1} B (residuals refer to that
+ * system).  The split-wave kernel shapes are not used with a clover term.
+ * mbbs_lattice_set_clover: csw = 0 removes the term.  Errors: EINVAL,
+ * ENOMEM, EBREAKDOWN (1 + T singular at a site; the lattice is left without
+ * clover term).  Synchronises `stream`.
+ * mbbs_lattice_clover_inverse: (1 + T(x))^{-1} as V x 12 x 12 FP64 complex
+ * site matrices (row 3*spin + colour) into out_dev (device, V*144 complex).
+ * mbbs_apply_clover_inverse: Y = (1 + T)^{-1} X, FP64 N x L device blocks. */
+int mbbs_lattice_set_clover(mbbs_lattice_t lat, double csw, void* stream);
+int mbbs_lattice_clover_inverse(mbbs_lattice_t lat, double* out_dev, void* stream);
+int mbbs_apply_clover_inverse(mbbs_lattice_t lat, int L, const double* X, double* Y, void* stream);
+
 /* ---------------------------------------------------------------- operator */
 
 /* Y = A X with A = 1 - kappa*H, H the hopping term of Sec. 2.1 applied to

@@ -24,7 +24,8 @@ TABLES = ("COORD", "NEIGHBOUR", "BOUNDARY", "PARITY", "EO", "DOMAIN", "COLOUR", 
 KERNEL_CLASSES = ("dslash64", "sap_resid", "mr_dslash", "mr_update", "convert", "gram", "update", "small", "ssor")
 
 EXPORTS = (
-    "mbbs_lattice_create", "mbbs_lattice_destroy", "mbbs_lattice_tune", "mbbs_lattice_table_size",
+    "mbbs_lattice_create", "mbbs_lattice_destroy", "mbbs_lattice_tune", "mbbs_lattice_set_clover",
+    "mbbs_lattice_clover_inverse", "mbbs_apply_clover_inverse", "mbbs_lattice_table_size",
     "mbbs_lattice_table",
     "mbbs_apply_dirac", "mbbs_apply_dirac_raw", "mbbs_convert_to", "mbbs_convert_from",
     "mbbs_apply_blocked", "mbbs_sap_workspace_size", "mbbs_sap_apply", "mbbs_ssor_workspace_size",
@@ -73,6 +74,9 @@ def lib():
                                         ctypes.POINTER(vp)]),
             "mbbs_lattice_destroy": (i, [vp]),
             "mbbs_lattice_tune": (i, [vp, i, i]),
+            "mbbs_lattice_set_clover": (i, [vp, d, vp]),
+            "mbbs_lattice_clover_inverse": (i, [vp, vp, vp]),
+            "mbbs_apply_clover_inverse": (i, [vp, i, vp, vp, vp]),
             "mbbs_lattice_table_size": (i, [vp, i, ctypes.POINTER(sz)]),
             "mbbs_lattice_table": (i, [vp, i, vp, sz]),
             "mbbs_apply_dirac": (i, [vp, i, vp, vp, i, vp]),
@@ -167,6 +171,19 @@ TUNE_HOP_PAIR = {0: 11, 1: 12, 2: 13}   # precision -> knob
 
 def mbbs_lattice_tune(lat, knob, value):
     return _check(lib().mbbs_lattice_tune(lat, knob, value))
+
+
+def mbbs_lattice_set_clover(lat, csw, stream=None):
+    return _check(lib().mbbs_lattice_set_clover(lat, ctypes.c_double(csw), _stream(stream)))
+
+
+def mbbs_lattice_clover_inverse(lat, out, stream=None):
+    """out: complex128 device tensor (V, 12, 12)."""
+    return _check(lib().mbbs_lattice_clover_inverse(lat, _dev(out, _c128()), _stream(stream)))
+
+
+def mbbs_apply_clover_inverse(lat, L, X, Y, stream=None):
+    return _check(lib().mbbs_apply_clover_inverse(lat, L, _dev(X, _c128()), _dev(Y, _c128()), _stream(stream)))
 
 
 def mbbs_lattice_table(lat, which):

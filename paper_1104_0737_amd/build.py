@@ -17,7 +17,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmbbs.so")
 BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-UNITS = ["lattice.hip", "dslash.hip", "ssor.hip", "blas.hip", "solver.hip", "capi.hip"]
+UNITS = ["lattice.hip", "dslash.hip", "ssor.hip", "clover.hip", "blas.hip", "solver.hip", "capi.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(HERE, "..", "include")]
@@ -48,7 +48,7 @@ def _compile(unit: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(len(UNITS), 5)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(len(UNITS), 7)) as ex:
         objs = list(ex.map(_compile, UNITS))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]

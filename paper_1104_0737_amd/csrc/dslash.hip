@@ -37,6 +37,7 @@ __global__ void __launch_bounds__(256) k_dslash(GeomK k, double kappa, int L,
 #pragma unroll
       for (int q = 0; q < C; ++q) acc[sp][a][q] = cmake<R>(0, 0);
   hop_sum<PIN, PL, C, ORDER, BLOCKED ? INSIDE : ALL, R, PAIR>(k, c, in, in_s, U, L, col0, acc);
+  if (k.clov) clover_apply<ORDER, C, R>(k, s, acc);
   const R kap = (R)kappa;
 #pragma unroll
   for (int q = 0; q < C; ++q) {
@@ -84,6 +85,7 @@ __global__ void __launch_bounds__(256) k_sap_resid(GeomK k, double kappa, int L,
     const SiteCtx c = site_ctx<DM>(k, s);
     if (mode == 1) hop_sum<PPSI, PL, C, DM, OUTSIDE, R>(k, c, psi, nullptr, U, L, col0, acc);
     else hop_sum<PPSI, PL, C, DM, ALL, R>(k, c, psi, nullptr, U, L, col0, acc);
+    if (k.clov) clover_apply<DM, C, R>(k, s, acc);
   }
   const R kap = (R)kappa;
 #pragma unroll
@@ -139,6 +141,7 @@ __global__ void __launch_bounds__(256) k_mr_dslash(GeomK k, double kappa, int L,
 #pragma unroll
       for (int q = 0; q < C; ++q) acc[sp][a][q] = cmake<R>(0, 0);
   hop_sum<PR, PL, C, DM, INSIDE, R>(k, c, r, r_s, U, L, col0, acc);
+  if (k.clov) clover_apply<DM, C, R>(k, s, acc);
   const R kap = (R)kappa;
   const int ny = blockDim.y, nx = blockDim.x * C;
 #pragma unroll
@@ -320,6 +323,7 @@ __global__ void __launch_bounds__(mr_fused_threads<PR>()) k_mr_fused(GeomK k, do
 #pragma unroll
           for (int a = 0; a < 3; ++a) acc[sp][a][0] = cmake<R>(0, 0);
         hop_sum<PR, PL, 1, DM, INSIDE, R>(k, c, r, r_s, U, L, col, acc);
+        if (k.clov) clover_apply<DM, 1, R>(k, s, acc);
         const size_t base = (size_t)s * 12 * L + col;
         const size_t sidx = (size_t)s * L + col;
         cplx<R> v[4][3], wv[4][3];
@@ -675,6 +679,8 @@ GeomK make_geomk(const Geom& g) {
   for (int m = 0; m < 4; ++m) k.fnd[m] = make_fastdiv(g.nd[m]);
   k.fVb = make_fastdiv(g.Vb);
   k.nt_store = 0;
+  for (int o = 0; o < 2; ++o) { k.cinv64[o] = nullptr; k.cinv32[o] = nullptr; }
+  k.clov = 0;
   k.lstride[0] = 1;
   k.stride[0] = 1;
   for (int m = 1; m < 4; ++m) {
@@ -817,7 +823,7 @@ static int dslash_dispatch_c(const mbbs_lattice_s* lat, int L, int order, bool b
                              const void* in, const float* in_s, void* out, float* out_s, int s0,
                              int n, const int* frozen, hipStream_t st) {
   const int P = lat->split[PL];
-  if (P == 2 || P == 4) {
+  if ((P == 2 || P == 4) && !lat->gk.clov) {   // the split kernels have no clover step
     const int S = split_sites(lat, L, PL, P);
     if (S > 0) {
       if (P == 4) return dslash_split_launch<PIN, POUT, PL, 4>(lat, L, order, blocked, in, in_s, out, out_s, s0, n, S, frozen, st);
@@ -929,7 +935,7 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
     for (int col = 0; col < 2; ++col) {
       const int s0 = col * g.Vh, n = g.Vh;
       const int P = lat->split[PL];
-      const int SS = (P == 2 || P == 4) ? split_sites(lat, L, PL, P) : 0;
+      const int SS = ((P == 2 || P == 4) && !lat->gk.clov) ? split_sites(lat, L, PL, P) : 0;
       if (prof) prof->begin(MBBS_K_SAP_RES);
       if (SS > 0) {
         const size_t smem = split_smem_bytes(PL, P, SS, L);

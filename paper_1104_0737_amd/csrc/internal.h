@@ -66,6 +66,11 @@ struct GeomK {
   int lstride[4];    // local strides inside a domain
   int stride[4];     // lexicographic strides
   int nt_store;      // operator output written with nontemporal stores
+  // clover (Jacobi preconditioned): (1 + T)^{-1} per site, packed (72 reals),
+  // indexed [order]; clov = 0 means the plain Wilson operator
+  const double* cinv64[2];
+  const float* cinv32[2];
+  int clov;
 };
 GeomK make_geomk(const Geom& g);
 
@@ -105,6 +110,11 @@ struct mbbs_lattice_s {
   // SSOR wavefront order inside a domain: local indices sorted by the
   // hyperplane h = l_0 + l_1 + l_2 + l_3 (then by local index); hyperplane h
   // holds entries hp_off[h] .. hp_off[h+1]-1 (device arrays)
+  double* cl64 = nullptr;    // (1 + T)^{-1}, packed, lexicographic / domain-major
+  float* cl32 = nullptr;
+  double* cl64dm = nullptr;
+  float* cl32dm = nullptr;
+  double csw = 0;
   int* hp_loc = nullptr;
   int* hp_off = nullptr;
   int nh = 0;          // number of hyperplanes, sum_mu (b_mu - 1) + 1
@@ -140,6 +150,12 @@ struct SapBuffers {
 };
 size_t sap_buffer_bytes(const mbbs_lattice_s* lat, int L, int prec, bool ssor = false);
 int sap_bind(const mbbs_lattice_s* lat, int L, int prec, void* ws, size_t bytes, SapBuffers* b, bool ssor = false);
+// Clover: build (1 + T)^{-1} from the lattice's links (csw = 0 removes it);
+// out = (1 + T)^{-1} in on an FP64 lexicographic block; unpack to 12 x 12.
+int clover_build(mbbs_lattice_s* lat, double csw, hipStream_t st);
+int launch_clover_apply(const mbbs_lattice_s* lat, int L, const double2* in, double2* out, hipStream_t st);
+int clover_unpack(const mbbs_lattice_s* lat, double2* out, hipStream_t st);
+
 // FP64 lexicographic block -> SAP storage of b.prec (dst, dst_s), optionally
 // right-multiplied by gam; SAP psi -> FP64 lexicographic block.
 int sap_to(const mbbs_lattice_s* lat, const SapBuffers& b, const double2* in, const double2* gam, void* dst,

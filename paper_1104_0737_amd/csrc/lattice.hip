@@ -248,8 +248,32 @@ extern "C" int mbbs_lattice_destroy(mbbs_lattice_t lat) {
   (void)hipFree(lat->U16dm);
   (void)hipFree(lat->hp_loc);
   (void)hipFree(lat->hp_off);
+  (void)hipFree(lat->cl64);
+  (void)hipFree(lat->cl32);
+  (void)hipFree(lat->cl64dm);
+  (void)hipFree(lat->cl32dm);
   delete lat;
   return MBBS_OK;
+}
+
+extern "C" int mbbs_lattice_set_clover(mbbs_lattice_t lat, double csw, void* stream) {
+  MBBS_CHECK(lat != nullptr, "null lattice");
+  MBBS_CHECK(std::isfinite(csw), "c_sw must be finite");
+  return clover_build(lat, csw, (hipStream_t)stream);
+}
+
+extern "C" int mbbs_lattice_clover_inverse(mbbs_lattice_t lat, double* out_dev, void* stream) {
+  MBBS_CHECK(lat != nullptr && out_dev != nullptr, "null argument");
+  MBBS_TRY(clover_unpack(lat, (double2*)out_dev, (hipStream_t)stream));
+  MBBS_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return MBBS_OK;
+}
+
+extern "C" int mbbs_apply_clover_inverse(mbbs_lattice_t lat, int L, const double* X, double* Y, void* stream) {
+  MBBS_CHECK(lat && X && Y, "null argument");
+  MBBS_CHECK(L >= 1 && L <= 256, "L must be in 1..256");
+  MBBS_CHECK(lat->gk.clov, "no clover term set on this lattice");
+  return launch_clover_apply(lat, L, (const double2*)X, (double2*)Y, (hipStream_t)stream);
 }
 
 extern "C" int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value) {

@@ -22,8 +22,8 @@ namespace {
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Work {
-  // FP64 N x L blocks
-  double2 *R, *P, *Rt, *V, *T, *Z, *U, *S;
+  // FP64 N x L blocks (Bp: the right-hand side times (1 + T)^{-1} with clover)
+  double2 *R, *P, *Rt, *V, *T, *Z, *U, *S, *Bp;
   SapBuffers sap;
   double2* partial;
   SolverDev d;
@@ -46,10 +46,13 @@ int nblocks_needed(const mbbs_solve_params& p) {
   if (p.precond) n += 1;
   return n;
 }
+int nblocks_needed(const mbbs_lattice_s* lat, const mbbs_solve_params& p) {
+  return nblocks_needed(p) + (lat->gk.clov ? 1 : 0);
+}
 
 size_t workspace_bytes(const mbbs_lattice_s* lat, int L, const mbbs_solve_params& p) {
   const size_t N = (size_t)lat->g.V * 12;
-  size_t b = nblocks_needed(p) * block_bytes(lat, L);
+  size_t b = nblocks_needed(lat, p) * block_bytes(lat, L);
   if (p.precond) b += al(sap_buffer_bytes(lat, L, p.sap_prec, p.domain_solver == 1));
   b += al(gram_partial_bytes(N, L));
   b += small_bytes(L);
@@ -70,6 +73,7 @@ int bind(const mbbs_lattice_s* lat, int L, const mbbs_solve_params& p, void* ws,
   w.U = (double2*)take(B);
   w.T = p.memsave ? w.R : (double2*)take(B);
   w.S = p.precond ? (double2*)take(B) : w.T;
+  w.Bp = lat->gk.clov ? (double2*)take(B) : nullptr;
   if (p.precond) {
     const bool ssor = p.domain_solver == 1;
     const size_t sb = sap_buffer_bytes(lat, L, p.sap_prec, ssor);
@@ -483,6 +487,10 @@ static int solve_impl(mbbs_lattice_t lat, int L, const double* B_dev, double* X_
   c.prof = nullptr;
   MBBS_TRY(bind(lat, L, c.p, ws, ws_bytes, c.w));
   c.frozen = &c.w.d.state->frozen;
+  if (c.w.Bp) {   // clover: solve A X = (1 + T)^{-1} B
+    MBBS_TRY(launch_clover_apply(lat, L, c.B, c.w.Bp, c.st));
+    c.B = c.w.Bp;
+  }
   if (c.p.profile) {
     prof.on = true;
     prof.st = c.st;
@@ -571,6 +579,10 @@ static int batch_record(BatchJob& b) {
 // the state record; ||b_i||^2 comes back for the host's check.
 static int batch_init(BatchJob& b) {
   Ctx& c = b.j.c;
+  if (c.w.Bp) {   // clover: solve A X = (1 + T)^{-1} B
+    MBBS_TRY(launch_clover_apply(c.lat, c.L, c.B, c.w.Bp, c.st));
+    c.B = c.w.Bp;
+  }
   MBBS_TRY(launch_fill(c.w.d.one, 1, make_double2(1, 0), c.st));
   MBBS_TRY(launch_fill(c.w.mone, 1, make_double2(-1, 0), c.st));
   if (!c.p.x0_is_guess) MBBS_TRY(launch_fill(c.X, c.N * c.L, make_double2(0, 0), c.st));

@@ -57,6 +57,7 @@ __device__ __forceinline__ void ssor_sweep(const GeomK& k, int L, int base_site,
 #pragma unroll
         for (int q = 0; q < 3; ++q) acc[sp][q][0] = cmake<R>(0, 0);
       hop_sum<PR, PL, 1, DM, FWD ? FWD_IN : BWD_IN, R>(k, c, X, X_s, U, L, col, acc);
+      if (k.clov) clover_apply<DM, 1, R>(k, s, acc);
       const size_t base = (size_t)s * 12 * L + col, sidx = (size_t)s * L + col;
       cplx<R> in[4][3];
       if constexpr (MODE == 0) {

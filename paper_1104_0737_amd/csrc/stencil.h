@@ -339,6 +339,40 @@ __device__ __forceinline__ void hop_group(int h, const GeomK& k, const SiteCtx& 
   }
 }
 
+// acc <- (1 + T(s))^{-1} acc for the C columns of a thread (clover, Jacobi
+// preconditioned).  The inverse is two hermitian 6 x 6 blocks (spins {0,1}
+// and {2,3}, row 3*spin' + colour), packed: 6 real diagonal entries, then
+// (i, j), i < j, row by row as (re, im).  Rows are read one at a time.
+template <int ORDER, int C, typename R>
+__device__ __forceinline__ void clover_apply(const GeomK& k, int s, cplx<R> (&acc)[4][3][C]) {
+  const R* m;
+  if constexpr (sizeof(R) == 8) m = (const R*)k.cinv64[ORDER] + (size_t)s * 72;
+  else m = (const R*)k.cinv32[ORDER] + (size_t)s * 72;
+#pragma unroll
+  for (int blk = 0; blk < 2; ++blk) {
+    const R* p = m + 36 * blk;
+    cplx<R> out[6][C];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+#pragma unroll
+      for (int q = 0; q < C; ++q) out[i][q] = p[i] * acc[2 * blk + i / 3][i % 3][q];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        if (j == i) continue;
+        const int lo = i < j ? i : j, hi = i < j ? j : i;
+        const int o = 6 + 2 * (lo * 6 - lo * (lo + 1) / 2 + (hi - lo - 1));
+        const cplx<R> e = cmake<R>(p[o], i < j ? p[o + 1] : -p[o + 1]);
+#pragma unroll
+        for (int q = 0; q < C; ++q) out[i][q] = out[i][q] + e * acc[2 * blk + j / 3][j % 3][q];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int q = 0; q < C; ++q) acc[2 * blk + i / 3][i % 3][q] = out[i][q];
+  }
+}
+
 // Store one (site, column) spinor; P16 computes the per-(site, column) scale.
 template <int POUT, typename R, bool NT = false>
 __device__ __forceinline__ void store_spinor(typename Store<POUT>::Elem* out, float* out_s,
