@@ -48,6 +48,8 @@ def parse():
                     help="storage precision of the SAP preconditioner in the mixed solve")
     ap.add_argument("--apply-tuning", default=None,
                     help="apply the launch settings of an earlier run's JSON line instead of tuning")
+    ap.add_argument("--csw", type=float, default=0.0,
+                    help="clover coefficient: O(a)-improved operator with Jacobi preconditioning (0: Wilson)")
     ap.add_argument("--domain-solver", choices=("mr", "ssor"), default="mr",
                     help="SAP domain solver: nmr MR steps, or SSOR (N_SSOR, omega) as in the paper")
     ap.add_argument("--nssor", type=int, default=1)
@@ -64,7 +66,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(cls, L, dims, block, ncy, nmr, sap_prec="fp32", nssor=1):
+def algorithmic_bytes(cls, L, dims, block, ncy, nmr, sap_prec="fp32", nssor=1, clover=False):
     """Compulsory HBM bytes of one launch of a kernel class, averaged over the
     launches of one SAP application where they differ.  SAP storage: FP32
     8-byte complex and 72-byte link, or FP16 storage 4-byte complex plus one
@@ -82,16 +84,19 @@ def algorithmic_bytes(cls, L, dims, block, ncy, nmr, sap_prec="fp32", nssor=1):
     ssor       one colour, all sweeps: N_SSOR = 1 moves 11 storage fields
                (r->a, a->b, a,b->r, a,b,r->b) and psi, 4 links per site and
                sweep; N_SSOR = 0 moves 4 (r->a, a->b) and psi, 2 sweeps.
+    With the clover term every stencil pass also reads the packed site
+    inverse (72 reals per site: FP64 576 bytes, FP32 288 bytes).
     """
     V = int(np.prod(dims))
     Vh = V // 2
     sp = 12 * L * 8 if sap_prec == "fp32" else 12 * L * 4 + 4 * L   # storage spinor row block
     ps = 12 * L * 8                                                  # psi (FP32)
     lk = 72 if sap_prec == "fp32" else 36
+    cl = 288 if clover else 0
     if cls == "dslash64":
-        return V * (48 * L + 72) * 8
+        return V * ((48 * L + 72) * 8 + (576 if clover else 0))
     if cls == "mr_dslash":
-        return Vh * (2 * sp + 4 * lk)
+        return Vh * (2 * sp + 4 * lk + cl)
     if cls == "mr_update":
         tot = 0
         for cy in range(ncy):
@@ -105,22 +110,24 @@ def algorithmic_bytes(cls, L, dims, block, ncy, nmr, sap_prec="fp32", nssor=1):
         tot = 2 * (2 * Vh * sp)                          # first cycle, colour 0 and 1: eta, r
         tot += Vh * (f * ps + 4 * lk)                    # first cycle, colour 1: psi of colour 0
         tot += 2 * (ncy - 1) * Vh * (2 * sp + (1 + f) * ps + 4 * lk)
+        tot += (2 * ncy - 1) * Vh * cl                   # every half-sweep but the first
         return tot / (2 * ncy)
     if cls == "ssor":
         fields, sweeps = (11, 4) if nssor == 1 else (4, 2)
         tot = 0
         for cy in range(ncy):
-            tot += 2 * Vh * (fields * sp + (1 if cy == 0 else 2) * ps + sweeps * 4 * lk)
+            tot += 2 * Vh * (fields * sp + (1 if cy == 0 else 2) * ps + sweeps * (4 * lk + cl))
         return tot / (2 * ncy)
     return None
 
 
-def measured_traffic(cls, dims, L, sap_prec):
+def measured_traffic(cls, dims, L, sap_prec, clover=False):
     """HBM bytes per launch of a kernel class from the committed counter
     summary (FETCH_SIZE / WRITE_SIZE, copy-calibrated) for this workload; None
     if there is none or the library's sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic_32x32x32x64_L12.json")
-    if tuple(dims) != (32, 32, 32, 64) or L != 12 or sap_prec != "fp32" or not os.path.exists(path):
+    if (tuple(dims) != (32, 32, 32, 64) or L != 12 or sap_prec != "fp32" or clover
+            or not os.path.exists(path)):
         return None
     from paper_1104_0737_amd.build import source_hash
     with open(path) as f:
@@ -169,6 +176,9 @@ def main():
     log(f"links ready in {time.time() - t0:.1f}s")
     Ud = torch.from_numpy(U).to(dev)
     lat = B.mbbs_lattice_create(dims, cfg.block, Ud, cfg.kappa, cfg.phases, stream=stream)
+    if args.csw:
+        B.mbbs_lattice_set_clover(lat, args.csw, stream=stream)
+        log(f"clover term set, c_sw = {args.csw}")
     del Ud
 
     # ------------------------------------------------------------ operator alone
@@ -195,7 +205,7 @@ def main():
         ev1.synchronize()
         ms = ev0.elapsed_time(ev1) / args.dslash_reps
         name = {B.FP64: "fp64", B.FP32: "fp32", B.FP16S: "fp16s"}[prec]
-        by = model.dslash_bytes_per_site(L, name) * V
+        by = model.dslash_bytes_per_site(L, name, bool(args.csw)) * V
         fl = model.dslash_flops_per_site(L) * V
         del X, Xr, Yr, Xs, Ys
         torch.cuda.empty_cache()
@@ -346,10 +356,11 @@ def main():
     dominant = max(("dslash64", "mr_dslash", "mr_update", "sap_resid", "ssor"), key=lambda c: km[c])
     roof = None
     if args.profile and kl[dominant] > 0:
-        byl = algorithmic_bytes(dominant, L, dims, cfg.block, cfg.ncy, cfg.nmr, args.sap_prec, args.nssor)
+        byl = algorithmic_bytes(dominant, L, dims, cfg.block, cfg.ncy, cfg.nmr, args.sap_prec, args.nssor,
+                                bool(args.csw))
         avg_ms = km[dominant] / kl[dominant]
         ach = byl / (avg_ms * 1e-3) / 1e9
-        traffic = measured_traffic(dominant, dims, L, args.sap_prec)
+        traffic = measured_traffic(dominant, dims, L, args.sap_prec, bool(args.csw))
         roof = {"kernel": dominant, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_over_algorithmic": round(traffic / byl, 3) if traffic else None,
@@ -373,7 +384,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64+f32" if args.sap_prec == "fp32" else "f64+f32 (fp16 storage)",
         "data": "synthetic",
-        "config": {"workload": f"{'x'.join(map(str, dims))} Wilson-Dirac, L={L} point sources, "
+        "config": {"workload": f"{'x'.join(map(str, dims))} "
+                               + (f"clover-Wilson (c_sw={args.csw}, Jacobi preconditioned)" if args.csw else "Wilson-Dirac")
+                               + f", L={L} point sources, "
                                f"SAP 8^4 domains ncy={cfg.ncy} "
                                + (f"nmr={cfg.nmr}" if args.domain_solver == "mr" else
                                   f"SSOR N_SSOR={args.nssor} omega={args.ssor_omega}")

@@ -42,11 +42,14 @@ def link_bytes_per_site(word_bytes: int) -> int:
     return 8 * 18 * word_bytes
 
 
-def dslash_bytes_per_site(L: int, prec: str) -> int:
-    """Compulsory HBM bytes of one full-lattice application, per site."""
+def dslash_bytes_per_site(L: int, prec: str, clover: bool = False) -> int:
+    """Compulsory HBM bytes of one full-lattice application, per site; with
+    the clover term also the packed site inverse (72 reals, FP32 for the
+    FP16-storage operator)."""
+    cl = 72 * (8 if prec == "fp64" else 4) if clover else 0
     if prec == "fp16s":
-        return 104 * L + 144
-    return (48 * L + 72) * WORD[prec]
+        return 104 * L + 144 + cl
+    return (48 * L + 72) * WORD[prec] + cl
 
 
 def dslash_flops_per_site(L: int) -> int:
