@@ -54,6 +54,8 @@ def parse():
                     help="SAP domain solver: nmr MR steps, or SSOR (N_SSOR, omega) as in the paper")
     ap.add_argument("--nssor", type=int, default=1)
     ap.add_argument("--ssor-omega", type=float, default=1.26)
+    ap.add_argument("--sweep", action="store_true",
+                    help="L sweep over 1,2,3,4,6,12 (12 point sources in 12/L blocks), operator and solves")
     ap.add_argument("--batched", action="store_true",
                     help="48 independent systems of uneven size solved together (batched form)")
     ap.add_argument("--graph-iters", type=int, default=4)
@@ -159,6 +161,8 @@ def main():
 
     if args.batched:
         return batched_main(args)
+    if args.sweep:
+        return sweep_main(args)
 
     dims = tuple(int(x) for x in args.dims.split(","))
     cfg = configs.c4(L=args.L)
@@ -408,6 +412,76 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    B.mbbs_lattice_destroy(lat)
+
+
+def sweep_main(args):
+    """The paper's Table 1 experiment on the 32^3x64 system: the 12 spin-colour
+    point sources are solved in 12/L blocks of L consecutive components, for
+    L = 1, 2, 3, 4, 6, 12.  Per L: the stand-alone operator (FP64, FP32,
+    FP16 storage, tuned for that L), and the summed time, iterations and
+    outer operator applications (per vector) over the blocks for the mixed
+    solve (FP32 SAP, MR domains), the all-FP64 solve, and the mixed solve with
+    SSOR domains (the paper's domain solver)."""
+    import torch
+    from paper_1104_0737_amd import autotune
+    from paper_1104_0737_amd import binding as B
+    from paper_1104_0737_amd import configs, model
+    dims = tuple(int(x) for x in args.dims.split(","))
+    cfg0 = configs.c4(L=1)
+    cfg0.dims = dims
+    V = int(np.prod(dims))
+    N = 12 * V
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
+    log(f"generating links for {dims}")
+    Ud = torch.from_numpy(cfg0.gauge()).to(dev)
+    lat = B.mbbs_lattice_create(dims, cfg0.block, Ud, cfg0.kappa, cfg0.phases, stream=stream)
+    del Ud
+    site = cfg0.src_site()
+    rows = []
+    for L in (1, 2, 3, 4, 6, 12):
+        row = {"L": L, "blocks": 12 // L, "dslash": {}}
+        for prec, name in ((B.FP64, "fp64"), (B.FP32, "fp32"), (B.FP16S, "fp16s")):
+            best, times = autotune.tune_operator(lat, V, L, prec, stream=stream)
+            ms = times[best]
+            by = model.dslash_bytes_per_site(L, name) * V
+            row["dslash"][name] = {"ms": ms, "site_rhs_per_s": V * L / (ms * 1e-3),
+                                   "algo_GBps": by / (ms * 1e-3) / 1e9, "setting": list(best)}
+            if prec != B.FP64:
+                autotune.tune_sap(lat, V, L, prec, times, stream=stream)
+        torch.cuda.empty_cache()
+        for key, sap_prec, dsolver in (("mixed_mr", B.FP32, 0), ("fp64_mr", B.FP64, 0), ("mixed_ssor", B.FP32, 1)):
+            p = B.mbbs_solve_params_default(tol=1e-10, sap_prec=sap_prec, ncy=cfg0.ncy, nmr=cfg0.nmr,
+                                            domain_solver=dsolver)
+            ws = torch.empty(B.mbbs_solve_workspace_size(lat, L, p), dtype=torch.uint8, device=dev)
+            tot, its, mvm, worst, ok = 0.0, [], 0, 0.0, True
+            for blk in range(12 // L):
+                Bd = torch.zeros((N, L), dtype=torch.complex128, device=dev)
+                for j in range(L):
+                    Bd[12 * site + blk * L + j, j] = 1.0
+                Xd = torch.empty_like(Bd)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                info = B.mbbs_solve(lat, L, Bd, Xd, p, ws, stream=stream)
+                torch.cuda.synchronize()
+                tot += time.perf_counter() - t
+                its.append(info["iterations"])
+                mvm += info["n_dslash_outer"] * L
+                worst = max(worst, float(info["true_res"].max()))
+                ok = ok and info["status"] == 0
+            row[key] = {"seconds": tot, "tts_per_rhs_s": tot / 12, "iterations": its, "outer_mvm": mvm,
+                        "max_true_res": worst, "converged": ok}
+            log(f"L={L:2d} {key:10s}: {tot:6.2f} s for 12 RHS, iterations {its}, max true res {worst:.1e}")
+            del ws
+            torch.cuda.empty_cache()
+        rows.append(row)
+    base = {k: rows[0][k]["seconds"] for k in ("mixed_mr", "fp64_mr", "mixed_ssor")}
+    for r in rows:
+        r["gain_vs_L1"] = {k: base[k] / r[k]["seconds"] for k in base}
+    print(json.dumps({"sweep": rows, "workload": f"{'x'.join(map(str, dims))} Wilson, 12 point sources "
+                      "in 12/L blocks, SAP 8^4 ncy=4 (MR nmr=4 or SSOR N=1 omega=1.26), tol 1e-10"}), flush=True)
     B.mbbs_lattice_destroy(lat)
 
 
