@@ -228,14 +228,14 @@ def main():
             prev = json.loads(f.read().strip().splitlines()[-1])["tuning"]
         for prec, name in ((B.FP64, "fp64"), (B.FP32, "fp32"), (B.FP16S, "fp16s")):
             t = prev[name]
-            op = (t["group_cols"], t["block_threads"], t["split"], t["hop_pair"], t["nt_store"])
+            op = (t["group_cols"], t["block_threads"], t["split"], t["hop_pair"], t["nt_store"], t.get("chunk", 0))
             autotune.apply(lat, prec, op)
             if not args.skip_dslash:
                 dslash[name] = time_dslash(prec)
                 dslash[name]["setting"] = list(op)
                 log(f"  operator {name}: {dslash[name]['ms']:.3f} ms")
             if "sap" in t:
-                autotune.apply(lat, prec, tuple(t["sap"]["setting"]))
+                autotune.apply(lat, prec, tuple(t["sap"]["setting"]))   # may set columns per thread
             tuning[name] = t
         log(f"applied tuning from {args.apply_tuning}")
     elif not args.no_tune:
@@ -243,7 +243,7 @@ def main():
         for prec, name in ((B.FP64, "fp64"), (B.FP32, "fp32"), (B.FP16S, "fp16s")):
             best, times = autotune.tune_operator(lat, V, L, prec, stream=stream)
             tuning[name] = {"group_cols": best[0], "block_threads": best[1], "split": best[2],
-                            "hop_pair": best[3], "nt_store": best[4],
+                            "hop_pair": best[3], "nt_store": best[4], "chunk": best[5] if len(best) > 5 else 0,
                             "ms": round(times[best], 4), "worst_ms": round(max(times.values()), 4),
                             "classic_best_ms": round(min(v for k, v in times.items() if k[2] == 0), 4)}
             log(f"tuned {name}: {best} ({times[best]:.3f} ms; "

@@ -129,6 +129,9 @@ int mbbs_lattice_table(mbbs_lattice_t lat, int which, int32_t* out, size_t count
  *  MBBS_TUNE_HOP_PAIR_FP64/FP32/FP16S  1: the one-thread-per-site operator keeps
  *      both hops of a direction in flight (more loads in flight per thread,
  *      more registers)
+ *  MBBS_TUNE_CHUNK_FP64/FP32/FP16S  columns per thread of the one-thread-per-site
+ *      stencil kernels (0: automatic, 1 for FP64 and 2 otherwise; 1..4 used
+ *      when it divides L)
  *  MBBS_TUNE_LDS_PAD_KB             extra LDS (KiB, 0..64) reserved per stencil
  *      block, which caps the blocks resident on a CU (fewer sites in flight
  *      per XCD, so more of their neighbour data stays in its L2)
@@ -138,7 +141,8 @@ enum { MBBS_TUNE_GROUP_FP64 = 0, MBBS_TUNE_GROUP_FP32 = 1, MBBS_TUNE_GROUP_FP16S
        MBBS_TUNE_SPLIT_FP32 = 6, MBBS_TUNE_SPLIT_FP16S = 7, MBBS_TUNE_PERSIST_BLOCKS = 8,
        MBBS_TUNE_MR_FUSED = 9, MBBS_TUNE_HOP_PAIR_FP64 = 11, MBBS_TUNE_HOP_PAIR_FP32 = 12,
        MBBS_TUNE_HOP_PAIR_FP16S = 13, MBBS_TUNE_NT_STORE_FP64 = 14, MBBS_TUNE_NT_STORE_FP32 = 15,
-       MBBS_TUNE_NT_STORE_FP16S = 16 };
+       MBBS_TUNE_NT_STORE_FP16S = 16, MBBS_TUNE_CHUNK_FP64 = 17, MBBS_TUNE_CHUNK_FP32 = 18,
+       MBBS_TUNE_CHUNK_FP16S = 19 };
 int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value);
 
 /* O(a)-improved (clover) Wilson operator with Jacobi preconditioning (Sec. 2.2:

@@ -32,17 +32,24 @@ def candidates(L, prec):
 
 
 def operator_candidates(L, prec):
-    """(group, threads, split, pair, nt) settings tried by tune_operator: all
-    L columns or half of them per group, three block sizes, paired hops and
-    nontemporal stores on or off, and the split-wave kernels."""
+    """(group, threads, split, pair, nt[, columns per thread]) settings tried
+    by tune_operator: all L columns or half of them per group, three block
+    sizes, paired hops and nontemporal stores on or off, the other number of
+    columns per thread, and the split-wave kernels."""
     c = next(c for c in range(_cmax(prec), 0, -1) if L % c == 0)
     groups = [L] + ([L // 2] if L % 2 == 0 and (L // 2) % c == 0 else [])
     out = [(g, t, 0, pr, nt) for g in groups for t in (128, 192, 256) for pr in (0, 1) for nt in (0, 1)]
+    # the other number of columns per thread (FP64 automatic 1, else 2)
+    other = 2 if prec == B.FP64 else 1
+    if L % other == 0:
+        out += [(L, t, 0, 0, nt, other) for t in (128, 256) for nt in (0, 1)]
     return out + [(L, 256, sp, 0, nt) for sp in (2, 4) for nt in (0, 1)]
 
 
 def apply(lat, prec, setting):
-    g, t, sp, pr, nt = setting
+    g, t, sp, pr, nt = setting[:5]
+    ch = setting[5] if len(setting) > 5 else 0
+    B.mbbs_lattice_tune(lat, B.TUNE_CHUNK[prec], ch)
     B.mbbs_lattice_tune(lat, B.TUNE_GROUP[prec], g)
     B.mbbs_lattice_tune(lat, B.TUNE_BLOCK_THREADS, t)
     B.mbbs_lattice_tune(lat, B.TUNE_SPLIT[prec], sp)
@@ -51,7 +58,7 @@ def apply(lat, prec, setting):
 
 
 def tune_operator(lat, V, L, prec, stream=None, reps=3):
-    """Return (best (group, threads, split, pair, nt), {setting: ms}) and apply the best."""
+    """Return (best setting, {setting: ms}) and apply the best."""
     import torch
     dev = torch.device("cuda")
     N = 12 * V
@@ -83,13 +90,18 @@ def tune_operator(lat, V, L, prec, stream=None, reps=3):
 
 
 def tune_sap(lat, V, L, prec, op_times, stream=None, ncy=4, nmr=4, reps=2):
-    """Between the fastest split and the fastest one-thread-per-site operator
-    settings (from tune_operator's timings), keep the one under which the SAP
-    preconditioner itself runs faster.  Returns (setting, {setting: ms})."""
+    """Among the fastest split and the fastest one-thread-per-site operator
+    settings (from tune_operator's timings), and one column per thread for
+    FP32 / FP16 storage, keep the one under which the SAP preconditioner
+    itself runs faster.  Returns (setting, {setting: ms})."""
     import torch
     split = [k for k in op_times if k[2] in (2, 4)]
     classic = [k for k in op_times if k[2] not in (2, 4)]
     cands = [min(c, key=op_times.get) for c in (split, classic) if c]
+    if classic and prec != B.FP64:
+        # one column per thread: more waves in flight per CU for the domain kernels
+        g, t, sp, pr, nt = min(classic, key=op_times.get)[:5]
+        cands += [(L, tt, 0, pr, nt, 1) for tt in (128, 256)]
     dev = torch.device("cuda")
     s = stream or torch.cuda.current_stream()
     X = torch.zeros((12 * V, L), dtype=torch.complex128, device=dev)

@@ -707,7 +707,7 @@ struct Plan {
 };
 static Plan make_plan(const mbbs_lattice_s* lat, int L, int prec, int nsites) {
   Plan p;
-  p.C = pick_chunk(L, prec);
+  p.C = pick_chunk(lat, L, prec);
   p.gw = lat->group_cols[prec];
   if (p.gw <= 0 || p.gw % p.C || L % p.gw) p.gw = L;
   p.nchunk = p.gw / p.C;
@@ -830,7 +830,7 @@ static int dslash_dispatch_c(const mbbs_lattice_s* lat, int L, int order, bool b
       return dslash_split_launch<PIN, POUT, PL, 2>(lat, L, order, blocked, in, in_s, out, out_s, s0, n, S, frozen, st);
     }
   }
-  switch (pick_chunk(L, PL)) {
+  switch (pick_chunk(lat, L, PL)) {
     case 4: return dslash_dispatch_order<PIN, POUT, PL, 4>(lat, L, order, blocked, in, in_s, out, out_s, s0, n, frozen, st);
     case 3: return dslash_dispatch_order<PIN, POUT, PL, 3>(lat, L, order, blocked, in, in_s, out, out_s, s0, n, frozen, st);
     case 2: return dslash_dispatch_order<PIN, POUT, PL, 2>(lat, L, order, blocked, in, in_s, out, out_s, s0, n, frozen, st);

@@ -107,6 +107,7 @@ struct mbbs_lattice_s {
   int mr_fused = -1;         // SAP domain solve in one launch per colour: -1 auto, 0 off, 1 on
   int hop_pair[3] = {0, 0, 0};  // operator: both hops of a direction in flight at once
   int nt_store[3] = {0, 0, 0};  // operator: nontemporal output stores
+  int chunk[3] = {0, 0, 0};     // columns per thread of the stencil kernels (0: automatic)
   // SSOR wavefront order inside a domain: local indices sorted by the
   // hyperplane h = l_0 + l_1 + l_2 + l_3 (then by local index); hyperplane h
   // holds entries hp_off[h] .. hp_off[h+1]-1 (device arrays)
@@ -202,8 +203,10 @@ struct Profiler {
 };
 
 // Launch configuration helpers.
-inline int pick_chunk(int L, int prec) {
+inline int pick_chunk(const mbbs_lattice_s* lat, int L, int prec) {
   // columns per thread: amortise link loads and index work over columns
+  const int forced = lat->chunk[prec];
+  if (forced >= 1 && forced <= 4 && L % forced == 0) return forced;
   int cmax = prec == P64 ? 1 : 2;
   for (int c = cmax; c > 1; --c)
     if (L % c == 0) return c;

@@ -311,6 +311,12 @@ extern "C" int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value) {
       MBBS_CHECK(value == 0 || value == 1, "hop pairing must be 0 or 1");
       lat->hop_pair[knob - MBBS_TUNE_HOP_PAIR_FP64] = value;
       return MBBS_OK;
+    case MBBS_TUNE_CHUNK_FP64:
+    case MBBS_TUNE_CHUNK_FP32:
+    case MBBS_TUNE_CHUNK_FP16S:
+      MBBS_CHECK(value >= 0 && value <= 4, "columns per thread must be 0 (automatic) or 1..4");
+      lat->chunk[knob - MBBS_TUNE_CHUNK_FP64] = value;
+      return MBBS_OK;
     case MBBS_TUNE_MR_FUSED:
       MBBS_CHECK(value >= -1 && value <= 1, "fused MR must be -1 (auto), 0 or 1");
       lat->mr_fused = value;

@@ -141,6 +141,7 @@ def test_tuning_is_bit_identical():
         for prec in (0, 1, 2):
             ref = None
             settings = [c + (0, 0) for c in autotune.candidates(L, prec)] + autotune.operator_candidates(L, prec)
+            settings = [x for x in settings if len(x) < 6]   # other columns per thread: another summation order
             for setting in settings:
                 if setting[2]:
                     continue          # the split kernels sum the hops in another order
