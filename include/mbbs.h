@@ -173,7 +173,7 @@ int mbbs_apply_clover_inverse(mbbs_lattice_t lat, int L, const double* X, double
  * equation).  X_dev, Y_dev: FP64 N x L blocks (layout above), distinct.
  * prec selects the arithmetic: FP64 directly; FP32 / FP16S convert X to
  * that storage, apply, and convert back (for accuracy checks).  Asynchronous
- * on `stream`.  Errors: EINVAL (L < 1, aliasing, bad prec). */
+ * on `stream`.  Errors: EINVAL (L outside 1..256, aliasing, bad prec). */
 int mbbs_apply_dirac(mbbs_lattice_t lat, int L, const double* X_dev, double* Y_dev,
                      int prec, void* stream);
 

@@ -31,7 +31,7 @@ struct Scratch {
 extern "C" int mbbs_apply_dirac_raw(mbbs_lattice_t lat, int L, int prec, const void* X, const float* Xs, void* Y,
                                     float* Ys, void* stream) {
   MBBS_CHECK(lat && X && Y && X != Y, "null or aliased arguments");
-  MBBS_CHECK(L >= 1, "L must be >= 1");
+  MBBS_CHECK(L >= 1 && L <= 256, "L must be in 1..256");
   MBBS_CHECK(prec_ok(prec), "bad precision");
   MBBS_CHECK(prec != MBBS_FP16S || (Xs && Ys), "FP16S needs scale arrays");
   return launch_dslash(lat, L, prec, prec, LEX, false, X, Xs, Y, Ys, 0, lat->g.V, nullptr, (hipStream_t)stream);
@@ -39,7 +39,7 @@ extern "C" int mbbs_apply_dirac_raw(mbbs_lattice_t lat, int L, int prec, const v
 
 static int apply_generic(mbbs_lattice_t lat, int L, const double* X, double* Y, int prec, bool blocked, void* stream) {
   MBBS_CHECK(lat && X && Y && X != Y, "null or aliased arguments");
-  MBBS_CHECK(L >= 1, "L must be >= 1");
+  MBBS_CHECK(L >= 1 && L <= 256, "L must be in 1..256");
   MBBS_CHECK(prec_ok(prec), "bad precision");
   hipStream_t st = (hipStream_t)stream;
   if (prec == MBBS_FP64)

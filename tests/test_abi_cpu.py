@@ -53,3 +53,15 @@ def test_create_validates_before_device_work():
     rc = lib.mbbs_lattice_create((ctypes.c_int * 4)(4, 4, 4, 4), (ctypes.c_int * 4)(2, 2, 2, 2), fake, 0.1, bad,
                                  None, ctypes.byref(out))
     assert rc == binding.EINVAL and "modulus" in binding.mbbs_last_error()
+
+
+def test_operator_rejects_bad_block_width_before_device_work():
+    """L outside 1..256 is rejected from the arguments alone (the handle and
+    the pointers are not dereferenced), so this runs without a GPU."""
+    import ctypes
+    lib = binding.lib()
+    fake = ctypes.c_void_p(16)
+    for L in (0, 257):
+        rc = lib.mbbs_apply_dirac(fake, L, ctypes.c_void_p(32), ctypes.c_void_p(64), binding.FP64, None)
+        assert rc == binding.EINVAL
+        assert "L must be" in binding.mbbs_last_error()

@@ -173,3 +173,21 @@ def test_split_wave_parity(split, L, prec):
         assert np.all(gu.rel_col_err(gu.host(Yd), ref) <= TOL[prec])
         B.mbbs_apply_blocked(lat.h, L, Xd, Yd, prec)
         assert np.all(gu.rel_col_err(gu.host(Yd), refb) <= TOL[prec])
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_operator_wide_block(prec):
+    """L = 64 (the operator's largest block) and L = 16 with every columns-per-thread setting."""
+    dims, block = (4, 4, 4, 8), (2, 2, 2, 4)
+    V = 512
+    U = inputs.gauge_field(dims, 0.35, 22)
+    for L, chunks in ((64, (0,)), (16, (1, 2, 4))):
+        X = inputs.gaussian_block(V, L, 23)
+        ref = dirac.apply_D(U, 0.12, PH_TWIST, X, dims).reshape(12 * V, L)
+        with gu.Lattice(dims, block, U, 0.12, PH_TWIST) as lat:
+            for ch in chunks:
+                B.mbbs_lattice_tune(lat.h, B.TUNE_CHUNK[prec], ch)
+                Xd = gu.dev(X)
+                Yd = torch.empty_like(Xd)
+                B.mbbs_apply_dirac(lat.h, L, Xd, Yd, prec)
+                assert np.all(gu.rel_col_err(gu.host(Yd), ref) <= TOL[prec]), (L, ch)

@@ -159,3 +159,25 @@ def test_sap_mr_fused_parity(dims, block, L, prec, tol):
             B.mbbs_sap_apply(lat.h, L, gu.dev(eta), Yd, 3, 4, prec, ws)
             err = gu.rel_col_err(gu.host(Yd), ref)
             assert np.all(err <= tol), (fused, err)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 3e-5), (2, 1e-2)])
+@pytest.mark.parametrize("group,chunk", [(6, 0), (4, 0), (12, 1), (6, 3)])
+def test_sap_launch_settings_parity(prec, tol, group, chunk):
+    """SAP under the launch settings the autotuner may pick (column groups,
+    columns per thread): same result as the oracle."""
+    dims, block, L = (8, 8, 8, 8), (4, 4, 4, 4), 12
+    V = 4096
+    U = inputs.gauge_field(dims, 0.3, 28)
+    eta = inputs.gaussian_block(V, L, 29)
+    dom = sap.Domains(dims, block)
+    ref = sap.sap(U, 0.12, gu.PH_AP, dom, eta, 2, 3).reshape(12 * V, L)
+    with gu.Lattice(dims, block, U, 0.12) as lat:
+        B.mbbs_lattice_tune(lat.h, B.TUNE_MR_FUSED, 0)
+        B.mbbs_lattice_tune(lat.h, B.TUNE_GROUP[prec], group)
+        B.mbbs_lattice_tune(lat.h, B.TUNE_CHUNK[prec], chunk)
+        ws = torch.empty(B.mbbs_sap_workspace_size(lat.h, L, prec), dtype=torch.uint8, device="cuda")
+        Yd = torch.empty((12 * V, L), dtype=torch.complex128, device="cuda")
+        B.mbbs_sap_apply(lat.h, L, gu.dev(eta), Yd, 2, 3, prec, ws)
+        err = gu.rel_col_err(gu.host(Yd), ref)
+    assert np.all(err <= tol), err
