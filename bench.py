@@ -83,9 +83,11 @@ def algorithmic_bytes(cls, L, dims, block, ncy, nmr, sap_prec="fp32", nssor=1, c
     sap_resid  one colour: read eta, write r; except on the first half-sweep
                also read psi on the colour and on the other colour's sites
                that touch it (a fraction f of them), and 4 links per site.
-    ssor       one colour, all sweeps: N_SSOR = 1 moves 11 storage fields
-               (r->a, a->b, a,b->r, a,b,r->b) and psi, 4 links per site and
-               sweep; N_SSOR = 0 moves 4 (r->a, a->b) and psi, 2 sweeps.
+    ssor       one colour, all sweeps, SAP residual included: N_SSOR = 1 moves
+               10 storage fields (eta->a, a->b, a,b->r,a, a->b), psi (the
+               residual's stencil as in sap_resid, then read + write, assign
+               in the first cycle), 4 links per site and sweep plus the
+               residual's; N_SSOR = 0 moves 4 (eta->a, a->b), 2 sweeps.
     With the clover term every stencil pass also reads the packed site
     inverse (72 reals per site: FP64 576 bytes, FP32 288 bytes).
     """
@@ -115,10 +117,17 @@ def algorithmic_bytes(cls, L, dims, block, ncy, nmr, sap_prec="fp32", nssor=1, c
         tot += (2 * ncy - 1) * Vh * cl                   # every half-sweep but the first
         return tot / (2 * ncy)
     if cls == "ssor":
-        fields, sweeps = (11, 4) if nssor == 1 else (4, 2)
+        # the SAP residual is formed inside the first sweep
+        inner = int(np.prod([b - 2 for b in block]))
+        f = 1 - inner / int(np.prod(block))
+        fields, sweeps = (10, 4) if nssor == 1 else (4, 2)
         tot = 0
         for cy in range(ncy):
-            tot += 2 * Vh * (fields * sp + (1 if cy == 0 else 2) * ps + sweeps * (4 * lk + cl))
+            for col in range(2):
+                mode = 2 if cy > 0 else col
+                resid = 0 if mode == 0 else (f * ps if mode == 1 else (1 + f) * ps) + 4 * lk + cl
+                upd = ps if cy == 0 else 2 * ps
+                tot += Vh * (fields * sp + resid + upd + sweeps * (4 * lk + cl))
         return tot / (2 * ncy)
     return None
 

@@ -934,6 +934,12 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
   for (int cy = 0; cy < ncy; ++cy) {
     for (int col = 0; col < 2; ++col) {
       const int s0 = col * g.Vh, n = g.Vh;
+      if (b.ssor) {   // the residual is formed inside the SSOR launch
+        if (prof) prof->begin(MBBS_K_SSOR);
+        MBBS_TRY(ssor_colour(lat, b, col, cy == 0, cy > 0 ? 2 : col, frozen, st));
+        if (prof) prof->end();
+        continue;
+      }
       const int P = lat->split[PL];
       const int SS = ((P == 2 || P == 4) && !lat->gk.clov) ? split_sites(lat, L, PL, P) : 0;
       if (prof) prof->begin(MBBS_K_SAP_RES);
@@ -962,12 +968,7 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
       }
       if (prof) prof->end();
       MBBS_HIP(hipGetLastError());
-      if (b.ssor) {
-        if (prof) prof->begin(MBBS_K_SSOR);
-        MBBS_TRY(ssor_colour(lat, b, col, cy == 0, frozen, st));
-        if (prof) prof->end();
-        continue;
-      }
+
       if (use_mr_fused(lat, L)) {
         const int spb = mr_fused_spb(g.Vb, L, mr_fused_threads<PR>());
         if (prof) prof->begin(MBBS_K_MR_DSLASH);

@@ -163,9 +163,11 @@ int sap_to(const mbbs_lattice_s* lat, const SapBuffers& b, const double2* in, co
            float* dst_s, const int* frozen, hipStream_t st);
 int sap_from(const mbbs_lattice_s* lat, const SapBuffers& b, double2* out, const int* frozen, hipStream_t st);
 // SSOR domain inverse B on every domain of one colour: psi (+)= B r on those
-// domains (assign: psi = B r); r and w are overwritten.
-int ssor_colour(const mbbs_lattice_s* lat, const SapBuffers& b, int colour, bool assign, const int* frozen,
-                hipStream_t st);
+// domains (assign: psi = B r).  rmode < 0: r holds the input; 0, 1, 2: the
+// input is the SAP residual eta - A psi (modes of the SAP residual kernel),
+// formed inside the first sweep.  r, w and x2 are overwritten.
+int ssor_colour(const mbbs_lattice_s* lat, const SapBuffers& b, int colour, bool assign, int rmode,
+                const int* frozen, hipStream_t st);
 // out = B in on every domain (both colours), FP64 lexicographic blocks.
 int ssor_blocked_apply(const mbbs_lattice_s* lat, const SapBuffers& b, const double2* in, double2* out,
                        hipStream_t st);
