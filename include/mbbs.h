@@ -126,9 +126,9 @@ int mbbs_lattice_table(mbbs_lattice_t lat, int which, int32_t* out, size_t count
  *  MBBS_TUNE_NT_STORE_FP64/FP32/FP16S  1: the operator writes its output with
  *      nontemporal stores (the output is not re-read by the same launch, so it
  *      need not displace neighbour data in L2)
- *  MBBS_TUNE_HOP_PAIR_FP64/FP32/FP16S  1: the one-thread-per-site operator keeps
- *      both hops of a direction in flight (more loads in flight per thread,
- *      more registers)
+ *  MBBS_TUNE_HOP_PAIR_FP64/FP32/FP16S  1: the one-thread-per-site operator and
+ *      SAP residual / MR kernels keep both hops of a direction in flight (more
+ *      loads in flight per thread, more registers; 1 or 2 columns per thread)
  *  MBBS_TUNE_CHUNK_FP64/FP32/FP16S  columns per thread of the one-thread-per-site
  *      stencil kernels (0: automatic, 1 for FP64 and 2 otherwise; 1..4 used
  *      when it divides L)

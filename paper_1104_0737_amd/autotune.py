@@ -101,7 +101,8 @@ def tune_sap(lat, V, L, prec, op_times, stream=None, ncy=4, nmr=4, reps=2):
     if classic and prec != B.FP64:
         # one column per thread: more waves in flight per CU for the domain kernels
         g, t, sp, pr, nt = min(classic, key=op_times.get)[:5]
-        cands += [(L, tt, 0, pr, nt, 1) for tt in (128, 256)]
+        cands += [(L, tt, 0, pv, nt, 1) for tt in (128, 256) for pv in (0, 1)]
+        cands += [(L, 256, 0, 1, nt, 0)]
     dev = torch.device("cuda")
     s = stream or torch.cuda.current_stream()
     X = torch.zeros((12 * V, L), dtype=torch.complex128, device=dev)

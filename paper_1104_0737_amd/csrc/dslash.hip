@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(256) k_dslash(GeomK k, double kappa, int L,
 // mode 1: psi = 0 on this colour (second half-sweep of the first cycle): only
 //         hops leaving the domain see a nonzero psi, r = eta + kappa H_out psi.
 // mode 2: general case.
-template <int PR, int PPSI, int PL, int C>
+template <int PR, int PPSI, int PL, int C, bool PAIR = false>
 __global__ void __launch_bounds__(256) k_sap_resid(GeomK k, double kappa, int L, int s0, int n, int mode,
                                                    const typename Store<PR>::Elem* __restrict__ eta,
                                                    const float* __restrict__ eta_s,
@@ -83,8 +83,8 @@ __global__ void __launch_bounds__(256) k_sap_resid(GeomK k, double kappa, int L,
       for (int q = 0; q < C; ++q) acc[sp][a][q] = cmake<R>(0, 0);
   if (mode != 0) {
     const SiteCtx c = site_ctx<DM>(k, s);
-    if (mode == 1) hop_sum<PPSI, PL, C, DM, OUTSIDE, R>(k, c, psi, nullptr, U, L, col0, acc);
-    else hop_sum<PPSI, PL, C, DM, ALL, R>(k, c, psi, nullptr, U, L, col0, acc);
+    if (mode == 1) hop_sum<PPSI, PL, C, DM, OUTSIDE, R, PAIR>(k, c, psi, nullptr, U, L, col0, acc);
+    else hop_sum<PPSI, PL, C, DM, ALL, R, PAIR>(k, c, psi, nullptr, U, L, col0, acc);
     if (k.clov) clover_apply<DM, C, R>(k, s, acc);
   }
   const R kap = (R)kappa;
@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(256) k_sap_resid(GeomK k, double kappa, int L,
 
 // MR step, part 1: w = A_DD r on one colour's domains, plus per-block sums of
 // <w, r> and <w, w> per column.
-template <int PR, int PL, int C>
+template <int PR, int PL, int C, bool PAIR = false>
 __global__ void __launch_bounds__(256) k_mr_dslash(GeomK k, double kappa, int L, int s0, int n,
                                                    const typename Store<PR>::Elem* __restrict__ r,
                                                    const float* __restrict__ r_s,
@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(256) k_mr_dslash(GeomK k, double kappa, int L,
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int q = 0; q < C; ++q) acc[sp][a][q] = cmake<R>(0, 0);
-  hop_sum<PR, PL, C, DM, INSIDE, R>(k, c, r, r_s, U, L, col0, acc);
+  hop_sum<PR, PL, C, DM, INSIDE, R, PAIR>(k, c, r, r_s, U, L, col0, acc);
   if (k.clov) clover_apply<DM, C, R>(k, s, acc);
   const R kap = (R)kappa;
   const int ny = blockDim.y, nx = blockDim.x * C;
@@ -958,12 +958,18 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
                              lat->gk, lat->kappa, L, s0, n, mode, (const ER*)b.eta, b.eta_s, (const EP*)b.psi, (ER*)b.r, b.r_s, U, SS, frozen);
         }
       } else {
-#define RES(CC)                                                                                      \
-  hipLaunchKernelGGL((k_sap_resid<PR, PPSI, PL, CC>), dim3(pl.nblocks), dim3(pl.nchunk, S),                  \
+#define RES(CC, PV)                                                                                  \
+  hipLaunchKernelGGL((k_sap_resid<PR, PPSI, PL, CC, PV>), dim3(pl.nblocks), dim3(pl.nchunk, S),              \
                      (size_t)lat->lds_pad_kb * 1024, st,                                                     \
                      lat->gk, lat->kappa, L, s0, n, cy > 0 ? 2 : col, (const ER*)b.eta,                \
                      b.eta_s, (const EP*)b.psi, (ER*)b.r, b.r_s, U, pl.bpt, pl.ngroups, frozen)
-      switch (C) { case 4: RES(4); break; case 3: RES(3); break; case 2: RES(2); break; default: RES(1); }
+      const bool pr = lat->hop_pair[PL] != 0;
+      switch (C) {
+        case 4: RES(4, false); break;
+        case 3: RES(3, false); break;
+        case 2: if (pr) RES(2, true); else RES(2, false); break;
+        default: if (pr) RES(1, true); else RES(1, false);
+      }
 #undef RES
       }
       if (prof) prof->end();
@@ -999,12 +1005,18 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
                                (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial, SS, frozen);
           }
         } else {
-#define MRD(CC)                                                                                       \
-  hipLaunchKernelGGL((k_mr_dslash<PR, PL, CC>), dim3(pl.nblocks), dim3(pl.nchunk, S),                       \
+#define MRD(CC, PV)                                                                                   \
+  hipLaunchKernelGGL((k_mr_dslash<PR, PL, CC, PV>), dim3(pl.nblocks), dim3(pl.nchunk, S),                   \
                      red_bytes + (size_t)lat->lds_pad_kb * 1024, st, lat->gk,                                \
                      lat->kappa, L, s0, n, (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial, pl.bpt,   \
                      pl.ngroups, frozen)
-        switch (C) { case 4: MRD(4); break; case 3: MRD(3); break; case 2: MRD(2); break; default: MRD(1); }
+        const bool pr = lat->hop_pair[PL] != 0;
+        switch (C) {
+          case 4: MRD(4, false); break;
+          case 3: MRD(3, false); break;
+          case 2: if (pr) MRD(2, true); else MRD(2, false); break;
+          default: if (pr) MRD(1, true); else MRD(1, false);
+        }
 #undef MRD
         }
         MBBS_HIP(hipGetLastError());

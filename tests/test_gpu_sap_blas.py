@@ -162,10 +162,10 @@ def test_sap_mr_fused_parity(dims, block, L, prec, tol):
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 3e-5), (2, 1e-2)])
-@pytest.mark.parametrize("group,chunk", [(6, 0), (4, 0), (12, 1), (6, 3)])
-def test_sap_launch_settings_parity(prec, tol, group, chunk):
+@pytest.mark.parametrize("group,chunk,pair", [(6, 0, 0), (4, 0, 0), (12, 1, 0), (6, 3, 0), (12, 0, 1), (12, 1, 1)])
+def test_sap_launch_settings_parity(prec, tol, group, chunk, pair):
     """SAP under the launch settings the autotuner may pick (column groups,
-    columns per thread): same result as the oracle."""
+    columns per thread, paired hops): same result as the oracle."""
     dims, block, L = (8, 8, 8, 8), (4, 4, 4, 4), 12
     V = 4096
     U = inputs.gauge_field(dims, 0.3, 28)
@@ -176,6 +176,7 @@ def test_sap_launch_settings_parity(prec, tol, group, chunk):
         B.mbbs_lattice_tune(lat.h, B.TUNE_MR_FUSED, 0)
         B.mbbs_lattice_tune(lat.h, B.TUNE_GROUP[prec], group)
         B.mbbs_lattice_tune(lat.h, B.TUNE_CHUNK[prec], chunk)
+        B.mbbs_lattice_tune(lat.h, B.TUNE_HOP_PAIR[prec], pair)
         ws = torch.empty(B.mbbs_sap_workspace_size(lat.h, L, prec), dtype=torch.uint8, device="cuda")
         Yd = torch.empty((12 * V, L), dtype=torch.complex128, device="cuda")
         B.mbbs_sap_apply(lat.h, L, gu.dev(eta), Yd, 2, 3, prec, ws)
