@@ -517,6 +517,26 @@ def batched_main(args):
         Ls.append(s.L)
         params.append(B.mbbs_solve_params_default(tol=1e-10, sap_prec=B.FP32, graph_iters=args.graph_iters))
     Xs = [torch.empty_like(b) for b in Bs]
+    # launch settings: tuned once per (lattice shape, L) on the group's first
+    # system, then applied to every system of the group
+    tuned = {}
+    if not args.no_tune:
+        from paper_1104_0737_amd import autotune
+        for s, lat in zip(systems, lats):
+            key = (s.dims, s.L)
+            if key not in tuned:
+                V = int(np.prod(s.dims))
+                st = {}
+                for prec in (B.FP64, B.FP32):
+                    best, times = autotune.tune_operator(lat, V, s.L, prec, stream=stream)
+                    if prec != B.FP64:
+                        best, _ = autotune.tune_sap(lat, V, s.L, prec, times, stream=stream)
+                    st[prec] = best
+                tuned[key] = st
+                log(f"tuned {'x'.join(map(str, s.dims))} L={s.L}: FP64 {st[B.FP64]}, FP32 SAP {st[B.FP32]}")
+            for prec, setting in tuned[key].items():
+                autotune.apply(lat, prec, setting)
+        torch.cuda.empty_cache()
     ws = torch.empty(B.mbbs_solve_batched_workspace_size(lats, Ls, params), dtype=torch.uint8, device=dev)
     rhs = sum(Ls)
 
@@ -558,6 +578,8 @@ def batched_main(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
            "data": "synthetic", "converged": ok, "max_true_res": max_true, "sequential_s": seq, "sequential_all_converged": seq_ok,
            "batched_over_sequential": seq / step_s, "iterations": {g: [min(v), max(v)] for g, v in groups.items()},
+           "tuning": {f"{'x'.join(map(str, k[0]))} L={k[1]}": {str(p): list(v) for p, v in st.items()}
+                      for k, st in tuned.items()},
            "config": {"workload": "16 x 8^4 L=4 + 16 x 12^4 L=6 + 16 x 16^3x32 L=12, SAP 4^4/6^4/8^4, "
                                   f"graph_iters={args.graph_iters}", "parallelism": "single GPU"}}
     print(json.dumps(out), flush=True)
