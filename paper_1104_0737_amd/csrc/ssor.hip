@@ -93,7 +93,9 @@ __device__ __forceinline__ void ssor_sweep(const GeomK& k, int L, int base_site,
       for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
         for (int q = 0; q < 3; ++q) acc[sp][q][0] = cmake<R>(0, 0);
-      hop_sum<PR, PL, 1, DM, FWD ? FWD_IN : BWD_IN, R>(k, c, X, X_s, U, L, col, acc);
+      // FP32 / FP16 storage: two directions' loads in flight; FP64 would spill
+      if constexpr (PR == P64) hop_sum<PR, PL, 1, DM, FWD ? FWD_IN : BWD_IN, R>(k, c, X, X_s, U, L, col, acc);
+      else hop_sense_sum<PR, PL, 1, DM, FWD ? FWD_IN : BWD_IN, R>(k, c, X, X_s, U, L, col, acc);
       if (k.clov) clover_apply<DM, 1, R>(k, s, acc);
       cplx<R> t[4][3], u[4][3];
       if constexpr (MODE == 0) {

@@ -298,6 +298,41 @@ __device__ __forceinline__ void hop_dir(const GeomK& k, const SiteCtx& c, const 
   }
 }
 
+// Two hops of one sense (forward if F) in directions MU1 and MU2, with the
+// loads of both in flight together.
+template <int PIN, int PL, int C, int ORDER, int HOPS, int MU1, int MU2, int F, typename R>
+__device__ __forceinline__ void hop_two_dirs(const GeomK& k, const SiteCtx& c, const typename Store<PIN>::Elem* in,
+                                             const float* in_s, const LinkElem<PL>* U, int L, int col0,
+                                             cplx<R> (&acc)[4][3][C], R& token) {
+  const bool s1 = hop_skipped<ORDER, HOPS, MU1, F>(k, c), s2 = hop_skipped<ORDER, HOPS, MU2, F>(k, c);
+  int sn1 = neighbour<ORDER>(k, c, MU1, F ? 1 : -1), sn2 = neighbour<ORDER>(k, c, MU2, F ? 1 : -1);
+  int ls1 = F ? c.s : sn1, ls2 = F ? c.s : sn2;
+  asm volatile("" : "+v"(sn1), "+v"(ls1), "+v"(sn2), "+v"(ls2) : "v"(token));
+  HopData<PIN, PL, C> d1, d2;
+  if (!s1) hop_load<PIN, PL, C, MU1>(sn1, ls1, in, in_s, U, L, col0, d1);
+  if (!s2) hop_load<PIN, PL, C, MU2>(sn2, ls2, in, in_s, U, L, col0, d2);
+  if (!s1) hop_pin(d1);
+  if (!s2) hop_pin(d2);
+  if (!s1) hop_compute<PIN, PL, C, HOPS, MU1, F, R>(k, c, d1, acc);
+  if (!s2) hop_compute<PIN, PL, C, HOPS, MU2, F, R>(k, c, d2, acc);
+  hop_settle(acc, token);
+}
+
+// The four hops of one sense (HOPS = FWD_IN or BWD_IN: the triangular parts
+// of A_DD), as two pairs of directions with each pair's loads in flight.
+template <int PIN, int PL, int C, int ORDER, int HOPS, typename R>
+__device__ __forceinline__ void hop_sense_sum(const GeomK& k, const SiteCtx& c,
+                                              const typename Store<PIN>::Elem* __restrict__ in,
+                                              const float* __restrict__ in_s,
+                                              const LinkElem<PL>* __restrict__ U, int L, int col0,
+                                              cplx<R> (&acc)[4][3][C]) {
+  static_assert(HOPS == FWD_IN || HOPS == BWD_IN, "one-sense hop sets only");
+  constexpr int F = HOPS == FWD_IN ? 1 : 0;
+  R token = 0;
+  hop_two_dirs<PIN, PL, C, ORDER, HOPS, 0, 1, F, R>(k, c, in, in_s, U, L, col0, acc, token);
+  hop_two_dirs<PIN, PL, C, ORDER, HOPS, 2, 3, F, R>(k, c, in, in_s, U, L, col0, acc, token);
+}
+
 // All eight hops.
 template <int PIN, int PL, int C, int ORDER, int HOPS, typename R, bool PAIR = false>
 __device__ __forceinline__ void hop_sum(const GeomK& k, const SiteCtx& c,
