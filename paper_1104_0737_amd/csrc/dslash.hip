@@ -395,6 +395,42 @@ __global__ void __launch_bounds__(mr_fused_threads<PR>()) k_mr_fused(GeomK k, do
   }
 }
 
+// MR step, part 2, FP32 storage: the same update as a flat stream over the
+// n*12*L complex entries of the colour, two adjacent entries (float4) per
+// thread, for full-width coalesced loads and stores.  Entry e of site s,
+// column j sits at (s*12 + e)*L + j, so both entries of a pair share the
+// site (L even) and the domain.
+__global__ void __launch_bounds__(256) k_mr_update_flat(GeomK k, int L, int s0, int n, float4* __restrict__ r,
+                                                        const float4* __restrict__ w, float4* __restrict__ psi,
+                                                        const double* __restrict__ omega, int update_r, int assign,
+                                                        const int* __restrict__ frozen) {
+  if (frozen && *frozen) return;
+  const size_t npair = (size_t)n * 6 * L;             // n*12*L entries, two per thread
+  const size_t q = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (q >= npair) return;
+  const size_t e0 = 2 * q;                             // first entry, relative to the colour
+  const int col = (int)(e0 % L);
+  const int s = (int)(e0 / (12 * (size_t)L));          // site within the colour
+  const int dom = s / k.g.Vb;
+  const double* om = omega + ((size_t)dom * L + col) * 2;
+  const float o0r = (float)om[0], o0i = (float)om[1], o1r = (float)om[2], o1i = (float)om[3];
+  const size_t g = (size_t)s0 * 6 * L + q;             // float4 index in the whole field
+  const float4 rv = r[g];
+  // d = omega * r
+  const float d0r = o0r * rv.x - o0i * rv.y, d0i = o0r * rv.y + o0i * rv.x;
+  const float d1r = o1r * rv.z - o1i * rv.w, d1i = o1r * rv.w + o1i * rv.z;
+  if (assign) {
+    psi[g] = make_float4(d0r, d0i, d1r, d1i);
+  } else {
+    const float4 p = psi[g];
+    psi[g] = make_float4(p.x + d0r, p.y + d0i, p.z + d1r, p.w + d1i);
+  }
+  if (!update_r) return;
+  const float4 wv = w[g];
+  r[g] = make_float4(rv.x - (o0r * wv.x - o0i * wv.y), rv.y - (o0r * wv.y + o0i * wv.x),
+                     rv.z - (o1r * wv.z - o1i * wv.w), rv.w - (o1r * wv.w + o1i * wv.z));
+}
+
 // ---------------------------------------------------------------- split-wave kernels
 // Block = (IPB items) x (P hop groups); item = (site, column), IPB = S * L is a
 // multiple of the wave size so every wave belongs to one hop group.  Group h
@@ -1025,9 +1061,22 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
         if (prof) prof->end();
         MBBS_HIP(hipGetLastError());
         if (prof) prof->begin(MBBS_K_MR_UPDATE);
-        hipLaunchKernelGGL((k_mr_update<PR, PPSI>), dim3(ceil_div(n, Su)), dim3(L, Su), 0, st, lat->gk, L, s0,
-                           n, (ER*)b.r, b.r_s, (const ER*)b.w, b.w_s, (EP*)b.psi, b.omega,
-                           (int)(it + 1 < nmr), (int)(cy == 0 && it == 0), frozen);
+        if constexpr (PR == P32 && PPSI == P32) {
+          if (L % 2 == 0) {
+            const size_t npair = (size_t)n * 6 * L;
+            hipLaunchKernelGGL(k_mr_update_flat, dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st, lat->gk,
+                               L, s0, n, (float4*)b.r, (const float4*)b.w, (float4*)b.psi, b.omega,
+                               (int)(it + 1 < nmr), (int)(cy == 0 && it == 0), frozen);
+          } else {
+            hipLaunchKernelGGL((k_mr_update<PR, PPSI>), dim3(ceil_div(n, Su)), dim3(L, Su), 0, st, lat->gk, L, s0,
+                               n, (ER*)b.r, b.r_s, (const ER*)b.w, b.w_s, (EP*)b.psi, b.omega,
+                               (int)(it + 1 < nmr), (int)(cy == 0 && it == 0), frozen);
+          }
+        } else {
+          hipLaunchKernelGGL((k_mr_update<PR, PPSI>), dim3(ceil_div(n, Su)), dim3(L, Su), 0, st, lat->gk, L, s0,
+                             n, (ER*)b.r, b.r_s, (const ER*)b.w, b.w_s, (EP*)b.psi, b.omega,
+                             (int)(it + 1 < nmr), (int)(cy == 0 && it == 0), frozen);
+        }
         if (prof) prof->end();
         MBBS_HIP(hipGetLastError());
       }
