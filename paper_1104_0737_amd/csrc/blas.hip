@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(256) k_gram(int L, size_t N, GramArgs a, doubl
   // pairs 0..NF-1 are full products, NF..NF+ND-1 diagonal-only
   constexpr int NP = NF + ND;
   if (frozen && *frozen) return;
-  extern __shared__ double2 sh[];  // [NP][S][L] Y rows, reused for the reduction
+  extern __shared__ double2 sh[];  // [2][GRAM_MAXPAIR][S][L] Y rows, reused for the reduction
   const int j = threadIdx.x, y = threadIdx.y, S = blockDim.y;
   cplx<double> acc[NF > 0 ? NF : 1][LMAX];
   cplx<double> dacc[ND > 0 ? ND : 1];
@@ -51,11 +51,12 @@ __global__ void __launch_bounds__(256) k_gram(int L, size_t N, GramArgs a, doubl
 #pragma unroll
   for (int p = 0; p < (ND > 0 ? ND : 1); ++p) dacc[p] = cmake(0.0, 0.0);
   const size_t stride = (size_t)gridDim.x * S;
-  for (size_t n0 = (size_t)blockIdx.x * S; n0 < N; n0 += stride) {
+  int buf = 0;   // two row buffers: one barrier per row tile
+  for (size_t n0 = (size_t)blockIdx.x * S; n0 < N; n0 += stride, buf ^= 1) {
     const size_t n = n0 + y;
     cplx<double> xv[NP];
     double2 yv[NP];
-    __syncthreads();
+    double2* rows = sh + (size_t)buf * GRAM_MAXPAIR * S * L;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       double2 xe = make_double2(0, 0), ye = make_double2(0, 0);
@@ -65,18 +66,20 @@ __global__ void __launch_bounds__(256) k_gram(int L, size_t N, GramArgs a, doubl
       }
       xv[p] = cmake(xe.x, xe.y);
       yv[p] = ye;
-      if (p < NF) sh[((size_t)p * S + y) * L + j] = ye;
+      if (p < NF) rows[((size_t)p * S + y) * L + j] = ye;
     }
 #pragma unroll
     for (int p = NF; p < NP; ++p) dacc[p - NF] = dacc[p - NF] + cdot(xv[p], cmake(yv[p].x, yv[p].y));
     if constexpr (NF > 0) {
+      // the buffer written here was last read two tiles ago, before the
+      // barrier of the previous tile
       __syncthreads();
 #pragma unroll
       for (int p = 0; p < NF; ++p)
 #pragma unroll
         for (int q = 0; q < LMAX; ++q) {
           if (q < L) {
-            double2 ye = sh[((size_t)p * S + y) * L + q];
+            double2 ye = rows[((size_t)p * S + y) * L + q];
             acc[p][q] = acc[p][q] + cdot(xv[p], cmake(ye.x, ye.y));
           }
         }
@@ -148,10 +151,15 @@ __global__ void __launch_bounds__(256) k_combo(int L, size_t N, ComboArgs a, dou
   cplx<double> g[LMAX];
 #pragma unroll
   for (int q = 0; q < LMAX; ++q) g[q] = cmake(0.0, 0.0);
+  // rows are staged through LDS only for matrix inputs (and for the output
+  // Gram); without them the rows are independent and need no barriers
+  bool anymat = false;
+  for (int k = 0; k < nin; ++k) anymat = anymat || a.mode[k] == 2;
+  const bool staged = anymat || GM == 2;
   const size_t stride = (size_t)gridDim.x * S;
   for (size_t n0 = (size_t)blockIdx.x * S; n0 < N; n0 += stride) {
     const size_t n = n0 + y;
-    __syncthreads();
+    if (staged) __syncthreads();
     cplx<double> acc = cmake(0.0, 0.0);
     for (int k = 0; k < nin; ++k) {
       if (a.mode[k] == 2) {
@@ -162,7 +170,7 @@ __global__ void __launch_bounds__(256) k_combo(int L, size_t N, ComboArgs a, dou
         else acc = acc + cmake(a.coef[k][0].x, a.coef[k][0].y) * cmake(v.x, v.y);
       }
     }
-    __syncthreads();
+    if (anymat) __syncthreads();
     for (int k = 0; k < nin; ++k) {
       if (a.mode[k] != 2) continue;
       const double2* row = sh + ((size_t)k * S + y) * L;
@@ -495,7 +503,7 @@ template <int LMAX>
 static void launch_gram_l(int L, size_t N, const GramArgs& a, double2* partial, const int* frozen, hipStream_t st) {
   const int S = gram_rows_per_block(L);
   const int nb = gram_blocks(N, L);
-  const size_t shb = (size_t)GRAM_MAXPAIR * S * L * sizeof(double2);
+  const size_t shb = 2 * (size_t)GRAM_MAXPAIR * S * L * sizeof(double2);
   int nf = 0;
   while (nf < a.npair && !a.diag[nf]) ++nf;
   const int nd = a.npair - nf;
