@@ -323,6 +323,8 @@ def mbbs_solve_batched_workspace_size(lats, Ls, params):
 
 
 def mbbs_solve_batched(lats, Ls, Bs, Xs, params, ws, stream=None):
+    """Returns (worst status, [info dict per system]).  Raises MbbsError only
+    when the call fails before any system is solved (arguments, workspace)."""
     n = len(lats)
     la = (ctypes.c_void_p * n)(*[x.value for x in lats])
     Li = (ctypes.c_int * n)(*Ls)
@@ -337,8 +339,14 @@ def mbbs_solve_batched(lats, Ls, Bs, Xs, params, ws, stream=None):
         infos[k].true_res = ctypes.cast(tr, ctypes.POINTER(ctypes.c_double))
         infos[k].rec_res = ctypes.cast(rr, ctypes.POINTER(ctypes.c_double))
         keep.append((tr, rr))
-    rc = _check(lib().mbbs_solve_batched(n, la, Li, Bp, Xp, pa, _dev(ws), ws.numel() * ws.element_size(), infos,
-                                         _stream(stream)))
+    unset = 99                          # not an mbbs status: marks an info the call never filled
+    for k in range(n):
+        infos[k].status = unset
+    rc = lib().mbbs_solve_batched(n, la, Li, Bp, Xp, pa, _dev(ws), ws.numel() * ws.element_size(), infos,
+                                  _stream(stream))
+    if rc < 0 and all(infos[k].status == unset for k in range(n)):
+        _check(rc)                      # the call failed before solving anything
+    # per-system failures: the return value is the worst status, each info has its own
     return rc, [_info_dict(infos[k], keep[k][0], keep[k][1], infos[k].status) for k in range(n)]
 
 

@@ -186,3 +186,43 @@ def test_batched_equals_single():
     finally:
         for l in lats:
             l.close()
+
+
+def test_batched_mixed_solvers_clover_and_a_bad_system():
+    """Batched systems with different domain solvers, precisions and a clover
+    term each equal their single solves; a system with a zero right-hand-side
+    column fails alone (EINVAL) while the others converge."""
+    specs = [((8, 8, 4, 4), (4, 4, 2, 2), 4, dict(domain_solver=1), 0.0),
+             ((4, 4, 4, 8), (2, 2, 2, 4), 3, dict(sap_prec=B.FP16S), 1.2),
+             ((8, 8, 4, 4), (4, 4, 2, 2), 2, dict(domain_solver=1, sap_prec=B.FP64), 1.0),
+             ((4, 4, 4, 4), (2, 2, 2, 2), 2, dict(), 0.0)]
+    lats, Bh, params, singles = [], [], [], []
+    try:
+        for k, (dims, block, L, kw, csw) in enumerate(specs):
+            V = int(np.prod(dims))
+            U = inputs.gauge_field(dims, 0.25, 70 + k)
+            lat = gu.Lattice(dims, block, U, 0.118)
+            if csw:
+                B.mbbs_lattice_set_clover(lat.h, csw)
+            b = inputs.z2_sources(V, L, 80 + k)
+            if k == 3:
+                b[:, 1] = 0            # a zero column: this system is rejected
+            lats.append(lat)
+            Bh.append(b)
+            params.append(B.mbbs_solve_params_default(tol=1e-10, **kw))
+            if k != 3:
+                singles.append(_solve(lat, L, b, tol=1e-10, **kw))
+        Ls = [s[2] for s in specs]
+        ws = torch.empty(B.mbbs_solve_batched_workspace_size([l.h for l in lats], Ls, params),
+                         dtype=torch.uint8, device="cuda")
+        Bs = [gu.dev(b) for b in Bh]
+        Xs = [torch.empty_like(b) for b in Bs]
+        rc, infos = B.mbbs_solve_batched([l.h for l in lats], Ls, Bs, Xs, params, ws)
+        assert rc == B.EINVAL
+        assert infos[3]["status"] == B.EINVAL
+        for (X1, i1), Xb, ib in zip(singles, Xs[:3], infos[:3]):
+            assert ib["status"] == B.OK and ib["iterations"] == i1["iterations"]
+            np.testing.assert_allclose(gu.host(Xb), X1, atol=1e-12 * np.abs(X1).max())
+    finally:
+        for l in lats:
+            l.close()
