@@ -12,7 +12,7 @@ namespace mbbs {
 // ---------------------------------------------------------------- kernels
 // Thread layout: threadIdx.x = column chunk (C columns each), threadIdx.y =
 // site within the block; blocks cover consecutive sites of the field order.
-template <int PIN, int POUT, int PL, int C, int ORDER, bool BLOCKED, bool PAIR = false>
+template <int PIN, int POUT, int PL, int C, int ORDER, bool BLOCKED, bool PAIR = false, int LT = 0>
 __global__ void __launch_bounds__(256) k_dslash(GeomK k, double kappa, int L,
                                                 const typename Store<PIN>::Elem* __restrict__ in,
                                                 const float* __restrict__ in_s,
@@ -21,6 +21,8 @@ __global__ void __launch_bounds__(256) k_dslash(GeomK k, double kappa, int L,
                                                 const LinkElem<PL>* __restrict__ U, int s0, int n,
                                                 int bpt, int ngroups, const int* __restrict__ frozen) {
   if (frozen && *frozen) return;
+  // LT > 0: L known at compile time, so element offsets become immediates
+  if constexpr (LT > 0) L = LT;
   using R = typename Store<PL>::Real;
   int i, grp;
   decompose(xcd_block(blockIdx.x, gridDim.x), bpt, ngroups, blockDim.y, i, grp);
@@ -58,7 +60,7 @@ __global__ void __launch_bounds__(256) k_dslash(GeomK k, double kappa, int L,
 // mode 1: psi = 0 on this colour (second half-sweep of the first cycle): only
 //         hops leaving the domain see a nonzero psi, r = eta + kappa H_out psi.
 // mode 2: general case.
-template <int PR, int PPSI, int PL, int C, bool PAIR = false>
+template <int PR, int PPSI, int PL, int C, bool PAIR = false, int LT = 0>
 __global__ void __launch_bounds__(256) k_sap_resid(GeomK k, double kappa, int L, int s0, int n, int mode,
                                                    const typename Store<PR>::Elem* __restrict__ eta,
                                                    const float* __restrict__ eta_s,
@@ -68,6 +70,7 @@ __global__ void __launch_bounds__(256) k_sap_resid(GeomK k, double kappa, int L,
                                                    const LinkElem<PL>* __restrict__ U, int bpt,
                                                    int ngroups, const int* __restrict__ frozen) {
   if (frozen && *frozen) return;
+  if constexpr (LT > 0) L = LT;
   using R = typename Store<PL>::Real;
   int i, grp;
   decompose(xcd_block(blockIdx.x, gridDim.x), bpt, ngroups, blockDim.y, i, grp);
@@ -115,7 +118,7 @@ __global__ void __launch_bounds__(256) k_sap_resid(GeomK k, double kappa, int L,
 
 // MR step, part 1: w = A_DD r on one colour's domains, plus per-block sums of
 // <w, r> and <w, w> per column.
-template <int PR, int PL, int C, bool PAIR = false>
+template <int PR, int PL, int C, bool PAIR = false, int LT = 0>
 __global__ void __launch_bounds__(256) k_mr_dslash(GeomK k, double kappa, int L, int s0, int n,
                                                    const typename Store<PR>::Elem* __restrict__ r,
                                                    const float* __restrict__ r_s,
@@ -125,6 +128,7 @@ __global__ void __launch_bounds__(256) k_mr_dslash(GeomK k, double kappa, int L,
                                                    double* __restrict__ partial, int bpt, int ngroups,
                                                    const int* __restrict__ frozen) {
   if (frozen && *frozen) return;
+  if constexpr (LT > 0) L = LT;
   using R = typename Store<PL>::Real;
   extern __shared__ double red[];  // [3][blockDim.y][blockDim.x*C]
   int i, grp;
@@ -841,7 +845,18 @@ static int dslash_dispatch_order(const mbbs_lattice_s* lat, int L, int order, bo
                      (const EI*)in, in_s, (EO*)out, out_s, (const EL*)U, s0, n, pl.bpt, pl.ngroups, frozen)
   if (order == LEX) {
     if (blocked) MBBS_LAUNCH(LEX, true);
-    else if (lat->hop_pair[PL])
+    else if (C <= 2 && L == 12) {   // the common block width, with compile-time element offsets
+      if constexpr (C <= 2) {
+        if (lat->hop_pair[PL])
+          hipLaunchKernelGGL((k_dslash<PIN, POUT, PL, C, LEX, false, true, 12>), grd, blk,
+                             (size_t)lat->lds_pad_kb * 1024, st, gk, lat->kappa, L, (const EI*)in, in_s, (EO*)out,
+                             out_s, (const EL*)U, s0, n, pl.bpt, pl.ngroups, frozen);
+        else
+          hipLaunchKernelGGL((k_dslash<PIN, POUT, PL, C, LEX, false, false, 12>), grd, blk,
+                             (size_t)lat->lds_pad_kb * 1024, st, gk, lat->kappa, L, (const EI*)in, in_s, (EO*)out,
+                             out_s, (const EL*)U, s0, n, pl.bpt, pl.ngroups, frozen);
+      }
+    } else if (lat->hop_pair[PL])
       hipLaunchKernelGGL((k_dslash<PIN, POUT, PL, C, LEX, false, true>), grd, blk, (size_t)lat->lds_pad_kb * 1024, st,
                          gk, lat->kappa, L, (const EI*)in, in_s, (EO*)out, out_s, (const EL*)U, s0, n, pl.bpt,
                          pl.ngroups, frozen);
@@ -995,14 +1010,26 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
         }
       } else {
 #define RES(CC, PV)                                                                                  \
+  if (L == 12)                                                                                       \
+    hipLaunchKernelGGL((k_sap_resid<PR, PPSI, PL, CC, PV, 12>), dim3(pl.nblocks), dim3(pl.nchunk, S),        \
+                       (size_t)lat->lds_pad_kb * 1024, st,                                                   \
+                       lat->gk, lat->kappa, L, s0, n, cy > 0 ? 2 : col, (const ER*)b.eta,              \
+                       b.eta_s, (const EP*)b.psi, (ER*)b.r, b.r_s, U, pl.bpt, pl.ngroups, frozen);      \
+  else                                                                                               \
   hipLaunchKernelGGL((k_sap_resid<PR, PPSI, PL, CC, PV>), dim3(pl.nblocks), dim3(pl.nchunk, S),              \
                      (size_t)lat->lds_pad_kb * 1024, st,                                                     \
                      lat->gk, lat->kappa, L, s0, n, cy > 0 ? 2 : col, (const ER*)b.eta,                \
                      b.eta_s, (const EP*)b.psi, (ER*)b.r, b.r_s, U, pl.bpt, pl.ngroups, frozen)
       const bool pr = lat->hop_pair[PL] != 0;
       switch (C) {
-        case 4: RES(4, false); break;
-        case 3: RES(3, false); break;
+        case 4: hipLaunchKernelGGL((k_sap_resid<PR, PPSI, PL, 4>), dim3(pl.nblocks), dim3(pl.nchunk, S),
+                                   (size_t)lat->lds_pad_kb * 1024, st, lat->gk, lat->kappa, L, s0, n,
+                                   cy > 0 ? 2 : col, (const ER*)b.eta, b.eta_s, (const EP*)b.psi, (ER*)b.r,
+                                   b.r_s, U, pl.bpt, pl.ngroups, frozen); break;
+        case 3: hipLaunchKernelGGL((k_sap_resid<PR, PPSI, PL, 3>), dim3(pl.nblocks), dim3(pl.nchunk, S),
+                                   (size_t)lat->lds_pad_kb * 1024, st, lat->gk, lat->kappa, L, s0, n,
+                                   cy > 0 ? 2 : col, (const ER*)b.eta, b.eta_s, (const EP*)b.psi, (ER*)b.r,
+                                   b.r_s, U, pl.bpt, pl.ngroups, frozen); break;
         case 2: if (pr) RES(2, true); else RES(2, false); break;
         default: if (pr) RES(1, true); else RES(1, false);
       }
@@ -1042,14 +1069,26 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
           }
         } else {
 #define MRD(CC, PV)                                                                                   \
+  if (L == 12)                                                                                        \
+    hipLaunchKernelGGL((k_mr_dslash<PR, PL, CC, PV, 12>), dim3(pl.nblocks), dim3(pl.nchunk, S),             \
+                       red_bytes + (size_t)lat->lds_pad_kb * 1024, st, lat->gk,                              \
+                       lat->kappa, L, s0, n, (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial, pl.bpt, \
+                       pl.ngroups, frozen);                                                                \
+  else                                                                                                \
   hipLaunchKernelGGL((k_mr_dslash<PR, PL, CC, PV>), dim3(pl.nblocks), dim3(pl.nchunk, S),                   \
                      red_bytes + (size_t)lat->lds_pad_kb * 1024, st, lat->gk,                                \
                      lat->kappa, L, s0, n, (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial, pl.bpt,   \
                      pl.ngroups, frozen)
         const bool pr = lat->hop_pair[PL] != 0;
         switch (C) {
-          case 4: MRD(4, false); break;
-          case 3: MRD(3, false); break;
+          case 4: hipLaunchKernelGGL((k_mr_dslash<PR, PL, 4>), dim3(pl.nblocks), dim3(pl.nchunk, S),
+                                     red_bytes + (size_t)lat->lds_pad_kb * 1024, st, lat->gk, lat->kappa, L, s0,
+                                     n, (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial, pl.bpt, pl.ngroups,
+                                     frozen); break;
+          case 3: hipLaunchKernelGGL((k_mr_dslash<PR, PL, 3>), dim3(pl.nblocks), dim3(pl.nchunk, S),
+                                     red_bytes + (size_t)lat->lds_pad_kb * 1024, st, lat->gk, lat->kappa, L, s0,
+                                     n, (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial, pl.bpt, pl.ngroups,
+                                     frozen); break;
           case 2: if (pr) MRD(2, true); else MRD(2, false); break;
           default: if (pr) MRD(1, true); else MRD(1, false);
         }
