@@ -34,9 +34,10 @@ __device__ inline double2 block_reduce_y(double2* sh, cplx<double> v, int j, int
 // LDS), reduces over y in LDS and writes its partial Gram matrices.  The pair
 // count NP and the column bound LMAX are compile-time so that the
 // accumulators stay in registers.
-template <int LMAX, int NF, int ND>
+template <int LMAX, int NF, int ND, bool EXACT = false>
 __global__ void __launch_bounds__(256) k_gram(int L, size_t N, GramArgs a, double2* __restrict__ partial,
                                               const int* __restrict__ frozen) {
+  if constexpr (EXACT) L = LMAX;   // L known at compile time: immediate offsets, no column bounds
   // pairs 0..NF-1 are full products, NF..NF+ND-1 diagonal-only
   constexpr int NP = NF + ND;
   if (frozen && *frozen) return;
@@ -136,9 +137,10 @@ __global__ void __launch_bounds__(256) k_gram_finish(int L, int nblk, const doub
 // inputs stage their rows in LDS before any output is written, so an output
 // may alias one of the inputs.  Optionally accumulates the Gram matrix (or
 // only the column norms) of the output, as GRAM partials.
-template <int LMAX, int GM>
+template <int LMAX, int GM, bool EXACT = false>
 __global__ void __launch_bounds__(256) k_combo(int L, size_t N, ComboArgs a, double2* __restrict__ out,
                                                double2* __restrict__ partial, const int* __restrict__ frozen) {
+  if constexpr (EXACT) L = LMAX;
   if (frozen && *frozen) return;
   extern __shared__ double2 sh[];  // [nmat][S][L] rows, then [nmat][L][L] coefficients
   const int j = threadIdx.x, y = threadIdx.y, S = blockDim.y;
@@ -507,7 +509,13 @@ static void launch_gram_l(int L, size_t N, const GramArgs& a, double2* partial, 
   int nf = 0;
   while (nf < a.npair && !a.diag[nf]) ++nf;
   const int nd = a.npair - nf;
-#define GL(F, D) hipLaunchKernelGGL((k_gram<LMAX, F, D>), dim3(nb), dim3(L, S), shb, st, L, N, a, partial, frozen)
+#define GL(F, D)                                                                                         \
+  do {                                                                                                   \
+    if (L == LMAX)                                                                                       \
+      hipLaunchKernelGGL((k_gram<LMAX, F, D, true>), dim3(nb), dim3(L, S), shb, st, L, N, a, partial, frozen); \
+    else                                                                                                 \
+      hipLaunchKernelGGL((k_gram<LMAX, F, D>), dim3(nb), dim3(L, S), shb, st, L, N, a, partial, frozen);     \
+  } while (0)
   if (nf == 1 && nd == 0) GL(1, 0);
   else if (nf == 2 && nd == 0) GL(2, 0);
   else if (nf == 1 && nd == 2) GL(1, 2);
@@ -542,7 +550,10 @@ static void launch_combo_l(int L, size_t N, const ComboArgs& a, double2* out, do
   const int S = gram_rows_per_block(L);
   const int nb = gram_blocks(N, L);
   const size_t shb = ((size_t)COMBO_MAXIN * S * L + (size_t)COMBO_MAXIN * L * L) * sizeof(double2);
-  hipLaunchKernelGGL((k_combo<LMAX, GM>), dim3(nb), dim3(L, S), shb, st, L, N, a, out, partial, frozen);
+  if (L == LMAX)
+    hipLaunchKernelGGL((k_combo<LMAX, GM, true>), dim3(nb), dim3(L, S), shb, st, L, N, a, out, partial, frozen);
+  else
+    hipLaunchKernelGGL((k_combo<LMAX, GM>), dim3(nb), dim3(L, S), shb, st, L, N, a, out, partial, frozen);
 }
 
 int launch_combo(int L, size_t N, const ComboArgs& a, double2* out, int gram_mode, const GramOut* o,

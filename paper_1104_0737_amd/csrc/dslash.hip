@@ -1127,12 +1127,13 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
 // Conversion kernels between the FP64 lexicographic block and the SAP
 // domain-major storage.  to_sap optionally right-multiplies by an L x L
 // matrix first (the Cholesky-QR factor gamma^{-1}, folded into the copy).
-template <int PR>
+template <int PR, int LT = 0>
 __global__ void __launch_bounds__(256) k_to_sap(GeomK k, int L, const double2* __restrict__ in,
                                                 const double2* __restrict__ gam,
                                                 typename Store<PR>::Elem* __restrict__ out,
                                                 float* __restrict__ out_s, const int* __restrict__ frozen) {
   if (frozen && *frozen) return;
+  if constexpr (LT > 0) L = LT;
   using R = typename Store<PR>::Real;
   extern __shared__ double2 gsh[];
   const int tid = threadIdx.y * blockDim.x + threadIdx.x;
@@ -1173,10 +1174,11 @@ __global__ void __launch_bounds__(256) k_to_sap(GeomK k, int L, const double2* _
   store_spinor<PR, R>(out, out_s, (size_t)s * 12 * L + j, L, (size_t)s * L + j, vr);
 }
 
-template <int PPSI>
+template <int PPSI, int LT = 0>
 __global__ void __launch_bounds__(256) k_from_sap(GeomK k, int L, const typename Store<PPSI>::Elem* __restrict__ in,
                                                   double2* __restrict__ out, const int* __restrict__ frozen) {
   if (frozen && *frozen) return;
+  if constexpr (LT > 0) L = LT;
   const int s = blockIdx.x * blockDim.y + threadIdx.y;
   if (s >= k.g.V) return;
   const int j = threadIdx.x;
@@ -1197,10 +1199,20 @@ int sap_to(const mbbs_lattice_s* lat, const SapBuffers& b, const double2* in, co
   const Geom& g = lat->g;
   const int S = sites_per_block(L, g.V);
   const size_t gsh = gam ? (size_t)L * L * sizeof(double2) : 0;
+  const bool l12 = L == 12;   // compile-time row offsets for the common block width
   switch (b.prec) {
-    case P64: hipLaunchKernelGGL((k_to_sap<P64>), dim3(ceil_div(g.V, S)), dim3(L, S), gsh, st, lat->gk, L, in, gam, (double2*)dst, nullptr, frozen); break;
-    case P32: hipLaunchKernelGGL((k_to_sap<P32>), dim3(ceil_div(g.V, S)), dim3(L, S), gsh, st, lat->gk, L, in, gam, (float2*)dst, nullptr, frozen); break;
-    default: hipLaunchKernelGGL((k_to_sap<P16>), dim3(ceil_div(g.V, S)), dim3(L, S), gsh, st, lat->gk, L, in, gam, (__half2*)dst, dst_s, frozen); break;
+    case P64:
+      if (l12) hipLaunchKernelGGL((k_to_sap<P64, 12>), dim3(ceil_div(g.V, S)), dim3(L, S), gsh, st, lat->gk, L, in, gam, (double2*)dst, nullptr, frozen);
+      else hipLaunchKernelGGL((k_to_sap<P64>), dim3(ceil_div(g.V, S)), dim3(L, S), gsh, st, lat->gk, L, in, gam, (double2*)dst, nullptr, frozen);
+      break;
+    case P32:
+      if (l12) hipLaunchKernelGGL((k_to_sap<P32, 12>), dim3(ceil_div(g.V, S)), dim3(L, S), gsh, st, lat->gk, L, in, gam, (float2*)dst, nullptr, frozen);
+      else hipLaunchKernelGGL((k_to_sap<P32>), dim3(ceil_div(g.V, S)), dim3(L, S), gsh, st, lat->gk, L, in, gam, (float2*)dst, nullptr, frozen);
+      break;
+    default:
+      if (l12) hipLaunchKernelGGL((k_to_sap<P16, 12>), dim3(ceil_div(g.V, S)), dim3(L, S), gsh, st, lat->gk, L, in, gam, (__half2*)dst, dst_s, frozen);
+      else hipLaunchKernelGGL((k_to_sap<P16>), dim3(ceil_div(g.V, S)), dim3(L, S), gsh, st, lat->gk, L, in, gam, (__half2*)dst, dst_s, frozen);
+      break;
   }
   MBBS_HIP(hipGetLastError());
   return MBBS_OK;
@@ -1210,10 +1222,13 @@ int sap_from(const mbbs_lattice_s* lat, const SapBuffers& b, double2* out, const
   const int L = b.L;
   const Geom& g = lat->g;
   const int S = sites_per_block(L, g.V);
-  if (b.prec == P64)
-    hipLaunchKernelGGL((k_from_sap<P64>), dim3(ceil_div(g.V, S)), dim3(L, S), 0, st, lat->gk, L, (const double2*)b.psi, out, frozen);
-  else
-    hipLaunchKernelGGL((k_from_sap<P32>), dim3(ceil_div(g.V, S)), dim3(L, S), 0, st, lat->gk, L, (const float2*)b.psi, out, frozen);
+  if (b.prec == P64) {
+    if (L == 12) hipLaunchKernelGGL((k_from_sap<P64, 12>), dim3(ceil_div(g.V, S)), dim3(L, S), 0, st, lat->gk, L, (const double2*)b.psi, out, frozen);
+    else hipLaunchKernelGGL((k_from_sap<P64>), dim3(ceil_div(g.V, S)), dim3(L, S), 0, st, lat->gk, L, (const double2*)b.psi, out, frozen);
+  } else {
+    if (L == 12) hipLaunchKernelGGL((k_from_sap<P32, 12>), dim3(ceil_div(g.V, S)), dim3(L, S), 0, st, lat->gk, L, (const float2*)b.psi, out, frozen);
+    else hipLaunchKernelGGL((k_from_sap<P32>), dim3(ceil_div(g.V, S)), dim3(L, S), 0, st, lat->gk, L, (const float2*)b.psi, out, frozen);
+  }
   MBBS_HIP(hipGetLastError());
   return MBBS_OK;
 }

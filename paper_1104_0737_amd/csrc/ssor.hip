@@ -152,7 +152,7 @@ __device__ __forceinline__ void ssor_sweep(const GeomK& k, int L, int base_site,
 // formed in the first sweep (modes as in the SAP residual kernel).  The
 // fields are written and read by other threads of the workgroup between
 // barriers: no restrict / const qualifiers on them.
-template <int PR, int PPSI, int PL>
+template <int PR, int PPSI, int PL, int LT = 0>
 __global__ void __launch_bounds__(ssor_threads<PR>()) k_ssor(GeomK k, double kappa, int L, int s0, double omega,
                                                              int nssor, int assign, int rmode,
                                                              SsorFields<PR, PPSI> f,
@@ -161,6 +161,7 @@ __global__ void __launch_bounds__(ssor_threads<PR>()) k_ssor(GeomK k, double kap
                                                              const int* __restrict__ hp_off, int nh,
                                                              const int* __restrict__ frozen) {
   if (frozen && *frozen) return;
+  if constexpr (LT > 0) L = LT;   // compile-time element offsets for the common block width
   const int base_site = s0 + blockIdx.x * k.g.Vb;
   if (rmode < 0)
     ssor_sweep<PR, PPSI, PL, true, 0>(k, L, base_site, kappa, omega, f, rmode, assign, U, hp_loc, hp_off, nh);
@@ -191,9 +192,14 @@ static int ssor_launch(const mbbs_lattice_s* lat, const SapBuffers& b, int colou
   f.a = (ER*)b.w; f.a_s = b.w_s;
   f.b = (ER*)b.x2; f.b_s = b.x2_s;
   f.psi = (EP*)b.psi;
-  hipLaunchKernelGGL((k_ssor<PR, PPSI, PL>), dim3(g.ndom / 2), dim3(T), 0, st, lat->gk, lat->kappa, b.L,
-                     colour * g.Vh, b.ssor_omega, b.nssor, (int)assign, rmode, f, U, (const int*)lat->hp_loc,
-                     (const int*)lat->hp_off, lat->nh, frozen);
+  if (b.L == 12)
+    hipLaunchKernelGGL((k_ssor<PR, PPSI, PL, 12>), dim3(g.ndom / 2), dim3(T), 0, st, lat->gk, lat->kappa, b.L,
+                       colour * g.Vh, b.ssor_omega, b.nssor, (int)assign, rmode, f, U, (const int*)lat->hp_loc,
+                       (const int*)lat->hp_off, lat->nh, frozen);
+  else
+    hipLaunchKernelGGL((k_ssor<PR, PPSI, PL>), dim3(g.ndom / 2), dim3(T), 0, st, lat->gk, lat->kappa, b.L,
+                       colour * g.Vh, b.ssor_omega, b.nssor, (int)assign, rmode, f, U, (const int*)lat->hp_loc,
+                       (const int*)lat->hp_off, lat->nh, frozen);
   MBBS_HIP(hipGetLastError());
   return MBBS_OK;
 }
