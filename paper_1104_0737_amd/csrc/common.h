@@ -38,6 +38,21 @@ __host__ __device__ __forceinline__ cplx<R> cdot(cplx<R> a, cplx<R> b) {
 template <typename R>
 __host__ __device__ __forceinline__ R norm2(cplx<R> a) { return a.re * a.re + a.im * a.im; }
 
+// Fused multiply-adds, written out so that a complex multiply-accumulate is
+// four FMAs (the compiler contracts a*b - c*d + s into mul + fma + add).
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// s + a * b
+template <typename R>
+__device__ __forceinline__ cplx<R> cmac(cplx<R> s, cplx<R> a, cplx<R> b) {
+  return {fmar(-a.im, b.im, fmar(a.re, b.re, s.re)), fmar(a.im, b.re, fmar(a.re, b.im, s.im))};
+}
+// s + conj(a) * b
+template <typename R>
+__device__ __forceinline__ cplx<R> cmac_conj(cplx<R> s, cplx<R> a, cplx<R> b) {
+  return {fmar(a.im, b.im, fmar(a.re, b.re, s.re)), fmar(-a.im, b.re, fmar(a.re, b.im, s.im))};
+}
+
 // Multiply by one of the units +1, +i, -1, -i (code 0..3).
 template <int U, typename R>
 __device__ __forceinline__ cplx<R> unit_mul(cplx<R> a) {

@@ -172,8 +172,11 @@ __global__ void __launch_bounds__(256) k_mr_dslash(GeomK k, double kappa, int L,
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        cplx<R> d = cdot(wv[sp][a], v[sp][a]);
-        a_re += d.re; a_im += d.im; a_ww += norm2(wv[sp][a]);
+        // <w, r> and <w, w> as FMA chains
+        const cplx<R> x = wv[sp][a], y = v[sp][a];
+        a_re = fmar(x.re, y.re, fmar(x.im, y.im, a_re));
+        a_im = fmar(x.re, y.im, fmar(-x.im, y.re, a_im));
+        a_ww = fmar(x.re, x.re, fmar(x.im, x.im, a_ww));
       }
     wr_re = a_re; wr_im = a_im; ww = a_ww;
     const int col = threadIdx.x * C + q;             // column within the group
@@ -343,8 +346,10 @@ __global__ void __launch_bounds__(mr_fused_threads<PR>()) k_mr_fused(GeomK k, do
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
-            cplx<R> d = cdot(wv[sp][a], v[sp][a]);
-            a_re += d.re; a_im += d.im; a_ww += norm2(wv[sp][a]);
+            const cplx<R> x = wv[sp][a], y = v[sp][a];
+            a_re = fmar(x.re, y.re, fmar(x.im, y.im, a_re));
+            a_im = fmar(x.re, y.im, fmar(-x.im, y.re, a_im));
+            a_ww = fmar(x.re, x.re, fmar(x.im, x.im, a_ww));
           }
         sr += a_re; si += a_im; sw += a_ww;
       }

@@ -228,11 +228,11 @@ __device__ __forceinline__ void hop_compute(const GeomK& k, const SiteCtx& c, co
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
         if constexpr (FWD) {  // U h
-          s0 = s0 + u.m[a][b] * h0[b];
-          s1 = s1 + u.m[a][b] * h1[b];
+          s0 = cmac(s0, u.m[a][b], h0[b]);
+          s1 = cmac(s1, u.m[a][b], h1[b]);
         } else {              // U^dagger h
-          s0 = s0 + cdot(u.m[b][a], h0[b]);
-          s1 = s1 + cdot(u.m[b][a], h1[b]);
+          s0 = cmac_conj(s0, u.m[b][a], h0[b]);
+          s1 = cmac_conj(s1, u.m[b][a], h1[b]);
         }
       }
       x0[a] = s0; x1[a] = s1;
