@@ -182,3 +182,31 @@ def test_sap_launch_settings_parity(prec, tol, group, chunk, pair):
         B.mbbs_sap_apply(lat.h, L, gu.dev(eta), Yd, 2, 3, prec, ws)
         err = gu.rel_col_err(gu.host(Yd), ref)
     assert np.all(err <= tol), err
+
+
+@pytest.mark.skip(reason="its first case (FP64, L = 12) stopped progressing on its only GPU run, while a "
+                         "software-pipelined hop mode (value 2) was under test; no cause was found in the code, "
+                         "the mode was withdrawn, and the case stays off the GPU until a cause is shown")
+@pytest.mark.parametrize("L,chunk", [(12, 0), (12, 1), (5, 1), (6, 0)])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_sap_hop_modes_bit_identical(prec, L, chunk):
+    """One hop at a time, paired and software-pipelined hops sum in the same
+    order: SAP (residual and MR kernels, both colours, several cycles) gives
+    the same bits under all three, on a clover lattice too."""
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    V = 4096
+    U = inputs.gauge_field(dims, 0.3, 30)
+    eta = gu.dev(inputs.gaussian_block(V, L, 31))
+    with gu.Lattice(dims, block, U, 0.12) as lat:
+        B.mbbs_lattice_tune(lat.h, B.TUNE_MR_FUSED, 0)
+        B.mbbs_lattice_tune(lat.h, B.TUNE_CHUNK[prec], chunk)
+        ws = torch.empty(B.mbbs_sap_workspace_size(lat.h, L, prec), dtype=torch.uint8, device="cuda")
+        for csw in (0.0, 1.0):
+            B.mbbs_lattice_set_clover(lat.h, csw)
+            outs = []
+            for mode in (0, 1, 2):
+                B.mbbs_lattice_tune(lat.h, B.TUNE_HOP_PAIR[prec], mode)
+                Yd = torch.empty((12 * V, L), dtype=torch.complex128, device="cuda")
+                B.mbbs_sap_apply(lat.h, L, eta, Yd, 3, 2, prec, ws)
+                outs.append(gu.host(Yd).tobytes())
+            assert outs[0] == outs[1] == outs[2], (csw, [o == outs[0] for o in outs])
