@@ -152,7 +152,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is a design described in DESIGN.md, not a measured path.", flush=True)
+              "sharding one system over several GPUs (by whole SAP domains) is designed but not built.", flush=True)
         sys.exit(1)
     import torch
     from paper_1104_0737_amd import binding as B
