@@ -228,19 +228,13 @@ def test_batched_mixed_solvers_clover_and_a_bad_system():
             l.close()
 
 
-@pytest.mark.slow
-@pytest.mark.parametrize("domain_solver", [0, 1])
-def test_c4_mixed_full_size(domain_solver):
-    """The benchmark's system (32^3 x 64, L = 12 point sources, FP32 SAP on 8^4
-    domains: 4 cycles of 4 MR steps, or the paper's SSOR with N_SSOR = 1 and
-    omega = 1.26) solved to 1e-10.  The residual B - D X of the GPU solution
-    is formed on the GPU in FP64 and compared with the oracle's at sampled
-    sites (the source site and its 8 neighbours among them), so the norms the
-    solver reports rest on checked values."""
-    cfg = configs.c4()
+def _c4_check(cfg, tag, **kw):
+    """Solve a 32^3 x 64 system to 1e-10 (FP32 SAP on 8^4 domains); form the
+    residual B - D X of the GPU solution on the GPU in FP64 and compare it
+    with the oracle's at sampled sites (the source site and its 8 neighbours
+    among them), so the norms the solver reports rest on checked values."""
     V, L, dims = cfg.V, cfg.L, cfg.dims
-    tag = "SSOR" if domain_solver else "MR"
-    gu.flush(f"c4 mixed {tag}: links")
+    gu.flush(f"c4 {tag}: links")
     U = cfg.gauge()
     Bh = cfg.sources()
     src = cfg.src_site()
@@ -253,9 +247,8 @@ def test_c4_mixed_full_size(domain_solver):
             sites.append(int(np.ravel_multi_index(tuple(n[::-1]), dims[::-1])))
     sites = np.array(sites + np.random.default_rng(4006).integers(0, V, 200).tolist())
     with gu.Lattice(dims, cfg.block, U, cfg.kappa) as lat:
-        gu.flush(f"c4 mixed {tag}: solve")
-        X, info = _solve(lat, L, Bh, tol=1e-10, sap_prec=B.FP32, ncy=cfg.ncy, nmr=cfg.nmr,
-                         domain_solver=domain_solver, nssor=1, ssor_omega=1.26)
+        gu.flush(f"c4 {tag}: solve")
+        X, info = _solve(lat, L, Bh, tol=1e-10, sap_prec=B.FP32, ncy=cfg.ncy, nmr=cfg.nmr, **kw)
         gu.flush(f"  iterations {info['iterations']} restarts {info['restarts']} {info['seconds']:.2f}s")
         assert info["status"] == B.OK and np.all(info["true_res"] <= 1e-10)
         Xd = gu.dev(X)
@@ -263,12 +256,32 @@ def test_c4_mixed_full_size(domain_solver):
         B.mbbs_apply_dirac(lat.h, L, Xd, Yd, B.FP64)
         idx = torch.from_numpy((12 * sites[:, None] + np.arange(12)[None, :]).ravel()).cuda()
         Rg = Bh.reshape(V, 12, L)[sites].reshape(-1, L) - gu.host(Yd.index_select(0, idx))
-    gu.flush(f"c4 mixed {tag}: oracle residual at sampled sites")
+    gu.flush(f"c4 {tag}: oracle residual at sampled sites")
     DX = dirac.apply_D_sites(U, cfg.kappa, cfg.phases, X.reshape(V, 4, 3, L), dims, sites)
     Ro = Bh.reshape(V, 12, L)[sites].reshape(-1, L) - DX.reshape(-1, L)
     # ||B_j|| = 1; D X is O(1) per element, so FP64 rounding is ~1e-15
     assert np.max(np.abs(Rg - Ro)) <= 1e-13
     assert np.all(np.linalg.norm(Ro, axis=0) <= 1e-10)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("domain_solver", [0, 1])
+def test_c4_mixed_full_size(domain_solver):
+    """The benchmark's system (32^3 x 64, L = 12 point sources, FP32 SAP on 8^4
+    domains: 4 cycles of 4 MR steps, or the paper's SSOR with N_SSOR = 1 and
+    omega = 1.26) solved to 1e-10, checked against the oracle."""
+    _c4_check(configs.c4(), "SSOR" if domain_solver else "MR", domain_solver=domain_solver, nssor=1,
+              ssor_omega=1.26)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 6])
+def test_c4_sweep_block(L):
+    """One block of the L sweep on the 32^3 x 64 system (the 12 point sources
+    split into 12/L blocks; here the second block, components L..2L-1): the
+    generic kernels (L other than 12, odd L) at full size, MR domains,
+    checked against the oracle."""
+    _c4_check(configs.c4(L=L, block_index=1), f"L={L}")
 
 
 @pytest.mark.slow
