@@ -319,6 +319,11 @@ def main():
     wall = time.perf_counter() - t_start
     ok = all(i["status"] == 0 and np.all(i["true_res"] <= cfg.tol) for i in infos)
 
+    def rel_diff(Xa, Xb):
+        """max over columns of ||Xa - Xb|| / ||Xb|| (two solutions of the same system)."""
+        return float((torch.linalg.vector_norm(Xa - Xb, dim=0) / torch.linalg.vector_norm(Xb, dim=0)).max())
+    X_main = Xd.clone() if not args.no_fp64_solve else None
+
     # the other SAP storage precision, once, for comparison
     other = None
     if not args.no_fp64_solve:
@@ -326,6 +331,7 @@ def main():
         oname = "fp16s" if oprec == B.FP16S else "fp32"
         log(f"{oname}-SAP solve")
         dto, io = run_solve(oprec, 0)
+        X_other = Xd.clone()
         other = {"sap_prec": oname, "seconds": dto, "tts_per_rhs_s": dto / L, "iterations": io["iterations"],
                  "max_true_res": float(io["true_res"].max()), "status": io["status"]}
         log(f"  {dto:.2f}s, {io['iterations']} iterations, max true residual {io['true_res'].max():.2e}")
@@ -337,6 +343,13 @@ def main():
         fp64 = {"seconds": dt64, "tts_per_rhs_s": dt64 / L, "iterations": i64["iterations"],
                 "max_true_res": float(i64["true_res"].max()), "status": i64["status"]}
         log(f"  {dt64:.2f}s, {i64['iterations']} iterations")
+        # how far the mixed-precision solutions lie from the all-FP64 one
+        X64 = Xd.clone()
+        fp64["max_rel_diff_of_main_solution"] = rel_diff(X_main, X64)
+        if other is not None:
+            other["max_rel_diff_vs_fp64_solution"] = rel_diff(X_other, X64)
+            del X_other
+        del X_main
 
     # the paper's own domain solver (SSOR, N_SSOR = 1, omega = 1.26), once, for comparison
     ssor_alt = None
@@ -347,7 +360,8 @@ def main():
         args.domain_solver = "mr"
         ssor_alt = {"seconds": dts, "tts_per_rhs_s": dts / L, "iterations": isr["iterations"],
                     "max_true_res": float(isr["true_res"].max()), "status": isr["status"],
-                    "nssor": args.nssor, "omega": args.ssor_omega}
+                    "nssor": args.nssor, "omega": args.ssor_omega,
+                    "max_rel_diff_vs_fp64_solution": rel_diff(Xd, X64)}
         log(f"  {dts:.2f}s, {isr['iterations']} iterations, max true residual {isr['true_res'].max():.2e}")
 
     # ------------------------------------------------------------ accounting
