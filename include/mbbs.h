@@ -112,7 +112,10 @@ int mbbs_lattice_table(mbbs_lattice_t lat, int which, int32_t* out, size_t count
  *  MBBS_TUNE_GROUP_FP64/FP32/FP16S  columns processed per column group by one
  *      pass of blocks over a tile (0 = all L columns; must divide L and be a
  *      multiple of the kernel's columns per thread, else all columns are used)
- *  MBBS_TUNE_BLOCK_THREADS          target threads per block (32..256)
+ *  MBBS_TUNE_BLOCK_THREADS          target threads per block (32..256) of every
+ *      precision's stencil kernels
+ *  MBBS_TUNE_BLOCK_THREADS_FP64/FP32/FP16S  the same for one precision's kernels
+ *      only (the operator and SAP kernels of the other precisions keep theirs)
  *  MBBS_TUNE_SPLIT_FP64/FP32/FP16S  hop groups per site (0 or 1: one thread applies
  *      all 8 hops; 2 or 4: the hops are split over wave-uniform groups that
  *      combine through LDS; falls back to 1 where no launch shape fits)
@@ -142,7 +145,8 @@ enum { MBBS_TUNE_GROUP_FP64 = 0, MBBS_TUNE_GROUP_FP32 = 1, MBBS_TUNE_GROUP_FP16S
        MBBS_TUNE_MR_FUSED = 9, MBBS_TUNE_HOP_PAIR_FP64 = 11, MBBS_TUNE_HOP_PAIR_FP32 = 12,
        MBBS_TUNE_HOP_PAIR_FP16S = 13, MBBS_TUNE_NT_STORE_FP64 = 14, MBBS_TUNE_NT_STORE_FP32 = 15,
        MBBS_TUNE_NT_STORE_FP16S = 16, MBBS_TUNE_CHUNK_FP64 = 17, MBBS_TUNE_CHUNK_FP32 = 18,
-       MBBS_TUNE_CHUNK_FP16S = 19 };
+       MBBS_TUNE_CHUNK_FP16S = 19, MBBS_TUNE_BLOCK_THREADS_FP64 = 20,
+       MBBS_TUNE_BLOCK_THREADS_FP32 = 21, MBBS_TUNE_BLOCK_THREADS_FP16S = 22 };
 int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value);
 
 /* O(a)-improved (clover) Wilson operator with Jacobi preconditioning (Sec. 2.2:

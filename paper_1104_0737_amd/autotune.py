@@ -51,7 +51,7 @@ def apply(lat, prec, setting):
     ch = setting[5] if len(setting) > 5 else 0
     B.mbbs_lattice_tune(lat, B.TUNE_CHUNK[prec], ch)
     B.mbbs_lattice_tune(lat, B.TUNE_GROUP[prec], g)
-    B.mbbs_lattice_tune(lat, B.TUNE_BLOCK_THREADS, t)
+    B.mbbs_lattice_tune(lat, B.TUNE_BLOCK_THREADS_PREC[prec], t)
     B.mbbs_lattice_tune(lat, B.TUNE_SPLIT[prec], sp)
     B.mbbs_lattice_tune(lat, B.TUNE_HOP_PAIR[prec], pr)
     B.mbbs_lattice_tune(lat, B.TUNE_NT_STORE[prec], nt)

@@ -160,7 +160,8 @@ def mbbs_lattice_destroy(lat):
 
 
 TUNE_GROUP = {0: 0, 1: 1, 2: 2}      # precision -> knob
-TUNE_BLOCK_THREADS = 3
+TUNE_BLOCK_THREADS = 3                 # every precision
+TUNE_BLOCK_THREADS_PREC = {0: 20, 1: 21, 2: 22}   # precision -> knob
 TUNE_LDS_PAD_KB = 4
 TUNE_SPLIT = {0: 5, 1: 6, 2: 7}      # precision -> knob
 TUNE_PERSIST_BLOCKS = 8

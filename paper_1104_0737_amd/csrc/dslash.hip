@@ -757,7 +757,7 @@ static Plan make_plan(const mbbs_lattice_s* lat, int L, int prec, int nsites) {
   if (p.gw <= 0 || p.gw % p.C || L % p.gw) p.gw = L;
   p.nchunk = p.gw / p.C;
   p.ngroups = L / p.gw;
-  p.S = sites_per_block(p.nchunk, lat->g.Vb, lat->block_threads);
+  p.S = sites_per_block(p.nchunk, lat->g.Vb, lat->block_threads[prec]);
   p.bpt = lat->g.Vb / p.S;
   p.nblocks = (nsites / lat->g.Vb) * p.ngroups * p.bpt;
   return p;

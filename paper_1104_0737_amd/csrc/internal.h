@@ -100,7 +100,7 @@ struct mbbs_lattice_s {
   // of the stencil kernels per precision (0: all columns in one group) and
   // the target number of threads per block
   int group_cols[3] = {0, 0, 0};
-  int block_threads = 256;
+  int block_threads[3] = {256, 256, 256};   // target threads per block, per precision
   int lds_pad_kb = 0;   // extra LDS per stencil block: caps resident blocks per CU
   int split[3] = {0, 0, 0};  // hop groups per site (0/1: one thread does all 8 hops)
   int persist_blocks = 0;    // resident blocks per CU of persistent split kernels (0: not persistent)

@@ -287,7 +287,13 @@ extern "C" int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value) {
       return MBBS_OK;
     case MBBS_TUNE_BLOCK_THREADS:
       MBBS_CHECK(value >= 32 && value <= 256, "threads per block must be in 32..256");
-      lat->block_threads = value;
+      for (int p = 0; p < 3; ++p) lat->block_threads[p] = value;
+      return MBBS_OK;
+    case MBBS_TUNE_BLOCK_THREADS_FP64:
+    case MBBS_TUNE_BLOCK_THREADS_FP32:
+    case MBBS_TUNE_BLOCK_THREADS_FP16S:
+      MBBS_CHECK(value >= 32 && value <= 256, "threads per block must be in 32..256");
+      lat->block_threads[knob - MBBS_TUNE_BLOCK_THREADS_FP64] = value;
       return MBBS_OK;
     case MBBS_TUNE_SPLIT_FP64:
     case MBBS_TUNE_SPLIT_FP32:

@@ -202,3 +202,32 @@ def test_operator_wide_block(prec):
                 Yd = torch.empty_like(Xd)
                 B.mbbs_apply_dirac(lat.h, L, Xd, Yd, prec)
                 assert np.all(gu.rel_col_err(gu.host(Yd), ref) <= TOL[prec]), (L, ch)
+
+
+def test_block_threads_per_precision():
+    """Threads per block can be set for one precision's kernels alone (out of
+    range values are rejected); every value leaves the result bits unchanged,
+    and the all-precision knob still applies to every precision."""
+    dims, L = (8, 8, 8, 8), 12
+    V = 4096
+    U = inputs.gauge_field(dims, 0.3, 24)
+    X = gu.dev(inputs.gaussian_block(V, L, 25))
+    with gu.Lattice(dims, (4, 4, 4, 4), U, 0.11) as lat:
+        for bad in (31, 257):
+            with pytest.raises(B.MbbsError) as e:
+                B.mbbs_lattice_tune(lat.h, B.TUNE_BLOCK_THREADS_PREC[1], bad)
+            assert e.value.code == B.EINVAL
+        with pytest.raises(B.MbbsError):
+            B.mbbs_lattice_tune(lat.h, 23, 128)            # no such knob
+        for prec in (0, 1, 2):
+            Y = torch.empty_like(X)
+            B.mbbs_apply_dirac(lat.h, L, X, Y, prec)
+            ref = gu.host(Y)
+            for t in (64, 96, 192):
+                B.mbbs_lattice_tune(lat.h, B.TUNE_BLOCK_THREADS_PREC[prec], t)
+                B.mbbs_lattice_tune(lat.h, B.TUNE_BLOCK_THREADS_PREC[(prec + 1) % 3], 256 - t)
+                B.mbbs_apply_dirac(lat.h, L, X, Y, prec)
+                assert gu.host(Y).tobytes() == ref.tobytes(), (prec, t)
+            B.mbbs_lattice_tune(lat.h, B.TUNE_BLOCK_THREADS, 128)
+            B.mbbs_apply_dirac(lat.h, L, X, Y, prec)
+            assert gu.host(Y).tobytes() == ref.tobytes(), prec
