@@ -65,3 +65,48 @@ def test_operator_rejects_bad_block_width_before_device_work():
         rc = lib.mbbs_apply_dirac(fake, L, ctypes.c_void_p(32), ctypes.c_void_p(64), binding.FP64, None)
         assert rc == binding.EINVAL
         assert "L must be" in binding.mbbs_last_error()
+
+
+def _header_enums():
+    """Every enumerator of include/mbbs.h with its value (implicit values
+    counted on from the previous one)."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    vals = {}
+    for body in re.findall(r"enum\s*\{(.*?)\}", text, flags=re.S):
+        nxt = 0
+        for item in body.split(","):
+            item = item.strip()
+            if not item:
+                continue
+            m = re.fullmatch(r"(MBBS_\w+)\s*(?:=\s*(-?\d+))?", item)
+            assert m, item
+            v = int(m.group(2)) if m.group(2) is not None else nxt
+            vals[m.group(1)] = v
+            nxt = v + 1
+    return vals
+
+
+def test_binding_constants_match_header_enums():
+    """The binding's precisions, status codes, table ids, kernel classes and
+    tuning knob numbers are the header's."""
+    e = _header_enums()
+    assert (e["MBBS_FP64"], e["MBBS_FP32"], e["MBBS_FP16S"]) == (binding.FP64, binding.FP32, binding.FP16S)
+    for name in ("OK", "NOT_CONVERGED", "EINVAL", "ENOMEM", "EHIP", "EBREAKDOWN"):
+        assert e["MBBS_" + name] == getattr(binding, name), name
+    for i, t in enumerate(binding.TABLES):
+        assert e["MBBS_TAB_" + t] == i, t
+    assert e["MBBS_TAB_COUNT"] == len(binding.TABLES)
+    header_name = {"sap_resid": "SAP_RES"}
+    for i, k in enumerate(binding.KERNEL_CLASSES):
+        assert e["MBBS_K_" + header_name.get(k, k.upper())] == i, k
+    assert e["MBBS_K_COUNT"] == len(binding.KERNEL_CLASSES)
+    per_prec = {"GROUP": binding.TUNE_GROUP, "SPLIT": binding.TUNE_SPLIT, "HOP_PAIR": binding.TUNE_HOP_PAIR,
+                "NT_STORE": binding.TUNE_NT_STORE, "CHUNK": binding.TUNE_CHUNK,
+                "BLOCK_THREADS": binding.TUNE_BLOCK_THREADS_PREC}
+    for knob, m in per_prec.items():
+        for prec, suffix in ((binding.FP64, "FP64"), (binding.FP32, "FP32"), (binding.FP16S, "FP16S")):
+            assert e[f"MBBS_TUNE_{knob}_{suffix}"] == m[prec], (knob, suffix)
+    for knob in ("BLOCK_THREADS", "LDS_PAD_KB", "PERSIST_BLOCKS", "MR_FUSED"):
+        assert e["MBBS_TUNE_" + knob] == getattr(binding, "TUNE_" + knob), knob
+    tune = {k for k in e if k.startswith("MBBS_TUNE_")}
+    assert len(tune) == 4 + 3 * len(per_prec)      # every knob of the header is mapped above
