@@ -89,6 +89,31 @@ def jacobi_inverse(U, dims, csw: float, kappa: float):
     return np.linalg.inv(np.eye(12)[None] + T)
 
 
+def jacobi_inverse_sites(U, dims, csw: float, kappa: float, sites):
+    """(1 + T(x))^{-1} at the listed sites only, (n, 12, 12): the same leaves,
+    field strength and sigma sum as `jacobi_inverse`, with the neighbours of
+    each listed site looked up in the periodic neighbour table, so that large
+    lattices can be checked at a sample of sites."""
+    sites = np.asarray(sites, dtype=np.int64)
+    nb = geometry.neighbours(dims)
+    fwd = lambda x, mu: nb[x, 2 * mu]          # noqa: E731
+    bwd = lambda x, mu: nb[x, 2 * mu + 1]      # noqa: E731
+    n = len(sites)
+    T = np.zeros((n, 12, 12), dtype=np.complex128)
+    x = sites
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            xm, xn = bwd(x, mu), bwd(x, nu)
+            p1 = U[x, mu] @ U[fwd(x, mu), nu] @ _dag(U[fwd(x, nu), mu]) @ _dag(U[x, nu])
+            p2 = U[x, nu] @ _dag(U[fwd(xm, nu), mu]) @ _dag(U[xm, nu]) @ U[xm, mu]
+            p3 = _dag(U[xm, mu]) @ _dag(U[bwd(xm, nu), nu]) @ U[bwd(xm, nu), mu] @ U[xn, nu]
+            p4 = _dag(U[xn, nu]) @ U[xn, mu] @ U[fwd(xn, mu), nu] @ _dag(U[x, mu])
+            Q = p1 + p2 + p3 + p4
+            F = (Q - _dag(Q)) / 8.0
+            T += 1j * csw * kappa * np.einsum("st,xab->xsatb", sigma(mu, nu), F).reshape(n, 12, 12)
+    return np.linalg.inv(np.eye(12)[None] + T)
+
+
 def site_mul(M, phi):
     """(M phi)(x) = M(x) phi(x) for (V, 12, 12) M and (V, 4, 3, L) phi."""
     V = M.shape[0]

@@ -133,3 +133,42 @@ def test_clover_solve(domain_solver):
     T = clover.clover_term(U, cfg.dims, CSW, cfg.kappa)
     rd = Bh - clover.apply_D(U, cfg.kappa, cfg.phases, T, X, cfg.dims).reshape(12 * cfg.V, cfg.L)
     assert np.all(np.linalg.norm(rd, axis=0) / np.linalg.norm(Bh, axis=0) <= 1e-9)
+
+
+@pytest.mark.slow
+def test_clover_operator_full_size_sampled():
+    """32^3 x 64, L = 12, c_sw = 1.0 (the benchmark's clover option): the site
+    inverses built on the device and the Jacobi-preconditioned operator in
+    FP64, FP32 and FP16 storage, against the oracle at sampled sites
+    (boundary sites among them)."""
+    cfg = configs.c4()
+    dims, L, V, csw = cfg.dims, 12, cfg.V, 1.0
+    gu.flush("clover full size: links")
+    U = cfg.gauge()
+    rng = np.random.default_rng(4010)
+    sites = np.concatenate([[0, V - 1, 31, 32 * 32 * 32 * 63], rng.integers(0, V, 150)]).astype(np.int64)
+    gu.flush("clover full size: oracle site inverses")
+    cinv = clover.jacobi_inverse_sites(U, dims, csw, cfg.kappa, sites)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4011)
+    with gu.Lattice(dims, cfg.block, U, cfg.kappa) as lat:
+        B.mbbs_lattice_set_clover(lat.h, csw)
+        gu.flush("clover full size: device inverses")
+        Cd = torch.empty((V, 12, 12), dtype=torch.complex128, device="cuda")
+        B.mbbs_lattice_clover_inverse(lat.h, Cd)
+        got = gu.host(Cd.index_select(0, torch.from_numpy(sites).cuda()))
+        np.testing.assert_allclose(got, cinv, rtol=0, atol=1e-13)
+        del Cd
+        Xd = torch.randn((12 * V, L), dtype=torch.complex128, device="cuda", generator=gen)
+        X = gu.host(Xd)
+        # A X = X + (1 + T)^{-1} (D_wilson X - X) at the sampled sites
+        DX = dirac.apply_D_sites(U, cfg.kappa, cfg.phases, X.reshape(V, 4, 3, L), dims, sites).reshape(-1, 12, L)
+        Xs = X.reshape(V, 12, L)[sites]
+        ref = (Xs + cinv @ (DX - Xs)).reshape(-1, L)
+        idx = torch.from_numpy((12 * sites[:, None] + np.arange(12)[None, :]).ravel()).cuda()
+        Yd = torch.empty_like(Xd)
+        for prec in (B.FP64, B.FP32, B.FP16S):
+            gu.flush(f"clover full size: operator prec {prec}")
+            B.mbbs_apply_dirac(lat.h, L, Xd, Yd, prec)
+            err = gu.rel_col_err(gu.host(Yd.index_select(0, idx)), ref)
+            assert np.all(err <= TOL[prec]), (prec, err)

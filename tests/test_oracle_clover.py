@@ -98,3 +98,16 @@ def test_jacobi_preconditioned_operator():
     a2 = clover.site_mul(cinv, clover.apply_D(U, 0.12, PH, T, dirac.as_field(phi, V), DIMS))
     np.testing.assert_allclose(a1, a2, atol=1e-13)
     np.testing.assert_allclose(cinv @ (np.eye(12) + T), np.broadcast_to(np.eye(12), T.shape), atol=1e-13)
+
+
+def test_inverse_at_sampled_sites_equals_all_sites():
+    """The per-site form used for large lattices gives the same (1 + T)^{-1}
+    as the all-sites form, on a lattice with every extent different and
+    sites at every boundary among the sample."""
+    dims = (4, 6, 4, 8)
+    U = inputs.gauge_field(dims, 0.4, 91)
+    full = clover.jacobi_inverse(U, dims, 1.3, 0.124)
+    V = int(np.prod(dims))
+    sites = np.concatenate([[0, V - 1, 3, 4 * 6 * 4 * 7], np.random.default_rng(92).integers(0, V, 40)])
+    np.testing.assert_allclose(clover.jacobi_inverse_sites(U, dims, 1.3, 0.124, sites), full[sites],
+                               rtol=0, atol=1e-14)
