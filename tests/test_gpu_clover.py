@@ -172,3 +172,55 @@ def test_clover_operator_full_size_sampled():
             B.mbbs_apply_dirac(lat.h, L, Xd, Yd, prec)
             err = gu.rel_col_err(gu.host(Yd.index_select(0, idx)), ref)
             assert np.all(err <= TOL[prec]), (prec, err)
+
+
+@pytest.mark.slow
+def test_clover_solve_full_size():
+    """The benchmark's system with the clover term (c_sw = 1.0), FP32 SAP with
+    MR domains: A X = (1 + T)^{-1} B solved to 1e-10.  The residual of the
+    GPU solution is formed on the GPU in FP64 and compared with the oracle's
+    at sampled sites (the source site and its 8 neighbours among them)."""
+    cfg = configs.c4()
+    dims, L, V, csw = cfg.dims, cfg.L, cfg.V, 1.0
+    gu.flush("clover solve full size: links")
+    U = cfg.gauge()
+    Bh = cfg.sources()
+    src = cfg.src_site()
+    c = np.array(np.unravel_index(src, dims[::-1])[::-1])
+    sites = [src]
+    for mu in range(4):
+        for d in (1, -1):
+            n = c.copy()
+            n[mu] = (n[mu] + d) % dims[mu]
+            sites.append(int(np.ravel_multi_index(tuple(n[::-1]), dims[::-1])))
+    sites = np.array(sites + np.random.default_rng(4012).integers(0, V, 120).tolist(), dtype=np.int64)
+    cinv = clover.jacobi_inverse_sites(U, dims, csw, cfg.kappa, sites)
+    with gu.Lattice(dims, cfg.block, U, cfg.kappa) as lat:
+        B.mbbs_lattice_set_clover(lat.h, csw)
+        gu.flush("clover solve full size: solve")
+        p = B.mbbs_solve_params_default(tol=1e-10, sap_prec=B.FP32, ncy=cfg.ncy, nmr=cfg.nmr)
+        ws = torch.empty(B.mbbs_solve_workspace_size(lat.h, L, p), dtype=torch.uint8, device="cuda")
+        Bd = gu.dev(Bh)
+        Xd = torch.empty_like(Bd)
+        info = B.mbbs_solve(lat.h, L, Bd, Xd, p, ws)
+        gu.flush(f"  iterations {info['iterations']} restarts {info['restarts']} {info['seconds']:.2f}s")
+        assert info["status"] == B.OK and np.all(info["true_res"] <= 1e-10)
+        del ws
+        X = gu.host(Xd)
+        # the device's FP64 residual (1 + T)^{-1} B - A X at the sampled sites
+        Bp_d = torch.empty_like(Bd)
+        B.mbbs_apply_clover_inverse(lat.h, L, Bd, Bp_d)
+        Yd = torch.empty_like(Xd)
+        B.mbbs_apply_dirac(lat.h, L, Xd, Yd, B.FP64)
+        idx = torch.from_numpy((12 * sites[:, None] + np.arange(12)[None, :]).ravel()).cuda()
+        Rg = gu.host((Bp_d - Yd).index_select(0, idx))
+    gu.flush("clover solve full size: oracle residual at sampled sites")
+    DX = dirac.apply_D_sites(U, cfg.kappa, cfg.phases, X.reshape(V, 4, 3, L), dims, sites).reshape(-1, 12, L)
+    Xs = X.reshape(V, 12, L)[sites]
+    AX = Xs + cinv @ (DX - Xs)
+    Bp = cinv @ Bh.reshape(V, 12, L)[sites]
+    Ro = (Bp - AX).reshape(-1, L)
+    # ||(1 + T)^{-1} B_j|| is O(1) (a unit source at one site); FP64 rounding of A X is ~1e-15
+    assert np.max(np.abs(Rg - Ro)) <= 1e-13
+    bn = np.linalg.norm(cinv[0] @ Bh.reshape(V, 12, L)[src], axis=0)   # the whole of (1 + T)^{-1} B
+    assert np.all(np.linalg.norm(Ro, axis=0) / bn <= 1e-10)
