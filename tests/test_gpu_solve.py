@@ -228,7 +228,7 @@ def test_batched_mixed_solvers_clover_and_a_bad_system():
             l.close()
 
 
-def _c4_check(cfg, tag, **kw):
+def _c4_check(cfg, tag, sap_prec=B.FP32, **kw):
     """Solve a 32^3 x 64 system to 1e-10 (FP32 SAP on 8^4 domains); form the
     residual B - D X of the GPU solution on the GPU in FP64 and compare it
     with the oracle's at sampled sites (the source site and its 8 neighbours
@@ -248,7 +248,7 @@ def _c4_check(cfg, tag, **kw):
     sites = np.array(sites + np.random.default_rng(4006).integers(0, V, 200).tolist())
     with gu.Lattice(dims, cfg.block, U, cfg.kappa) as lat:
         gu.flush(f"c4 {tag}: solve")
-        X, info = _solve(lat, L, Bh, tol=1e-10, sap_prec=B.FP32, ncy=cfg.ncy, nmr=cfg.nmr, **kw)
+        X, info = _solve(lat, L, Bh, tol=1e-10, sap_prec=sap_prec, ncy=cfg.ncy, nmr=cfg.nmr, **kw)
         gu.flush(f"  iterations {info['iterations']} restarts {info['restarts']} {info['seconds']:.2f}s")
         assert info["status"] == B.OK and np.all(info["true_res"] <= 1e-10)
         Xd = gu.dev(X)
@@ -272,6 +272,17 @@ def test_c4_mixed_full_size(domain_solver):
     omega = 1.26) solved to 1e-10, checked against the oracle."""
     _c4_check(configs.c4(), "SSOR" if domain_solver else "MR", domain_solver=domain_solver, nssor=1,
               ssor_omega=1.26)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("variant", ["alg2", "fp16s"])
+def test_c4_variants_full_size(variant):
+    """The benchmark's system solved with the memory-saving Alg. 2, or with
+    FP16-storage SAP, to 1e-10, checked against the oracle."""
+    if variant == "alg2":
+        _c4_check(configs.c4(), "Alg. 2", memsave=1)
+    else:
+        _c4_check(configs.c4(), "FP16S SAP", sap_prec=B.FP16S)
 
 
 @pytest.mark.slow
