@@ -110,3 +110,14 @@ def test_binding_constants_match_header_enums():
         assert e["MBBS_TUNE_" + knob] == getattr(binding, "TUNE_" + knob), knob
     tune = {k for k in e if k.startswith("MBBS_TUNE_")}
     assert len(tune) == 4 + 3 * len(per_prec)      # every knob of the header is mapped above
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """With the HIP library absent the binding raises at once: there is no
+    other path (no CPU fallback) behind any entry point."""
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "libmbbs.so"))
+    monkeypatch.setattr(binding, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        binding.lib()
+    with pytest.raises(RuntimeError, match="missing"):
+        binding.mbbs_solve_params_default()
