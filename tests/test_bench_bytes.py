@@ -74,3 +74,14 @@ def test_ssor(nssor, fields, sweeps):
             psi = PS if cy == 0 else 2 * PS
             launches.append(fields * sp + resid + psi + sweeps * 4 * lk)
     assert ab("ssor", nssor=nssor) == pytest.approx(VH * sum(launches) / (2 * NCY), rel=1e-12)
+
+
+def test_bench_refuses_several_gpus():
+    """The benchmark measures one GPU: asked for more it says so and exits
+    non-zero before touching any device."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60)
+    assert r.returncode != 0
+    assert "one GPU only" in r.stdout
