@@ -65,8 +65,14 @@ def apply_A(U, kappa, phases, dims, phi, cinv=None):
     return clover.apply_A(U, kappa, phases, cinv, phi, dims)
 
 
-def mr_domains(U, kappa, phases, dom: Domains, rho, colour: int, nmr: int, cinv=None):
-    """MR approximation of A_DD^{-1} rho_D on every domain of one colour."""
+def mr_domains(U, kappa, phases, dom: Domains, rho, colour: int, nmr: int, cinv=None, trace=None):
+    """MR approximation of A_DD^{-1} rho_D on every domain of one colour.
+
+    Each step takes the complex step size that minimises ||r - omega A_DD r||
+    on its domain, separately for each column: omega = <w, r> / <w, w> with
+    <a, b> = sum conj(a) b.  If `trace` is a list, one record per step is
+    appended: the residual norms^2 before and after the step and <w, r_new>,
+    each per domain and column (what the MR pins check)."""
     r = dirac.as_field(rho, dom.V) * dom.mask(colour)
     x = np.zeros_like(r)
     for _ in range(nmr):
@@ -78,26 +84,17 @@ def mr_domains(U, kappa, phases, dom: Domains, rho, colour: int, nmr: int, cinv=
         omega[nz] = wr[nz] / ww[nz]
         om = omega[dom.did][:, None, None, :]
         x = x + om * r
-        r = r - om * w
+        r_new = r - om * w
+        if trace is not None:
+            trace.append({
+                "before": dom.per_domain_sum(np.sum(np.abs(r) ** 2, axis=(1, 2))),
+                "after": dom.per_domain_sum(np.sum(np.abs(r_new) ** 2, axis=(1, 2))),
+                "w_rnew": dom.per_domain_sum(np.sum(np.conj(w) * r_new, axis=(1, 2))),
+                "ww": ww,
+                "omega": omega,
+            })
+        r = r_new
     return x
-
-
-def mr_trace(U, kappa, phases, dom: Domains, rho, colour: int, nmr: int):
-    """As `mr_domains`, also returning per-step residual norms and <w, r_new>."""
-    r = dirac.as_field(rho, dom.V) * dom.mask(colour)
-    norms, orth = [dom.per_domain_sum(np.sum(np.abs(r) ** 2, axis=(1, 2)))], []
-    x = np.zeros_like(r)
-    for _ in range(nmr):
-        w = apply_blocked(U, kappa, phases, dom, r)
-        wr = dom.per_domain_sum(np.sum(np.conj(w) * r, axis=(1, 2)))
-        ww = dom.per_domain_sum(np.sum(np.abs(w) ** 2, axis=(1, 2)))
-        omega = np.where(ww != 0, wr / np.where(ww != 0, ww, 1), 0)
-        om = omega[dom.did][:, None, None, :]
-        x = x + om * r
-        r = r - om * w
-        norms.append(dom.per_domain_sum(np.sum(np.abs(r) ** 2, axis=(1, 2))))
-        orth.append(dom.per_domain_sum(np.sum(np.conj(w) * r, axis=(1, 2))))
-    return x, norms, orth
 
 
 def sap(U, kappa, phases, dom: Domains, eta, ncy: int, nmr: int, domain_solve=None, cinv=None):

@@ -1,7 +1,8 @@
 """Pins of the oracle's SAP preconditioner and MR domain solver (Sec. 2.2).
 
 * kappa = 0: A = 1, so MR is exact in one step and M = 1;
-* MR: residual norm never increases, and <w, r_new> = 0 after each step;
+* MR: residual norm never increases, <w, r_new> = 0 after each step, and one
+  step equals LAPACK's least-squares step size on the dense domain block;
 * ncy = 1 with exact domain inverses equals the block lower-triangular K
   written out from its definition, and ncy cycles equal K sum_j (1 - A K)^j;
 * with exact domain inverses and many cycles, M eta tends to A^{-1} eta;
@@ -11,6 +12,8 @@
 import numpy as np
 
 from oracle import dirac, geometry, sap
+
+import oracle_pins
 from paper_1104_0737_amd import inputs
 
 PH = ((1.0, 0.0), (1.0, 0.0), (1.0, 0.0), (-1.0, 0.0))
@@ -33,22 +36,24 @@ def test_kappa_zero_identity():
 
 
 def test_mr_monotone_and_orthogonal():
-    dims, block = (8, 4, 4, 4), (4, 2, 2, 2)
-    V = geometry.volume(dims)
-    U = inputs.gauge_field(dims, 0.3, 2)
-    dom = sap.Domains(dims, block)
-    rho = _field(V, 2, 2)
-    x, norms, orth = sap.mr_trace(U, 0.12, PH, dom, rho, 1, 5)
-    for a, b in zip(norms[:-1], norms[1:]):
-        assert np.all(b.real <= a.real * (1 + 1e-13))
-    for o, n in zip(orth, norms[:-1]):
-        assert np.all(np.abs(o) <= 1e-12 * np.sqrt(n.real) * np.sqrt(n.real) + 1e-300)
-    # x solves the domain problem with exactly the final residual
-    r_final = rho * dom.mask(1) - sap.apply_blocked(U, 0.12, PH, dom, x)
-    fin = dom.per_domain_sum(np.sum(np.abs(r_final) ** 2, axis=(1, 2)))
-    np.testing.assert_allclose(fin, norms[-1], rtol=1e-10)
+    oracle_pins.check_mr_orthogonal_monotone(sap)
+
+
+def test_mr_step_is_least_squares_minimiser():
+    oracle_pins.check_mr_least_squares(sap)
+
+
+def test_mr_trace_matches_plain_call():
+    # recording the trace does not change the result
+    U, _ = oracle_pins.mr_system()
+    dom = sap.Domains(oracle_pins.MR_DIMS, oracle_pins.MR_BLOCK)
+    rho = _field(geometry.volume(oracle_pins.MR_DIMS), 2, 24)
+    tr = []
+    a = sap.mr_domains(U, 0.12, PH, dom, rho, 1, 3, trace=tr)
+    b = sap.mr_domains(U, 0.12, PH, dom, rho, 1, 3)
+    assert len(tr) == 3 and np.array_equal(a, b)
     # the increment lives on the colour-1 domains only
-    assert np.all(x * dom.mask(0) == 0)
+    assert np.all(a * dom.mask(0) == 0)
 
 
 def test_mr_zero_domain_stays_zero():
