@@ -602,26 +602,57 @@ def batched_main(args):
 
 
 def cpu_baseline(cfg, L):
-    """The oracle's operator on a bounded sample of the workload: a 32^3 x 4
-    slab of the lattice (same per-site work, periodic in its own t extent)."""
-    from oracle import dirac
-    from paper_1104_0737_amd import inputs
+    """The oracle, untuned, on bounded samples of the workload, on the host's
+    cores with BLAS held to one thread (numpy's elementwise work is
+    single-threaded anyway):
+    - its operator on a 32^3 x 4 slab of the lattice (the same per-site work,
+      periodic in its own t extent) at the benchmark's L (the headline value)
+      and at L = 1;
+    - its full solve (Alg. 1, FP64, SAP with MR domains, every step in the
+      oracle) of the small 8^4 system (L = 4 point sources, tol 1e-12), for a
+      time to solution per right-hand side."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from oracle import dirac, krylov, sap
+    from paper_1104_0737_amd import configs, inputs
     dims = (cfg.dims[0], cfg.dims[1], cfg.dims[2], 4)
     V = int(np.prod(dims))
     U = inputs.gauge_field(dims, cfg.eps, 99)
-    X = inputs.gaussian_block(V, L, 98)
-    t = time.perf_counter()
-    reps = 0
-    while True:
-        dirac.apply_D(U, cfg.kappa, cfg.phases, X, dims)
-        reps += 1
-        if time.perf_counter() - t > 10:
-            break
-    dt = (time.perf_counter() - t) / reps
-    return {"value": V * L / dt, "unit": "site·RHS/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle Wilson-Dirac (numpy, FP64) on a {'x'.join(map(str, dims))} slab, L={L}, "
-                      f"{reps} application(s), {dt:.2f}s each; {len(os.sched_getaffinity(0))} host cores "
-                      "visible, numpy ran single-threaded"}
+
+    def op_rate(Lc, budget):
+        X = inputs.gaussian_block(V, Lc, 98)
+        t = time.perf_counter()
+        reps = 0
+        while True:
+            dirac.apply_D(U, cfg.kappa, cfg.phases, X, dims)
+            reps += 1
+            if time.perf_counter() - t > budget:
+                break
+        dt = (time.perf_counter() - t) / reps
+        return V * Lc / dt, reps, dt
+
+    with threadpool_limits(limits=1):
+        blas = sorted({(i["internal_api"], i["num_threads"]) for i in threadpool_info()})
+        rate, reps, dt = op_rate(L, 10.0)
+        rate1, reps1, dt1 = op_rate(1, 4.0)
+        c1 = configs.c1()
+        U1, B1 = c1.gauge(), c1.sources()
+        dom = sap.Domains(c1.dims, c1.block)
+        A = lambda X: dirac.apply_D(U1, c1.kappa, c1.phases, X, c1.dims).reshape(12 * c1.V, -1)
+        M = lambda X: sap.sap(U1, c1.kappa, c1.phases, dom, X, c1.ncy, c1.nmr).reshape(12 * c1.V, -1)
+        t = time.perf_counter()
+        res = krylov.block_bicgstab(A, M, B1, c1.tol, maxiter=100)
+        ts = time.perf_counter() - t
+    return {"value": rate, "unit": "site·RHS/s", "cores": 1, "kind": "oracle",
+            "operator_L1_site_rhs_per_s": rate1,
+            "solve": {"workload": f"{'x'.join(map(str, c1.dims))}, L={c1.L} point sources, kappa={c1.kappa}, "
+                                  f"SAP {'x'.join(map(str, c1.block))} ncy={c1.ncy} nmr={c1.nmr}, FP64, tol {c1.tol:g}",
+                      "seconds": ts, "iterations": res.iterations, "converged": res.converged,
+                      "tts_per_rhs_s": ts / c1.L},
+            "blas_threads": [list(b) for b in blas],
+            "sample": f"oracle Wilson-Dirac (numpy, FP64) on a {'x'.join(map(str, dims))} slab: L={L} "
+                      f"{reps} application(s) of {dt:.2f}s, L=1 {reps1} of {dt1:.2f}s; oracle solve of the "
+                      f"{'x'.join(map(str, c1.dims))} system {ts:.1f}s; {len(os.sched_getaffinity(0))} host "
+                      "cores visible, BLAS limited to 1 thread"}
 
 
 if __name__ == "__main__":

@@ -264,7 +264,8 @@ typedef struct {
   int nmr;             /* MR steps per domain                                     */
   int sap_prec;        /* mbbs_prec of the preconditioner                         */
   int x0_is_guess;     /* 1: X_dev holds an initial guess; 0: start from X = 0    */
-  int qr_passes;       /* 1 = Cholesky QR, 2 = CholQR2                            */
+  int qr_passes;       /* 1 = Cholesky QR, 2 = CholQR2, 0 = no QR step (the plain
+                          block BiCGSTAB the paper's QR is measured against)      */
   int graph_iters;     /* iterations per captured HIP graph (0/1: no graph)       */
   int precond;         /* 1: SAP right preconditioner; 0: M = 1                   */
   int memsave;         /* 1: memory-saving form (Alg. 2); 0: Alg. 1               */
@@ -272,6 +273,8 @@ typedef struct {
   int domain_solver;   /* SAP domain solver: 0 = nmr MR steps, 1 = SSOR           */
   int nssor;           /* SSOR correction terms N_SSOR (0 or 1)                   */
   double ssor_omega;   /* SSOR relaxation, 0 < omega < 2                          */
+  const double* rtilde;/* R~ of Alg. 1 ("choose R~"): a device FP64 N x L block,
+                          read once at the start; NULL: R~ = R_0                  */
 } mbbs_solve_params;
 
 /* Kernel classes timed when params.profile = 1. */
@@ -289,6 +292,12 @@ typedef struct {
   double seconds;               /* wall time of the call                           */
   double kernel_ms[MBBS_K_COUNT];        /* summed kernel time per class (profile) */
   long long kernel_launches[MBBS_K_COUNT];
+  double* res_history;          /* caller-owned host array of history_cap doubles, or
+                                   NULL: max_i ||r_i||/||b_i|| of the recursive residual
+                                   after each iteration (Sec. 3.3, residual against
+                                   iterations); at most 4096 entries are kept        */
+  int history_cap;
+  int history_len;              /* entries written (iterations, capped)            */
 } mbbs_solve_info;
 
 void mbbs_solve_params_default(mbbs_solve_params* p);
@@ -299,7 +308,12 @@ int mbbs_solve_workspace_size(mbbs_lattice_t lat, int L, const mbbs_solve_params
 
 /* Solve A X = B (Alg. 1, or Alg. 2 if params->memsave): B_dev, X_dev FP64
  * N x L blocks; X_dev is read as the initial guess when x0_is_guess and
- * always receives the result.  R~ = R_0.  The outer recurrences, Gram
+ * always receives the result.  R~ = R_0 unless params->rtilde supplies it.
+ * The loop test (continue while max_i ||r_i||/||b_i|| > tol) runs on the
+ * device on R_0 and after step 4.10 of every iteration; once the recursion
+ * stops, the FP64 true residual B - A X is formed, and if it is above tol the
+ * iteration restarts from R = B - A X, P = R, keeping R~ (at most
+ * max_restarts times).  The outer recurrences, Gram
  * products, Cholesky QR, L x L solves and the true residual run in FP64;
  * SAP runs in params->sap_prec.  Allocates nothing: ws_dev (caller-owned,
  * mbbs_solve_workspace_size bytes) holds every intermediate.  Blocks until

@@ -47,7 +47,8 @@ class SolveParams(ctypes.Structure):
                 ("ncy", ctypes.c_int), ("nmr", ctypes.c_int), ("sap_prec", ctypes.c_int),
                 ("x0_is_guess", ctypes.c_int), ("qr_passes", ctypes.c_int), ("graph_iters", ctypes.c_int),
                 ("precond", ctypes.c_int), ("memsave", ctypes.c_int), ("profile", ctypes.c_int),
-                ("domain_solver", ctypes.c_int), ("nssor", ctypes.c_int), ("ssor_omega", ctypes.c_double)]
+                ("domain_solver", ctypes.c_int), ("nssor", ctypes.c_int), ("ssor_omega", ctypes.c_double),
+                ("rtilde", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -55,7 +56,11 @@ class SolveInfo(ctypes.Structure):
                 ("n_dslash_outer", ctypes.c_longlong), ("n_sap", ctypes.c_longlong),
                 ("true_res", ctypes.POINTER(ctypes.c_double)), ("rec_res", ctypes.POINTER(ctypes.c_double)),
                 ("seconds", ctypes.c_double), ("kernel_ms", ctypes.c_double * len(KERNEL_CLASSES)),
-                ("kernel_launches", ctypes.c_longlong * len(KERNEL_CLASSES))]
+                ("kernel_launches", ctypes.c_longlong * len(KERNEL_CLASSES)),
+                ("res_history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int),
+                ("history_len", ctypes.c_int)]
+
+HISTORY_CAP = 4096   # residual-history entries the library keeps
 
 
 _lib = None
@@ -273,11 +278,15 @@ def mbbs_lu_solve(L, m, G, R, X, stream=None):
 
 # ----------------------------------------------------------------- solver
 def mbbs_solve_params_default(**overrides):
+    """Default parameters with overrides; rtilde may be a complex128 device
+    tensor (N, L) holding R~ (the caller keeps it alive during the solve)."""
     p = SolveParams()
     lib().mbbs_solve_params_default(ctypes.byref(p))
     for k, v in overrides.items():
         if not hasattr(p, k):
             raise KeyError(k)
+        if k == "rtilde":
+            v = None if v is None else _dev(v, _c128()).value
         setattr(p, k, v)
     return p
 
@@ -288,29 +297,37 @@ def mbbs_solve_workspace_size(lat, L, params):
     return n.value
 
 
-def _info(L):
-    info = SolveInfo()
+def _attach(info, L):
     tr = (ctypes.c_double * L)()
     rr = (ctypes.c_double * L)()
+    hist = (ctypes.c_double * HISTORY_CAP)()
     info.true_res = ctypes.cast(tr, ctypes.POINTER(ctypes.c_double))
     info.rec_res = ctypes.cast(rr, ctypes.POINTER(ctypes.c_double))
-    return info, tr, rr
+    info.res_history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+    info.history_cap = HISTORY_CAP
+    return tr, rr, hist
 
 
-def _info_dict(info, tr, rr, rc):
+def _info(L):
+    info = SolveInfo()
+    return (info, *_attach(info, L))
+
+
+def _info_dict(info, tr, rr, hist, rc):
     return {"status": rc, "iterations": info.iterations, "restarts": info.restarts,
             "n_dslash_outer": info.n_dslash_outer, "n_sap": info.n_sap,
             "true_res": np.array(tr[:]), "rec_res": np.array(rr[:]), "seconds": info.seconds,
             "kernel_ms": dict(zip(KERNEL_CLASSES, info.kernel_ms[:])),
-            "kernel_launches": dict(zip(KERNEL_CLASSES, info.kernel_launches[:]))}
+            "kernel_launches": dict(zip(KERNEL_CLASSES, info.kernel_launches[:])),
+            "history": np.array(hist[:max(0, info.history_len)])}
 
 
 def mbbs_solve(lat, L, B, X, params, ws, stream=None):
     """Returns a dict: status, iterations, restarts, residuals, timings."""
-    info, tr, rr = _info(L)
+    info, tr, rr, hist = _info(L)
     rc = _check(lib().mbbs_solve(lat, L, _dev(B, _c128()), _dev(X, _c128()), ctypes.byref(params), _dev(ws),
                                  ws.numel() * ws.element_size(), ctypes.byref(info), _stream(stream)))
-    return _info_dict(info, tr, rr, rc)
+    return _info_dict(info, tr, rr, hist, rc)
 
 
 def mbbs_solve_batched_workspace_size(lats, Ls, params):
@@ -333,13 +350,7 @@ def mbbs_solve_batched(lats, Ls, Bs, Xs, params, ws, stream=None):
     Xp = (ctypes.c_void_p * n)(*[_dev(x, _c128()).value for x in Xs])
     pa = (SolveParams * n)(*params)
     infos = (SolveInfo * n)()
-    keep = []
-    for k in range(n):
-        tr = (ctypes.c_double * Ls[k])()
-        rr = (ctypes.c_double * Ls[k])()
-        infos[k].true_res = ctypes.cast(tr, ctypes.POINTER(ctypes.c_double))
-        infos[k].rec_res = ctypes.cast(rr, ctypes.POINTER(ctypes.c_double))
-        keep.append((tr, rr))
+    keep = [_attach(infos[k], Ls[k]) for k in range(n)]
     unset = 99                          # not an mbbs status: marks an info the call never filled
     for k in range(n):
         infos[k].status = unset
@@ -348,7 +359,7 @@ def mbbs_solve_batched(lats, Ls, Bs, Xs, params, ws, stream=None):
     if rc < 0 and all(infos[k].status == unset for k in range(n)):
         _check(rc)                      # the call failed before solving anything
     # per-system failures: the return value is the worst status, each info has its own
-    return rc, [_info_dict(infos[k], keep[k][0], keep[k][1], infos[k].status) for k in range(n)]
+    return rc, [_info_dict(infos[k], *keep[k], infos[k].status) for k in range(n)]
 
 
 def mbbs_last_error():

@@ -38,10 +38,12 @@ struct SolverState {
   int status;      // ST_*
   int iter;        // iterations started
   int maxiter;
-  int reason;      // breakdown: 1 Cholesky, 2 LU pivot, 3 zeta
-  int pad[3];
+  int reason;      // breakdown: 1 Cholesky, 2 LU pivot, 3 zeta, 4 non-finite residual
+  int hist_len;    // entries written to the residual history
+  int pad[2];
   double tol2;     // tol^2
 };
+constexpr int HIST_CAP = 4096;   // residual-history entries kept on the device
 
 // Pointers to every small device array the coefficient kernels touch.
 struct SolverDev {
@@ -66,7 +68,8 @@ struct SolverDev {
   double2* zeta;
   double2* nzeta;
   double2* one;       // constant 1 (scalar coefficient)
-  int qr_passes;
+  double* hist;       // max_i ||r_i||^2/||b_i||^2 after each iteration (HIST_CAP)
+  int qr_passes;      // 0: no QR (gamma = 1), 1: Cholesky QR, 2: CholQR2
 };
 
 int gram_blocks(size_t N, int L);
@@ -75,8 +78,12 @@ int launch_gram(int L, size_t N, const GramArgs& a, const GramOut& o, double2* p
                 hipStream_t st);
 int launch_combo(int L, size_t N, const ComboArgs& a, double2* out, int gram_mode, const GramOut* o,
                  double2* partial, const int* frozen, hipStream_t st);
-// which: 0 CholQR factor + loop test, 1 second CholQR pass, 2 alpha, 3 zeta/beta
+// which: 0 CholQR factor, 1 second CholQR pass, 2 alpha, 3 zeta/beta
 int launch_coef(int which, int L, const SolverDev& d, hipStream_t st);
+// Loop test of Alg. 1 on the current ||r_i||^2 (sets frozen and the status
+// once it stops the iteration) and the residual-history entry of the
+// iteration just finished.
+int launch_loop_test(int L, const SolverDev& d, hipStream_t st);
 int launch_fill(double2* p, size_t n, double2 v, hipStream_t st);
 int launch_chol_standalone(int L, const double2* G, double2* gam, double2* ginv, int* ok, hipStream_t st);
 int launch_matmul_small(int L, const double2* A, const double2* B, double2* C, hipStream_t st);

@@ -307,31 +307,50 @@ __device__ void lu_solve(int L, int m, const double2* A, const int* piv, const d
   __syncthreads();
 }
 
-// Step 4.1 (Cholesky QR factor) and the loop test of Alg. 1.
+// Loop test of Alg. 1 (iterate while max_i ||r_i||/||b_i|| > tol), run after
+// step 4.10 has formed the new column norms, so that a stop is visible to the
+// host before it enqueues another iteration; also run once on R_0.
+__global__ void k_loop_test(int L, SolverDev d) {
+  SolverState* S = d.state;
+  if (S->frozen) return;
+  if (threadIdx.x != 0) return;
+  double worst = 0;
+  int bad = 0;
+  for (int i = 0; i < L; ++i) {
+    const double r = d.rnorm2[i] / d.bnorm2[i];
+    if (!isfinite(r)) bad = 1;
+    worst = fmax(worst, r);
+  }
+  if (S->iter >= 1 && S->iter <= HIST_CAP) {
+    d.hist[S->iter - 1] = bad ? (double)NAN : worst;
+    S->hist_len = S->iter;
+  }
+  if (bad) {
+    S->frozen = 1;
+    S->status = ST_BREAKDOWN;
+    S->reason = 4;
+  } else if (worst <= S->tol2) {
+    S->frozen = 1;
+    S->status = ST_CONVERGED;
+  } else if (S->iter >= S->maxiter) {
+    S->frozen = 1;
+    S->status = ST_MAXITER;
+  }
+}
+
+// Step 4.1: Cholesky QR factor of P (gamma^{-1} for the consumers); with
+// qr_passes = 0 the QR step is left out (gamma = 1, the unmodified block
+// BiCGSTAB the paper's QR is compared against).  Counts the iteration.
 __global__ void k_coef_qr(int L, SolverDev d) {
   SolverState* S = d.state;
   if (S->frozen) return;
   extern __shared__ double2 sm[];
   double2* G = sm;
   double2* gi = sm + L * L;
-  __shared__ int conv;
-  if (threadIdx.x == 0) {
-    double worst = 0;
-    int bad = 0;
-    for (int i = 0; i < L; ++i) {
-      double r = d.rnorm2[i] / d.bnorm2[i];
-      if (!isfinite(r)) bad = 1;
-      worst = fmax(worst, r);
-    }
-    conv = bad ? -1 : (worst <= S->tol2 ? 1 : 0);
-    if (!bad && worst > S->tol2 && S->iter >= S->maxiter) conv = 2;
-  }
-  __syncthreads();
-  if (conv != 0) {
-    if (threadIdx.x == 0) {
-      S->frozen = 1;
-      S->status = conv == 1 ? ST_CONVERGED : conv == 2 ? ST_MAXITER : ST_BREAKDOWN;
-    }
+  if (d.qr_passes == 0) {
+    for (int e = threadIdx.x; e < L * L; e += blockDim.x)
+      d.ginv[e] = make_double2(e / L == e % L ? 1.0 : 0.0, 0.0);
+    if (threadIdx.x == 0) S->iter += 1;
     return;
   }
   for (int e = threadIdx.x; e < L * L; e += blockDim.x) G[e] = d.Gpp[e];
@@ -586,6 +605,12 @@ int launch_coef(int which, int L, const SolverDev& d, hipStream_t st) {
     case 2: hipLaunchKernelGGL(k_coef_alpha, dim3(1), dim3(64), sh, st, L, d); break;
     default: hipLaunchKernelGGL(k_coef_zeta, dim3(1), dim3(64), sh, st, L, d); break;
   }
+  MBBS_HIP(hipGetLastError());
+  return MBBS_OK;
+}
+
+int launch_loop_test(int L, const SolverDev& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_loop_test, dim3(1), dim3(64), 0, st, L, d);
   MBBS_HIP(hipGetLastError());
   return MBBS_OK;
 }

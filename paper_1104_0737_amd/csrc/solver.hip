@@ -2,9 +2,11 @@
 // the host with every coefficient computed on the device: the host only
 // enqueues iterations (optionally captured in a HIP graph of k iterations)
 // and reads a small state record after each batch.  The loop test of Alg. 1
-// (continue while max_i ||r_i||/||b_i|| > tol) runs on the device at the
-// start of each iteration; once it fails, the device sets `frozen` and every
-// later kernel of the batch returns at once.  After the recursive residual
+// (continue while max_i ||r_i||/||b_i|| > tol) runs on the device on R_0 and
+// after step 4.10 of each iteration, where the new residual norms are formed;
+// once it fails, the device sets `frozen`, step 4.12 and every later kernel of
+// the batch return at once, and the host sees the stop after the iteration
+// that caused it.  After the recursive residual
 // converges, the true residual B - A X is checked in FP64 and the iteration
 // restarts from it if needed.
 #include <algorithm>
@@ -34,7 +36,7 @@ struct Work {
 size_t small_bytes(int L) {
   const size_t LL = (size_t)L * L * sizeof(double2);
   return al(sizeof(SolverState)) + 3 * al(L * sizeof(double)) + 16 * al(LL) + al(L * sizeof(int)) +
-         4 * al(sizeof(double2));
+         4 * al(sizeof(double2)) + al(HIST_CAP * sizeof(double));
 }
 
 size_t block_bytes(const mbbs_lattice_s* lat, int L) { return al((size_t)lat->g.V * 12 * L * sizeof(double2)); }
@@ -109,6 +111,7 @@ int bind(const mbbs_lattice_s* lat, int L, const mbbs_solve_params& p, void* ws,
   d.nzeta = (double2*)take(sizeof(double2));
   d.one = (double2*)take(sizeof(double2));
   w.mone = (double2*)take(sizeof(double2));
+  d.hist = (double*)take(HIST_CAP * sizeof(double));
   d.qr_passes = p.qr_passes;
   return MBBS_OK;
 }
@@ -189,7 +192,7 @@ int enqueue_iteration(Ctx& c) {
   Work& w = c.w;
   SolverDev& d = w.d;
   const int* fz = c.frozen;
-  // loop test + 4.1 (Cholesky QR factor of P, folded into the consumers)
+  // 4.1 (Cholesky QR factor of P, folded into the consumers)
   MBBS_TRY(coef(c, 0));
   if (c.p.qr_passes == 2) {
     ComboArgs a{};
@@ -263,8 +266,10 @@ int enqueue_iteration(Ctx& c) {
     MBBS_TRY(combo(c, a, w.R, 1, d.Gpp2, fz));
     if (c.prof) c.prof->begin(MBBS_K_SMALL);
     hipLaunchKernelGGL(k_diag_real, dim3(1), dim3(64), 0, c.st, c.L, (const double2*)d.Gpp2, d.rnorm2, fz);
-    if (c.prof) c.prof->end();
     MBBS_HIP(hipGetLastError());
+    // loop test on the new residual: a stop skips step 4.12
+    MBBS_TRY(launch_loop_test(c.L, d, c.st));
+    if (c.prof) c.prof->end();
   }
   // 4.12 P <- R + (Q - zeta V) beta = R + P (gamma^{-1} beta) - V (zeta beta), with P^H P
   {
@@ -292,7 +297,7 @@ int start(Ctx& c, bool x_zero, bool set_rt) {
     MBBS_TRY(combo(c, a, w.R, 0, nullptr, nullptr));
   }
   MBBS_TRY(launch_copy(w.R, w.P, c.N * c.L, c.st));
-  if (set_rt) MBBS_TRY(launch_copy(w.R, w.Rt, c.N * c.L, c.st));
+  if (set_rt) MBBS_TRY(launch_copy(c.p.rtilde ? (const double2*)c.p.rtilde : w.R, w.Rt, c.N * c.L, c.st));
   MBBS_TRY(col_norms(c, w.R, w.d.rnorm2, nullptr));
   {
     GramArgs g{};
@@ -361,6 +366,7 @@ static int job_init(SolveJob& j) {
   s.maxiter = c.p.maxiter;
   s.tol2 = c.p.tol * c.p.tol;
   MBBS_HIP(hipMemcpyAsync(c.w.d.state, &s, sizeof(s), hipMemcpyHostToDevice, c.st));
+  MBBS_TRY(launch_loop_test(c.L, c.w.d, c.st));   // R_0 may already satisfy the test
   MBBS_HIP(hipStreamSynchronize(c.st));
   return MBBS_OK;
 }
@@ -397,7 +403,8 @@ static int job_check(SolveJob& j) {
     j.rc = ok ? MBBS_OK : MBBS_EBREAKDOWN;
     if (!ok) set_error("block BiCGSTAB breakdown (" +
                        std::string(j.hs.reason == 1 ? "P^H P not positive definite" :
-                                   j.hs.reason == 2 ? "singular R~^H V" : "non-finite zeta") + ")");
+                                   j.hs.reason == 2 ? "singular R~^H V" :
+                                   j.hs.reason == 4 ? "non-finite residual" : "non-finite zeta") + ")");
     return MBBS_OK;
   }
   if (ok) { j.done = true; j.rc = MBBS_OK; return MBBS_OK; }
@@ -447,6 +454,15 @@ static void job_fill_info(SolveJob& j, mbbs_solve_info* info, double seconds) {
       info->kernel_launches[k] = c.prof->launches[k];
     }
   }
+  info->history_len = 0;
+  const int nh = std::min(std::min(j.hs.hist_len, HIST_CAP), info->history_cap);
+  if (info->res_history && nh > 0) {
+    std::vector<double> h(nh);
+    if (read_dev(c, h.data(), c.w.d.hist, nh * sizeof(double)) == MBBS_OK) {
+      for (int i = 0; i < nh; ++i) info->res_history[i] = std::sqrt(h[i]);
+      info->history_len = nh;
+    }
+  }
 }
 
 static int validate(const mbbs_lattice_s* lat, int L, const mbbs_solve_params* p) {
@@ -454,7 +470,7 @@ static int validate(const mbbs_lattice_s* lat, int L, const mbbs_solve_params* p
   MBBS_CHECK(L >= 1 && L <= LMAX_SOLVER, "L must be in 1..16 for the solver");
   MBBS_CHECK(p->tol > 0 && std::isfinite(p->tol), "tol must be positive");
   MBBS_CHECK(p->maxiter >= 0, "maxiter must be >= 0");
-  MBBS_CHECK(p->qr_passes == 1 || p->qr_passes == 2, "qr_passes must be 1 or 2");
+  MBBS_CHECK(p->qr_passes >= 0 && p->qr_passes <= 2, "qr_passes must be 0 (no QR), 1 or 2");
   MBBS_CHECK(p->sap_prec >= 0 && p->sap_prec <= 2, "bad sap_prec");
   if (p->precond) {
     MBBS_CHECK(p->domain_solver == 0 || p->domain_solver == 1, "domain_solver must be 0 (MR) or 1 (SSOR)");
@@ -594,6 +610,7 @@ static int batch_init(BatchJob& b) {
   s.tol2 = c.p.tol * c.p.tol;
   b.h->st = s;
   MBBS_HIP(hipMemcpyAsync(c.w.d.state, &b.h->st, sizeof(SolverState), hipMemcpyHostToDevice, c.st));
+  MBBS_TRY(launch_loop_test(c.L, c.w.d, c.st));   // R_0 may already satisfy the test
   MBBS_HIP(hipMemcpyAsync(b.h->bn, c.w.d.bnorm2, c.L * sizeof(double), hipMemcpyDeviceToHost, c.st));
   b.phase = PH_INIT;
   return batch_record(b);
@@ -813,6 +830,7 @@ extern "C" void mbbs_solve_params_default(mbbs_solve_params* p) {
   p->domain_solver = 0;
   p->nssor = 1;
   p->ssor_omega = 1.26;
+  p->rtilde = nullptr;
 }
 
 extern "C" int mbbs_solve_workspace_size(mbbs_lattice_t lat, int L, const mbbs_solve_params* params, size_t* bytes) {

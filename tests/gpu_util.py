@@ -25,6 +25,15 @@ def rel_col_err(got, ref):
     return np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
 
 
+def max_elem_err(got, ref):
+    """Per column: the largest elementwise deviation over the column's largest
+    reference magnitude (a wrong value at a few sites, which a norm-wise
+    comparison can hide, shows here)."""
+    ref = ref.reshape(-1, ref.shape[-1])
+    got = got.reshape(ref.shape)
+    return np.max(np.abs(got - ref), axis=0) / np.max(np.abs(ref), axis=0)
+
+
 class Lattice:
     def __init__(self, dims, block, U, kappa, phases=PH_AP):
         self.dims, self.block, self.kappa, self.phases = tuple(dims), tuple(block), kappa, phases

@@ -121,3 +121,27 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
         binding.lib()
     with pytest.raises(RuntimeError, match="missing"):
         binding.mbbs_solve_params_default()
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes images of mbbs_solve_params and mbbs_solve_info
+    have the header's size and field offsets (checked by compiling a small
+    host program against include/mbbs.h)."""
+    import subprocess
+    structs = {"mbbs_solve_params": binding.SolveParams, "mbbs_solve_info": binding.SolveInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {(a, b): int(c) for a, b, c in (ln.split() for ln in out if ln)}
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

@@ -37,8 +37,11 @@ def test_dslash_parity(dims, block, L, prec):
         Xd = gu.dev(X)
         Yd = torch.empty_like(Xd)
         B.mbbs_apply_dirac(lat.h, L, Xd, Yd, prec)
-        err = gu.rel_col_err(gu.host(Yd), ref)
+        Y = gu.host(Yd)
+        err = gu.rel_col_err(Y, ref)
+        emax = gu.max_elem_err(Y, ref)
     assert np.all(err <= TOL[prec]), err
+    assert np.all(emax <= TOL[prec]), emax
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
@@ -52,8 +55,11 @@ def test_blocked_operator_parity(prec):
         Xd = gu.dev(X)
         Yd = torch.empty_like(Xd)
         B.mbbs_apply_blocked(lat.h, L, Xd, Yd, prec)
-        err = gu.rel_col_err(gu.host(Yd), ref)
+        Y = gu.host(Yd)
+        err = gu.rel_col_err(Y, ref)
+        emax = gu.max_elem_err(Y, ref)
     assert np.all(err <= TOL[prec]), err
+    assert np.all(emax <= TOL[prec]), emax
 
 
 def test_point_source_and_zero_columns():
@@ -118,6 +124,15 @@ def test_dslash_full_size_sampled():
         got = gu.host(Yd.index_select(0, idx))
         err = gu.rel_col_err(got, ref.reshape(-1, L))
         assert np.all(err <= 1e-14), err
+        # two columns over the whole lattice, every element
+        gu.flush("full-size: FP64, columns 0 and 7 over the whole lattice")
+        cols = [0, 7]
+        Xc = np.ascontiguousarray(X[:, cols])
+        refc = dirac.apply_D(U, cfg.kappa, cfg.phases, Xc, dims).reshape(12 * V, 2)
+        Yc = gu.host(Yd)[:, cols]
+        assert np.all(gu.rel_col_err(Yc, refc) <= 1e-14)
+        assert np.all(gu.max_elem_err(Yc, refc) <= 1e-14)
+        del refc, Yc, Xc
         gu.flush("full-size: FP32 storage")
         X32 = torch.empty((12 * V, L, 2), dtype=torch.float32, device="cuda")
         Y32 = torch.empty_like(X32)
@@ -138,6 +153,7 @@ def test_dslash_full_size_sampled():
         got = gu.host(Yd.index_select(0, idx))
         err = gu.rel_col_err(got, ref.reshape(-1, L))
         assert np.all(err <= 2e-3), err
+        assert np.all(gu.max_elem_err(got, ref.reshape(-1, L)) <= 2e-3)
 
 
 def test_tuning_is_bit_identical():

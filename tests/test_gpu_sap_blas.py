@@ -37,8 +37,11 @@ def test_sap_parity(dims, block, L, ncy, nmr, prec, tol):
         ws = torch.empty(B.mbbs_sap_workspace_size(lat.h, L, prec), dtype=torch.uint8, device="cuda")
         Yd = torch.empty((12 * V, L), dtype=torch.complex128, device="cuda")
         B.mbbs_sap_apply(lat.h, L, gu.dev(eta), Yd, ncy, nmr, prec, ws)
-        err = gu.rel_col_err(gu.host(Yd), ref)
+        Y = gu.host(Yd)
+        err = gu.rel_col_err(Y, ref)
+        emax = gu.max_elem_err(Y, ref)
     assert np.all(err <= tol), err
+    assert np.all(emax <= tol), emax
 
 
 def test_sap_point_source_fp16():
@@ -58,6 +61,7 @@ def test_sap_point_source_fp16():
             assert np.all(np.isfinite(Y))
             err = gu.rel_col_err(Y, ref)
             assert np.all(err <= tol), (prec, err)
+            assert np.all(gu.max_elem_err(Y, ref) <= tol), prec
 
 
 @pytest.mark.parametrize("N,L", [(1000, 1), (12 * 4096, 4), (12 * 777, 12), (12 * 8192, 7), (300, 16)])

@@ -87,6 +87,91 @@ def test_memsave_matches_alg1(c1):
     np.testing.assert_allclose(X2, X1, atol=1e-9 * np.abs(X1).max())
 
 
+def test_memsave_matches_oracle_alg2(c1):
+    """GPU Alg. 2 against the oracle's own Alg. 2 (block_bicgstab_memsave) on
+    the config-1 system, all FP64: same iteration count (+-1), X to 1e-8."""
+    cfg, U, Bh, ref, lat = c1
+    gu.flush("c1 Alg. 2 vs oracle Alg. 2")
+    dom = sap.Domains(cfg.dims, cfg.block)
+    A = lambda X: dirac.apply_D(U, cfg.kappa, cfg.phases, X, cfg.dims).reshape(12 * cfg.V, -1)
+    M = lambda X: sap.sap(U, cfg.kappa, cfg.phases, dom, X, cfg.ncy, cfg.nmr).reshape(12 * cfg.V, -1)
+    ref2 = krylov.block_bicgstab_memsave(A, M, Bh, cfg.tol, maxiter=100)
+    X, info = _solve(lat, cfg.L, Bh, tol=cfg.tol, sap_prec=B.FP64, memsave=1)
+    assert info["status"] == B.OK and ref2.converged
+    assert abs(info["iterations"] - ref2.iterations) <= 1, (info["iterations"], ref2.iterations)
+    err = np.linalg.norm(X - ref2.X, axis=0) / np.linalg.norm(ref2.X, axis=0)
+    assert np.all(err <= 1e-8), err
+    assert np.all(_oracle_true_res(cfg, U, Bh, X) <= cfg.tol * 1.01)
+
+
+def test_history_matches_oracle(c1):
+    """The residual history (max_i ||r_i||/||b_i|| after each iteration, the
+    quantity of the paper's residual-against-iterations figure) of the GPU
+    FP64 solve follows the oracle's, iteration by iteration."""
+    cfg, U, Bh, ref, lat = c1
+    X, info = _solve(lat, cfg.L, Bh, tol=cfg.tol, sap_prec=B.FP64)
+    h = info["history"]
+    assert len(h) == info["iterations"]
+    n = min(len(h), len(ref.history))
+    assert n >= len(ref.history) - 1
+    np.testing.assert_allclose(h[:n], ref.history[:n], rtol=1e-4)
+    assert h[-1] <= cfg.tol and np.all(h[:-1] > cfg.tol)
+    np.testing.assert_allclose(h[-1], np.max(info["rec_res"]), rtol=1e-12)
+
+
+def test_rtilde_given_matches_oracle(c1):
+    """R~ chosen by the caller (Alg. 1: "choose R~"; here a seeded Gaussian
+    block): GPU FP64 solve against the oracle run with the same R~."""
+    cfg, U, Bh, ref, lat = c1
+    gu.flush("c1 with a given R~")
+    Rt = inputs.gaussian_block(cfg.V, cfg.L, 4100)
+    dom = sap.Domains(cfg.dims, cfg.block)
+    A = lambda X: dirac.apply_D(U, cfg.kappa, cfg.phases, X, cfg.dims).reshape(12 * cfg.V, -1)
+    M = lambda X: sap.sap(U, cfg.kappa, cfg.phases, dom, X, cfg.ncy, cfg.nmr).reshape(12 * cfg.V, -1)
+    refr = krylov.block_bicgstab(A, M, Bh, cfg.tol, maxiter=100, Rt=Rt)
+    Rtd = gu.dev(Rt)
+    X, info = _solve(lat, cfg.L, Bh, tol=cfg.tol, sap_prec=B.FP64, rtilde=Rtd)
+    assert info["status"] == B.OK and refr.converged
+    assert abs(info["iterations"] - refr.iterations) <= 1, (info["iterations"], refr.iterations)
+    n = min(len(info["history"]), len(refr.history)) - 1
+    np.testing.assert_allclose(info["history"][:n], refr.history[:n], rtol=1e-4)
+    err = np.linalg.norm(X - refr.X, axis=0) / np.linalg.norm(refr.X, axis=0)
+    assert np.all(err <= 1e-8), err
+    # a different R~ gives a different iteration path than R~ = R_0
+    assert not np.allclose(info["history"][:3], ref.history[:3], rtol=1e-3)
+
+
+def test_restart_from_true_residual_vs_oracle():
+    """The restart branch: without the QR step (qr_passes = 0, the plain block
+    BiCGSTAB) the true residual of this system stalls about two decades above
+    the recursive one, so at tol = 1e-14 the recursion stops early; the
+    solver must then restart from R = B - A X, P = R (keeping R~) and reach
+    the tolerance.  Checked against the oracle's run of the same system with
+    the same reading: both restart at least once, the oracle's own residual of
+    the GPU solution is <= tol, and the two solutions agree."""
+    dims, block, L, kappa, tol = (4, 4, 4, 4), (2, 2, 2, 2), 6, 0.15, 1e-14
+    U = inputs.gauge_field(dims, 0.3, 31)
+    Bh = inputs.z2_sources(256, L, 9)
+    D = dirac.dense_D(U, kappa, gu.PH_AP, dims)
+    ref = krylov.block_bicgstab(lambda X: D @ X, lambda X: X, Bh, tol, maxiter=400, qr=False, max_restarts=6)
+    assert ref.restarts >= 1 and ref.converged
+    with gu.Lattice(dims, block, U, kappa) as lat:
+        X, info = _solve(lat, L, Bh, tol=tol, precond=0, qr_passes=0, max_restarts=6, maxiter=400)
+    gu.flush(f"  restart: GPU {info['iterations']} iterations {info['restarts']} restarts, "
+             f"oracle {ref.iterations} / {ref.restarts}")
+    assert info["restarts"] >= 1
+    assert info["status"] == B.OK
+    tr = np.linalg.norm(Bh - D @ X, axis=0) / np.linalg.norm(Bh, axis=0)
+    assert np.all(tr <= tol * 1.01), tr
+    assert np.all(info["true_res"] <= tol)
+    err = np.linalg.norm(X - ref.X, axis=0) / np.linalg.norm(ref.X, axis=0)
+    assert np.all(err <= 1e-10), err
+    # with the QR step the same system needs no restart
+    with gu.Lattice(dims, block, U, kappa) as lat:
+        Xq, iq = _solve(lat, L, Bh, tol=tol, precond=0, max_restarts=6, maxiter=400)
+    assert iq["status"] == B.OK and iq["restarts"] == 0
+
+
 def test_graph_and_cholqr2(c1):
     cfg, U, Bh, ref, lat = c1
     s = torch.cuda.Stream()
@@ -228,11 +313,13 @@ def test_batched_mixed_solvers_clover_and_a_bad_system():
             l.close()
 
 
-def _c4_check(cfg, tag, sap_prec=B.FP32, **kw):
+def _c4_check(cfg, tag, sap_prec=B.FP32, full=False, **kw):
     """Solve a 32^3 x 64 system to 1e-10 (FP32 SAP on 8^4 domains); form the
     residual B - D X of the GPU solution on the GPU in FP64 and compare it
     with the oracle's at sampled sites (the source site and its 8 neighbours
-    among them), so the norms the solver reports rest on checked values."""
+    among them), so the norms the solver reports rest on checked values.
+    full: also the oracle's own true residual of the GPU solution over the
+    whole lattice (its operator applied to X, four columns at a time)."""
     V, L, dims = cfg.V, cfg.L, cfg.dims
     gu.flush(f"c4 {tag}: links")
     U = cfg.gauge()
@@ -262,6 +349,17 @@ def _c4_check(cfg, tag, sap_prec=B.FP32, **kw):
     # ||B_j|| = 1; D X is O(1) per element, so FP64 rounding is ~1e-15
     assert np.max(np.abs(Rg - Ro)) <= 1e-13
     assert np.all(np.linalg.norm(Ro, axis=0) <= 1e-10)
+    if full:
+        tr = []
+        for j0 in range(0, L, 4):
+            gu.flush(f"c4 {tag}: oracle true residual over the whole lattice, columns {j0}..{min(L, j0 + 4) - 1}")
+            Xj = np.ascontiguousarray(X[:, j0:j0 + 4])
+            R = Bh[:, j0:j0 + 4] - dirac.apply_D(U, cfg.kappa, cfg.phases, Xj, dims).reshape(Xj.shape)
+            tr += (np.linalg.norm(R, axis=0) / np.linalg.norm(Bh[:, j0:j0 + 4], axis=0)).tolist()
+            del R
+        gu.flush(f"  oracle true residuals {np.max(tr):.2e} (GPU reported {np.max(info['true_res']):.2e})")
+        assert np.all(np.array(tr) <= 1e-10 * 1.01), tr
+        np.testing.assert_allclose(tr, info["true_res"], rtol=1e-3)
 
 
 @pytest.mark.slow
@@ -271,7 +369,7 @@ def test_c4_mixed_full_size(domain_solver):
     domains: 4 cycles of 4 MR steps, or the paper's SSOR with N_SSOR = 1 and
     omega = 1.26) solved to 1e-10, checked against the oracle."""
     _c4_check(configs.c4(), "SSOR" if domain_solver else "MR", domain_solver=domain_solver, nssor=1,
-              ssor_omega=1.26)
+              ssor_omega=1.26, full=domain_solver == 0)
 
 
 @pytest.mark.slow
@@ -282,7 +380,7 @@ def test_c4_variants_full_size(variant):
     if variant == "alg2":
         _c4_check(configs.c4(), "Alg. 2", memsave=1)
     else:
-        _c4_check(configs.c4(), "FP16S SAP", sap_prec=B.FP16S)
+        _c4_check(configs.c4(), "FP16S SAP", sap_prec=B.FP16S, full=True)
 
 
 @pytest.mark.slow
