@@ -240,6 +240,18 @@ int mbbs_gram_workspace_size(size_t N, int L, size_t* bytes);
 int mbbs_gram(size_t N, int L, const double* X_dev, const double* Y_dev, double* G_dev,
               void* ws_dev, size_t ws_bytes, void* stream);
 
+/* No-allocation form of mbbs_gram, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): same product, same kernels and the same bits as
+ * mbbs_gram, with the partial sums kept in a static device buffer the
+ * library owns (12 MiB on each device it runs on, held until the process
+ * ends) instead of a caller workspace.  L in 1..16 (EINVAL otherwise), any
+ * N.  Allocates nothing.  Every call on one device shares that buffer, so
+ * calls that overlap on one device (other streams or threads) race; calls in
+ * one stream's order do not.  Errors: EINVAL, EHIP. */
+int mbbs_gram_noalloc(size_t N, int L, const double* X_dev, const double* Y_dev, double* G_dev,
+                      void* stream);
+
 /* Cholesky QR (step 4.1, QR of P): G = P^H P = gamma^H gamma, Q = P gamma^{-1},
  * gamma upper triangular with positive real diagonal (the unique QR factor).
  * passes = 2 repeats the factorisation on Q (CholQR2).  Q_dev may equal P_dev.

@@ -30,7 +30,7 @@ EXPORTS = (
     "mbbs_apply_dirac", "mbbs_apply_dirac_raw", "mbbs_convert_to", "mbbs_convert_from",
     "mbbs_apply_blocked", "mbbs_sap_workspace_size", "mbbs_sap_apply", "mbbs_ssor_workspace_size",
     "mbbs_sap_apply_ssor", "mbbs_apply_ssor_blocked", "mbbs_gram_workspace_size",
-    "mbbs_gram", "mbbs_cholqr", "mbbs_lu_solve", "mbbs_solve_params_default",
+    "mbbs_gram", "mbbs_gram_noalloc", "mbbs_cholqr", "mbbs_lu_solve", "mbbs_solve_params_default",
     "mbbs_solve_workspace_size", "mbbs_solve", "mbbs_solve_batched_workspace_size",
     "mbbs_solve_batched", "mbbs_last_error",
 )
@@ -96,6 +96,7 @@ def lib():
             "mbbs_apply_ssor_blocked": (i, [vp, i, vp, vp, i, d, i, vp, sz, vp]),
             "mbbs_gram_workspace_size": (i, [sz, i, ctypes.POINTER(sz)]),
             "mbbs_gram": (i, [sz, i, vp, vp, vp, vp, sz, vp]),
+            "mbbs_gram_noalloc": (i, [sz, i, vp, vp, vp, vp]),
             "mbbs_cholqr": (i, [sz, i, vp, vp, vp, i, vp, sz, vp]),
             "mbbs_lu_solve": (i, [i, i, vp, vp, vp, vp]),
             "mbbs_solve_params_default": (None, [ctypes.POINTER(SolveParams)]),
@@ -264,6 +265,11 @@ def mbbs_gram_workspace_size(N, L):
 def mbbs_gram(N, L, X, Y, G, ws, stream=None):
     return _check(lib().mbbs_gram(N, L, _dev(X, _c128()), _dev(Y, _c128()), _dev(G, _c128()), _dev(ws),
                                   ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def mbbs_gram_noalloc(N, L, X, Y, G, stream=None):
+    return _check(lib().mbbs_gram_noalloc(N, L, _dev(X, _c128()), _dev(Y, _c128()), _dev(G, _c128()),
+                                          _stream(stream)))
 
 
 def mbbs_cholqr(N, L, P, Q, gamma, passes, ws, stream=None):

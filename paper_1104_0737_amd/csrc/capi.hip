@@ -1,6 +1,7 @@
 // C-ABI entry points for the operator, the SAP preconditioner and the block
 // linear algebra (the solver's own entry points live with the solver).
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "blas.h"
@@ -156,6 +157,60 @@ extern "C" int mbbs_gram(size_t N, int L, const double* X, const double* Y, doub
   GramOut o{};
   o.G[0] = (double2*)G;
   return launch_gram(L, N, a, o, (double2*)ws, nullptr, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------- no allocation
+// Static device scratch of mbbs_gram_noalloc: the per-block partial Gram
+// matrices (at most GRAM_MAXBLK blocks x GRAM_MAXPAIR products x 16 x 16
+// complex doubles, 12 MiB).  Each device the library runs on holds its own
+// copy until the process ends.  In host code `scratch` is only a stand-in
+// for the symbol: its device address, per device, comes from
+// hipGetSymbolAddress and is the only form passed to kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES =
+    (size_t)GRAM_MAXBLK * GRAM_MAXPAIR * LMAX_SOLVER * LMAX_SOLVER * sizeof(double2);
+static __device__ __align__(256) double2 scratch[NOALLOC_SCRATCH_BYTES / sizeof(double2)];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// The current device's address of `scratch`, looked up once per device (with
+// that device current) on the first call there.
+int scratch_address(double2** out) {
+  int dev = -1;
+  MBBS_HIP(hipGetDevice(&dev));
+  MBBS_CHECK(dev >= 0 && dev < NOALLOC_MAX_DEVICES, "device index beyond the no-allocation table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      return MBBS_EHIP;
+    }
+    g_scratch_dev[dev] = p;
+  }
+  *out = (double2*)g_scratch_dev[dev];
+  return MBBS_OK;
+}
+}  // namespace
+
+extern "C" int mbbs_gram_noalloc(size_t N, int L, const double* X, const double* Y, double* G, void* stream) {
+  MBBS_CHECK(X && Y && G, "null argument");
+  MBBS_CHECK(L >= 1 && L <= LMAX_SOLVER, "L must be in 1..16 (the static scratch holds 16 x 16 partials)");
+  MBBS_CHECK(gram_partial_bytes(N, L) <= NOALLOC_SCRATCH_BYTES, "Gram partials exceed the static scratch");
+  double2* partial = nullptr;
+  MBBS_TRY(scratch_address(&partial));
+  // every block writes its own partial before the finishing pass reads it:
+  // nothing in the scratch has to start at zero
+  GramArgs a{};
+  a.npair = 1;
+  a.X[0] = (const double2*)X;
+  a.Y[0] = (const double2*)Y;
+  GramOut o{};
+  o.G[0] = (double2*)G;
+  return launch_gram(L, N, a, o, partial, nullptr, (hipStream_t)stream);
 }
 
 extern "C" int mbbs_cholqr(size_t N, int L, const double* P, double* Q, double* gamma, int passes, void* ws,
