@@ -512,8 +512,11 @@ def batched_main(args):
     """Batched form: 16 x 8^4 (L=4), 16 x 12^4 (L=6), 16 x 16^3x32 (L=12) systems,
     seeded links with eps ~ U[0.15, 0.3] and kappa ~ U[0.11, 0.123], half Z2 and
     half point sources, FP32 SAP, tolerance 1e-10 per column.  One step solves
-    all 48 together (interleaved iterations captured in HIP graphs); beside it,
-    the same systems solved one after another."""
+    all 48 together: each size group is one batch handle whose 16 systems share
+    every launch (fused), the three groups run concurrently in one batched call
+    with graph_iters iterations per captured HIP graph.  Beside it: the same
+    48 systems as separate handles in one batched call (concurrent but not
+    fused), and one after another."""
     import torch
     from paper_1104_0737_amd import binding as B
     from paper_1104_0737_amd import configs
@@ -521,83 +524,109 @@ def batched_main(args):
     stream = torch.cuda.Stream(device=dev)
     torch.cuda.set_stream(stream)
     systems = configs.c5_systems()
+    groups = [systems[16 * g:16 * g + 16] for g in range(3)]
     log("generating 48 systems")
-    lats, Bs, Ls, params = [], [], [], []
-    for s in systems:
-        U = configs.c5_gauge(s)
-        lat = B.mbbs_lattice_create(s.dims, s.block, torch.from_numpy(U).to(dev), s.kappa, s.phases, stream=stream)
-        lats.append(lat)
-        Bs.append(torch.from_numpy(configs.c5_sources(s)).to(dev))
-        Ls.append(s.L)
-        params.append(B.mbbs_solve_params_default(tol=1e-10, sap_prec=B.FP32, graph_iters=args.graph_iters))
-    Xs = [torch.empty_like(b) for b in Bs]
-    # launch settings: tuned once per (lattice shape, L) on the group's first
-    # system, then applied to every system of the group
+    singles, batches, Bs_single, Bs_group, Ls = [], [], [], [], []
+    for grp in groups:
+        Ud = []
+        for s in grp:
+            U = torch.from_numpy(configs.c5_gauge(s)).to(dev)
+            Ud.append(U)
+            singles.append(B.mbbs_lattice_create(s.dims, s.block, U, s.kappa, s.phases, stream=stream))
+            Bs_single.append(torch.from_numpy(configs.c5_sources(s)).to(dev))
+        s0 = grp[0]
+        batches.append(B.mbbs_lattice_create_batch(s0.dims, s0.block, Ud, [s.kappa for s in grp], s0.phases,
+                                                   stream=stream))
+        Bs_group.append(torch.cat(Bs_single[-16:]))
+        Ls.append(s0.L)
+        del Ud
+    torch.cuda.empty_cache()
+    # launch settings: tuned on each batch handle, applied to its systems' single handles too
     tuned = {}
     if not args.no_tune:
         from paper_1104_0737_amd import autotune
-        for s, lat in zip(systems, lats):
-            key = (s.dims, s.L)
-            if key not in tuned:
-                V = int(np.prod(s.dims))
-                st = {}
-                for prec in (B.FP64, B.FP32):
-                    best, times = autotune.tune_operator(lat, V, s.L, prec, stream=stream)
-                    if prec != B.FP64:
-                        best, _ = autotune.tune_sap(lat, V, s.L, prec, times, stream=stream)
-                    st[prec] = best
-                tuned[key] = st
-                log(f"tuned {'x'.join(map(str, s.dims))} L={s.L}: FP64 {st[B.FP64]}, FP32 SAP {st[B.FP32]}")
-            for prec, setting in tuned[key].items():
-                autotune.apply(lat, prec, setting)
+        for g, (grp, bh) in enumerate(zip(groups, batches)):
+            V = 16 * grp[0].V
+            st = {}
+            for prec in (B.FP64, B.FP32):
+                best, times = autotune.tune_operator(bh, V, grp[0].L, prec, stream=stream)
+                if prec != B.FP64:
+                    best, _ = autotune.tune_sap(bh, V, grp[0].L, prec, times, stream=stream)
+                st[prec] = best
+                for lat in singles[16 * g:16 * g + 16]:
+                    autotune.apply(lat, prec, best)
+            tuned[(grp[0].dims, grp[0].L)] = st
+            log(f"tuned {'x'.join(map(str, grp[0].dims))} L={grp[0].L}: FP64 {st[B.FP64]}, FP32 SAP {st[B.FP32]}")
         torch.cuda.empty_cache()
-    ws = torch.empty(B.mbbs_solve_batched_workspace_size(lats, Ls, params), dtype=torch.uint8, device=dev)
-    rhs = sum(Ls)
+    params = [B.mbbs_solve_params_default(tol=1e-10, sap_prec=B.FP32, graph_iters=args.graph_iters) for _ in batches]
+    ws = torch.empty(B.mbbs_solve_batched_workspace_size(batches, Ls, params), dtype=torch.uint8, device=dev)
+    Xs_group = [torch.empty_like(b) for b in Bs_group]
+    rhs = sum(16 * L for L in Ls)
 
-    def run_batched():
+    def run_fused():
         torch.cuda.synchronize()
         t = time.perf_counter()
-        rc, infos = B.mbbs_solve_batched(lats, Ls, Bs, Xs, params, ws, stream=stream)
+        rc, infos = B.mbbs_solve_batched(batches, Ls, Bs_group, Xs_group, params, ws, stream=stream)
         torch.cuda.synchronize()
         return time.perf_counter() - t, rc, infos
 
     for w in range(args.warmup):
-        dt, rc, _ = run_batched()
-        log(f"warmup batched: {dt:.3f}s rc {rc}")
+        dt, rc, _ = run_fused()
+        log(f"warmup fused batched: {dt:.3f}s rc {rc}")
     times, infos = [], None
     for k in range(args.steps):
-        dt, rc, infos = run_batched()
+        dt, rc, infos = run_fused()
         times.append(dt)
         log(f"step {k}: {dt:.3f}s rc {rc}")
-    # the same systems one by one (no graphs), for comparison
+    del ws
+    torch.cuda.empty_cache()
+    # the same 48 systems as separate handles in one batched call (concurrent, not fused)
+    Ls48 = [s.L for s in systems]
+    p48 = [B.mbbs_solve_params_default(tol=1e-10, sap_prec=B.FP32, graph_iters=args.graph_iters) for _ in systems]
+    ws48 = torch.empty(B.mbbs_solve_batched_workspace_size(singles, Ls48, p48), dtype=torch.uint8, device=dev)
+    Xs48 = [torch.empty_like(b) for b in Bs_single]
+    B.mbbs_solve_batched(singles, Ls48, Bs_single, Xs48, p48, ws48, stream=stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rc48, infos48 = B.mbbs_solve_batched(singles, Ls48, Bs_single, Xs48, p48, ws48, stream=stream)
+    torch.cuda.synchronize()
+    unfused = time.perf_counter() - t
+    del ws48
+    torch.cuda.empty_cache()
+    log(f"separate handles, one batched call: {unfused:.3f}s rc {rc48}")
+    # one after another (no graphs)
     torch.cuda.synchronize()
     t = time.perf_counter()
     seq_ok = True
-    for lat, L, b, x in zip(lats, Ls, Bs, Xs):
+    for lat, L, b, x in zip(singles, Ls48, Bs_single, Xs48):
         p = B.mbbs_solve_params_default(tol=1e-10, sap_prec=B.FP32)
         w1 = torch.empty(B.mbbs_solve_workspace_size(lat, L, p), dtype=torch.uint8, device=dev)
         info = B.mbbs_solve(lat, L, b, x, p, w1, stream=stream)
         seq_ok = seq_ok and info["status"] == 0
     torch.cuda.synchronize()
     seq = time.perf_counter() - t
+    log(f"one by one: {seq:.3f}s")
     step_s = sum(times) / len(times)
     ok = all(i["status"] == 0 for i in infos)
     max_true = max(float(np.max(i["true_res"])) for i in infos)
-    groups = {}
+    groups_it = {}
     for s, i in zip(systems, infos):
-        g = "x".join(map(str, s.dims))
-        groups.setdefault(g, []).append(i["iterations"])
+        groups_it.setdefault("x".join(map(str, s.dims)), []).append(i["iterations"])
     out = {"metric": "batched solve, RHS/s (48 systems, 352 RHS, FP32 SAP, tol 1e-10)", "value": rhs / step_s,
            "unit": "RHS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_s * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
-           "data": "synthetic", "converged": ok, "max_true_res": max_true, "sequential_s": seq, "sequential_all_converged": seq_ok,
-           "batched_over_sequential": seq / step_s, "iterations": {g: [min(v), max(v)] for g, v in groups.items()},
+           "data": "synthetic", "converged": ok, "max_true_res": max_true,
+           "separate_handles_s": unfused, "separate_handles_all_converged": rc48 == 0,
+           "sequential_s": seq, "sequential_all_converged": seq_ok,
+           "fused_over_sequential": seq / step_s, "fused_over_separate_handles": unfused / step_s,
+           "iterations": {g: [min(v), max(v)] for g, v in groups_it.items()},
            "tuning": {f"{'x'.join(map(str, k[0]))} L={k[1]}": {str(p): list(v) for p, v in st.items()}
                       for k, st in tuned.items()},
            "config": {"workload": "16 x 8^4 L=4 + 16 x 12^4 L=6 + 16 x 16^3x32 L=12, SAP 4^4/6^4/8^4, "
-                                  f"graph_iters={args.graph_iters}", "parallelism": "single GPU"}}
+                                  f"three batch handles (16 systems fused per launch), graph_iters={args.graph_iters}",
+                      "parallelism": "single GPU"}}
     print(json.dumps(out), flush=True)
-    for lat in lats:
+    for lat in singles + batches:
         B.mbbs_lattice_destroy(lat)
 
 

@@ -68,6 +68,23 @@ int mbbs_lattice_create(const int dims[4], const int block[4], const double* U_d
                         double kappa, const double phase[8], void* stream,
                         mbbs_lattice_t* out);
 
+/* A batch of nsys independent systems of one shape (dims, block, phases) in
+ * one handle, each with its own links U_dev[s] (FP64, layout above, copied)
+ * and hopping parameter kappa[s] (host array).  Every kernel launched on the
+ * handle serves all of its systems at once: fields hold the systems one
+ * after the other (system s occupies rows [s N, (s + 1) N) of an
+ * (nsys N) x L block, N = 12 Lx Ly Lz Lt), so the operator, SAP and the
+ * solver act on each system exactly as a single-system handle would, while
+ * one launch covers every system (the fused form of many small solves).
+ * mbbs_solve on a batch handle solves all systems together: B_dev and X_dev
+ * are the stacked blocks and `info` points to nsys records; a system that
+ * stops early is skipped by every later kernel.  The clover term is not
+ * available on batch handles.  Errors as for mbbs_lattice_create.
+ * mbbs_lattice_nsys: the number of systems of a handle (1 for a single one). */
+int mbbs_lattice_create_batch(int nsys, const int dims[4], const int block[4], const double* const* U_dev,
+                              const double* kappa, const double phase[8], void* stream, mbbs_lattice_t* out);
+int mbbs_lattice_nsys(mbbs_lattice_t lat, int* nsys);
+
 /* Release every device buffer of the handle.  NULL is accepted. */
 int mbbs_lattice_destroy(mbbs_lattice_t lat);
 
@@ -285,8 +302,9 @@ typedef struct {
   int domain_solver;   /* SAP domain solver: 0 = nmr MR steps, 1 = SSOR           */
   int nssor;           /* SSOR correction terms N_SSOR (0 or 1)                   */
   double ssor_omega;   /* SSOR relaxation, 0 < omega < 2                          */
-  const double* rtilde;/* R~ of Alg. 1 ("choose R~"): a device FP64 N x L block,
-                          read once at the start; NULL: R~ = R_0                  */
+  const double* rtilde;/* R~ of Alg. 1 ("choose R~"): a device FP64 N x L block
+                          (a batch handle: the systems' blocks stacked), read
+                          once at the start; NULL: R~ = R_0                       */
 } mbbs_solve_params;
 
 /* Kernel classes timed when params.profile = 1. */
@@ -337,19 +355,22 @@ int mbbs_solve(mbbs_lattice_t lat, int L, const double* B_dev, double* X_dev,
                const mbbs_solve_params* params, void* ws_dev, size_t ws_bytes,
                mbbs_solve_info* info, void* stream);
 
-/* Solve nsys independent systems (each its own lattice, L, B, X, params and
- * info) together.  The systems are spread over up to 4 internal streams
- * (created and destroyed by the call, default priority; the first waits for
- * the work already on `stream`), largest first onto the least loaded one, so
- * the launches of small systems run concurrently.  Each system advances in
- * batches of graph_iters iterations (captured once in a per-system HIP graph
- * and replayed when graph_iters > 1); the host polls one event per system and
- * enqueues its next batch, true-residual check or restart as soon as its
- * previous batch has drained, without waiting for the other systems.  A
- * system that converges inside a batch stops on a device flag.  ws_dev holds
- * mbbs_solve_batched_workspace_size bytes (device); the call also takes a
- * small pinned host buffer for the state records.  Blocks until every system
- * is done; infos[i] and the return value are as for mbbs_solve (the worst
+/* Solve nsys independent jobs (each its own lattice handle, L, B, X and
+ * params) together.  A job on a batch handle (mbbs_lattice_create_batch)
+ * covers all of that handle's systems in fused launches (stacked B and X);
+ * `infos` holds one record per system, the jobs' systems in argument order.
+ * The jobs are spread over up to 4 internal streams (created and destroyed
+ * by the call, default priority; the first waits for the work already on
+ * `stream`), largest first onto the least loaded one, so the launches of
+ * small jobs run concurrently.  Each job advances in batches of graph_iters
+ * iterations (captured once in a per-job HIP graph and replayed when
+ * graph_iters > 1); the host polls one event per job and enqueues its next
+ * batch, true-residual check or restarts as soon as its previous batch has
+ * drained, without waiting for the other jobs.  A system that converges
+ * inside a batch stops on a device flag.  ws_dev holds
+ * mbbs_solve_batched_workspace_size bytes (device); the call also takes small
+ * pinned host buffers for the state records.  Blocks until every system is
+ * done; each record and the return value are as for mbbs_solve (the worst
  * status over the systems). */
 int mbbs_solve_batched_workspace_size(int nsys, const mbbs_lattice_t* lats, const int* Ls,
                                       const mbbs_solve_params* params, size_t* bytes);

@@ -24,7 +24,7 @@ TABLES = ("COORD", "NEIGHBOUR", "BOUNDARY", "PARITY", "EO", "DOMAIN", "COLOUR", 
 KERNEL_CLASSES = ("dslash64", "sap_resid", "mr_dslash", "mr_update", "convert", "gram", "update", "small", "ssor")
 
 EXPORTS = (
-    "mbbs_lattice_create", "mbbs_lattice_destroy", "mbbs_lattice_tune", "mbbs_lattice_set_clover",
+    "mbbs_lattice_create", "mbbs_lattice_create_batch", "mbbs_lattice_nsys", "mbbs_lattice_destroy", "mbbs_lattice_tune", "mbbs_lattice_set_clover",
     "mbbs_lattice_clover_inverse", "mbbs_apply_clover_inverse", "mbbs_lattice_table_size",
     "mbbs_lattice_table",
     "mbbs_apply_dirac", "mbbs_apply_dirac_raw", "mbbs_convert_to", "mbbs_convert_from",
@@ -77,6 +77,9 @@ def lib():
         sig = {
             "mbbs_lattice_create": (i, [ctypes.POINTER(i), ctypes.POINTER(i), vp, d, ctypes.POINTER(d), vp,
                                         ctypes.POINTER(vp)]),
+            "mbbs_lattice_create_batch": (i, [i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(vp),
+                                              ctypes.POINTER(d), ctypes.POINTER(d), vp, ctypes.POINTER(vp)]),
+            "mbbs_lattice_nsys": (i, [vp, ctypes.POINTER(i)]),
             "mbbs_lattice_destroy": (i, [vp]),
             "mbbs_lattice_tune": (i, [vp, i, i]),
             "mbbs_lattice_set_clover": (i, [vp, d, vp]),
@@ -159,6 +162,28 @@ def mbbs_lattice_create(dims, block, U, kappa, phases, stream=None):
     out = ctypes.c_void_p()
     _check(lib().mbbs_lattice_create(d, b, _dev(U, _c128()), float(kappa), ph, _stream(stream), ctypes.byref(out)))
     return out
+
+
+def mbbs_lattice_create_batch(dims, block, Us, kappas, phases, stream=None):
+    """A batch of len(Us) same-shape systems in one handle: Us are complex128
+    device tensors (V, 4, 3, 3), kappas one value per system."""
+    n = len(Us)
+    if len(kappas) != n:
+        raise ValueError("one kappa per system")
+    d = (ctypes.c_int * 4)(*dims)
+    b = (ctypes.c_int * 4)(*block)
+    up = (ctypes.c_void_p * n)(*[_dev(u, _c128()).value for u in Us])
+    kp = (ctypes.c_double * n)(*[float(k) for k in kappas])
+    ph = (ctypes.c_double * 8)(*[float(x) for p in phases for x in p])
+    out = ctypes.c_void_p()
+    _check(lib().mbbs_lattice_create_batch(n, d, b, up, kp, ph, _stream(stream), ctypes.byref(out)))
+    return out
+
+
+def mbbs_lattice_nsys(lat):
+    n = ctypes.c_int()
+    _check(lib().mbbs_lattice_nsys(lat, ctypes.byref(n)))
+    return n.value
 
 
 def mbbs_lattice_destroy(lat):
@@ -329,11 +354,24 @@ def _info_dict(info, tr, rr, hist, rc):
 
 
 def mbbs_solve(lat, L, B, X, params, ws, stream=None):
-    """Returns a dict: status, iterations, restarts, residuals, timings."""
-    info, tr, rr, hist = _info(L)
-    rc = _check(lib().mbbs_solve(lat, L, _dev(B, _c128()), _dev(X, _c128()), ctypes.byref(params), _dev(ws),
-                                 ws.numel() * ws.element_size(), ctypes.byref(info), _stream(stream)))
-    return _info_dict(info, tr, rr, hist, rc)
+    """Single-system handle: returns a dict (status, iterations, restarts,
+    residuals, timings, history).  Batch handle (B, X the stacked blocks):
+    returns (worst status, [dict per system]) and raises only when the call
+    failed before any system was solved."""
+    ns = mbbs_lattice_nsys(lat)
+    infos = (SolveInfo * ns)()
+    keep = [_attach(infos[k], L) for k in range(ns)]
+    unset = 99                          # not an mbbs status: marks a record the call never filled
+    for k in range(ns):
+        infos[k].status = unset
+    rc = lib().mbbs_solve(lat, L, _dev(B, _c128()), _dev(X, _c128()), ctypes.byref(params), _dev(ws),
+                          ws.numel() * ws.element_size(), infos, _stream(stream))
+    if ns == 1:
+        _check(rc)
+        return _info_dict(infos[0], *keep[0], rc)
+    if rc < 0 and all(infos[k].status in (unset, rc) for k in range(ns)):
+        _check(rc)
+    return rc, [_info_dict(infos[k], *keep[k], infos[k].status) for k in range(ns)]
 
 
 def mbbs_solve_batched_workspace_size(lats, Ls, params):
@@ -355,17 +393,20 @@ def mbbs_solve_batched(lats, Ls, Bs, Xs, params, ws, stream=None):
     Bp = (ctypes.c_void_p * n)(*[_dev(b, _c128()).value for b in Bs])
     Xp = (ctypes.c_void_p * n)(*[_dev(x, _c128()).value for x in Xs])
     pa = (SolveParams * n)(*params)
-    infos = (SolveInfo * n)()
-    keep = [_attach(infos[k], Ls[k]) for k in range(n)]
-    unset = 99                          # not an mbbs status: marks an info the call never filled
-    for k in range(n):
+    nsys = [mbbs_lattice_nsys(x) for x in lats]
+    sysL = [L for L, m in zip(Ls, nsys) for _ in range(m)]
+    ntot = len(sysL)
+    infos = (SolveInfo * ntot)()
+    keep = [_attach(infos[k], sysL[k]) for k in range(ntot)]
+    unset = 99                          # not an mbbs status: marks a record the call never filled
+    for k in range(ntot):
         infos[k].status = unset
     rc = lib().mbbs_solve_batched(n, la, Li, Bp, Xp, pa, _dev(ws), ws.numel() * ws.element_size(), infos,
                                   _stream(stream))
-    if rc < 0 and all(infos[k].status == unset for k in range(n)):
+    if rc < 0 and all(infos[k].status == unset for k in range(ntot)):
         _check(rc)                      # the call failed before solving anything
-    # per-system failures: the return value is the worst status, each info has its own
-    return rc, [_info_dict(infos[k], *keep[k], infos[k].status) for k in range(n)]
+    # per-system failures: the return value is the worst status, each record has its own
+    return rc, [_info_dict(infos[k], *keep[k], infos[k].status) for k in range(ntot)]
 
 
 def mbbs_last_error():

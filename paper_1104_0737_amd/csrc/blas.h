@@ -72,18 +72,48 @@ struct SolverDev {
   int qr_passes;      // 0: no QR (gamma = 1), 1: Cholesky QR, 2: CholQR2
 };
 
+// A batch of systems solved together: every N x L block holds the systems one
+// after the other (rows [s N, (s + 1) N) for system s), and every small
+// per-system array is repeated per system (L x L matrices every L*L entries,
+// length-L vectors every L, scalars and solver states every 1, histories
+// every HIST_CAP).  The streaming kernels take the system from blockIdx.y,
+// the one-workgroup coefficient kernels from blockIdx.x; a system whose flag
+// frozen[s * fstride] is set is skipped.  A single system is n = 1.
+struct SysBatch {
+  int n = 1;
+  int fstride = 0;
+};
+static_assert(sizeof(SolverState) == SOLVER_FLAG_STRIDE * sizeof(int), "solver state record layout");
+
+// The pointers of system s in a batch laid out as above.
+__host__ __device__ inline SolverDev sys_view(SolverDev d, int s, int L) {
+  const size_t LL = (size_t)L * L;
+  d.state += s;
+  d.rnorm2 += (size_t)s * L; d.bnorm2 += (size_t)s * L;
+  d.Gpp += s * LL; d.Gpp2 += s * LL; d.ginv += s * LL; d.RtV += s * LL; d.RtR += s * LL; d.RtZ += s * LL;
+  d.ZT += s * LL; d.ZZ += s * LL; d.lu += s * LL; d.alpha += s * LL; d.nalpha += s * LL; d.beta += s * LL;
+  d.C1 += s * LL; d.C2 += s * LL;
+  d.piv += (size_t)s * L;
+  d.zeta += s; d.nzeta += s; d.one += s;
+  d.hist += (size_t)s * HIST_CAP;
+  return d;
+}
+
 int gram_blocks(size_t N, int L);
-size_t gram_partial_bytes(size_t N, int L);
+size_t gram_partial_bytes(size_t N, int L, int nsys = 1);
 int launch_gram(int L, size_t N, const GramArgs& a, const GramOut& o, double2* partial, const int* frozen,
-                hipStream_t st);
+                hipStream_t st, SysBatch sb = SysBatch());
 int launch_combo(int L, size_t N, const ComboArgs& a, double2* out, int gram_mode, const GramOut* o,
-                 double2* partial, const int* frozen, hipStream_t st);
-// which: 0 CholQR factor, 1 second CholQR pass, 2 alpha, 3 zeta/beta
-int launch_coef(int which, int L, const SolverDev& d, hipStream_t st);
+                 double2* partial, const int* frozen, hipStream_t st, SysBatch sb = SysBatch());
+// which: 0 CholQR factor, 1 second CholQR pass, 2 alpha, 3 zeta/beta; one
+// workgroup per system
+int launch_coef(int which, int L, const SolverDev& d, hipStream_t st, int nsys = 1);
 // Loop test of Alg. 1 on the current ||r_i||^2 (sets frozen and the status
 // once it stops the iteration) and the residual-history entry of the
-// iteration just finished.
-int launch_loop_test(int L, const SolverDev& d, hipStream_t st);
+// iteration just finished, per system.
+int launch_loop_test(int L, const SolverDev& d, hipStream_t st, int nsys = 1);
+// b = a on n_per_sys entries of every system whose flag is clear.
+int launch_copy_sys(const double2* a, double2* b, size_t n_per_sys, const int* frozen, hipStream_t st, SysBatch sb);
 int launch_fill(double2* p, size_t n, double2 v, hipStream_t st);
 int launch_chol_standalone(int L, const double2* G, double2* gam, double2* ginv, int* ok, hipStream_t st);
 int launch_matmul_small(int L, const double2* A, const double2* B, double2* C, hipStream_t st);

@@ -36,11 +36,18 @@ __device__ inline double2 block_reduce_y(double2* sh, cplx<double> v, int j, int
 // accumulators stay in registers.
 template <int LMAX, int NF, int ND, bool EXACT = false>
 __global__ void __launch_bounds__(256) k_gram(int L, size_t N, GramArgs a, double2* __restrict__ partial,
-                                              const int* __restrict__ frozen) {
+                                              const int* __restrict__ frozen, int fstride) {
   if constexpr (EXACT) L = LMAX;   // L known at compile time: immediate offsets, no column bounds
   // pairs 0..NF-1 are full products, NF..NF+ND-1 diagonal-only
   constexpr int NP = NF + ND;
-  if (frozen && *frozen) return;
+  const int sys = blockIdx.y;
+  if (frozen && frozen[sys * fstride]) return;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    a.X[p] += (size_t)sys * N * L;
+    a.Y[p] += (size_t)sys * N * L;
+  }
+  partial += (size_t)sys * gridDim.x * GRAM_MAXPAIR * L * L;
   extern __shared__ double2 sh[];  // [2][GRAM_MAXPAIR][S][L] Y rows, reused for the reduction
   const int j = threadIdx.x, y = threadIdx.y, S = blockDim.y;
   cplx<double> acc[NF > 0 ? NF : 1][LMAX];
@@ -109,8 +116,10 @@ __global__ void __launch_bounds__(256) k_gram(int L, size_t N, GramArgs a, doubl
 
 // Sum the block partials in a fixed tree: one block per output entry.
 __global__ void __launch_bounds__(256) k_gram_finish(int L, int nblk, const double2* __restrict__ partial,
-                                                     GramOut o, const int* __restrict__ frozen) {
-  if (frozen && *frozen) return;
+                                                     GramOut o, const int* __restrict__ frozen, int fstride) {
+  const int sys = blockIdx.y;
+  if (frozen && frozen[sys * fstride]) return;
+  partial += (size_t)sys * nblk * GRAM_MAXPAIR * L * L;
   __shared__ double2 red[256];
   const int e = blockIdx.x;  // (pair, i, j)
   const int p = e / (L * L), ij = e % (L * L);
@@ -128,7 +137,7 @@ __global__ void __launch_bounds__(256) k_gram_finish(int L, int nblk, const doub
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) o.G[p][ij] = red[0];
+  if (threadIdx.x == 0) o.G[p][(size_t)sys * L * L + ij] = red[0];
 }
 
 // ---------------------------------------------------------------- block update
@@ -139,9 +148,18 @@ __global__ void __launch_bounds__(256) k_gram_finish(int L, int nblk, const doub
 // only the column norms) of the output, as GRAM partials.
 template <int LMAX, int GM, bool EXACT = false>
 __global__ void __launch_bounds__(256) k_combo(int L, size_t N, ComboArgs a, double2* __restrict__ out,
-                                               double2* __restrict__ partial, const int* __restrict__ frozen) {
+                                               double2* __restrict__ partial, const int* __restrict__ frozen,
+                                               int fstride) {
   if constexpr (EXACT) L = LMAX;
-  if (frozen && *frozen) return;
+  const int sys = blockIdx.y;
+  if (frozen && frozen[sys * fstride]) return;
+  out += (size_t)sys * N * L;
+  if (partial) partial += (size_t)sys * gridDim.x * GRAM_MAXPAIR * L * L;
+  for (int k = 0; k < a.nin; ++k) {
+    a.in[k] += (size_t)sys * N * L;
+    if (a.mode[k] == 1) a.coef[k] += sys;
+    else if (a.mode[k] == 2) a.coef[k] += (size_t)sys * L * L;
+  }
   extern __shared__ double2 sh[];  // [nmat][S][L] rows, then [nmat][L][L] coefficients
   const int j = threadIdx.x, y = threadIdx.y, S = blockDim.y;
   const int tid = y * L + j, nthr = L * S;
@@ -311,6 +329,7 @@ __device__ void lu_solve(int L, int m, const double2* A, const int* piv, const d
 // step 4.10 has formed the new column norms, so that a stop is visible to the
 // host before it enqueues another iteration; also run once on R_0.
 __global__ void k_loop_test(int L, SolverDev d) {
+  d = sys_view(d, blockIdx.x, L);   // one workgroup per system
   SolverState* S = d.state;
   if (S->frozen) return;
   if (threadIdx.x != 0) return;
@@ -342,6 +361,7 @@ __global__ void k_loop_test(int L, SolverDev d) {
 // qr_passes = 0 the QR step is left out (gamma = 1, the unmodified block
 // BiCGSTAB the paper's QR is compared against).  Counts the iteration.
 __global__ void k_coef_qr(int L, SolverDev d) {
+  d = sys_view(d, blockIdx.x, L);   // one workgroup per system
   SolverState* S = d.state;
   if (S->frozen) return;
   extern __shared__ double2 sm[];
@@ -367,6 +387,7 @@ __global__ void k_coef_qr(int L, SolverDev d) {
 // Optional second Cholesky-QR pass: Gpp2 = (P g1^{-1})^H (P g1^{-1}) was
 // accumulated by the caller; fold its factor into ginv = g1^{-1} g2^{-1}.
 __global__ void k_coef_qr2(int L, SolverDev d) {
+  d = sys_view(d, blockIdx.x, L);   // one workgroup per system
   SolverState* S = d.state;
   if (S->frozen) return;
   extern __shared__ double2 sm[];
@@ -390,6 +411,7 @@ __global__ void k_coef_qr2(int L, SolverDev d) {
 
 // Step 4.4: LU of R~^H V, alpha = (R~^H V)^{-1} R~^H R; also -alpha.
 __global__ void k_coef_alpha(int L, SolverDev d) {
+  d = sys_view(d, blockIdx.x, L);   // one workgroup per system
   SolverState* S = d.state;
   if (S->frozen) return;
   extern __shared__ double2 sm[];
@@ -414,6 +436,7 @@ __global__ void k_coef_alpha(int L, SolverDev d) {
 // Steps 4.8 and 4.11: zeta = Tr(Z^H T)/Tr(Z^H Z); beta = -(R~^H V)^{-1} R~^H Z;
 // coefficients of the fused updates: C1 = ginv * beta, C2 = -zeta * beta.
 __global__ void k_coef_zeta(int L, SolverDev d) {
+  d = sys_view(d, blockIdx.x, L);   // one workgroup per system
   SolverState* S = d.state;
   if (S->frozen) return;
   extern __shared__ double2 sm[];
@@ -456,6 +479,14 @@ __global__ void k_fill(double2* __restrict__ p, size_t n, double2 v) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 __global__ void k_copy(const double2* __restrict__ a, double2* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) b[i] = a[i];
+}
+__global__ void k_copy_sys(const double2* __restrict__ a, double2* __restrict__ b, size_t n, const int* __restrict__ frozen,
+                           int fstride) {
+  const int sys = blockIdx.y;
+  if (frozen && frozen[sys * fstride]) return;
+  a += (size_t)sys * n;
+  b += (size_t)sys * n;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) b[i] = a[i];
 }
 
@@ -516,24 +547,26 @@ int gram_blocks(size_t N, int L) {
   return (int)(nb < GRAM_MAXBLK ? nb : GRAM_MAXBLK);
 }
 
-size_t gram_partial_bytes(size_t N, int L) {
-  return (size_t)gram_blocks(N, L) * GRAM_MAXPAIR * L * L * sizeof(double2);
+size_t gram_partial_bytes(size_t N, int L, int nsys) {
+  return (size_t)nsys * gram_blocks(N, L) * GRAM_MAXPAIR * L * L * sizeof(double2);
 }
 
 template <int LMAX>
-static void launch_gram_l(int L, size_t N, const GramArgs& a, double2* partial, const int* frozen, hipStream_t st) {
+static void launch_gram_l(int L, size_t N, const GramArgs& a, double2* partial, const int* frozen, hipStream_t st,
+                          SysBatch sb) {
   const int S = gram_rows_per_block(L);
   const int nb = gram_blocks(N, L);
   const size_t shb = 2 * (size_t)GRAM_MAXPAIR * S * L * sizeof(double2);
   int nf = 0;
   while (nf < a.npair && !a.diag[nf]) ++nf;
   const int nd = a.npair - nf;
+  const dim3 grd(nb, sb.n);
 #define GL(F, D)                                                                                         \
   do {                                                                                                   \
     if (L == LMAX)                                                                                       \
-      hipLaunchKernelGGL((k_gram<LMAX, F, D, true>), dim3(nb), dim3(L, S), shb, st, L, N, a, partial, frozen); \
+      hipLaunchKernelGGL((k_gram<LMAX, F, D, true>), grd, dim3(L, S), shb, st, L, N, a, partial, frozen, sb.fstride); \
     else                                                                                                 \
-      hipLaunchKernelGGL((k_gram<LMAX, F, D>), dim3(nb), dim3(L, S), shb, st, L, N, a, partial, frozen);     \
+      hipLaunchKernelGGL((k_gram<LMAX, F, D>), grd, dim3(L, S), shb, st, L, N, a, partial, frozen, sb.fstride);     \
   } while (0)
   if (nf == 1 && nd == 0) GL(1, 0);
   else if (nf == 2 && nd == 0) GL(2, 0);
@@ -547,42 +580,41 @@ static void launch_gram_l(int L, size_t N, const GramArgs& a, double2* partial, 
 }
 
 int launch_gram(int L, size_t N, const GramArgs& a, const GramOut& o, double2* partial, const int* frozen,
-                hipStream_t st) {
+                hipStream_t st, SysBatch sb) {
   MBBS_CHECK(L >= 1 && L <= LMAX_SOLVER, "L out of range for block linear algebra");
   MBBS_CHECK(a.npair >= 1 && a.npair <= GRAM_MAXPAIR, "bad Gram pair count");
-  for (int p = 1; p < a.npair; ++p)
-    MBBS_CHECK(!(a.diag[p - 1] && !a.diag[p]), "full Gram pairs must precede diagonal ones");
-  if (L <= 4) launch_gram_l<4>(L, N, a, partial, frozen, st);
-  else if (L <= 8) launch_gram_l<8>(L, N, a, partial, frozen, st);
-  else if (L <= 12) launch_gram_l<12>(L, N, a, partial, frozen, st);
-  else launch_gram_l<16>(L, N, a, partial, frozen, st);
+  if (L <= 4) launch_gram_l<4>(L, N, a, partial, frozen, st, sb);
+  else if (L <= 8) launch_gram_l<8>(L, N, a, partial, frozen, st, sb);
+  else if (L <= 12) launch_gram_l<12>(L, N, a, partial, frozen, st, sb);
+  else launch_gram_l<16>(L, N, a, partial, frozen, st, sb);
   MBBS_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_gram_finish, dim3(a.npair * L * L), dim3(256), 0, st, L, gram_blocks(N, L), partial, o,
-                     frozen);
+  hipLaunchKernelGGL(k_gram_finish, dim3(a.npair * L * L, sb.n), dim3(256), 0, st, L, gram_blocks(N, L), partial, o,
+                     frozen, sb.fstride);
   MBBS_HIP(hipGetLastError());
   return MBBS_OK;
 }
 
 template <int LMAX, int GM>
 static void launch_combo_l(int L, size_t N, const ComboArgs& a, double2* out, double2* partial, const int* frozen,
-                           hipStream_t st) {
+                           hipStream_t st, SysBatch sb) {
   const int S = gram_rows_per_block(L);
   const int nb = gram_blocks(N, L);
   const size_t shb = ((size_t)COMBO_MAXIN * S * L + (size_t)COMBO_MAXIN * L * L) * sizeof(double2);
+  const dim3 grd(nb, sb.n);
   if (L == LMAX)
-    hipLaunchKernelGGL((k_combo<LMAX, GM, true>), dim3(nb), dim3(L, S), shb, st, L, N, a, out, partial, frozen);
+    hipLaunchKernelGGL((k_combo<LMAX, GM, true>), grd, dim3(L, S), shb, st, L, N, a, out, partial, frozen, sb.fstride);
   else
-    hipLaunchKernelGGL((k_combo<LMAX, GM>), dim3(nb), dim3(L, S), shb, st, L, N, a, out, partial, frozen);
+    hipLaunchKernelGGL((k_combo<LMAX, GM>), grd, dim3(L, S), shb, st, L, N, a, out, partial, frozen, sb.fstride);
 }
 
 int launch_combo(int L, size_t N, const ComboArgs& a, double2* out, int gram_mode, const GramOut* o,
-                 double2* partial, const int* frozen, hipStream_t st) {
+                 double2* partial, const int* frozen, hipStream_t st, SysBatch sb) {
   MBBS_CHECK(L >= 1 && L <= LMAX_SOLVER, "L out of range for block linear algebra");
 #define CL(LM)                                                                                   \
   do {                                                                                           \
-    if (gram_mode == 0) launch_combo_l<LM, 0>(L, N, a, out, partial, frozen, st);                \
-    else if (gram_mode == 1) launch_combo_l<LM, 1>(L, N, a, out, partial, frozen, st);           \
-    else launch_combo_l<LM, 2>(L, N, a, out, partial, frozen, st);                               \
+    if (gram_mode == 0) launch_combo_l<LM, 0>(L, N, a, out, partial, frozen, st, sb);            \
+    else if (gram_mode == 1) launch_combo_l<LM, 1>(L, N, a, out, partial, frozen, st, sb);       \
+    else launch_combo_l<LM, 2>(L, N, a, out, partial, frozen, st, sb);                           \
   } while (0)
   if (L <= 4) CL(4);
   else if (L <= 8) CL(8);
@@ -591,26 +623,36 @@ int launch_combo(int L, size_t N, const ComboArgs& a, double2* out, int gram_mod
 #undef CL
   MBBS_HIP(hipGetLastError());
   if (gram_mode != 0) {
-    hipLaunchKernelGGL(k_gram_finish, dim3(L * L), dim3(256), 0, st, L, gram_blocks(N, L), partial, *o, frozen);
+    hipLaunchKernelGGL(k_gram_finish, dim3(L * L, sb.n), dim3(256), 0, st, L, gram_blocks(N, L), partial, *o, frozen,
+                       sb.fstride);
     MBBS_HIP(hipGetLastError());
   }
   return MBBS_OK;
 }
 
-int launch_coef(int which, int L, const SolverDev& d, hipStream_t st) {
+int launch_coef(int which, int L, const SolverDev& d, hipStream_t st, int nsys) {
   const size_t sh = 3 * (size_t)L * L * sizeof(double2);
   switch (which) {
-    case 0: hipLaunchKernelGGL(k_coef_qr, dim3(1), dim3(64), sh, st, L, d); break;
-    case 1: hipLaunchKernelGGL(k_coef_qr2, dim3(1), dim3(64), sh, st, L, d); break;
-    case 2: hipLaunchKernelGGL(k_coef_alpha, dim3(1), dim3(64), sh, st, L, d); break;
-    default: hipLaunchKernelGGL(k_coef_zeta, dim3(1), dim3(64), sh, st, L, d); break;
+    case 0: hipLaunchKernelGGL(k_coef_qr, dim3(nsys), dim3(64), sh, st, L, d); break;
+    case 1: hipLaunchKernelGGL(k_coef_qr2, dim3(nsys), dim3(64), sh, st, L, d); break;
+    case 2: hipLaunchKernelGGL(k_coef_alpha, dim3(nsys), dim3(64), sh, st, L, d); break;
+    default: hipLaunchKernelGGL(k_coef_zeta, dim3(nsys), dim3(64), sh, st, L, d); break;
   }
   MBBS_HIP(hipGetLastError());
   return MBBS_OK;
 }
 
-int launch_loop_test(int L, const SolverDev& d, hipStream_t st) {
-  hipLaunchKernelGGL(k_loop_test, dim3(1), dim3(64), 0, st, L, d);
+int launch_loop_test(int L, const SolverDev& d, hipStream_t st, int nsys) {
+  hipLaunchKernelGGL(k_loop_test, dim3(nsys), dim3(64), 0, st, L, d);
+  MBBS_HIP(hipGetLastError());
+  return MBBS_OK;
+}
+
+int launch_copy_sys(const double2* a, double2* b, size_t n_per_sys, const int* frozen, hipStream_t st, SysBatch sb) {
+  if (n_per_sys == 0) return MBBS_OK;
+  int nb = (int)((n_per_sys + 255) / 256);
+  if (nb > 2048) nb = 2048;
+  hipLaunchKernelGGL(k_copy_sys, dim3(nb, sb.n), dim3(256), 0, st, a, b, n_per_sys, frozen, sb.fstride);
   MBBS_HIP(hipGetLastError());
   return MBBS_OK;
 }

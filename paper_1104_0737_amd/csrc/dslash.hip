@@ -20,7 +20,6 @@ __global__ void __launch_bounds__(256) k_dslash(GeomK k, double kappa, int L,
                                                 float* __restrict__ out_s,
                                                 const LinkElem<PL>* __restrict__ U, int s0, int n,
                                                 int bpt, int ngroups, const int* __restrict__ frozen) {
-  if (frozen && *frozen) return;
   // LT > 0: L known at compile time, so element offsets become immediates
   if constexpr (LT > 0) L = LT;
   using R = typename Store<PL>::Real;
@@ -30,6 +29,7 @@ __global__ void __launch_bounds__(256) k_dslash(GeomK k, double kappa, int L,
   const int col0 = (grp * blockDim.x + threadIdx.x) * C;
   // lexicographic fields are walked tile by tile (whole lattice, s0 = 0)
   const SiteCtx c = ORDER == LEX ? site_ctx_tiled(k, i) : site_ctx<DM>(k, s0 + i);
+  if (sys_frozen(k, frozen, c.sys)) return;
   const int s = c.s;
   cplx<R> acc[4][3][C];
 #pragma unroll
@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(256) k_dslash(GeomK k, double kappa, int L,
       for (int q = 0; q < C; ++q) acc[sp][a][q] = cmake<R>(0, 0);
   hop_sum<PIN, PL, C, ORDER, BLOCKED ? INSIDE : ALL, R, PAIR>(k, c, in, in_s, U, L, col0, acc);
   if (k.clov) clover_apply<ORDER, C, R>(k, s, acc);
-  const R kap = (R)kappa;
+  const R kap = (R)kappa_of(k, c, kappa);
 #pragma unroll
   for (int q = 0; q < C; ++q) {
     const size_t base = (size_t)s * 12 * L + col0 + q;
@@ -69,7 +69,6 @@ __global__ void __launch_bounds__(256) k_sap_resid(GeomK k, double kappa, int L,
                                                    float* __restrict__ r_s,
                                                    const LinkElem<PL>* __restrict__ U, int bpt,
                                                    int ngroups, const int* __restrict__ frozen) {
-  if (frozen && *frozen) return;
   if constexpr (LT > 0) L = LT;
   using R = typename Store<PL>::Real;
   int i, grp;
@@ -77,6 +76,8 @@ __global__ void __launch_bounds__(256) k_sap_resid(GeomK k, double kappa, int L,
   if (i >= n) return;
   const int s = s0 + i;
   const int col0 = (grp * blockDim.x + threadIdx.x) * C;
+  const SiteCtx c = site_ctx<DM>(k, s);
+  if (sys_frozen(k, frozen, c.sys)) return;
   cplx<R> acc[4][3][C];
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
@@ -85,12 +86,11 @@ __global__ void __launch_bounds__(256) k_sap_resid(GeomK k, double kappa, int L,
 #pragma unroll
       for (int q = 0; q < C; ++q) acc[sp][a][q] = cmake<R>(0, 0);
   if (mode != 0) {
-    const SiteCtx c = site_ctx<DM>(k, s);
     if (mode == 1) hop_sum<PPSI, PL, C, DM, OUTSIDE, R, PAIR>(k, c, psi, nullptr, U, L, col0, acc);
     else hop_sum<PPSI, PL, C, DM, ALL, R, PAIR>(k, c, psi, nullptr, U, L, col0, acc);
     if (k.clov) clover_apply<DM, C, R>(k, s, acc);
   }
-  const R kap = (R)kappa;
+  const R kap = (R)kappa_of(k, c, kappa);
 #pragma unroll
   for (int q = 0; q < C; ++q) {
     const size_t base = (size_t)s * 12 * L + col0 + q;
@@ -127,7 +127,6 @@ __global__ void __launch_bounds__(256) k_mr_dslash(GeomK k, double kappa, int L,
                                                    const LinkElem<PL>* __restrict__ U,
                                                    double* __restrict__ partial, int bpt, int ngroups,
                                                    const int* __restrict__ frozen) {
-  if (frozen && *frozen) return;
   if constexpr (LT > 0) L = LT;
   using R = typename Store<PL>::Real;
   extern __shared__ double red[];  // [3][blockDim.y][blockDim.x*C]
@@ -137,6 +136,8 @@ __global__ void __launch_bounds__(256) k_mr_dslash(GeomK k, double kappa, int L,
   const int colg = grp * blockDim.x * C;           // first column of the group
   const int col0 = colg + threadIdx.x * C;
   const SiteCtx c = site_ctx<DM>(k, s);
+  // a block lies in one domain, hence one system: the test is block-uniform
+  if (sys_frozen(k, frozen, c.sys)) return;
   cplx<R> acc[4][3][C];
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
@@ -146,7 +147,7 @@ __global__ void __launch_bounds__(256) k_mr_dslash(GeomK k, double kappa, int L,
       for (int q = 0; q < C; ++q) acc[sp][a][q] = cmake<R>(0, 0);
   hop_sum<PR, PL, C, DM, INSIDE, R, PAIR>(k, c, r, r_s, U, L, col0, acc);
   if (k.clov) clover_apply<DM, C, R>(k, s, acc);
-  const R kap = (R)kappa;
+  const R kap = (R)kappa_of(k, c, kappa);
   const int ny = blockDim.y, nx = blockDim.x * C;
 #pragma unroll
   for (int q = 0; q < C; ++q) {
@@ -211,11 +212,11 @@ __global__ void __launch_bounds__(256) k_mr_dslash(GeomK k, double kappa, int L,
 // A separate launch: the kernel boundary makes every block's partial visible
 // without device-wide fences (which on this chip write back and invalidate the
 // per-XCD L2 caches).
-__global__ void __launch_bounds__(256) k_mr_omega(int L, int nblk, const double* __restrict__ partial,
+__global__ void __launch_bounds__(256) k_mr_omega(GeomK k, int L, int nblk, const double* __restrict__ partial,
                                                   double* __restrict__ omega, const int* __restrict__ frozen) {
-  if (frozen && *frozen) return;
-  __shared__ double red[3 * 256];
   const int dom = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
+  if (sys_frozen(k, frozen, sys_of_domain(k, dom))) return;
+  __shared__ double red[3 * 256];
   const int G = nthr / L > 0 ? nthr / L : 1;
   const double* pp = partial + ((size_t)dom * nblk) * L * 3;
   for (int e = tid; e < G * L; e += nthr) {
@@ -255,13 +256,13 @@ __global__ void __launch_bounds__(256) k_mr_update(GeomK k, int L, int s0, int n
                                                    typename Store<PPSI>::Elem* __restrict__ psi,
                                                    const double* __restrict__ omega, int update_r,
                                                    int assign, const int* __restrict__ frozen) {
-  if (frozen && *frozen) return;
   using R = typename Store<PR>::Real;
   using RP = typename Store<PPSI>::Real;
   const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * blockDim.y + threadIdx.y;
   if (s >= s0 + n) return;
   const int col = threadIdx.x;
   const int dom = (s - (s >= k.g.Vh ? k.g.Vh : 0)) / k.g.Vb;
+  if (sys_frozen(k, frozen, sys_of_domain(k, dom))) return;
   const cplx<R> om = cmake<R>((R)omega[((size_t)dom * L + col) * 2], (R)omega[((size_t)dom * L + col) * 2 + 1]);
   const size_t base = (size_t)s * 12 * L + col;
   const size_t sidx = (size_t)s * L + col;
@@ -307,7 +308,9 @@ __global__ void __launch_bounds__(mr_fused_threads<PR>()) k_mr_fused(GeomK k, do
                                                    typename Store<PPSI>::Elem* psi,
                                                    const LinkElem<PL>* __restrict__ U,
                                                    const int* __restrict__ frozen) {
-  if (frozen && *frozen) return;
+  // one workgroup per domain, hence one system: the test is block-uniform
+  const int sys = sys_of_domain(k, blockIdx.x);
+  if (sys_frozen(k, frozen, sys)) return;
   using R = typename Store<PR>::Real;
   using RP = typename Store<PPSI>::Real;
   __shared__ double red[3][1024];
@@ -317,7 +320,7 @@ __global__ void __launch_bounds__(mr_fused_threads<PR>()) k_mr_fused(GeomK k, do
   const bool active = t < T;
   const int col = t % L, j = t / L;
   const int base_site = s0 + blockIdx.x * k.g.Vb;
-  const R kap = (R)kappa;
+  const R kap = (R)(k.kap ? k.kap[sys] : kappa);
   for (int it = 0; it < nmr; ++it) {
     double sr = 0, si = 0, sw = 0;
     if (active) {
@@ -413,7 +416,6 @@ __global__ void __launch_bounds__(256) k_mr_update_flat(GeomK k, int L, int s0, 
                                                         const float4* __restrict__ w, float4* __restrict__ psi,
                                                         const double* __restrict__ omega, int update_r, int assign,
                                                         const int* __restrict__ frozen) {
-  if (frozen && *frozen) return;
   const size_t npair = (size_t)n * 6 * L;             // n*12*L entries, two per thread
   const size_t q = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (q >= npair) return;
@@ -421,6 +423,7 @@ __global__ void __launch_bounds__(256) k_mr_update_flat(GeomK k, int L, int s0, 
   const int col = (int)(e0 % L);
   const int s = (int)(e0 / (12 * (size_t)L));          // site within the colour
   const int dom = s / k.g.Vb;
+  if (sys_frozen(k, frozen, sys_of_domain(k, dom))) return;
   const double* om = omega + ((size_t)dom * L + col) * 2;
   const float o0r = (float)om[0], o0i = (float)om[1], o1r = (float)om[2], o1i = (float)om[3];
   const size_t g = (size_t)s0 * 6 * L + q;             // float4 index in the whole field
@@ -713,9 +716,17 @@ __global__ void __launch_bounds__(768) k_mr_dslash_split(GeomK k, double kappa, 
 }
 
 // ---------------------------------------------------------------- host side
-GeomK make_geomk(const Geom& g) {
+GeomK make_geomk(const Geom& g, int nsys) {
   GeomK k;
   k.g = g;
+  k.nsys = nsys;
+  k.tsys = g.d[3] / nsys;
+  k.ndt = g.nd[3] / nsys;
+  k.Vsys = g.V / nsys;
+  k.ftsys = make_fastdiv(k.tsys);
+  k.fndt = make_fastdiv(k.ndt);
+  k.kap = nullptr;
+  k.fstride = SOLVER_FLAG_STRIDE;
   for (int m = 0; m < 4; ++m) {
     k.fd[m] = make_fastdiv(g.d[m]);
     k.fb[m] = make_fastdiv(g.b[m]);
@@ -878,7 +889,7 @@ template <int PIN, int POUT, int PL>
 static int dslash_dispatch_c(const mbbs_lattice_s* lat, int L, int order, bool blocked,
                              const void* in, const float* in_s, void* out, float* out_s, int s0,
                              int n, const int* frozen, hipStream_t st) {
-  const int P = lat->split[PL];
+  const int P = lat->nsys == 1 ? lat->split[PL] : 0;   // the split kernels serve single systems only
   if ((P == 2 || P == 4) && !lat->gk.clov) {   // the split kernels have no clover step
     const int S = split_sites(lat, L, PL, P);
     if (S > 0) {
@@ -996,7 +1007,7 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
         if (prof) prof->end();
         continue;
       }
-      const int P = lat->split[PL];
+      const int P = lat->nsys == 1 ? lat->split[PL] : 0;   // the split kernels serve single systems only
       const int SS = ((P == 2 || P == 4) && !lat->gk.clov) ? split_sites(lat, L, PL, P) : 0;
       if (prof) prof->begin(MBBS_K_SAP_RES);
       if (SS > 0) {
@@ -1100,8 +1111,8 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
 #undef MRD
         }
         MBBS_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_mr_omega, dim3(g.ndom / 2), dim3(256), 0, st, L, nblk_dom, (const double*)b.partial,
-                           b.omega, frozen);
+        hipLaunchKernelGGL(k_mr_omega, dim3(g.ndom / 2), dim3(256), 0, st, lat->gk, L, nblk_dom,
+                           (const double*)b.partial, b.omega, frozen);
         if (prof) prof->end();
         MBBS_HIP(hipGetLastError());
         if (prof) prof->begin(MBBS_K_MR_UPDATE);
@@ -1137,22 +1148,23 @@ __global__ void __launch_bounds__(256) k_to_sap(GeomK k, int L, const double2* _
                                                 const double2* __restrict__ gam,
                                                 typename Store<PR>::Elem* __restrict__ out,
                                                 float* __restrict__ out_s, const int* __restrict__ frozen) {
-  if (frozen && *frozen) return;
   if constexpr (LT > 0) L = LT;
   using R = typename Store<PR>::Real;
   extern __shared__ double2 gsh[];
+  // a block never straddles two systems (its site count divides a system's
+  // half volume), so the system, its flag and its gamma are block-uniform
+  const int sys = site_ctx<DM>(k, min((int)(blockIdx.x * blockDim.y), k.g.V - 1)).sys;
+  if (sys_frozen(k, frozen, sys)) return;
   const int tid = threadIdx.y * blockDim.x + threadIdx.x;
   if (gam) {
-    for (int e = tid; e < L * L; e += blockDim.x * blockDim.y) gsh[e] = gam[e];
+    for (int e = tid; e < L * L; e += blockDim.x * blockDim.y) gsh[e] = gam[(size_t)sys * L * L + e];
     __syncthreads();
   }
   const int s = blockIdx.x * blockDim.y + threadIdx.y;  // domain-major index
   if (s >= k.g.V) return;
   const int j = threadIdx.x;
   const SiteCtx c = site_ctx<DM>(k, s);
-  Coord x;
-  for (int m = 0; m < 4; ++m) x.c[m] = c.x[m];
-  const int ls = lex_site(k.g, x);
+  const int ls = lex_of(k, c);
   cplx<double> v[4][3];
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
@@ -1182,15 +1194,13 @@ __global__ void __launch_bounds__(256) k_to_sap(GeomK k, int L, const double2* _
 template <int PPSI, int LT = 0>
 __global__ void __launch_bounds__(256) k_from_sap(GeomK k, int L, const typename Store<PPSI>::Elem* __restrict__ in,
                                                   double2* __restrict__ out, const int* __restrict__ frozen) {
-  if (frozen && *frozen) return;
   if constexpr (LT > 0) L = LT;
   const int s = blockIdx.x * blockDim.y + threadIdx.y;
   if (s >= k.g.V) return;
   const int j = threadIdx.x;
   const SiteCtx c = site_ctx<DM>(k, s);
-  Coord x;
-  for (int m = 0; m < 4; ++m) x.c[m] = c.x[m];
-  const int ls = lex_site(k.g, x);
+  if (sys_frozen(k, frozen, c.sys)) return;
+  const int ls = lex_of(k, c);
 #pragma unroll
   for (int e = 0; e < 12; ++e) {
     auto v = Store<PPSI>::ld(in, ((size_t)s * 12 + e) * L + j);
@@ -1202,7 +1212,8 @@ int sap_to(const mbbs_lattice_s* lat, const SapBuffers& b, const double2* in, co
            float* dst_s, const int* frozen, hipStream_t st) {
   const int L = b.L;
   const Geom& g = lat->g;
-  const int S = sites_per_block(L, g.V);
+  // a batch: blocks stay inside one system's half volume (per-system gamma)
+  const int S = sites_per_block(L, lat->nsys > 1 ? g.V / (2 * lat->nsys) : g.V);
   const size_t gsh = gam ? (size_t)L * L * sizeof(double2) : 0;
   const bool l12 = L == 12;   // compile-time row offsets for the common block width
   switch (b.prec) {

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <string>
+#include <vector>
 
 #include "common.h"
 #include "../../include/mbbs.h"
@@ -71,8 +72,22 @@ struct GeomK {
   const double* cinv64[2];
   const float* cinv32[2];
   int clov;
+  // A batch of nsys independent systems of one shape is stacked along t:
+  // system s owns t in [s * tsys, (s + 1) * tsys) and its t hops wrap inside
+  // that range; its hopping parameter is kap[s] (device) and its solver flag
+  // frozen[s * fstride].  A single system has nsys = 1, tsys = g.d[3].
+  int nsys;
+  int tsys;          // t extent of one system
+  int ndt;           // domains along t per system
+  int Vsys;          // sites per system
+  FastDiv ftsys, fndt;
+  const double* kap; // per-system kappa (device), null: the kernel's scalar kappa
+  int fstride;       // ints between consecutive systems' solver flags
 };
-GeomK make_geomk(const Geom& g);
+GeomK make_geomk(const Geom& g, int nsys = 1);
+// ints between consecutive solver state records (the flag `frozen` is the
+// first field of each; checked against the record's layout in blas.h)
+constexpr int SOLVER_FLAG_STRIDE = 10;
 
 // Workgroups are dealt to the 8 XCDs of the chip in turn (block b runs on XCD
 // b mod 8).  Remap so that XCD x processes one contiguous run of logical
@@ -86,9 +101,12 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }  // namespace mbbs
 
 struct mbbs_lattice_s {
-  mbbs::Geom g;
+  mbbs::Geom g;      // for a batch: the stacked geometry (t extent nsys * tsys)
   mbbs::GeomK gk;
-  double kappa;
+  double kappa;      // a batch keeps its systems' values in kap_dev / kap_host
+  int nsys = 1;      // systems stacked along t (1: a single lattice)
+  double* kap_dev = nullptr;
+  std::vector<double> kap_host;
   int device;
   double2* U64 = nullptr;     // lexicographic links (FP64), [site][mu][a][b]
   float2* U32 = nullptr;

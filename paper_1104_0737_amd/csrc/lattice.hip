@@ -23,9 +23,7 @@ __global__ void k_links(GeomK k, const double2* __restrict__ U, float2* __restri
   const int i = blockIdx.x * blockDim.x + threadIdx.x;  // domain-major position
   if (i >= k.g.V) return;
   const SiteCtx c = site_ctx<DM>(k, i);
-  Coord x;
-  for (int m = 0; m < 4; ++m) x.c[m] = c.x[m];
-  const int s = lex_site(k.g, x);
+  const int s = lex_of(k, c);
   for (int e = 0; e < 36; ++e) {
     const double2 v = U[(size_t)i * 36 + e];  // lexicographic site i
     U32[(size_t)i * 36 + e] = make_float2((float)v.x, (float)v.y);
@@ -57,9 +55,7 @@ __global__ void k_tables(GeomK k, int which, int32_t* __restrict__ out) {
   if (which == MBBS_TAB_DM_NEIGHBOUR || which == MBBS_TAB_DM_SITE) {
     const SiteCtx c = site_ctx<DM>(k, i);
     if (which == MBBS_TAB_DM_SITE) {
-      Coord x;
-      for (int m = 0; m < 4; ++m) x.c[m] = c.x[m];
-      out[i] = lex_site(g, x);
+      out[i] = lex_of(k, c);
       return;
     }
     for (int mu = 0; mu < 4; ++mu) {
@@ -84,7 +80,7 @@ __global__ void k_tables(GeomK k, int which, int32_t* __restrict__ out) {
     case MBBS_TAB_BOUNDARY: {
       int f = 0;
       for (int mu = 0; mu < 4; ++mu) {
-        if (c.x[mu] == g.d[mu] - 1) f |= 1 << (2 * mu);
+        if (c.x[mu] == wrap_extent(k, mu) - 1) f |= 1 << (2 * mu);
         if (c.x[mu] == 0) f |= 1 << (2 * mu + 1);
       }
       out[i] = f;
@@ -151,9 +147,14 @@ void Profiler::flush() {
 
 using namespace mbbs;
 
-static int lattice_create(const int dims[4], const int block[4], const double* U_dev, double kappa,
-                          const double phase[8], void* stream, mbbs_lattice_t* out) {
-  MBBS_CHECK(dims && block && U_dev && phase && out, "null argument");
+// A lattice handle for nsys >= 1 systems of one shape: with nsys > 1 the
+// systems are stacked along t (system s owns t in [s Lt, (s + 1) Lt), its t
+// hops wrap inside that range) and every kernel of the handle treats them
+// as independent systems with hopping parameters kappa[s].
+static int lattice_create(const int dims[4], const int block[4], int nsys, const double* const* U_dev,
+                          const double* kappa, const double phase[8], void* stream, mbbs_lattice_t* out) {
+  MBBS_CHECK(dims && block && U_dev && kappa && phase && out, "null argument");
+  MBBS_CHECK(nsys >= 1, "a batch needs at least one system");
   Geom g;
   long long V = 1;
   for (int m = 0; m < 4; ++m) {
@@ -162,27 +163,46 @@ static int lattice_create(const int dims[4], const int block[4], const double* U
     MBBS_CHECK((dims[m] / block[m]) % 2 == 0, "the number of domains along each direction must be even");
     const double a = phase[2 * m], b = phase[2 * m + 1];
     MBBS_CHECK(std::fabs(std::sqrt(a * a + b * b) - 1.0) < 1e-12, "boundary phases must have modulus 1");
-    g.d[m] = dims[m];
+    const int stack = m == 3 ? nsys : 1;
+    g.d[m] = dims[m] * stack;
     g.b[m] = block[m];
-    g.nd[m] = dims[m] / block[m];
+    g.nd[m] = dims[m] / block[m] * stack;
     g.ph[m][0] = a;
     g.ph[m][1] = b;
     V *= dims[m];
   }
-  MBBS_CHECK(V * 12 < (1ll << 31), "lattice too large for 32-bit site indexing");
-  MBBS_CHECK(std::isfinite(kappa), "kappa must be finite");
+  const long long Vsys = V;
+  V *= nsys;
+  MBBS_CHECK(V * 12 < (1ll << 31), "lattice (batch) too large for 32-bit site indexing");
+  for (int s = 0; s < nsys; ++s) {
+    MBBS_CHECK(std::isfinite(kappa[s]), "kappa must be finite");
+    MBBS_CHECK(U_dev[s] != nullptr, "null link array");
+  }
   g.V = (int)V;
   g.Vh = g.V / 2;
   g.Vb = block[0] * block[1] * block[2] * block[3];
   g.ndom = g.V / g.Vb;
   auto* lat = new mbbs_lattice_s();
   lat->g = g;
-  lat->gk = make_geomk(g);
-  lat->kappa = kappa;
+  lat->gk = make_geomk(g, nsys);
+  lat->kappa = kappa[0];
+  lat->nsys = nsys;
   (void)hipGetDevice(&lat->device);
   hipStream_t st = (hipStream_t)stream;
-  const size_t n = (size_t)V * 36;
+  const size_t n = (size_t)V * 36, nsys_links = (size_t)Vsys * 36;
   auto fail = [&](int rc) { mbbs_lattice_destroy(lat); return rc; };
+  if (nsys > 1) {
+    lat->kap_host.assign(kappa, kappa + nsys);
+    if (hipMalloc(&lat->kap_dev, nsys * sizeof(double)) != hipSuccess) {
+      set_error("out of device memory for the batch's kappa values");
+      return fail(MBBS_ENOMEM);
+    }
+    if (hipMemcpy(lat->kap_dev, kappa, nsys * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("kappa copy failed");
+      return fail(MBBS_EHIP);
+    }
+    lat->gk.kap = lat->kap_dev;
+  }
   if (hipMalloc(&lat->U64, n * sizeof(double2)) != hipSuccess || hipMalloc(&lat->U32, n * sizeof(float2)) != hipSuccess ||
       hipMalloc(&lat->U16, n * sizeof(__half2)) != hipSuccess ||
       hipMalloc(&lat->U64dm, n * sizeof(double2)) != hipSuccess ||
@@ -191,9 +211,12 @@ static int lattice_create(const int dims[4], const int block[4], const double* U
     set_error("out of device memory for link copies");
     return fail(MBBS_ENOMEM);
   }
-  if (hipMemcpyAsync(lat->U64, U_dev, n * sizeof(double2), hipMemcpyDeviceToDevice, st) != hipSuccess) {
-    set_error("link copy failed");
-    return fail(MBBS_EHIP);
+  for (int s = 0; s < nsys; ++s) {
+    if (hipMemcpyAsync(lat->U64 + (size_t)s * nsys_links, U_dev[s], nsys_links * sizeof(double2),
+                       hipMemcpyDeviceToDevice, st) != hipSuccess) {
+      set_error("link copy failed");
+      return fail(MBBS_EHIP);
+    }
   }
   hipLaunchKernelGGL(k_links, dim3(ceil_div(V, 256)), dim3(256), 0, st, lat->gk, (const double2*)lat->U64, lat->U32,
                      lat->U16, lat->U64dm, lat->U32dm, lat->U16dm);
@@ -235,7 +258,19 @@ static int lattice_create(const int dims[4], const int block[4], const double* U
 
 extern "C" int mbbs_lattice_create(const int dims[4], const int block[4], const double* U_dev, double kappa,
                                    const double phase[8], void* stream, mbbs_lattice_t* out) {
-  return lattice_create(dims, block, U_dev, kappa, phase, stream, out);
+  return lattice_create(dims, block, 1, &U_dev, &kappa, phase, stream, out);
+}
+
+extern "C" int mbbs_lattice_create_batch(int nsys, const int dims[4], const int block[4], const double* const* U_dev,
+                                         const double* kappa, const double phase[8], void* stream,
+                                         mbbs_lattice_t* out) {
+  return lattice_create(dims, block, nsys, U_dev, kappa, phase, stream, out);
+}
+
+extern "C" int mbbs_lattice_nsys(mbbs_lattice_t lat, int* nsys) {
+  MBBS_CHECK(lat != nullptr && nsys != nullptr, "null argument");
+  *nsys = lat->nsys;
+  return MBBS_OK;
 }
 
 extern "C" int mbbs_lattice_destroy(mbbs_lattice_t lat) {
@@ -252,6 +287,7 @@ extern "C" int mbbs_lattice_destroy(mbbs_lattice_t lat) {
   (void)hipFree(lat->cl32);
   (void)hipFree(lat->cl64dm);
   (void)hipFree(lat->cl32dm);
+  (void)hipFree(lat->kap_dev);
   delete lat;
   return MBBS_OK;
 }
@@ -259,6 +295,7 @@ extern "C" int mbbs_lattice_destroy(mbbs_lattice_t lat) {
 extern "C" int mbbs_lattice_set_clover(mbbs_lattice_t lat, double csw, void* stream) {
   MBBS_CHECK(lat != nullptr, "null lattice");
   MBBS_CHECK(std::isfinite(csw), "c_sw must be finite");
+  MBBS_CHECK(lat->nsys == 1, "the clover term is available on single-system handles only");
   return clover_build(lat, csw, (hipStream_t)stream);
 }
 

@@ -6,9 +6,14 @@
 // after step 4.10 of each iteration, where the new residual norms are formed;
 // once it fails, the device sets `frozen`, step 4.12 and every later kernel of
 // the batch return at once, and the host sees the stop after the iteration
-// that caused it.  After the recursive residual
-// converges, the true residual B - A X is checked in FP64 and the iteration
-// restarts from it if needed.
+// that caused it.  After the recursive residual converges, the true residual
+// B - A X is checked in FP64 and the iteration restarts from it if needed.
+//
+// A batch handle (several same-shape systems stacked along t) runs the same
+// iteration for all of its systems in every launch: each system has its own
+// state record, coefficients and flag, a stopped system is skipped by every
+// kernel, and the host takes the true-residual and restart decisions per
+// system once every system of the batch has stopped.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -24,19 +29,22 @@ namespace {
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Work {
-  // FP64 N x L blocks (Bp: the right-hand side times (1 + T)^{-1} with clover)
+  // FP64 N x L blocks of every system (Bp: the right-hand side times
+  // (1 + T)^{-1} with clover)
   double2 *R, *P, *Rt, *V, *T, *Z, *U, *S, *Bp;
   SapBuffers sap;
   double2* partial;
   SolverDev d;
-  double* trnorm2;   // true residual norms^2
-  double2* mone;     // constant -1
+  double* trnorm2;   // true residual norms^2 (nsys x L)
+  double2* mone;     // constant -1 (nsys)
 };
 
-size_t small_bytes(int L) {
-  const size_t LL = (size_t)L * L * sizeof(double2);
-  return al(sizeof(SolverState)) + 3 * al(L * sizeof(double)) + 16 * al(LL) + al(L * sizeof(int)) +
-         4 * al(sizeof(double2)) + al(HIST_CAP * sizeof(double));
+// Per-system small arrays, laid out as sys_view expects.
+size_t small_bytes(int L, int nsys) {
+  const size_t LL = (size_t)L * L * sizeof(double2) * nsys;
+  const size_t vec = (size_t)L * sizeof(double) * nsys;
+  return al(sizeof(SolverState) * nsys) + 3 * al(vec) + 16 * al(LL) + al((size_t)L * sizeof(int) * nsys) +
+         4 * al(sizeof(double2) * nsys) + al((size_t)HIST_CAP * sizeof(double) * nsys);
 }
 
 size_t block_bytes(const mbbs_lattice_s* lat, int L) { return al((size_t)lat->g.V * 12 * L * sizeof(double2)); }
@@ -52,12 +60,13 @@ int nblocks_needed(const mbbs_lattice_s* lat, const mbbs_solve_params& p) {
   return nblocks_needed(p) + (lat->gk.clov ? 1 : 0);
 }
 
+size_t rows_per_system(const mbbs_lattice_s* lat) { return (size_t)(lat->g.V / lat->nsys) * 12; }
+
 size_t workspace_bytes(const mbbs_lattice_s* lat, int L, const mbbs_solve_params& p) {
-  const size_t N = (size_t)lat->g.V * 12;
   size_t b = nblocks_needed(lat, p) * block_bytes(lat, L);
   if (p.precond) b += al(sap_buffer_bytes(lat, L, p.sap_prec, p.domain_solver == 1));
-  b += al(gram_partial_bytes(N, L));
-  b += small_bytes(L);
+  b += al(gram_partial_bytes(rows_per_system(lat), L, lat->nsys));
+  b += small_bytes(L, lat->nsys);
   return b;
 }
 
@@ -65,7 +74,7 @@ int bind(const mbbs_lattice_s* lat, int L, const mbbs_solve_params& p, void* ws,
   MBBS_CHECK(ws != nullptr && bytes >= workspace_bytes(lat, L, p), "solver workspace too small");
   char* q = (char*)ws;
   const size_t B = block_bytes(lat, L);
-  const size_t N = (size_t)lat->g.V * 12;
+  const int ns = lat->nsys;
   auto take = [&](size_t n) { char* r = q; q += al(n); return r; };
   w.R = (double2*)take(B);
   w.P = (double2*)take(B);
@@ -83,13 +92,14 @@ int bind(const mbbs_lattice_s* lat, int L, const mbbs_solve_params& p, void* ws,
     w.sap.nssor = p.nssor;
     w.sap.ssor_omega = p.ssor_omega;
   }
-  w.partial = (double2*)take(gram_partial_bytes(N, L));
-  const size_t LL = (size_t)L * L * sizeof(double2);
+  w.partial = (double2*)take(gram_partial_bytes(rows_per_system(lat), L, ns));
+  const size_t LL = (size_t)L * L * sizeof(double2) * ns;
+  const size_t vec = (size_t)L * sizeof(double) * ns;
   SolverDev& d = w.d;
-  d.state = (SolverState*)take(sizeof(SolverState));
-  d.rnorm2 = (double*)take(L * sizeof(double));
-  d.bnorm2 = (double*)take(L * sizeof(double));
-  w.trnorm2 = (double*)take(L * sizeof(double));
+  d.state = (SolverState*)take(sizeof(SolverState) * ns);
+  d.rnorm2 = (double*)take(vec);
+  d.bnorm2 = (double*)take(vec);
+  w.trnorm2 = (double*)take(vec);
   d.Gpp = (double2*)take(LL);
   d.Gpp2 = (double2*)take(LL);
   d.ginv = (double2*)take(LL);
@@ -106,34 +116,39 @@ int bind(const mbbs_lattice_s* lat, int L, const mbbs_solve_params& p, void* ws,
   d.C2 = (double2*)take(LL);
   take(LL);
   take(LL);
-  d.piv = (int*)take(L * sizeof(int));
-  d.zeta = (double2*)take(sizeof(double2));
-  d.nzeta = (double2*)take(sizeof(double2));
-  d.one = (double2*)take(sizeof(double2));
-  w.mone = (double2*)take(sizeof(double2));
-  d.hist = (double*)take(HIST_CAP * sizeof(double));
+  d.piv = (int*)take((size_t)L * sizeof(int) * ns);
+  d.zeta = (double2*)take(sizeof(double2) * ns);
+  d.nzeta = (double2*)take(sizeof(double2) * ns);
+  d.one = (double2*)take(sizeof(double2) * ns);
+  w.mone = (double2*)take(sizeof(double2) * ns);
+  d.hist = (double*)take((size_t)HIST_CAP * sizeof(double) * ns);
   d.qr_passes = p.qr_passes;
   return MBBS_OK;
 }
 
 // Column norms^2 of a block through a diagonal Gram product into dst (L doubles
-// as the real parts of the diagonal, gathered by a tiny copy kernel).
-__global__ void k_diag_real(int L, const double2* __restrict__ G, double* __restrict__ out, const int* frozen) {
-  if (frozen && *frozen) return;
-  for (int i = threadIdx.x; i < L; i += blockDim.x) out[i] = G[i * L + i].x;
+// per system as the real parts of the diagonal, gathered by a tiny kernel).
+__global__ void k_diag_real(int L, const double2* __restrict__ G, double* __restrict__ out, const int* frozen,
+                            int fstride) {
+  const int sys = blockIdx.x;
+  if (frozen && frozen[sys * fstride]) return;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) out[(size_t)sys * L + i] = G[(size_t)sys * L * L + i * L + i].x;
 }
 
 struct Ctx {
   const mbbs_lattice_s* lat;
   int L;
-  size_t N;
+  int nsys;
+  size_t N;          // rows per system
+  size_t NL;         // complex entries of one stacked N x L block (all systems)
+  SysBatch sb;
   mbbs_solve_params p;
   Work w;
   const double2* B;
   double2* X;
   hipStream_t st;
   Profiler* prof;
-  const int* frozen;
+  const int* frozen;  // first system's flag; the others follow at sb.fstride
 };
 
 int col_norms(Ctx& c, const double2* A, double* out, const int* frozen) {
@@ -143,17 +158,17 @@ int col_norms(Ctx& c, const double2* A, double* out, const int* frozen) {
   g.X[0] = A;
   g.Y[0] = A;
   GramOut o{};
-  o.G[0] = c.w.d.Gpp2;  // scratch L x L
+  o.G[0] = c.w.d.Gpp2;  // scratch L x L per system
   if (c.prof) c.prof->begin(MBBS_K_GRAM);
-  MBBS_TRY(launch_gram(c.L, c.N, g, o, c.w.partial, frozen, c.st));
-  hipLaunchKernelGGL(k_diag_real, dim3(1), dim3(64), 0, c.st, c.L, (const double2*)c.w.d.Gpp2, out, frozen);
+  MBBS_TRY(launch_gram(c.L, c.N, g, o, c.w.partial, frozen, c.st, c.sb));
+  hipLaunchKernelGGL(k_diag_real, dim3(c.nsys), dim3(64), 0, c.st, c.L, (const double2*)c.w.d.Gpp2, out, frozen,
+                     c.sb.fstride);
   if (c.prof) c.prof->end();
   MBBS_HIP(hipGetLastError());
   return MBBS_OK;
 }
 
-// A applied in FP64; `frozen` is the iteration flag inside the loop and null
-// for the set-up, true-residual and restart steps (which run after a stop).
+// A applied in FP64 to every system whose flag (if given) is clear.
 int dslash64(Ctx& c, const double2* in, double2* out, const int* frozen) {
   if (c.prof) c.prof->begin(MBBS_K_DSLASH64);
   int rc = launch_dslash(c.lat, c.L, P64, P64, LEX, false, in, nullptr, out, nullptr, 0, c.lat->g.V, frozen, c.st);
@@ -165,7 +180,14 @@ int combo(Ctx& c, ComboArgs a, double2* out, int gm, double2* gout, const int* f
   GramOut o{};
   o.G[0] = gout;
   if (c.prof) c.prof->begin(gm ? MBBS_K_GRAM : MBBS_K_UPDATE);
-  int rc = launch_combo(c.L, c.N, a, out, gm, &o, c.w.partial, frozen, c.st);
+  int rc = launch_combo(c.L, c.N, a, out, gm, &o, c.w.partial, frozen, c.st, c.sb);
+  if (c.prof) c.prof->end();
+  return rc;
+}
+
+int gram(Ctx& c, const GramArgs& g, const GramOut& o, const int* frozen) {
+  if (c.prof) c.prof->begin(MBBS_K_GRAM);
+  int rc = launch_gram(c.L, c.N, g, o, c.w.partial, frozen, c.st, c.sb);
   if (c.prof) c.prof->end();
   return rc;
 }
@@ -182,7 +204,7 @@ int precondition(Ctx& c, const double2* in, const double2* gam, double2* out) {
 
 int coef(Ctx& c, int which) {
   if (c.prof) c.prof->begin(MBBS_K_SMALL);
-  int rc = launch_coef(which, c.L, c.w.d, c.st);
+  int rc = launch_coef(which, c.L, c.w.d, c.st, c.nsys);
   if (c.prof) c.prof->end();
   return rc;
 }
@@ -211,9 +233,7 @@ int enqueue_iteration(Ctx& c) {
     g.X[1] = w.Rt; g.Y[1] = w.R;
     GramOut o{};
     o.G[0] = d.RtV; o.G[1] = d.RtR;
-    if (c.prof) c.prof->begin(MBBS_K_GRAM);
-    MBBS_TRY(launch_gram(c.L, c.N, g, o, w.partial, fz, c.st));
-    if (c.prof) c.prof->end();
+    MBBS_TRY(gram(c, g, o, fz));
   }
   MBBS_TRY(coef(c, 2));
   // 4.5 T = R - V alpha   (Alg. 2: R <- R - V alpha, X <- X + U alpha)
@@ -243,9 +263,7 @@ int enqueue_iteration(Ctx& c) {
     g.diag[2] = 1; g.X[2] = w.Z; g.Y[2] = w.Z;
     GramOut o{};
     o.G[0] = d.RtZ; o.G[1] = d.ZT; o.G[2] = d.ZZ;
-    if (c.prof) c.prof->begin(MBBS_K_GRAM);
-    MBBS_TRY(launch_gram(c.L, c.N, g, o, w.partial, fz, c.st));
-    if (c.prof) c.prof->end();
+    MBBS_TRY(gram(c, g, o, fz));
   }
   MBBS_TRY(coef(c, 3));
   // 4.9 X <- X + U alpha + zeta S   (Alg. 2: X <- X + zeta S)
@@ -257,7 +275,7 @@ int enqueue_iteration(Ctx& c) {
     if (!c.p.memsave) { a.mode[2] = 2; a.in[2] = w.U; a.coef[2] = d.alpha; }
     MBBS_TRY(combo(c, a, c.X, 0, nullptr, fz));
   }
-  // 4.10 R = T - zeta Z, with ||r_i||^2 for the next loop test
+  // 4.10 R = T - zeta Z, with ||r_i||^2 for the loop test
   {
     ComboArgs a{};
     a.nin = 2;
@@ -265,10 +283,11 @@ int enqueue_iteration(Ctx& c) {
     a.mode[1] = 1; a.in[1] = w.Z; a.coef[1] = d.nzeta;
     MBBS_TRY(combo(c, a, w.R, 1, d.Gpp2, fz));
     if (c.prof) c.prof->begin(MBBS_K_SMALL);
-    hipLaunchKernelGGL(k_diag_real, dim3(1), dim3(64), 0, c.st, c.L, (const double2*)d.Gpp2, d.rnorm2, fz);
+    hipLaunchKernelGGL(k_diag_real, dim3(c.nsys), dim3(64), 0, c.st, c.L, (const double2*)d.Gpp2, d.rnorm2, fz,
+                       c.sb.fstride);
     MBBS_HIP(hipGetLastError());
     // loop test on the new residual: a stop skips step 4.12
-    MBBS_TRY(launch_loop_test(c.L, d, c.st));
+    MBBS_TRY(launch_loop_test(c.L, d, c.st, c.nsys));
     if (c.prof) c.prof->end();
   }
   // 4.12 P <- R + (Q - zeta V) beta = R + P (gamma^{-1} beta) - V (zeta beta), with P^H P
@@ -283,96 +302,79 @@ int enqueue_iteration(Ctx& c) {
   return MBBS_OK;
 }
 
-// R = B - A X (or B when X = 0), P = R, R~ = R, norms and P^H P.
+// R = B - A X (or B when X = 0), P = R, R~ (= R unless given), the norms of
+// R and P^H P, for every system whose flag is clear (the others keep theirs).
 int start(Ctx& c, bool x_zero, bool set_rt) {
   Work& w = c.w;
+  const int* fz = c.frozen;
   if (x_zero) {
-    MBBS_TRY(launch_copy(c.B, w.R, c.N * c.L, c.st));
+    MBBS_TRY(launch_copy_sys(c.B, w.R, c.N * c.L, fz, c.st, c.sb));
   } else {
-    MBBS_TRY(dslash64(c, c.X, w.V, nullptr));
+    MBBS_TRY(dslash64(c, c.X, w.V, fz));
     ComboArgs a{};
     a.nin = 2;
     a.mode[0] = 0; a.in[0] = c.B;
     a.mode[1] = 1; a.in[1] = w.V; a.coef[1] = w.mone;
-    MBBS_TRY(combo(c, a, w.R, 0, nullptr, nullptr));
+    MBBS_TRY(combo(c, a, w.R, 0, nullptr, fz));
   }
-  MBBS_TRY(launch_copy(w.R, w.P, c.N * c.L, c.st));
-  if (set_rt) MBBS_TRY(launch_copy(c.p.rtilde ? (const double2*)c.p.rtilde : w.R, w.Rt, c.N * c.L, c.st));
-  MBBS_TRY(col_norms(c, w.R, w.d.rnorm2, nullptr));
+  MBBS_TRY(launch_copy_sys(w.R, w.P, c.N * c.L, fz, c.st, c.sb));
+  if (set_rt)
+    MBBS_TRY(launch_copy_sys(c.p.rtilde ? (const double2*)c.p.rtilde : w.R, w.Rt, c.N * c.L, fz, c.st, c.sb));
+  MBBS_TRY(col_norms(c, w.R, w.d.rnorm2, fz));
   {
     GramArgs g{};
     g.npair = 1;
     g.X[0] = w.P; g.Y[0] = w.P;
     GramOut o{};
     o.G[0] = w.d.Gpp;
-    MBBS_TRY(launch_gram(c.L, c.N, g, o, w.partial, nullptr, c.st));
+    MBBS_TRY(gram(c, g, o, fz));
   }
   return MBBS_OK;
 }
 
-// True residual T = B - A X and its column norms.
+// True residual T = B - A X and its column norms, every system.
 int true_residual(Ctx& c) {
   Work& w = c.w;
+  double2* t = w.T == w.R ? w.Z : w.T;
   MBBS_TRY(dslash64(c, c.X, w.V, nullptr));
   ComboArgs a{};
   a.nin = 2;
   a.mode[0] = 0; a.in[0] = c.B;
   a.mode[1] = 1; a.in[1] = w.V; a.coef[1] = w.mone;
-  MBBS_TRY(combo(c, a, w.T == w.R ? w.Z : w.T, 0, nullptr, nullptr));
-  MBBS_TRY(col_norms(c, w.T == w.R ? w.Z : w.T, w.trnorm2, nullptr));
+  MBBS_TRY(combo(c, a, t, 0, nullptr, nullptr));
+  MBBS_TRY(col_norms(c, t, w.trnorm2, nullptr));
   return MBBS_OK;
 }
 
 }  // namespace
 
-// Host-visible parts of one system's solve, shared with the batched driver.
+// Host-visible parts of one (batch of) systems' solve, shared with the
+// batched driver.  Per-system vectors have nsys entries.
 struct SolveJob {
   Ctx c;
-  SolverState hs{};
-  int restarts = 0;
-  int rc = MBBS_OK;
-  bool done = false;
+  std::vector<SolverState> hs;   // last state records read back
+  std::vector<int> restarts, rc;
+  std::vector<char> done;
+  std::vector<long long> n_outer;
+  int ndone = 0;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
-  long long n_outer = 0;
+  void init(int n) {
+    hs.assign(n, SolverState{});
+    restarts.assign(n, 0);
+    rc.assign(n, MBBS_OK);
+    done.assign(n, 0);
+    n_outer.assign(n, 0);
+    ndone = 0;
+  }
+  void finish(int s, int code) {
+    if (done[s]) return;
+    done[s] = 1;
+    rc[s] = code;
+    ++ndone;
+  }
 };
 
-static int set_scalars(Ctx& c) {
-  const double2 h[2] = {make_double2(1, 0), make_double2(-1, 0)};
-  MBBS_HIP(hipMemcpyAsync(c.w.d.one, &h[0], sizeof(double2), hipMemcpyHostToDevice, c.st));
-  MBBS_HIP(hipMemcpyAsync(c.w.mone, &h[1], sizeof(double2), hipMemcpyHostToDevice, c.st));
-  MBBS_HIP(hipStreamSynchronize(c.st));
-  return MBBS_OK;
-}
-
-static int job_init(SolveJob& j) {
-  Ctx& c = j.c;
-  MBBS_TRY(set_scalars(c));
-  if (!c.p.x0_is_guess) MBBS_TRY(launch_fill(c.X, c.N * c.L, make_double2(0, 0), c.st));
-  // ||b_i||^2
-  MBBS_TRY(col_norms(c, c.B, c.w.d.bnorm2, nullptr));
-  std::vector<double> bn(c.L);
-  MBBS_HIP(hipMemcpyAsync(bn.data(), c.w.d.bnorm2, c.L * sizeof(double), hipMemcpyDeviceToHost, c.st));
-  MBBS_HIP(hipStreamSynchronize(c.st));
-  for (int i = 0; i < c.L; ++i) {
-    if (!(bn[i] > 0) || !std::isfinite(bn[i])) {
-      set_error("right-hand side column " + std::to_string(i) + (bn[i] > 0 ? " is not finite" : " is zero"));
-      return MBBS_EINVAL;
-    }
-  }
-  MBBS_TRY(start(c, !c.p.x0_is_guess, true));
-  j.n_outer += c.p.x0_is_guess ? 1 : 0;
-  SolverState s{};
-  s.maxiter = c.p.maxiter;
-  s.tol2 = c.p.tol * c.p.tol;
-  MBBS_HIP(hipMemcpyAsync(c.w.d.state, &s, sizeof(s), hipMemcpyHostToDevice, c.st));
-  MBBS_TRY(launch_loop_test(c.L, c.w.d, c.st));   // R_0 may already satisfy the test
-  MBBS_HIP(hipStreamSynchronize(c.st));
-  return MBBS_OK;
-}
-
-// After a batch: read the state; on a stop, check the true residual and
-// restart if it disagrees with the recursive one.
 // Copy device memory to the host in stream order (the caller's stream may be
 // non-blocking with respect to the legacy default stream).
 static int read_dev(Ctx& c, void* dst, const void* src, size_t n) {
@@ -381,46 +383,116 @@ static int read_dev(Ctx& c, void* dst, const void* src, size_t n) {
   return MBBS_OK;
 }
 
+static SolverState fresh_state(const Ctx& c, bool stopped) {
+  SolverState s{};
+  s.maxiter = c.p.maxiter;
+  s.tol2 = c.p.tol * c.p.tol;
+  s.frozen = stopped ? 1 : 0;
+  s.status = ST_RUNNING;
+  return s;
+}
+
+// Per-system validity of B (a zero or non-finite column is rejected).
+static bool bad_rhs(const double* bn, int L, int* col) {
+  for (int i = 0; i < L; ++i)
+    if (!(bn[i] > 0) || !std::isfinite(bn[i])) { *col = i; return true; }
+  return false;
+}
+
+static int job_init(SolveJob& j) {
+  Ctx& c = j.c;
+  const int ns = c.nsys;
+  MBBS_TRY(launch_fill(c.w.d.one, ns, make_double2(1, 0), c.st));
+  MBBS_TRY(launch_fill(c.w.mone, ns, make_double2(-1, 0), c.st));
+  if (!c.p.x0_is_guess) MBBS_TRY(launch_fill(c.X, c.NL, make_double2(0, 0), c.st));
+  // ||b_i||^2 of every system
+  MBBS_TRY(col_norms(c, c.B, c.w.d.bnorm2, nullptr));
+  std::vector<double> bn((size_t)ns * c.L);
+  MBBS_TRY(read_dev(c, bn.data(), c.w.d.bnorm2, bn.size() * sizeof(double)));
+  std::vector<SolverState> s(ns);
+  for (int k = 0; k < ns; ++k) {
+    int col = 0;
+    const bool bad = bad_rhs(&bn[(size_t)k * c.L], c.L, &col);
+    if (bad) {
+      set_error("right-hand side column " + std::to_string(col) + (ns > 1 ? " of system " + std::to_string(k) : "") +
+                (bn[(size_t)k * c.L + col] > 0 ? " is not finite" : " is zero"));
+      j.finish(k, MBBS_EINVAL);
+    }
+    s[k] = fresh_state(c, bad);
+  }
+  if (j.ndone == ns) return MBBS_EINVAL;
+  MBBS_HIP(hipMemcpyAsync(c.w.d.state, s.data(), sizeof(SolverState) * ns, hipMemcpyHostToDevice, c.st));
+  MBBS_TRY(start(c, !c.p.x0_is_guess, true));
+  for (int k = 0; k < ns; ++k)
+    if (!j.done[k]) j.n_outer[k] += c.p.x0_is_guess ? 1 : 0;
+  MBBS_TRY(launch_loop_test(c.L, c.w.d, c.st, ns));   // R_0 may already satisfy the test
+  MBBS_HIP(hipStreamSynchronize(c.st));
+  return MBBS_OK;
+}
+
+// Host decision once every system has stopped: the true residual of each
+// system still open decides success, failure or a restart from it.
+// *restarted receives the number of systems restarted (their records in
+// j.hs are reset to running).
+static int decide(SolveJob& j, const double* tn, const double* bn, int* restarted) {
+  Ctx& c = j.c;
+  const int ns = c.nsys;
+  std::vector<SolverState> s = j.hs;
+  int nr = 0;
+  for (int k = 0; k < ns; ++k) {
+    if (j.done[k]) continue;
+    j.n_outer[k] += 1;
+    double worst = 0;
+    bool finite = true;
+    for (int i = 0; i < c.L; ++i) {
+      const double r = tn[(size_t)k * c.L + i] / bn[(size_t)k * c.L + i];
+      finite = finite && std::isfinite(r);
+      worst = std::max(worst, r);
+    }
+    const bool ok = finite && worst <= c.p.tol * c.p.tol;
+    const SolverState& h = j.hs[k];
+    if (h.status == ST_BREAKDOWN) {
+      if (!ok) set_error("block BiCGSTAB breakdown (" +
+                         std::string(h.reason == 1 ? "P^H P not positive definite" :
+                                     h.reason == 2 ? "singular R~^H V" :
+                                     h.reason == 4 ? "non-finite residual" : "non-finite zeta") + ")" +
+                         (ns > 1 ? " in system " + std::to_string(k) : ""));
+      j.finish(k, ok ? MBBS_OK : MBBS_EBREAKDOWN);
+    } else if (ok) {
+      j.finish(k, MBBS_OK);
+    } else if (h.status == ST_MAXITER || j.restarts[k] >= c.p.max_restarts || h.iter >= c.p.maxiter) {
+      j.finish(k, MBBS_NOT_CONVERGED);
+    } else {
+      // restart from the true residual: R = B - A X, P = R, keep R~
+      j.restarts[k] += 1;
+      j.n_outer[k] += 1;
+      s[k].frozen = 0;
+      s[k].status = ST_RUNNING;
+      ++nr;
+    }
+  }
+  *restarted = nr;
+  if (nr) j.hs = s;
+  return MBBS_OK;
+}
+
+// After a batch of iterations: read the states; once every system has
+// stopped, check the true residuals and restart the systems that need it.
 static int job_check(SolveJob& j) {
   Ctx& c = j.c;
-  MBBS_TRY(read_dev(c, &j.hs, c.w.d.state, sizeof(SolverState)));
-  if (!j.hs.frozen) return MBBS_OK;
+  const int ns = c.nsys;
+  MBBS_TRY(read_dev(c, j.hs.data(), c.w.d.state, sizeof(SolverState) * ns));
+  for (int k = 0; k < ns; ++k)
+    if (!j.hs[k].frozen) return MBBS_OK;
   MBBS_TRY(true_residual(c));
-  j.n_outer += 1;
-  std::vector<double> tn(c.L), bn(c.L);
-  MBBS_TRY(read_dev(c, tn.data(), c.w.trnorm2, c.L * sizeof(double)));
-  MBBS_TRY(read_dev(c, bn.data(), c.w.d.bnorm2, c.L * sizeof(double)));
-  double worst = 0;
-  bool finite = true;
-  for (int i = 0; i < c.L; ++i) {
-    double r = tn[i] / bn[i];
-    finite = finite && std::isfinite(r);
-    worst = std::max(worst, r);
-  }
-  const bool ok = finite && worst <= c.p.tol * c.p.tol;
-  if (j.hs.status == ST_BREAKDOWN) {
-    j.done = true;
-    j.rc = ok ? MBBS_OK : MBBS_EBREAKDOWN;
-    if (!ok) set_error("block BiCGSTAB breakdown (" +
-                       std::string(j.hs.reason == 1 ? "P^H P not positive definite" :
-                                   j.hs.reason == 2 ? "singular R~^H V" :
-                                   j.hs.reason == 4 ? "non-finite residual" : "non-finite zeta") + ")");
-    return MBBS_OK;
-  }
-  if (ok) { j.done = true; j.rc = MBBS_OK; return MBBS_OK; }
-  if (j.hs.status == ST_MAXITER || j.restarts >= c.p.max_restarts || j.hs.iter >= c.p.maxiter) {
-    j.done = true;
-    j.rc = MBBS_NOT_CONVERGED;
-    return MBBS_OK;
-  }
-  // restart from the true residual: R = B - A X, P = R, keep R~
-  j.restarts += 1;
-  MBBS_TRY(start(j.c, false, false));
-  j.n_outer += 1;
-  SolverState s = j.hs;
-  s.frozen = 0;
-  s.status = ST_RUNNING;
-  MBBS_HIP(hipMemcpyAsync(c.w.d.state, &s, sizeof(s), hipMemcpyHostToDevice, c.st));
+  std::vector<double> tn((size_t)ns * c.L), bn((size_t)ns * c.L);
+  MBBS_TRY(read_dev(c, tn.data(), c.w.trnorm2, tn.size() * sizeof(double)));
+  MBBS_TRY(read_dev(c, bn.data(), c.w.d.bnorm2, bn.size() * sizeof(double)));
+  int nr = 0;
+  MBBS_TRY(decide(j, tn.data(), bn.data(), &nr));
+  if (nr == 0) return MBBS_OK;
+  MBBS_HIP(hipMemcpyAsync(c.w.d.state, j.hs.data(), sizeof(SolverState) * ns, hipMemcpyHostToDevice, c.st));
+  MBBS_TRY(start(c, false, false));
   MBBS_HIP(hipStreamSynchronize(c.st));
   return MBBS_OK;
 }
@@ -430,37 +502,44 @@ static int job_enqueue(SolveJob& j, int k) {
   return MBBS_OK;
 }
 
+// Per-system result records (info has nsys entries).
 static void job_fill_info(SolveJob& j, mbbs_solve_info* info, double seconds) {
   if (!info) return;
   Ctx& c = j.c;
-  info->status = j.rc;
-  info->iterations = j.hs.iter;
-  info->restarts = j.restarts;
-  info->n_dslash_outer = 2ll * j.hs.iter + j.n_outer;
-  info->n_sap = c.p.precond ? 2ll * j.hs.iter : 0;
-  info->seconds = seconds;
-  std::vector<double> tn(c.L), rn(c.L), bn(c.L);
-  if (read_dev(c, tn.data(), c.w.trnorm2, c.L * sizeof(double)) == MBBS_OK &&
-      read_dev(c, rn.data(), c.w.d.rnorm2, c.L * sizeof(double)) == MBBS_OK &&
-      read_dev(c, bn.data(), c.w.d.bnorm2, c.L * sizeof(double)) == MBBS_OK) {
-    for (int i = 0; i < c.L; ++i) {
-      if (info->true_res) info->true_res[i] = std::sqrt(tn[i] / bn[i]);
-      if (info->rec_res) info->rec_res[i] = std::sqrt(rn[i] / bn[i]);
+  const int ns = c.nsys;
+  std::vector<double> tn((size_t)ns * c.L), rn((size_t)ns * c.L), bn((size_t)ns * c.L);
+  const bool norms = read_dev(c, tn.data(), c.w.trnorm2, tn.size() * sizeof(double)) == MBBS_OK &&
+                     read_dev(c, rn.data(), c.w.d.rnorm2, rn.size() * sizeof(double)) == MBBS_OK &&
+                     read_dev(c, bn.data(), c.w.d.bnorm2, bn.size() * sizeof(double)) == MBBS_OK;
+  for (int k = 0; k < ns; ++k) {
+    mbbs_solve_info* in = info + k;
+    in->status = j.rc[k];
+    in->iterations = j.hs[k].iter;
+    in->restarts = j.restarts[k];
+    in->n_dslash_outer = 2ll * j.hs[k].iter + j.n_outer[k];
+    in->n_sap = c.p.precond ? 2ll * j.hs[k].iter : 0;
+    in->seconds = seconds;
+    if (norms) {
+      for (int i = 0; i < c.L; ++i) {
+        const size_t e = (size_t)k * c.L + i;
+        if (in->true_res) in->true_res[i] = std::sqrt(tn[e] / bn[e]);
+        if (in->rec_res) in->rec_res[i] = std::sqrt(rn[e] / bn[e]);
+      }
     }
-  }
-  if (c.prof) {
-    for (int k = 0; k < MBBS_K_COUNT; ++k) {
-      info->kernel_ms[k] = c.prof->ms[k];
-      info->kernel_launches[k] = c.prof->launches[k];
+    if (c.prof) {
+      for (int q = 0; q < MBBS_K_COUNT; ++q) {
+        in->kernel_ms[q] = c.prof->ms[q];
+        in->kernel_launches[q] = c.prof->launches[q];
+      }
     }
-  }
-  info->history_len = 0;
-  const int nh = std::min(std::min(j.hs.hist_len, HIST_CAP), info->history_cap);
-  if (info->res_history && nh > 0) {
-    std::vector<double> h(nh);
-    if (read_dev(c, h.data(), c.w.d.hist, nh * sizeof(double)) == MBBS_OK) {
-      for (int i = 0; i < nh; ++i) info->res_history[i] = std::sqrt(h[i]);
-      info->history_len = nh;
+    in->history_len = 0;
+    const int nh = std::min(std::min(j.hs[k].hist_len, HIST_CAP), in->history_cap);
+    if (in->res_history && nh > 0) {
+      std::vector<double> h(nh);
+      if (read_dev(c, h.data(), c.w.d.hist + (size_t)k * HIST_CAP, nh * sizeof(double)) == MBBS_OK) {
+        for (int i = 0; i < nh; ++i) in->res_history[i] = std::sqrt(h[i]);
+        in->history_len = nh;
+      }
     }
   }
 }
@@ -485,6 +564,21 @@ static int validate(const mbbs_lattice_s* lat, int L, const mbbs_solve_params* p
   return MBBS_OK;
 }
 
+static void ctx_setup(Ctx& c, const mbbs_lattice_s* lat, int L, const mbbs_solve_params& p, const double* B,
+                      double* X) {
+  c.lat = lat;
+  c.L = L;
+  c.nsys = lat->nsys;
+  c.N = rows_per_system(lat);
+  c.NL = (size_t)lat->g.V * 12 * L;
+  c.sb.n = lat->nsys;
+  c.sb.fstride = SOLVER_FLAG_STRIDE;
+  c.p = p;
+  c.B = (const double2*)B;
+  c.X = (double2*)X;
+  c.prof = nullptr;
+}
+
 static int solve_impl(mbbs_lattice_t lat, int L, const double* B_dev, double* X_dev, const mbbs_solve_params* params,
                       void* ws, size_t ws_bytes, mbbs_solve_info* info, void* stream) {
   auto t0 = std::chrono::steady_clock::now();
@@ -492,15 +586,10 @@ static int solve_impl(mbbs_lattice_t lat, int L, const double* B_dev, double* X_
   MBBS_CHECK(B_dev && X_dev && B_dev != X_dev, "B and X must be distinct device blocks");
   SolveJob j;
   Ctx& c = j.c;
-  c.lat = lat;
-  c.L = L;
-  c.N = (size_t)lat->g.V * 12;
-  c.p = *params;
-  c.B = (const double2*)B_dev;
-  c.X = (double2*)X_dev;
+  ctx_setup(c, lat, L, *params, B_dev, X_dev);
+  j.init(c.nsys);
   c.st = (hipStream_t)stream;
   Profiler prof;
-  c.prof = nullptr;
   MBBS_TRY(bind(lat, L, c.p, ws, ws_bytes, c.w));
   c.frozen = &c.w.d.state->frozen;
   if (c.w.Bp) {   // clover: solve A X = (1 + T)^{-1} B
@@ -516,7 +605,7 @@ static int solve_impl(mbbs_lattice_t lat, int L, const double* B_dev, double* X_
   int rc = job_init(j);
   const int k = std::max(1, c.p.graph_iters);
   const bool use_graph = c.p.graph_iters > 1 && c.st != nullptr && !c.p.profile;
-  while (rc == MBBS_OK && !j.done) {
+  while (rc == MBBS_OK && j.ndone < c.nsys) {
     if (use_graph) {
       if (!j.exec) {
         if (hipStreamBeginCapture(c.st, hipStreamCaptureModeThreadLocal) != hipSuccess) { rc = MBBS_EHIP; break; }
@@ -544,11 +633,17 @@ static int solve_impl(mbbs_lattice_t lat, int L, const double* B_dev, double* X_
   if (prof.on) prof.flush();
   (void)hipStreamSynchronize(c.st);
   double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  if (rc < 0 && !j.done) {
-    if (info) info->status = rc;
+  if (rc < 0) {
+    // a call that failed before or while iterating: nothing is reported as solved
+    if (info)
+      for (int s = 0; s < c.nsys; ++s) info[s].status = j.done[s] ? j.rc[s] : rc;
   } else {
     job_fill_info(j, info, secs);
-    rc = j.rc;
+    // the call's status: the worst over the systems
+    for (int s = 0; s < c.nsys; ++s) {
+      if (j.rc[s] < 0) rc = std::min(rc, j.rc[s]);
+      else if (rc == MBBS_OK && j.rc[s] == MBBS_NOT_CONVERGED) rc = MBBS_NOT_CONVERGED;
+    }
   }
   if (prof.on)
     for (int i = 0; i < 2 * Profiler::CAP; ++i) (void)hipEventDestroy(prof.ev[i]);
@@ -556,25 +651,28 @@ static int solve_impl(mbbs_lattice_t lat, int L, const double* B_dev, double* X_
 }
 
 // ---------------------------------------------------------------- batched
-// Batched driver.  Systems are spread over up to BATCH_LANES internal streams
-// (largest first, each to the least loaded lane); each lane is an independent
-// chain on its own hardware queue, so the latency-bound launches of small
-// systems overlap.  The host never waits for a whole round: it polls one event
-// per system and, as soon as a system's previous batch of k iterations (and
-// the copy of its state record) has drained, decides on the host what that
-// system does next (more iterations, a true-residual check, a restart, stop)
-// and enqueues it behind whatever its lane still holds.
+// Batched driver.  Jobs (each a lattice handle: one system, or a batch of
+// same-shape systems fused into every launch) are spread over up to
+// BATCH_LANES internal streams (largest first, each to the least loaded
+// lane); each lane is an independent chain on its own hardware queue, so the
+// latency-bound launches of small jobs overlap.  The host never waits for a
+// whole round: it polls one event per job and, as soon as a job's previous
+// batch of k iterations (and the copy of its state records) has drained,
+// decides on the host what that job does next (more iterations, a
+// true-residual check, restarts, stop) and enqueues it behind whatever its
+// lane still holds.
 constexpr int BATCH_LANES = 4;
 
-// Host-side mirror of the small device records one system reports back
-// (pinned memory, written by asynchronous copies).
-struct HostRec {
-  SolverState st;
-  double tn[LMAX_SOLVER];
-  double bn[LMAX_SOLVER];
-};
-
 enum BatchPhase { PH_INIT = 0, PH_ITER = 1, PH_TRUE = 2 };
+
+// Host-side mirror of the small device records one job reports back (pinned
+// memory, written by asynchronous copies): nsys states, then nsys x L true
+// and right-hand-side norms.
+struct HostRec {
+  SolverState* st;
+  double* tn;
+  double* bn;
+};
 
 struct BatchJob {
   SolveJob j;
@@ -582,7 +680,8 @@ struct BatchJob {
   int phase = PH_INIT;
   bool pending = false;
   hipEvent_t ev = nullptr;
-  HostRec* h = nullptr;
+  HostRec h{};
+  void* pinned = nullptr;
 };
 
 static int batch_record(BatchJob& b) {
@@ -591,33 +690,25 @@ static int batch_record(BatchJob& b) {
   return MBBS_OK;
 }
 
-// Set-up without host synchronisation: constants, X = 0, ||b_i||^2, R, P, R~,
-// the state record; ||b_i||^2 comes back for the host's check.
+// Set-up without host synchronisation: constants, X = 0, ||b_i||^2 (back to
+// the host for its check).
 static int batch_init(BatchJob& b) {
   Ctx& c = b.j.c;
   if (c.w.Bp) {   // clover: solve A X = (1 + T)^{-1} B
     MBBS_TRY(launch_clover_apply(c.lat, c.L, c.B, c.w.Bp, c.st));
     c.B = c.w.Bp;
   }
-  MBBS_TRY(launch_fill(c.w.d.one, 1, make_double2(1, 0), c.st));
-  MBBS_TRY(launch_fill(c.w.mone, 1, make_double2(-1, 0), c.st));
-  if (!c.p.x0_is_guess) MBBS_TRY(launch_fill(c.X, c.N * c.L, make_double2(0, 0), c.st));
+  MBBS_TRY(launch_fill(c.w.d.one, c.nsys, make_double2(1, 0), c.st));
+  MBBS_TRY(launch_fill(c.w.mone, c.nsys, make_double2(-1, 0), c.st));
+  if (!c.p.x0_is_guess) MBBS_TRY(launch_fill(c.X, c.NL, make_double2(0, 0), c.st));
   MBBS_TRY(col_norms(c, c.B, c.w.d.bnorm2, nullptr));
-  MBBS_TRY(start(c, !c.p.x0_is_guess, true));
-  b.j.n_outer += c.p.x0_is_guess ? 1 : 0;
-  SolverState s{};
-  s.maxiter = c.p.maxiter;
-  s.tol2 = c.p.tol * c.p.tol;
-  b.h->st = s;
-  MBBS_HIP(hipMemcpyAsync(c.w.d.state, &b.h->st, sizeof(SolverState), hipMemcpyHostToDevice, c.st));
-  MBBS_TRY(launch_loop_test(c.L, c.w.d, c.st));   // R_0 may already satisfy the test
-  MBBS_HIP(hipMemcpyAsync(b.h->bn, c.w.d.bnorm2, c.L * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  MBBS_HIP(hipMemcpyAsync(b.h.bn, c.w.d.bnorm2, (size_t)c.nsys * c.L * sizeof(double), hipMemcpyDeviceToHost, c.st));
   b.phase = PH_INIT;
   return batch_record(b);
 }
 
-// k iterations (replayed from a per-system graph when graph_iters > 1), then
-// the state record back to the host.
+// k iterations (replayed from a per-job graph when graph_iters > 1), then the
+// state records back to the host.
 static int batch_iterate(BatchJob& b, int k) {
   SolveJob& j = b.j;
   Ctx& c = j.c;
@@ -636,7 +727,7 @@ static int batch_iterate(BatchJob& b, int k) {
   } else {
     MBBS_TRY(job_enqueue(j, 1));
   }
-  MBBS_HIP(hipMemcpyAsync(&b.h->st, c.w.d.state, sizeof(SolverState), hipMemcpyDeviceToHost, c.st));
+  MBBS_HIP(hipMemcpyAsync(b.h.st, c.w.d.state, sizeof(SolverState) * c.nsys, hipMemcpyDeviceToHost, c.st));
   b.phase = PH_ITER;
   return batch_record(b);
 }
@@ -644,76 +735,62 @@ static int batch_iterate(BatchJob& b, int k) {
 static int batch_true(BatchJob& b) {
   Ctx& c = b.j.c;
   MBBS_TRY(true_residual(c));
-  b.j.n_outer += 1;
-  MBBS_HIP(hipMemcpyAsync(b.h->tn, c.w.trnorm2, c.L * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  MBBS_HIP(hipMemcpyAsync(b.h.tn, c.w.trnorm2, (size_t)c.nsys * c.L * sizeof(double), hipMemcpyDeviceToHost, c.st));
   b.phase = PH_TRUE;
   return batch_record(b);
 }
 
-// The host's decision once a system's pending work has drained.
+// The host's decision once a job's pending work has drained.
 static int batch_step(BatchJob& b, int k) {
   SolveJob& j = b.j;
   Ctx& c = j.c;
+  const int ns = c.nsys;
   if (b.phase == PH_INIT) {
-    for (int i = 0; i < c.L; ++i) {
-      const double bn = b.h->bn[i];
-      if (!(bn > 0) || !std::isfinite(bn)) {
-        set_error("right-hand side column " + std::to_string(i) + (bn > 0 ? " is not finite" : " is zero"));
-        j.rc = MBBS_EINVAL;
-        j.done = true;
-        return MBBS_OK;
+    for (int s = 0; s < ns; ++s) {
+      int col = 0;
+      const bool bad = bad_rhs(&b.h.bn[(size_t)s * c.L], c.L, &col);
+      if (bad) {
+        set_error("right-hand side column " + std::to_string(col) + " is zero or not finite");
+        j.finish(s, MBBS_EINVAL);
       }
+      b.h.st[s] = fresh_state(c, bad);
     }
+    if (j.ndone == ns) return MBBS_OK;
+    MBBS_HIP(hipMemcpyAsync(c.w.d.state, b.h.st, sizeof(SolverState) * ns, hipMemcpyHostToDevice, c.st));
+    MBBS_TRY(start(c, !c.p.x0_is_guess, true));
+    for (int s = 0; s < ns; ++s)
+      if (!j.done[s]) j.n_outer[s] += c.p.x0_is_guess ? 1 : 0;
+    MBBS_TRY(launch_loop_test(c.L, c.w.d, c.st, ns));
     return batch_iterate(b, k);
   }
   if (b.phase == PH_ITER) {
-    j.hs = b.h->st;
-    if (!j.hs.frozen) return batch_iterate(b, k);
+    for (int s = 0; s < ns; ++s) j.hs[s] = b.h.st[s];
+    for (int s = 0; s < ns; ++s)
+      if (!j.hs[s].frozen) return batch_iterate(b, k);
     return batch_true(b);
   }
-  // PH_TRUE: same decisions as the single-system driver
-  double worst = 0;
-  bool finite = true;
-  for (int i = 0; i < c.L; ++i) {
-    const double r = b.h->tn[i] / b.h->bn[i];
-    finite = finite && std::isfinite(r);
-    worst = std::max(worst, r);
-  }
-  const bool ok = finite && worst <= c.p.tol * c.p.tol;
-  if (j.hs.status == ST_BREAKDOWN) {
-    j.done = true;
-    j.rc = ok ? MBBS_OK : MBBS_EBREAKDOWN;
-    if (!ok) set_error("block BiCGSTAB breakdown in a batched system");
-    return MBBS_OK;
-  }
-  if (ok) { j.done = true; j.rc = MBBS_OK; return MBBS_OK; }
-  if (j.hs.status == ST_MAXITER || j.restarts >= c.p.max_restarts || j.hs.iter >= c.p.maxiter) {
-    j.done = true;
-    j.rc = MBBS_NOT_CONVERGED;
-    return MBBS_OK;
-  }
-  j.restarts += 1;
+  // PH_TRUE: the same decisions as the single-call driver
+  int nr = 0;
+  MBBS_TRY(decide(j, b.h.tn, b.h.bn, &nr));
+  if (nr == 0) return MBBS_OK;
+  for (int s = 0; s < ns; ++s) b.h.st[s] = j.hs[s];
+  MBBS_HIP(hipMemcpyAsync(c.w.d.state, b.h.st, sizeof(SolverState) * ns, hipMemcpyHostToDevice, c.st));
   MBBS_TRY(start(c, false, false));
-  j.n_outer += 1;
-  b.h->st = j.hs;
-  b.h->st.frozen = 0;
-  b.h->st.status = ST_RUNNING;
-  MBBS_HIP(hipMemcpyAsync(c.w.d.state, &b.h->st, sizeof(SolverState), hipMemcpyHostToDevice, c.st));
   return batch_iterate(b, k);
 }
 
-static int batched_impl(int nsys, const mbbs_lattice_t* lats, const int* Ls, const double* const* B, double* const* X,
+static int batched_impl(int njob, const mbbs_lattice_t* lats, const int* Ls, const double* const* B, double* const* X,
                         const mbbs_solve_params* params, void* ws, size_t ws_bytes, mbbs_solve_info* infos,
                         void* stream) {
   auto t0 = std::chrono::steady_clock::now();
-  MBBS_CHECK(nsys >= 1 && lats && Ls && B && X && params, "null argument");
+  MBBS_CHECK(njob >= 1 && lats && Ls && B && X && params, "null argument");
   hipStream_t caller = (hipStream_t)stream;
-  std::vector<BatchJob> jobs(nsys);
-  // lanes: largest systems first, each to the least loaded lane
-  const int nl = std::min(nsys, BATCH_LANES);
-  std::vector<int> order(nsys);
-  for (int i = 0; i < nsys; ++i) order[i] = i;
-  for (int i = 0; i < nsys; ++i) MBBS_TRY(validate(lats[i], Ls[i], &params[i]));
+  std::vector<BatchJob> jobs(njob);
+  // lanes: largest jobs first, each to the least loaded lane
+  const int nl = std::min(njob, BATCH_LANES);
+  std::vector<int> order(njob);
+  for (int i = 0; i < njob; ++i) order[i] = i;
+  for (int i = 0; i < njob; ++i) MBBS_TRY(validate(lats[i], Ls[i], &params[i]));
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     return (double)lats[a]->g.V * Ls[a] > (double)lats[b]->g.V * Ls[b];
   });
@@ -723,21 +800,20 @@ static int batched_impl(int nsys, const mbbs_lattice_t* lats, const int* Ls, con
     jobs[i].lane = l;
     load[l] += (double)lats[i]->g.V * Ls[i];
   }
+  // infos: one record per system, jobs in argument order
+  std::vector<int> first(njob, 0);
+  for (int i = 1; i < njob; ++i) first[i] = first[i - 1] + lats[i - 1]->nsys;
   char* q = (char*)ws;
   size_t left = ws_bytes;
-  for (int i = 0; i < nsys; ++i) {
+  for (int i = 0; i < njob; ++i) {
     const size_t need = workspace_bytes(lats[i], Ls[i], params[i]);
     MBBS_CHECK(q != nullptr && left >= need, "batched workspace too small");
     Ctx& c = jobs[i].j.c;
-    c.lat = lats[i];
-    c.L = Ls[i];
-    c.N = (size_t)lats[i]->g.V * 12;
-    c.p = params[i];
-    c.p.profile = 0;
-    c.B = (const double2*)B[i];
-    c.X = (double2*)X[i];
-    c.prof = nullptr;
+    mbbs_solve_params p = params[i];
+    p.profile = 0;
     MBBS_CHECK(B[i] && X[i] && B[i] != X[i], "B and X must be distinct device blocks");
+    ctx_setup(c, lats[i], Ls[i], p, B[i], X[i]);
+    jobs[i].j.init(c.nsys);
     MBBS_TRY(bind(lats[i], Ls[i], c.p, q, need, c.w));
     c.frozen = &c.w.d.state->frozen;
     q += al(need);
@@ -745,12 +821,21 @@ static int batched_impl(int nsys, const mbbs_lattice_t* lats, const int* Ls, con
   }
   // resources, released on every exit path below
   std::vector<hipStream_t> lanes(nl, nullptr);
-  HostRec* host = nullptr;
   hipEvent_t fork = nullptr;
   int rc = MBBS_OK;
   auto fail = [&](int code, const char* msg) { if (rc >= 0) { rc = code; set_error(msg); } };
-  if (hipHostMalloc((void**)&host, sizeof(HostRec) * nsys, hipHostMallocDefault) != hipSuccess)
-    fail(MBBS_ENOMEM, "pinned host memory for the batched state records");
+  for (int i = 0; i < njob && rc >= 0; ++i) {
+    BatchJob& b = jobs[i];
+    const int ns = b.j.c.nsys, L = b.j.c.L;
+    const size_t bytes = sizeof(SolverState) * ns + 2 * sizeof(double) * ns * L;
+    if (hipHostMalloc(&b.pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+      fail(MBBS_ENOMEM, "pinned host memory for the batched state records");
+      break;
+    }
+    b.h.st = (SolverState*)b.pinned;
+    b.h.tn = (double*)((char*)b.pinned + sizeof(SolverState) * ns);
+    b.h.bn = b.h.tn + (size_t)ns * L;
+  }
   for (int l = 0; l < nl && rc >= 0; ++l)
     if (hipStreamCreateWithFlags(&lanes[l], hipStreamNonBlocking) != hipSuccess) fail(MBBS_EHIP, "stream creation");
   if (rc >= 0 && (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
@@ -758,23 +843,23 @@ static int batched_impl(int nsys, const mbbs_lattice_t* lats, const int* Ls, con
     fail(MBBS_EHIP, "event creation");
   for (int l = 0; l < nl && rc >= 0; ++l)
     if (hipStreamWaitEvent(lanes[l], fork, 0) != hipSuccess) fail(MBBS_EHIP, "stream wait");
-  for (int i = 0; i < nsys && rc >= 0; ++i) {
+  for (int i = 0; i < njob && rc >= 0; ++i) {
     BatchJob& b = jobs[i];
     b.j.c.st = lanes[b.lane];
-    b.h = host + i;
     if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) fail(MBBS_EHIP, "event creation");
   }
-  // set-up of every system, then the polling loop
-  for (int i = 0; i < nsys && rc >= 0; ++i) {
+  // set-up of every job, then the polling loop
+  for (int i = 0; i < njob && rc >= 0; ++i) {
     const int e = batch_init(jobs[i]);
     if (e < 0) rc = e;
   }
-  int remaining = nsys;
+  auto job_done = [](const BatchJob& b) { return b.j.ndone == b.j.c.nsys; };
+  int remaining = njob;
   while (rc >= 0 && remaining > 0) {
     bool progress = false;
-    for (int i = 0; i < nsys && rc >= 0; ++i) {
+    for (int i = 0; i < njob && rc >= 0; ++i) {
       BatchJob& b = jobs[i];
-      if (b.j.done || !b.pending) continue;
+      if (job_done(b) || !b.pending) continue;
       const hipError_t e = hipEventQuery(b.ev);
       if (e == hipErrorNotReady) continue;
       if (e != hipSuccess) { fail(MBBS_EHIP, "batched solve: device error"); break; }
@@ -783,7 +868,7 @@ static int batched_impl(int nsys, const mbbs_lattice_t* lats, const int* Ls, con
       const int k = std::max(1, b.j.c.p.graph_iters);
       const int s = batch_step(b, k);
       if (s < 0) { rc = s; break; }
-      if (b.j.done) --remaining;
+      if (job_done(b)) --remaining;
     }
     if (!progress) std::this_thread::yield();
   }
@@ -791,21 +876,25 @@ static int batched_impl(int nsys, const mbbs_lattice_t* lats, const int* Ls, con
     if (lanes[l]) (void)hipStreamSynchronize(lanes[l]);
   double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   int worst = MBBS_OK;
-  for (int i = 0; i < nsys; ++i) {
+  for (int i = 0; i < njob; ++i) {
     SolveJob& j = jobs[i].j;
-    if (rc >= 0) job_fill_info(j, infos ? &infos[i] : nullptr, secs);
-    else if (infos) infos[i].status = j.done ? j.rc : rc;
-    if (j.rc < 0) worst = std::min(worst, j.rc);
-    else if (worst == MBBS_OK && j.rc == MBBS_NOT_CONVERGED) worst = MBBS_NOT_CONVERGED;
+    mbbs_solve_info* in = infos ? infos + first[i] : nullptr;
+    if (rc >= 0) job_fill_info(j, in, secs);
+    else if (in)
+      for (int s = 0; s < j.c.nsys; ++s) in[s].status = j.done[s] ? j.rc[s] : rc;
+    for (int s = 0; s < j.c.nsys; ++s) {
+      if (j.rc[s] < 0) worst = std::min(worst, j.rc[s]);
+      else if (worst == MBBS_OK && j.rc[s] == MBBS_NOT_CONVERGED) worst = MBBS_NOT_CONVERGED;
+    }
     if (j.exec) (void)hipGraphExecDestroy(j.exec);
     if (j.graph) (void)hipGraphDestroy(j.graph);
     if (jobs[i].ev) (void)hipEventDestroy(jobs[i].ev);
+    if (jobs[i].pinned) (void)hipHostFree(jobs[i].pinned);
   }
   // the caller's stream sees every lane's work as complete
   for (int l = 0; l < nl; ++l)
     if (lanes[l]) (void)hipStreamDestroy(lanes[l]);
   if (fork) (void)hipEventDestroy(fork);
-  if (host) (void)hipHostFree(host);
   return rc < 0 ? rc : worst;
 }
 

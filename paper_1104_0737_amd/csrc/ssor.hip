@@ -160,7 +160,10 @@ __global__ void __launch_bounds__(ssor_threads<PR>()) k_ssor(GeomK k, double kap
                                                              const int* __restrict__ hp_loc,
                                                              const int* __restrict__ hp_off, int nh,
                                                              const int* __restrict__ frozen) {
-  if (frozen && *frozen) return;
+  // one workgroup per domain, hence one system: block-uniform test and kappa
+  const int sys = sys_of_domain(k, blockIdx.x);
+  if (sys_frozen(k, frozen, sys)) return;
+  if (k.kap) kappa = k.kap[sys];
   if constexpr (LT > 0) L = LT;   // compile-time element offsets for the common block width
   const int base_site = s0 + blockIdx.x * k.g.Vb;
   if (rmode < 0)

@@ -187,7 +187,7 @@ __device__ __forceinline__ void hop_pin(HopData<PIN, PL, C>& d) {
 template <int PIN, int PL, int C, int HOPS, int MU, int FWD, typename R>
 __device__ __forceinline__ void hop_compute(const GeomK& k, const SiteCtx& c, const HopData<PIN, PL, C>& d,
                                             cplx<R> (&acc)[4][3][C]) {
-  const bool wrap = FWD ? (c.x[MU] == k.g.d[MU] - 1) : (c.x[MU] == 0);
+  const bool wrap = FWD ? (c.x[MU] == wrap_extent(k, MU) - 1) : (c.x[MU] == 0);
   cplx<R> ph = cmake<R>((R)1, (R)0);
   constexpr bool may_wrap = HOPS == ALL || HOPS == OUTSIDE;   // in-domain hops never cross the boundary
   if (may_wrap && wrap) ph = cmake<R>((R)k.g.ph[MU][0], (R)(FWD ? k.g.ph[MU][1] : -k.g.ph[MU][1]));
