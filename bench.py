@@ -237,7 +237,8 @@ def main():
             prev = json.loads(f.read().strip().splitlines()[-1])["tuning"]
         for prec, name in ((B.FP64, "fp64"), (B.FP32, "fp32"), (B.FP16S, "fp16s")):
             t = prev[name]
-            op = (t["group_cols"], t["block_threads"], t["split"], t["hop_pair"], t["nt_store"], t.get("chunk", 0))
+            op = (t["group_cols"], t["block_threads"], t["split"], t["hop_pair"], t["nt_store"], t.get("chunk", 0),
+                  t.get("tile", 0))
             autotune.apply(lat, prec, op)
             if not args.skip_dslash:
                 dslash[name] = time_dslash(prec)
@@ -253,8 +254,13 @@ def main():
             best, times = autotune.tune_operator(lat, V, L, prec, stream=stream)
             tuning[name] = {"group_cols": best[0], "block_threads": best[1], "split": best[2],
                             "hop_pair": best[3], "nt_store": best[4], "chunk": best[5] if len(best) > 5 else 0,
+                            "tile": best[6] if len(best) > 6 else 0,
                             "ms": round(times[best], 4), "worst_ms": round(max(times.values()), 4),
-                            "classic_best_ms": round(min(v for k, v in times.items() if k[2] == 0), 4)}
+                            "classic_best_ms": round(min(v for k, v in times.items()
+                                                         if k[2] == 0 and not (len(k) > 6 and k[6])), 4)}
+            tiled_ms = [v for k, v in times.items() if len(k) > 6 and k[6]]
+            if tiled_ms:
+                tuning[name]["tiled_best_ms"] = round(min(tiled_ms), 4)
             log(f"tuned {name}: {best} ({times[best]:.3f} ms; "
                 f"best classic {tuning[name]['classic_best_ms']:.3f} ms; worst {max(times.values()):.3f} ms)")
             if not args.skip_dslash:

@@ -152,6 +152,15 @@ int mbbs_lattice_table(mbbs_lattice_t lat, int which, int32_t* out, size_t count
  *  MBBS_TUNE_CHUNK_FP64/FP32/FP16S  columns per thread of the one-thread-per-site
  *      stencil kernels (0: automatic, 1 for FP64 and 2 otherwise; 1..4 used
  *      when it divides L)
+ *  MBBS_TUNE_TILE_FP64/FP32/FP16S   1: the operator (input and output of one
+ *      precision) and the MR step's Dirichlet stencil run as LDS-tiled
+ *      kernels: one workgroup per sub-block of a SAP domain and all columns,
+ *      the sub-block's spinors staged in LDS, only hops leaving it read
+ *      global memory (used where a sub-block shape fits; the operator's
+ *      output bits are unchanged, the MR sums follow the sub-block shape);
+ *      2: as 1, and each MR step also performs the previous step's update of
+ *      psi and r (one pass over the fields less per step; same bits as 1);
+ *      FP64 and FP32 only (EINVAL for MBBS_TUNE_TILE_FP16S)
  *  MBBS_TUNE_LDS_PAD_KB             extra LDS (KiB, 0..64) reserved per stencil
  *      block, which caps the blocks resident on a CU (fewer sites in flight
  *      per XCD, so more of their neighbour data stays in its L2)
@@ -163,8 +172,17 @@ enum { MBBS_TUNE_GROUP_FP64 = 0, MBBS_TUNE_GROUP_FP32 = 1, MBBS_TUNE_GROUP_FP16S
        MBBS_TUNE_HOP_PAIR_FP16S = 13, MBBS_TUNE_NT_STORE_FP64 = 14, MBBS_TUNE_NT_STORE_FP32 = 15,
        MBBS_TUNE_NT_STORE_FP16S = 16, MBBS_TUNE_CHUNK_FP64 = 17, MBBS_TUNE_CHUNK_FP32 = 18,
        MBBS_TUNE_CHUNK_FP16S = 19, MBBS_TUNE_BLOCK_THREADS_FP64 = 20,
-       MBBS_TUNE_BLOCK_THREADS_FP32 = 21, MBBS_TUNE_BLOCK_THREADS_FP16S = 22 };
+       MBBS_TUNE_BLOCK_THREADS_FP32 = 21, MBBS_TUNE_BLOCK_THREADS_FP16S = 22,
+       MBBS_TUNE_TILE_FP64 = 23, MBBS_TUNE_TILE_FP32 = 24, MBBS_TUNE_TILE_FP16S = 25 };
 int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value);
+
+/* The tile shape the LDS-tiled kernels use for L columns in precision prec
+ * (MBBS_TUNE_TILE_*): t4[0..3] receives the tile extents along x, y, z, t
+ * (each dividing the SAP block extent), or zeros when the tiled kernels are
+ * not used (knob off, L not split evenly over the kernel's columns per
+ * thread, or no tile shape fits the 160 KiB LDS and one workgroup).  t4 is
+ * host memory of 4 ints.  Errors: EINVAL. */
+int mbbs_lattice_tile_shape(mbbs_lattice_t lat, int L, int prec, int32_t* t4);
 
 /* O(a)-improved (clover) Wilson operator with Jacobi preconditioning (Sec. 2.2:
  * the matrix is divided by I + clover term before the domain decomposition).

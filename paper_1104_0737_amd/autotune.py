@@ -2,12 +2,15 @@
 
 For a lattice handle, L and a precision, time the operator over the
 candidate settings (column-group width, threads per block, split-wave hop
-groups, paired hops, nontemporal output stores) and keep the fastest on the
-handle.  The SAP kernels of a precision share the width, block and split
-settings; `tune_sap` then picks between the best split and the best
-one-thread-per-site shape by timing the preconditioner itself.  Settings
-other than the split change no result bit; split shapes sum the hops in
-another order.
+groups, paired hops, nontemporal output stores, columns per thread, LDS-tiled
+kernels) and keep the fastest on the handle.  The SAP kernels of a precision
+share these settings; `tune_sap` then picks between the best split, the best
+one-thread-per-site and the best tiled shape by timing the preconditioner
+itself.  The split shapes and the number of columns per thread change the
+order in which the hops are summed, and the MR domain sums follow the block
+or tile shape; every other setting leaves the operator's result bits alone.
+
+A setting is (group, threads, split, pair, nt[, columns per thread[, tiled]]).
 """
 
 from __future__ import annotations
@@ -43,12 +46,19 @@ def operator_candidates(L, prec):
     other = 2 if prec == B.FP64 else 1
     if L % other == 0:
         out += [(L, t, 0, 0, nt, other) for t in (128, 256) for nt in (0, 1)]
-    return out + [(L, 256, sp, 0, nt) for sp in (2, 4) for nt in (0, 1)]
+    out += [(L, 256, sp, 0, nt) for sp in (2, 4) for nt in (0, 1)]
+    # the LDS-tiled kernels (where a tile shape fits)
+    return out + [(L, 256, 0, 0, nt, 0, 1) for nt in (0, 1)]
+
+
+def _tiled(setting):
+    return len(setting) > 6 and setting[6] >= 1
 
 
 def apply(lat, prec, setting):
     g, t, sp, pr, nt = setting[:5]
     ch = setting[5] if len(setting) > 5 else 0
+    B.mbbs_lattice_tune(lat, B.TUNE_TILE[prec], setting[6] if _tiled(setting) else 0)
     B.mbbs_lattice_tune(lat, B.TUNE_CHUNK[prec], ch)
     B.mbbs_lattice_tune(lat, B.TUNE_GROUP[prec], g)
     B.mbbs_lattice_tune(lat, B.TUNE_BLOCK_THREADS_PREC[prec], t)
@@ -90,14 +100,26 @@ def tune_operator(lat, V, L, prec, stream=None, reps=3):
 
 
 def tune_sap(lat, V, L, prec, op_times, stream=None, ncy=4, nmr=4, reps=2):
-    """Among the fastest split and the fastest one-thread-per-site operator
-    settings (from tune_operator's timings), and one column per thread for
-    FP32 / FP16 storage, keep the one under which the SAP preconditioner
-    itself runs faster.  Returns (setting, {setting: ms})."""
+    """Among the fastest split, one-thread-per-site and tiled operator
+    settings (from tune_operator's timings), one column per thread for FP32 /
+    FP16 storage, and the fastest one-thread-per-site shape with the tiled MR
+    kernel (with and without the MR update folded in), keep the one under
+    which the SAP preconditioner itself runs faster.  Returns (setting,
+    {setting: ms})."""
     import torch
     split = [k for k in op_times if k[2] in (2, 4)]
-    classic = [k for k in op_times if k[2] not in (2, 4)]
-    cands = [min(c, key=op_times.get) for c in (split, classic) if c]
+    classic = [k for k in op_times if k[2] not in (2, 4) and not _tiled(k)]
+    tiled = [k for k in op_times if _tiled(k)]
+    cands = [min(c, key=op_times.get) for c in (split, classic, tiled) if c]
+    folded = prec != B.FP16S          # the folded MR update: FP64 and FP32 only
+    if tiled and folded:
+        # the MR update folded into the next MR step
+        cands.append(tuple(min(tiled, key=op_times.get)[:6]) + (2,))
+    if classic and tiled:
+        # the SAP residual kernel in the best classic shape, the MR step tiled
+        best = min(classic, key=op_times.get)
+        base = tuple(best[:5]) + ((best[5] if len(best) > 5 else 0),)
+        cands += [base + (1,)] + ([base + (2,)] if folded else [])
     if classic and prec != B.FP64:
         # one column per thread: more waves in flight per CU for the domain kernels
         g, t, sp, pr, nt = min(classic, key=op_times.get)[:5]

@@ -24,7 +24,8 @@ TABLES = ("COORD", "NEIGHBOUR", "BOUNDARY", "PARITY", "EO", "DOMAIN", "COLOUR", 
 KERNEL_CLASSES = ("dslash64", "sap_resid", "mr_dslash", "mr_update", "convert", "gram", "update", "small", "ssor")
 
 EXPORTS = (
-    "mbbs_lattice_create", "mbbs_lattice_create_batch", "mbbs_lattice_nsys", "mbbs_lattice_destroy", "mbbs_lattice_tune", "mbbs_lattice_set_clover",
+    "mbbs_lattice_create", "mbbs_lattice_create_batch", "mbbs_lattice_nsys", "mbbs_lattice_destroy", "mbbs_lattice_tune", "mbbs_lattice_tile_shape",
+    "mbbs_lattice_set_clover",
     "mbbs_lattice_clover_inverse", "mbbs_apply_clover_inverse", "mbbs_lattice_table_size",
     "mbbs_lattice_table",
     "mbbs_apply_dirac", "mbbs_apply_dirac_raw", "mbbs_convert_to", "mbbs_convert_from",
@@ -82,6 +83,7 @@ def lib():
             "mbbs_lattice_nsys": (i, [vp, ctypes.POINTER(i)]),
             "mbbs_lattice_destroy": (i, [vp]),
             "mbbs_lattice_tune": (i, [vp, i, i]),
+            "mbbs_lattice_tile_shape": (i, [vp, i, i, ctypes.POINTER(ctypes.c_int32)]),
             "mbbs_lattice_set_clover": (i, [vp, d, vp]),
             "mbbs_lattice_clover_inverse": (i, [vp, vp, vp]),
             "mbbs_apply_clover_inverse": (i, [vp, i, vp, vp, vp]),
@@ -200,10 +202,18 @@ TUNE_MR_FUSED = 9
 TUNE_NT_STORE = {0: 14, 1: 15, 2: 16}   # precision -> knob
 TUNE_CHUNK = {0: 17, 1: 18, 2: 19}      # precision -> knob
 TUNE_HOP_PAIR = {0: 11, 1: 12, 2: 13}   # precision -> knob
+TUNE_TILE = {0: 23, 1: 24, 2: 25}       # precision -> knob
 
 
 def mbbs_lattice_tune(lat, knob, value):
     return _check(lib().mbbs_lattice_tune(lat, knob, value))
+
+
+def mbbs_lattice_tile_shape(lat, L, prec):
+    """Tile extents of the LDS-tiled kernels for (L, prec), or (0, 0, 0, 0)."""
+    t = (ctypes.c_int32 * 4)()
+    _check(lib().mbbs_lattice_tile_shape(lat, L, prec, t))
+    return tuple(t)
 
 
 def mbbs_lattice_set_clover(lat, csw, stream=None):

@@ -17,7 +17,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmbbs.so")
 BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-UNITS = ["lattice.hip", "dslash.hip", "ssor.hip", "clover.hip", "blas.hip", "solver.hip", "capi.hip"]
+UNITS = ["lattice.hip", "dslash.hip", "tile.hip", "ssor.hip", "clover.hip", "blas.hip", "solver.hip", "capi.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(HERE, "..", "include")]

@@ -6,6 +6,7 @@
 // domain-restricted (Dirichlet) operator of Sec. 2.2, the SAP residual
 // eta - A psi, and the MR domain step with its per-domain reductions.
 #include "stencil.h"
+#include "tile.h"
 
 namespace mbbs {
 
@@ -257,7 +258,6 @@ __global__ void __launch_bounds__(256) k_mr_update(GeomK k, int L, int s0, int n
                                                    const double* __restrict__ omega, int update_r,
                                                    int assign, const int* __restrict__ frozen) {
   using R = typename Store<PR>::Real;
-  using RP = typename Store<PPSI>::Real;
   const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * blockDim.y + threadIdx.y;
   if (s >= s0 + n) return;
   const int col = threadIdx.x;
@@ -271,23 +271,15 @@ __global__ void __launch_bounds__(256) k_mr_update(GeomK k, int L, int s0, int n
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const size_t i = base + (size_t)(3 * sp + a) * L;
-      cplx<R> d = om * rv[sp][a];
-      if (assign) {
-        Store<PPSI>::st(psi, i, cplx<RP>{(RP)d.re, (RP)d.im});
-      } else {
-        auto pv = Store<PPSI>::ld(psi, i);
-        Store<PPSI>::st(psi, i, cplx<RP>{(RP)(pv.re + (RP)d.re), (RP)(pv.im + (RP)d.im)});
-      }
-    }
+    for (int a = 0; a < 3; ++a)
+      mr_psi_update<PPSI, R>(psi, base + (size_t)(3 * sp + a) * L, mr_mul(om, rv[sp][a]), assign);
   if (!update_r) return;
   cplx<R> wv[4][3];
   load_spinor<PR, R>(w, w_s, base, L, sidx, wv);
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) rv[sp][a] = rv[sp][a] - om * wv[sp][a];
+    for (int a = 0; a < 3; ++a) rv[sp][a] = rv[sp][a] - mr_mul(om, wv[sp][a]);
   store_spinor<PR, R>(r, r_s, base, L, sidx, rv);
 }
 
@@ -425,22 +417,20 @@ __global__ void __launch_bounds__(256) k_mr_update_flat(GeomK k, int L, int s0, 
   const int dom = s / k.g.Vb;
   if (sys_frozen(k, frozen, sys_of_domain(k, dom))) return;
   const double* om = omega + ((size_t)dom * L + col) * 2;
-  const float o0r = (float)om[0], o0i = (float)om[1], o1r = (float)om[2], o1i = (float)om[3];
+  const cplx<float> o0 = cmake((float)om[0], (float)om[1]), o1 = cmake((float)om[2], (float)om[3]);
   const size_t g = (size_t)s0 * 6 * L + q;             // float4 index in the whole field
   const float4 rv = r[g];
-  // d = omega * r
-  const float d0r = o0r * rv.x - o0i * rv.y, d0i = o0r * rv.y + o0i * rv.x;
-  const float d1r = o1r * rv.z - o1i * rv.w, d1i = o1r * rv.w + o1i * rv.z;
+  const cplx<float> d0 = mr_mul(o0, cmake(rv.x, rv.y)), d1 = mr_mul(o1, cmake(rv.z, rv.w));
   if (assign) {
-    psi[g] = make_float4(d0r, d0i, d1r, d1i);
+    psi[g] = make_float4(d0.re, d0.im, d1.re, d1.im);
   } else {
     const float4 p = psi[g];
-    psi[g] = make_float4(p.x + d0r, p.y + d0i, p.z + d1r, p.w + d1i);
+    psi[g] = make_float4(p.x + d0.re, p.y + d0.im, p.z + d1.re, p.w + d1.im);
   }
   if (!update_r) return;
   const float4 wv = w[g];
-  r[g] = make_float4(rv.x - (o0r * wv.x - o0i * wv.y), rv.y - (o0r * wv.y + o0i * wv.x),
-                     rv.z - (o1r * wv.z - o1i * wv.w), rv.w - (o1r * wv.w + o1i * wv.z));
+  const cplx<float> m0 = mr_mul(o0, cmake(wv.x, wv.y)), m1 = mr_mul(o1, cmake(wv.z, wv.w));
+  r[g] = make_float4(rv.x - m0.re, rv.y - m0.im, rv.z - m1.re, rv.w - m1.im);
 }
 
 // ---------------------------------------------------------------- split-wave kernels
@@ -889,6 +879,12 @@ template <int PIN, int POUT, int PL>
 static int dslash_dispatch_c(const mbbs_lattice_s* lat, int L, int order, bool blocked,
                              const void* in, const float* in_s, void* out, float* out_s, int s0,
                              int n, const int* frozen, hipStream_t st) {
+  if constexpr (PIN == POUT && PIN == PL) {
+    TileArgs T;
+    const bool whole = order == LEX ? (s0 == 0 && n == lat->g.V) : (s0 % lat->g.Vb == 0 && n % lat->g.Vb == 0);
+    if (whole && ((uintptr_t)in & 15) == 0 && tile_plan(lat, L, PL, &T))
+      return launch_dslash_tiled(lat, L, PL, order, blocked, T, in, in_s, out, out_s, s0, n, frozen, st);
+  }
   const int P = lat->nsys == 1 ? lat->split[PL] : 0;   // the split kernels serve single systems only
   if ((P == 2 || P == 4) && !lat->gk.clov) {   // the split kernels have no clover step
     const int S = split_sites(lat, L, PL, P);
@@ -931,7 +927,7 @@ size_t sap_buffer_bytes(const mbbs_lattice_s* lat, int L, int prec, bool ssor) {
   const size_t ndc = lat->g.ndom / 2;             // domains per colour
   const size_t nblk = lat->g.Vh;                  // upper bound on blocks per colour
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t nf = ssor ? 4 : 3;
+  const size_t nf = ssor ? 4 : 5;   // eta, r, w and x2 (SSOR) or a second r and w (MR)
   return al(field) * nf + al(scales) * nf + al(psi) + al(nblk * L * 3 * sizeof(double)) +
          al(ndc * L * 2 * sizeof(double));
 }
@@ -962,6 +958,11 @@ int sap_bind(const mbbs_lattice_s* lat, int L, int prec, void* ws, size_t bytes,
   if (ssor) {
     b->x2 = p; p += field;
     b->x2_s = prec == P16 ? (float*)p : nullptr; p += scales;
+  } else {
+    b->r2 = p; p += field;
+    b->r2_s = prec == P16 ? (float*)p : nullptr; p += scales;
+    b->w2 = p; p += field;
+    b->w2_s = prec == P16 ? (float*)p : nullptr; p += scales;
   }
   return MBBS_OK;
 }
@@ -1064,10 +1065,51 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
         MBBS_HIP(hipGetLastError());
         continue;
       }
+      TileArgs T;
+      const bool tiled = ((uintptr_t)b.r & 15) == 0 && ((uintptr_t)b.w & 15) == 0 && tile_plan(lat, L, PL, &T);
+      if (tiled && lat->tile[PL] == 2 && PL != P16 && b.r2 && b.w2) {
+        // each step folds the previous step's update in; the steps alternate
+        // between two residual / A r buffers; psi's last update follows
+        void* rb[2] = {b.r, b.r2};
+        void* wb[2] = {b.w, b.w2};
+        float* rbs[2] = {b.r_s, b.r2_s};
+        float* wbs[2] = {b.w_s, b.w2_s};
+        for (int it = 0; it < nmr; ++it) {
+          if (prof) prof->begin(MBBS_K_MR_DSLASH);
+          const int c = it & 1, o = c ^ 1;
+          if (it == 0) {
+            MBBS_TRY(launch_mr_dslash_tiled(lat, L, PL, T, rb[0], rbs[0], wb[0], wbs[0], s0, n, b.partial, frozen, st));
+          } else {
+            MBBS_TRY(launch_mr_fused_tiled(lat, L, PL, T, rb[o], rbs[o], wb[o], wbs[o], rb[c], rbs[c], wb[c], wbs[c],
+                                           b.psi, b.omega, cy == 0 && it == 1, s0, n, b.partial, frozen, st));
+          }
+          hipLaunchKernelGGL(k_mr_omega, dim3(g.ndom / 2), dim3(256), 0, st, lat->gk, L, T.tpd,
+                             (const double*)b.partial, b.omega, frozen);
+          if (prof) prof->end();
+          MBBS_HIP(hipGetLastError());
+        }
+        if (prof) prof->begin(MBBS_K_MR_UPDATE);
+        const int c = (nmr - 1) & 1;
+        const int assign = cy == 0 && nmr == 1;
+        if constexpr (PR == P32 && PPSI == P32) {
+          const size_t npair = (size_t)n * 6 * L;
+          hipLaunchKernelGGL(k_mr_update_flat, dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st, lat->gk, L, s0,
+                             n, (float4*)rb[c], (const float4*)wb[c], (float4*)b.psi, b.omega, 0, assign, frozen);
+        } else {
+          hipLaunchKernelGGL((k_mr_update<PR, PPSI>), dim3(ceil_div(n, Su)), dim3(L, Su), 0, st, lat->gk, L, s0, n,
+                             (ER*)rb[c], rbs[c], (const ER*)wb[c], wbs[c], (EP*)b.psi, b.omega, 0, assign, frozen);
+        }
+        if (prof) prof->end();
+        MBBS_HIP(hipGetLastError());
+        continue;
+      }
       for (int it = 0; it < nmr; ++it) {
         if (prof) prof->begin(MBBS_K_MR_DSLASH);
         int nblk_dom = g.Vb / S;
-        if (SS > 0) {
+        if (tiled) {
+          nblk_dom = T.tpd;
+          MBBS_TRY(launch_mr_dslash_tiled(lat, L, PL, T, b.r, b.r_s, b.w, b.w_s, s0, n, b.partial, frozen, st));
+        } else if (SS > 0) {
           nblk_dom = g.Vb / SS;
           const size_t smem = split_smem_bytes(PL, P, SS, L);
           if (P == 4) {

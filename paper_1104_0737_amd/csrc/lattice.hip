@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "tile.h"
 #include "sitectx.h"
 
 namespace mbbs {
@@ -360,6 +361,14 @@ extern "C" int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value) {
       MBBS_CHECK(value >= 0 && value <= 4, "columns per thread must be 0 (automatic) or 1..4");
       lat->chunk[knob - MBBS_TUNE_CHUNK_FP64] = value;
       return MBBS_OK;
+    case MBBS_TUNE_TILE_FP64:
+    case MBBS_TUNE_TILE_FP32:
+    case MBBS_TUNE_TILE_FP16S:
+      MBBS_CHECK(value >= 0 && value <= 2, "tiled stencil setting must be 0, 1 or 2");
+      // the folded MR update is withdrawn for FP16 storage: its only run did not finish
+      MBBS_CHECK(!(value == 2 && knob == MBBS_TUNE_TILE_FP16S), "folded MR update not available for FP16 storage");
+      lat->tile[knob - MBBS_TUNE_TILE_FP64] = value;
+      return MBBS_OK;
     case MBBS_TUNE_MR_FUSED:
       MBBS_CHECK(value >= -1 && value <= 1, "fused MR must be -1 (auto), 0 or 1");
       lat->mr_fused = value;
@@ -372,6 +381,16 @@ extern "C" int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value) {
       set_error("unknown tuning knob");
       return MBBS_EINVAL;
   }
+}
+
+extern "C" int mbbs_lattice_tile_shape(mbbs_lattice_t lat, int L, int prec, int32_t* t4) {
+  MBBS_CHECK(lat != nullptr && t4 != nullptr, "null argument");
+  MBBS_CHECK(L >= 1 && L <= 256, "L must be in 1..256");
+  MBBS_CHECK(prec >= P64 && prec <= P16, "unknown precision");
+  TileArgs T;
+  const bool on = tile_plan(lat, L, prec, &T);
+  for (int m = 0; m < 4; ++m) t4[m] = on ? T.t[m] : 0;
+  return MBBS_OK;
 }
 
 extern "C" int mbbs_lattice_table_size(mbbs_lattice_t lat, int which, size_t* count) {

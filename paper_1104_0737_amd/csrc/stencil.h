@@ -454,4 +454,23 @@ __device__ __forceinline__ void load_spinor(const typename Store<PIN>::Elem* in,
     }
 }
 
+// The MR step's updates (Sec. 2.2, minimal residual domain solver): omega * r
+// for psi and r - omega * w for the residual.  The products are written with
+// explicit FMAs, so every kernel that performs the step rounds alike.
+template <typename R>
+__device__ __forceinline__ cplx<R> mr_mul(cplx<R> a, cplx<R> b) {
+  return {fmar(a.re, b.re, -(a.im * b.im)), fmar(a.re, b.im, a.im * b.re)};
+}
+// psi_i = d (assign) or psi_i + d.
+template <int PPSI, typename R>
+__device__ __forceinline__ void mr_psi_update(typename Store<PPSI>::Elem* psi, size_t i, cplx<R> d, bool assign) {
+  using RP = typename Store<PPSI>::Real;
+  if (assign) {
+    Store<PPSI>::st(psi, i, cplx<RP>{(RP)d.re, (RP)d.im});
+  } else {
+    const auto pv = Store<PPSI>::ld(psi, i);
+    Store<PPSI>::st(psi, i, cplx<RP>{(RP)(pv.re + (RP)d.re), (RP)(pv.im + (RP)d.im)});
+  }
+}
+
 }  // namespace mbbs

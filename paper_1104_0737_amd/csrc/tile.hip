@@ -1,0 +1,523 @@
+// LDS-tiled stencil kernels (Sec. 2.1, block hopping-term equation; Sec. 2.2,
+// the Dirichlet operator A_DD of the MR domain solve).  A workgroup owns one
+// tile of sites (a sub-block of a SAP domain) and all L columns: it copies
+// the tile's input spinors into LDS with full-width coalesced loads, then
+// every hop whose neighbour lies in the tile reads it from LDS and only the
+// hops that leave the tile read global memory.  Each spinor of the tile thus
+// passes the L1/L2 path once instead of once per neighbour.  A thread owns
+// one site and C columns and applies each link to all of them.  The per-site
+// arithmetic, hop order included, is that of the one-thread-per-site kernels,
+// so the operator's output bits are the same.
+#include "stencil.h"
+#include "tile.h"
+
+namespace mbbs {
+
+namespace {
+
+constexpr int TILE_THREADS = 768;   // at most 3 waves per SIMD: 168 VGPRs per lane
+
+// Origin of tile tb inside its domain, and the domain (rank among the
+// launch's domains).  Tiles are walked domain by domain, inside a domain in
+// lexicographic order of the tile grid.
+struct TilePos {
+  int base[4];
+  int dom;
+};
+
+__device__ __forceinline__ TilePos tile_pos(const GeomK& k, const TileArgs& T, int tb) {
+  TilePos p;
+  p.dom = tb / T.tpd;
+  int q = tb - p.dom * T.tpd;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int nt = k.g.b[m] / T.t[m];
+    const int r = q / nt;
+    p.base[m] = (q - r * nt) * T.t[m];
+    q = r;
+  }
+  return p;
+}
+
+// Index of the first site of row r (t[0] consecutive sites along x) of the
+// tile: domain-major index (DM) or index of the tiled lexicographic traversal
+// (LEX: domains in lexicographic order of the domain grid, then local
+// lexicographic order).
+__device__ __forceinline__ int tile_row_index(const GeomK& k, const TileArgs& T, const TilePos& p, int s0, int r) {
+  const int l1 = p.base[1] + r % T.t[1];
+  const int r2 = r / T.t[1];
+  const int l2 = p.base[2] + r2 % T.t[2];
+  const int l3 = p.base[3] + r2 / T.t[2];
+  const int loc = p.base[0] + k.g.b[0] * (l1 + k.g.b[1] * (l2 + k.g.b[2] * l3));
+  return s0 + p.dom * k.g.Vb + loc;
+}
+
+// C consecutive columns of element e of a spinor into the hop's registers
+// (column q at d.sp[(q * 12 + e) * per]); one 16- or 8-byte load where the
+// columns are adjacent and aligned (C = 2, L even, col0 even).
+template <int P, int C>
+__device__ __forceinline__ void ld_cols(const typename Store<P>::Elem* p, int e, typename RawT<P>::T* sp) {
+  constexpr int per = RawT<P>::per;
+  if constexpr (P == P32 && C == 2) {
+    const float4 v = *(const float4*)p;
+    sp[e * per] = v.x; sp[e * per + 1] = v.y;
+    sp[(12 + e) * per] = v.z; sp[(12 + e) * per + 1] = v.w;
+  } else if constexpr (P == P16 && C == 2) {
+    const uint2 v = *(const uint2*)p;
+    sp[e] = v.x; sp[12 + e] = v.y;
+  } else {
+#pragma unroll
+    for (int q = 0; q < C; ++q) raw_split<P>(p[q], &sp[(q * 12 + e) * per]);
+  }
+}
+
+// The new MR residual r - omega w of C columns of a site outside the tile,
+// formed from the previous residual and A r in global memory, in storage
+// format (FP16 storage: rounded and scaled as a store of it would be).
+template <int P, int C, typename R>
+__device__ __forceinline__ void mr_residual_cols(const typename Store<P>::Elem* qr, const float* qr_s,
+                                                 const typename Store<P>::Elem* qw, const float* qw_s, int L,
+                                                 const cplx<R> (&om)[C], HopData<P, P, C>& d) {
+  constexpr int per = RawT<P>::per;
+  if constexpr (!Store<P>::scaled) {
+    // element by element into the hop's registers (few values live at once)
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+      typename RawT<P>::T rr[C * 12 * per], ww[C * 12 * per];
+      ld_cols<P, C>(qr + (size_t)e * L, e, rr);
+      ld_cols<P, C>(qw + (size_t)e * L, e, ww);
+#pragma unroll
+      for (int q = 0; q < C; ++q) {
+        const cplx<R> rv = raw_join<P, R>(&rr[(q * 12 + e) * per]), wv = raw_join<P, R>(&ww[(q * 12 + e) * per]);
+        const cplx<R> v = rv - mr_mul(om[q], wv);
+        d.sp[(q * 12 + e) * per] = v.re;
+        d.sp[(q * 12 + e) * per + 1] = v.im;
+      }
+    }
+  } else {
+  typename RawT<P>::T rr[C * 12 * per], ww[C * 12 * per];
+#pragma unroll
+  for (int e = 0; e < 12; ++e) {
+    ld_cols<P, C>(qr + (size_t)e * L, e, rr);
+    ld_cols<P, C>(qw + (size_t)e * L, e, ww);
+  }
+#pragma unroll
+  for (int q = 0; q < C; ++q) {
+    const R scr = (R)qr_s[q], scw = (R)qw_s[q];
+    cplx<R> v[4][3];
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+      // dequantised as a load of the stored values would be
+      const cplx<R> a = raw_join<P, R>(&rr[(q * 12 + e) * per]), b = raw_join<P, R>(&ww[(q * 12 + e) * per]);
+      const cplx<R> rv = cmake<R>(a.re * scr, a.im * scr), wv = cmake<R>(b.re * scw, b.im * scw);
+      v[e / 3][e % 3] = rv - mr_mul(om[q], wv);
+    }
+    {
+      R m = 0;
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) m = fmaxf(m, fmaxf(fabsf(v[sp][a].re), fabsf(v[sp][a].im)));
+      const R inv = m > 0 ? (R)1 / m : (R)0;
+#pragma unroll
+      for (int e = 0; e < 12; ++e) {
+        const cplx<R> x = inv * v[e / 3][e % 3];
+        const __half2 h = __floats2half2_rn(x.re, x.im);
+        __builtin_memcpy(&d.sp[q * 12 + e], &h, sizeof(unsigned));
+      }
+      d.sc[q] = m;
+    }
+  }
+  }
+}
+
+// Arguments of the MR step with the previous step's update folded in.
+struct MrfArgs {
+  const void* w_old;     // A r of the previous step
+  const float* w_old_s;
+  void* r_new;           // receives r - omega w
+  float* r_new_s;
+  void* psi;             // psi (+)= omega r (previous step's r and omega)
+  const double* omega;   // previous step's omega per domain and column
+  int assign;
+};
+
+// One hop for the C columns of a thread: the neighbour's spinor from LDS when
+// it lies in the tile, else from global memory (HALO = 1: formed as the new MR
+// residual from the previous residual and A r there); the link from global
+// memory.
+template <int PIN, int PL, int C, int ORDER, int HOPS, int MU, int FWD, int HALO, typename R>
+__device__ __forceinline__ void hop_tiled(const GeomK& k, const SiteCtx& c, const TileArgs& T, const int (&lt)[4],
+                                          int ts, const typename Store<PIN>::Elem* __restrict__ in,
+                                          const float* __restrict__ in_s, const typename Store<PIN>::Elem* lds,
+                                          const float* lds_s, const LinkElem<PL>* __restrict__ U, int L, int col0,
+                                          const MrfArgs& mf, const cplx<R> (&om)[C],
+                                          cplx<R> (&acc)[4][3][C], R& token) {
+  if (hop_skipped<ORDER, HOPS, MU, FWD>(k, c)) return;
+  const bool inside = FWD ? lt[MU] < T.t[MU] - 1 : lt[MU] > 0;
+  // an in-tile neighbour lies in the same domain: no boundary is crossed
+  const int step = ORDER == DM ? k.lstride[MU] : k.stride[MU];
+  int sn = inside ? c.s + (FWD ? step : -step) : neighbour<ORDER>(k, c, MU, FWD ? 1 : -1);
+  int ls = FWD ? c.s : sn;
+  int tn = ts + (FWD ? T.tstr[MU] : -T.tstr[MU]);
+  // the hop's addresses wait for the previous hop (one hop's data in flight)
+  asm volatile("" : "+v"(sn), "+v"(ls), "+v"(tn) : "v"(token));
+  HopData<PIN, PL, C> d;
+  const LinkElem<PL>* lp = U + ((size_t)ls * 4 + MU) * 9;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) raw_split<PL>(lp[e], &d.lk[e * RawT<PL>::per]);
+  if (inside) {
+    const typename Store<PIN>::Elem* q = lds + (size_t)tn * 12 * L + col0;
+#pragma unroll
+    for (int e = 0; e < 12; ++e) ld_cols<PIN, C>(q + e * L, e, d.sp);
+    if constexpr (Store<PIN>::scaled) {
+#pragma unroll
+      for (int qq = 0; qq < C; ++qq) d.sc[qq] = lds_s[tn * L + col0 + qq];
+    }
+  } else if constexpr (HALO == 1) {
+    using E = typename Store<PIN>::Elem;
+    const size_t off = (size_t)sn * 12 * L + col0, soff = (size_t)sn * L + col0;
+    mr_residual_cols<PIN, C, R>(in + off, Store<PIN>::scaled ? in_s + soff : nullptr, (const E*)mf.w_old + off,
+                                Store<PIN>::scaled ? mf.w_old_s + soff : nullptr, L, om, d);
+  } else {
+    const typename Store<PIN>::Elem* q = in + (size_t)sn * 12 * L + col0;
+#pragma unroll
+    for (int e = 0; e < 12; ++e) ld_cols<PIN, C>(q + (size_t)e * L, e, d.sp);
+    if constexpr (Store<PIN>::scaled) {
+#pragma unroll
+      for (int qq = 0; qq < C; ++qq) d.sc[qq] = in_s[(size_t)sn * L + col0 + qq];
+    }
+  }
+  if constexpr (HALO == 0) hop_pin(d);
+  hop_compute<PIN, PL, C, HOPS, MU, FWD, R>(k, c, d, acc);
+  hop_settle(acc, token);
+}
+
+enum { OP_DSLASH = 0, OP_MR = 1, OP_MRF = 2 };
+
+// OP_DSLASH: out = in - kappa H in (HOPS: all hops or in-domain hops).
+// OP_MR: w = r - kappa H_DD r on one colour's domains (in = r, out = w), plus
+// the tile's per-column sums <w, r> and <w, w> (the MR step's partials).
+// OP_MRF: the previous MR step's update first (in = previous r; mf holds the
+// previous A r, omega and psi): psi (+)= omega r, r <- r - omega w (written to
+// mf.r_new), then OP_MR on the new r.  The new r of the tile is formed once,
+// in LDS; neighbours outside the tile form theirs from the previous r and A r.
+// Launch: one workgroup per tile, T.ts * L / C threads, T.lds bytes of LDS.
+template <int PIN, int PL, int C, int ORDER, int HOPS, int OP, int LT, int PPSI = PIN>
+__global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, int L, TileArgs T,
+                                                       const typename Store<PIN>::Elem* __restrict__ in,
+                                                       const float* __restrict__ in_s,
+                                                       typename Store<PIN>::Elem* __restrict__ out,
+                                                       float* __restrict__ out_s,
+                                                       const LinkElem<PL>* __restrict__ U, int s0,
+                                                       double* __restrict__ partial,
+                                                       const int* __restrict__ frozen, MrfArgs mf) {
+  if constexpr (LT > 0) L = LT;
+  using E = typename Store<PIN>::Elem;
+  using R = typename Store<PL>::Real;
+  extern __shared__ float4 tile_lds[];
+  __shared__ int row_site[256];
+  E* lds = (E*)tile_lds;
+  float* lds_s = (float*)(lds + (size_t)T.ts * 12 * L);
+  const int tb = xcd_block(blockIdx.x, gridDim.x);
+  const TilePos p = tile_pos(k, T, tb);
+  const int nrows = T.ts / T.t[0];
+  // a tile lies in one domain, hence one system: the flag test is block-uniform
+  {
+    const int i0 = tile_row_index(k, T, p, s0, 0);
+    const int sys = ORDER == DM ? site_ctx<DM>(k, i0).sys : site_ctx_tiled(k, i0).sys;
+    if (sys_frozen(k, frozen, sys)) return;
+  }
+  for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
+    const int i = tile_row_index(k, T, p, s0, r);
+    row_site[r] = ORDER == DM ? i : site_ctx_tiled(k, i).s;
+  }
+  __syncthreads();
+  // stage: each row of t[0] sites is contiguous in the field (all L columns)
+  {
+    const int row_f4 = T.t[0] * 12 * L * (int)sizeof(E) / 16;
+    for (int f = threadIdx.x; f < nrows * row_f4; f += blockDim.x) {
+      const int r = f / row_f4, w = f - r * row_f4;
+      tile_lds[f] = ((const float4*)(in + (size_t)row_site[r] * 12 * L))[w];
+    }
+    if constexpr (Store<PIN>::scaled) {
+      const int row_n = T.t[0] * L;
+      for (int f = threadIdx.x; f < nrows * row_n; f += blockDim.x) {
+        const int r = f / row_n, w = f - r * row_n;
+        lds_s[f] = in_s[(size_t)row_site[r] * L + w];
+      }
+    }
+  }
+  __syncthreads();
+  const int nchunk = L / C;
+  const int ts = threadIdx.x / nchunk;
+  const int col0 = (threadIdx.x - ts * nchunk) * C;
+  int lt[4];
+  {
+    int q = ts;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const int r = q / T.t[m];
+      lt[m] = q - r * T.t[m];
+      q = r;
+    }
+    lt[3] = q;
+  }
+  const int row = ts / T.t[0];
+  const SiteCtx c = ORDER == DM ? site_ctx<DM>(k, row_site[row] + lt[0])
+                                : site_ctx_tiled(k, tile_row_index(k, T, p, s0, row) + lt[0]);
+  const int s = c.s;
+  cplx<R> om[C];
+  if constexpr (OP == OP_MRF) {
+    // the previous step's update of this thread's site and columns
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const double* o = mf.omega + ((size_t)p.dom * L + col0 + q) * 2;
+      om[q] = cmake<R>((R)o[0], (R)o[1]);
+      const size_t lb = (size_t)ts * 12 * L + col0 + q, ls = (size_t)ts * L + col0 + q;
+      const size_t base = (size_t)s * 12 * L + col0 + q, sidx = (size_t)s * L + col0 + q;
+      cplx<R> rv[4][3], wv[4][3];
+      load_spinor<PIN, R>(lds, lds_s, lb, L, ls, rv);
+      load_spinor<PIN, R>((const E*)mf.w_old, mf.w_old_s, base, L, sidx, wv);
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          mr_psi_update<PPSI, R>((typename Store<PPSI>::Elem*)mf.psi, base + (size_t)(3 * sp + a) * L,
+                                 mr_mul(om[q], rv[sp][a]), mf.assign);
+          rv[sp][a] = rv[sp][a] - mr_mul(om[q], wv[sp][a]);
+        }
+      store_spinor<PIN, R>(lds, lds_s, lb, L, ls, rv);
+    }
+    __syncthreads();
+    // the tile's new r to global memory, row by row
+    const int row_f4 = T.t[0] * 12 * L * (int)sizeof(E) / 16;
+    for (int f = threadIdx.x; f < nrows * row_f4; f += blockDim.x) {
+      const int r = f / row_f4, w = f - r * row_f4;
+      ((float4*)((E*)mf.r_new + (size_t)row_site[r] * 12 * L))[w] = tile_lds[f];
+    }
+    if constexpr (Store<PIN>::scaled) {
+      const int row_n = T.t[0] * L;
+      for (int f = threadIdx.x; f < nrows * row_n; f += blockDim.x) {
+        const int r = f / row_n, w = f - r * row_n;
+        mf.r_new_s[(size_t)row_site[r] * L + w] = lds_s[f];
+      }
+    }
+  }
+  constexpr int HALO = OP == OP_MRF ? 1 : 0;
+  cplx<R> acc[4][3][C];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int q = 0; q < C; ++q) acc[sp][a][q] = cmake<R>(0, 0);
+  // the hops in the order of the one-thread-per-site kernels
+  R token = 0;
+  hop_tiled<PIN, PL, C, ORDER, HOPS, 0, 1, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, mf, om, acc, token);
+  hop_tiled<PIN, PL, C, ORDER, HOPS, 0, 0, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, mf, om, acc, token);
+  hop_tiled<PIN, PL, C, ORDER, HOPS, 1, 1, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, mf, om, acc, token);
+  hop_tiled<PIN, PL, C, ORDER, HOPS, 1, 0, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, mf, om, acc, token);
+  hop_tiled<PIN, PL, C, ORDER, HOPS, 2, 1, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, mf, om, acc, token);
+  hop_tiled<PIN, PL, C, ORDER, HOPS, 2, 0, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, mf, om, acc, token);
+  hop_tiled<PIN, PL, C, ORDER, HOPS, 3, 1, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, mf, om, acc, token);
+  hop_tiled<PIN, PL, C, ORDER, HOPS, 3, 0, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, mf, om, acc, token);
+  if (k.clov) clover_apply<ORDER, C, R>(k, s, acc);
+  const R kap = (R)kappa_of(k, c, kappa);
+  double sums[C][3];
+#pragma unroll
+  for (int q = 0; q < C; ++q) {
+    const size_t base = (size_t)s * 12 * L + col0 + q;
+    const size_t sidx = (size_t)s * L + col0 + q;
+    cplx<R> v[4][3], wv[4][3];
+    load_spinor<PIN, R>(lds, lds_s, (size_t)ts * 12 * L + col0 + q, L, (size_t)ts * L + col0 + q, v);
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) wv[sp][a] = v[sp][a] - kap * acc[sp][a][q];
+    if constexpr (OP == OP_DSLASH) {
+      if (k.nt_store) store_spinor<PIN, R, true>(out, out_s, base, L, sidx, wv);
+      else store_spinor<PIN, R>(out, out_s, base, L, sidx, wv);
+    } else {
+      store_spinor<PIN, R>(out, out_s, base, L, sidx, wv);
+      // the update must see the stored (rounded) w
+      if constexpr (Store<PIN>::scaled) load_spinor<PIN, R>(out, out_s, base, L, sidx, wv);
+      R a_re = 0, a_im = 0, a_ww = 0;
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const cplx<R> x = wv[sp][a], y = v[sp][a];
+          a_re = fmar(x.re, y.re, fmar(x.im, y.im, a_re));
+          a_im = fmar(x.re, y.im, fmar(-x.im, y.re, a_im));
+          a_ww = fmar(x.re, x.re, fmar(x.im, x.im, a_ww));
+        }
+      sums[q][0] = a_re; sums[q][1] = a_im; sums[q][2] = a_ww;
+    }
+  }
+  if constexpr (OP != OP_DSLASH) {
+    // per-column sums over the tile's sites in a fixed order, in two stages
+    // (G interleaved groups of sites, then the groups), through the LDS the
+    // tile's spinors no longer need
+    __syncthreads();
+    double* red = (double*)tile_lds;                 // [3][ts][L]
+    double* red2 = red + (size_t)3 * T.ts * L;       // [3][G][L]
+#pragma unroll
+    for (int q = 0; q < C; ++q)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) red[((size_t)m * T.ts + ts) * L + col0 + q] = sums[q][m];
+    __syncthreads();
+    const int G = T.ts >= 16 ? 16 : T.ts;
+    for (int e = threadIdx.x; e < 3 * G * L; e += blockDim.x) {
+      const int m = e / (G * L), rem = e - m * G * L, g = rem / L, col = rem - g * L;
+      double a = 0;
+      for (int y = g; y < T.ts; y += G) a += red[((size_t)m * T.ts + y) * L + col];
+      red2[((size_t)m * G + g) * L + col] = a;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 3 * L; e += blockDim.x) {
+      const int m = e / L, col = e - m * L;
+      double a = 0;
+      for (int g = 0; g < G; ++g) a += red2[((size_t)m * G + g) * L + col];
+      partial[((size_t)tb * L + col) * 3 + m] = a;
+    }
+  }
+}
+
+// Largest tile shape (of a fixed candidate list) that divides the SAP block,
+// keeps TS * L / C threads within one workgroup (and at least one wave), and
+// whose LDS (the spinors, or the reduction that reuses them) fits 160 KiB.
+bool pick_tile(const mbbs_lattice_s* lat, int L, int prec, TileArgs* out) {
+  static const int cand[][4] = {{4, 4, 4, 4}, {8, 4, 4, 2}, {4, 4, 4, 2}, {8, 4, 2, 2}, {4, 4, 2, 2},
+                                {8, 2, 2, 2}, {4, 2, 2, 2}, {2, 2, 2, 2}, {4, 4, 2, 1}, {2, 2, 2, 1},
+                                {2, 2, 1, 1}};
+  const int C = tile_cols(prec);
+  const size_t es = prec == P64 ? 16 : prec == P32 ? 8 : 4;
+  const Geom& g = lat->g;
+  if (L % C) return false;
+  for (const auto& t : cand) {
+    bool ok = true;
+    for (int m = 0; m < 4; ++m) ok = ok && g.b[m] % t[m] == 0;
+    if (!ok) continue;
+    const int ts = t[0] * t[1] * t[2] * t[3];
+    const int nthr = ts * (L / C);
+    if (nthr > TILE_THREADS || nthr < 64) continue;
+    if (ts / t[0] > 256) continue;
+    const size_t spin = (size_t)ts * 12 * L * es + (prec == P16 ? (size_t)ts * L * sizeof(float) : 0);
+    const int G = ts >= 16 ? 16 : ts;
+    const size_t red = (size_t)3 * (ts + G) * L * sizeof(double);
+    const size_t lds = std::max(spin, red);
+    if (lds + 256 * sizeof(int) > 160 * 1024) continue;
+    if (((size_t)t[0] * 12 * L * es) % 16) continue;
+    TileArgs T;
+    for (int m = 0; m < 4; ++m) T.t[m] = t[m];
+    T.ts = ts;
+    T.tstr[0] = 1;
+    for (int m = 1; m < 4; ++m) T.tstr[m] = T.tstr[m - 1] * t[m - 1];
+    T.tpd = g.Vb / ts;
+    T.lds = (unsigned)lds;
+    *out = T;
+    return true;
+  }
+  return false;
+}
+
+void allow_tile_lds(const void* fn) {
+  static const void* seen[64];
+  static int nseen = 0;
+  for (int i = 0; i < nseen; ++i)
+    if (seen[i] == fn) return;
+  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256 * (int)sizeof(int));
+  if (nseen < 64) seen[nseen++] = fn;
+}
+
+template <int P, int C, int ORDER, int HOPS, int OP, int PPSI = P>
+int launch_tile_t(const mbbs_lattice_s* lat, int L, const TileArgs& T, const void* in, const float* in_s,
+                  void* out, float* out_s, const void* U, int s0, int ntiles, double* partial, const int* frozen,
+                  hipStream_t st, const MrfArgs& mf = MrfArgs{}) {
+  using E = typename Store<P>::Elem;
+  using EL = LinkElem<P>;
+  GeomK gk = lat->gk;
+  gk.nt_store = lat->nt_store[P];
+  const dim3 blk(T.ts * (L / C)), grd(ntiles);
+  if (L == 12) {
+    auto fn = k_tile<P, P, C, ORDER, HOPS, OP, 12, PPSI>;
+    allow_tile_lds((const void*)fn);
+    hipLaunchKernelGGL(fn, grd, blk, T.lds, st, gk, lat->kappa, L, T, (const E*)in, in_s, (E*)out, out_s,
+                       (const EL*)U, s0, partial, frozen, mf);
+  } else {
+    auto fn = k_tile<P, P, C, ORDER, HOPS, OP, 0, PPSI>;
+    allow_tile_lds((const void*)fn);
+    hipLaunchKernelGGL(fn, grd, blk, T.lds, st, gk, lat->kappa, L, T, (const E*)in, in_s, (E*)out, out_s,
+                       (const EL*)U, s0, partial, frozen, mf);
+  }
+  MBBS_HIP(hipGetLastError());
+  return MBBS_OK;
+}
+
+template <int P>
+int dslash_tiled_p(const mbbs_lattice_s* lat, int L, int order, bool blocked, const TileArgs& T, const void* in,
+                   const float* in_s, void* out, float* out_s, int s0, int ntiles, const int* frozen,
+                   hipStream_t st) {
+  constexpr int C = P == P64 ? 1 : 2;
+  const void* U;
+  if (order == LEX) U = P == P64 ? (const void*)lat->U64 : P == P32 ? (const void*)lat->U32 : (const void*)lat->U16;
+  else U = P == P64 ? (const void*)lat->U64dm : P == P32 ? (const void*)lat->U32dm : (const void*)lat->U16dm;
+  if (order == LEX) {
+    if (blocked) return launch_tile_t<P, C, LEX, INSIDE, OP_DSLASH>(lat, L, T, in, in_s, out, out_s, U, 0, ntiles, nullptr, frozen, st);
+    return launch_tile_t<P, C, LEX, ALL, OP_DSLASH>(lat, L, T, in, in_s, out, out_s, U, 0, ntiles, nullptr, frozen, st);
+  }
+  if (blocked) return launch_tile_t<P, C, DM, INSIDE, OP_DSLASH>(lat, L, T, in, in_s, out, out_s, U, s0, ntiles, nullptr, frozen, st);
+  return launch_tile_t<P, C, DM, ALL, OP_DSLASH>(lat, L, T, in, in_s, out, out_s, U, s0, ntiles, nullptr, frozen, st);
+}
+
+}  // namespace
+
+bool tile_plan(const mbbs_lattice_s* lat, int L, int prec, TileArgs* out) {
+  if (lat->tile[prec] < 1) return false;
+  return pick_tile(lat, L, prec, out);
+}
+
+int launch_dslash_tiled(const mbbs_lattice_s* lat, int L, int prec, int order, bool blocked, const TileArgs& T,
+                        const void* in, const float* in_s, void* out, float* out_s, int s0, int n,
+                        const int* frozen, hipStream_t st) {
+  const int ntiles = n / T.ts;
+  if (ntiles <= 0) return MBBS_OK;
+  if (prec == P64) return dslash_tiled_p<P64>(lat, L, order, blocked, T, in, in_s, out, out_s, s0, ntiles, frozen, st);
+  if (prec == P32) return dslash_tiled_p<P32>(lat, L, order, blocked, T, in, in_s, out, out_s, s0, ntiles, frozen, st);
+  return dslash_tiled_p<P16>(lat, L, order, blocked, T, in, in_s, out, out_s, s0, ntiles, frozen, st);
+}
+
+int launch_mr_dslash_tiled(const mbbs_lattice_s* lat, int L, int prec, const TileArgs& T, const void* r,
+                           const float* r_s, void* w, float* w_s, int s0, int n, double* partial, const int* frozen,
+                           hipStream_t st) {
+  const int ntiles = n / T.ts;
+  if (ntiles <= 0) return MBBS_OK;
+  if (prec == P64)
+    return launch_tile_t<P64, 1, DM, INSIDE, OP_MR>(lat, L, T, r, r_s, w, w_s, lat->U64dm, s0, ntiles, partial, frozen, st);
+  if (prec == P32)
+    return launch_tile_t<P32, 2, DM, INSIDE, OP_MR>(lat, L, T, r, r_s, w, w_s, lat->U32dm, s0, ntiles, partial, frozen, st);
+  return launch_tile_t<P16, 2, DM, INSIDE, OP_MR>(lat, L, T, r, r_s, w, w_s, lat->U16dm, s0, ntiles, partial, frozen, st);
+}
+
+int launch_mr_fused_tiled(const mbbs_lattice_s* lat, int L, int prec, const TileArgs& T, const void* r_old,
+                          const float* r_old_s, const void* w_old, const float* w_old_s, void* r_new, float* r_new_s,
+                          void* w_new, float* w_new_s, void* psi, const double* omega, bool assign, int s0, int n,
+                          double* partial, const int* frozen, hipStream_t st) {
+  const int ntiles = n / T.ts;
+  if (ntiles <= 0) return MBBS_OK;
+  MrfArgs mf;
+  mf.w_old = w_old; mf.w_old_s = w_old_s; mf.r_new = r_new; mf.r_new_s = r_new_s;
+  mf.psi = psi; mf.omega = omega; mf.assign = assign ? 1 : 0;
+  if (prec == P64)
+    return launch_tile_t<P64, 1, DM, INSIDE, OP_MRF, P64>(lat, L, T, r_old, r_old_s, w_new, w_new_s, lat->U64dm, s0,
+                                                          ntiles, partial, frozen, st, mf);
+  if (prec == P32)
+    return launch_tile_t<P32, 2, DM, INSIDE, OP_MRF, P32>(lat, L, T, r_old, r_old_s, w_new, w_new_s, lat->U32dm, s0,
+                                                          ntiles, partial, frozen, st, mf);
+  // FP16 storage: withdrawn (its only run did not finish; no cause found)
+  set_error("folded MR update not available for FP16 storage");
+  return MBBS_EINVAL;
+}
+
+}  // namespace mbbs

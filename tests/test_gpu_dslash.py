@@ -168,7 +168,8 @@ def test_tuning_is_bit_identical():
         for prec in (0, 1, 2):
             ref = None
             settings = [c + (0, 0) for c in autotune.candidates(L, prec)] + autotune.operator_candidates(L, prec)
-            settings = [x for x in settings if len(x) < 6]   # other columns per thread: another summation order
+            # other columns per thread: another summation order
+            settings = [x for x in settings if len(x) < 6 or x[5] == 0]
             for setting in settings:
                 if setting[2]:
                     continue          # the split kernels sum the hops in another order
@@ -234,7 +235,7 @@ def test_block_threads_per_precision():
                 B.mbbs_lattice_tune(lat.h, B.TUNE_BLOCK_THREADS_PREC[1], bad)
             assert e.value.code == B.EINVAL
         with pytest.raises(B.MbbsError):
-            B.mbbs_lattice_tune(lat.h, 23, 128)            # no such knob
+            B.mbbs_lattice_tune(lat.h, 99, 128)            # no such knob
         for prec in (0, 1, 2):
             Y = torch.empty_like(X)
             B.mbbs_apply_dirac(lat.h, L, X, Y, prec)

@@ -1,0 +1,290 @@
+"""LDS-tiled stencil kernels (operator and MR Dirichlet step) on the GPU.
+
+The tiled operator sums the same hops in the same order as the
+one-thread-per-site kernels, so its output must match them bit for bit, in
+every precision, on the full and the Dirichlet operator, with a clover term
+and on a batch handle.  The tiled MR kernel sums <w, r> and <w, w> over
+tiles instead of thread blocks (another summation order), so SAP and whole
+solves with it are checked against the oracle at the usual tolerances, and a
+batch handle against its single handles bit for bit (both tiled).  With the
+MR update folded into the next step (setting 2) every value is computed as
+with the separate update (setting 1), so SAP must match it bit for bit.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import dirac, sap
+from paper_1104_0737_amd import inputs
+
+pytestmark = pytest.mark.gpu
+gu = pytest.importorskip("tests.gpu_util")
+torch = gu.torch
+B = gu.binding
+
+PH_TWIST = ((np.cos(0.3), np.sin(0.3)), (1.0, 0.0), (np.cos(1.1), -np.sin(1.1)), (-1.0, 0.0))
+TOL = {B.FP64: 1e-14, B.FP32: 1e-6, B.FP16S: 2e-3}
+SAP_TOL = {B.FP64: 1e-12, B.FP32: 3e-5, B.FP16S: 1e-2}
+
+
+def _set_tile(h, prec, on):
+    B.mbbs_lattice_tune(h, B.TUNE_TILE[prec], int(on))
+
+
+def test_tile_knob_and_shapes():
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    U = inputs.gauge_field(dims, 0.3, 400)
+    with gu.Lattice(dims, block, U, 0.12) as lat:
+        for prec in (0, 1, 2):
+            with pytest.raises(B.MbbsError) as e:
+                B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[prec], 3)
+            assert e.value.code == B.EINVAL
+        with pytest.raises(B.MbbsError) as e:
+            B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[2], 2)      # folded update: FP64 and FP32 only
+        assert e.value.code == B.EINVAL
+        for prec in (0, 1, 2):
+            _set_tile(lat.h, prec, 0)
+            assert B.mbbs_lattice_tile_shape(lat.h, 12, prec) == (0, 0, 0, 0)
+            _set_tile(lat.h, prec, 1)
+        # FP32 / FP16 storage: two columns per thread, so odd L has no tiled form
+        assert B.mbbs_lattice_tile_shape(lat.h, 5, 1) == (0, 0, 0, 0)
+        assert B.mbbs_lattice_tile_shape(lat.h, 5, 2) == (0, 0, 0, 0)
+        assert B.mbbs_lattice_tile_shape(lat.h, 5, 0) != (0, 0, 0, 0)
+        assert B.mbbs_lattice_tile_shape(lat.h, 12, 1) == (4, 4, 4, 2)
+        assert B.mbbs_lattice_tile_shape(lat.h, 12, 2) == (4, 4, 4, 2)
+        assert B.mbbs_lattice_tile_shape(lat.h, 12, 0) == (4, 4, 2, 2)
+        for L in (1, 4, 12, 16, 64):
+            for prec in (0, 1, 2):
+                t = B.mbbs_lattice_tile_shape(lat.h, L, prec)
+                assert all(x == 0 or block[m] % x == 0 for m, x in enumerate(t))
+
+
+OPERATOR_CASES = [((8, 8, 8, 8), (4, 4, 4, 4), 12), ((8, 8, 8, 8), (4, 4, 4, 4), 4),
+                  ((16, 8, 8, 8), (8, 4, 4, 4), 12), ((8, 8, 4, 8), (4, 4, 2, 4), 6),
+                  ((8, 8, 8, 8), (4, 4, 4, 4), 16), ((8, 8, 8, 8), (4, 4, 4, 4), 5)]
+
+
+@pytest.mark.parametrize("dims,block,L", OPERATOR_CASES)
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_tiled_operator_bit_identical(dims, block, L, prec):
+    gu.flush(f"tiled operator {dims} L={L} prec={prec}")
+    V = int(np.prod(dims))
+    U = inputs.gauge_field(dims, 0.35, 401)
+    X = inputs.gaussian_block(V, L, 402)
+    ref = dirac.apply_D(U, 0.1235, PH_TWIST, X, dims).reshape(12 * V, L)
+    with gu.Lattice(dims, block, U, 0.1235, PH_TWIST) as lat:
+        Xd = gu.dev(X)
+        outs = {}
+        for on in (0, 1):
+            _set_tile(lat.h, prec, on)
+            Y = torch.empty_like(Xd)
+            Yb = torch.empty_like(Xd)
+            B.mbbs_apply_dirac(lat.h, L, Xd, Y, prec)
+            B.mbbs_apply_blocked(lat.h, L, Xd, Yb, prec)
+            outs[on] = (gu.host(Y), gu.host(Yb))
+        tiled = B.mbbs_lattice_tile_shape(lat.h, L, prec) != (0, 0, 0, 0)
+    assert tiled == (L % 2 == 0 or prec == 0)
+    assert outs[1][0].tobytes() == outs[0][0].tobytes()
+    assert outs[1][1].tobytes() == outs[0][1].tobytes()
+    assert np.all(gu.rel_col_err(outs[1][0], ref) <= TOL[prec])
+    assert np.all(gu.max_elem_err(outs[1][0], ref) <= TOL[prec])
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_tiled_operator_clover_bit_identical(prec):
+    dims, block, L = (8, 8, 8, 8), (4, 4, 4, 4), 12
+    V = 4096
+    U = inputs.gauge_field(dims, 0.3, 403)
+    X = gu.dev(inputs.gaussian_block(V, L, 404))
+    with gu.Lattice(dims, block, U, 0.12) as lat:
+        B.mbbs_lattice_set_clover(lat.h, 1.3)
+        outs = []
+        for on in (0, 1):
+            _set_tile(lat.h, prec, on)
+            Y = torch.empty_like(X)
+            B.mbbs_apply_dirac(lat.h, L, X, Y, prec)
+            Yb = torch.empty_like(X)
+            B.mbbs_apply_blocked(lat.h, L, X, Yb, prec)
+            outs.append((gu.host(Y).tobytes(), gu.host(Yb).tobytes()))
+    assert outs[0] == outs[1]
+
+
+def _batch(dims, block, n, seed):
+    Us = [inputs.gauge_field(dims, 0.3, seed + k) for k in range(n)]
+    ks = [0.112 + 0.004 * k for k in range(n)]
+    singles = [gu.Lattice(dims, block, U, k, PH_TWIST) for U, k in zip(Us, ks)]
+    U_dev = [gu.dev(U) for U in Us]
+    h = B.mbbs_lattice_create_batch(dims, block, U_dev, ks, PH_TWIST)
+    return singles, U_dev, h
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_tiled_batch_operator_bit_identical(prec):
+    """Tiled batch handle (three systems stacked along t) against untiled
+    single handles: the same bits."""
+    dims, block, L = (8, 8, 4, 8), (4, 4, 2, 4), 12
+    V = int(np.prod(dims))
+    singles, U_dev, h = _batch(dims, block, 3, 410)
+    try:
+        _set_tile(h, prec, 1)
+        assert B.mbbs_lattice_tile_shape(h, L, prec) != (0, 0, 0, 0)
+        Xs = [inputs.gaussian_block(V, L, 420 + k) for k in range(3)]
+        Xst = gu.dev(np.concatenate(Xs))
+        Y = torch.empty_like(Xst)
+        Yb = torch.empty_like(Xst)
+        B.mbbs_apply_dirac(h, L, Xst, Y, prec)
+        B.mbbs_apply_blocked(h, L, Xst, Yb, prec)
+        Y, Yb = gu.host(Y), gu.host(Yb)
+        N = 12 * V
+        for k, (lat, X) in enumerate(zip(singles, Xs)):
+            _set_tile(lat.h, prec, 0)
+            Xd = gu.dev(X)
+            R = torch.empty_like(Xd)
+            Rb = torch.empty_like(Xd)
+            B.mbbs_apply_dirac(lat.h, L, Xd, R, prec)
+            B.mbbs_apply_blocked(lat.h, L, Xd, Rb, prec)
+            assert Y[k * N:(k + 1) * N].tobytes() == gu.host(R).tobytes(), k
+            assert Yb[k * N:(k + 1) * N].tobytes() == gu.host(Rb).tobytes(), k
+    finally:
+        for s in singles:
+            s.close()
+        B.mbbs_lattice_destroy(h)
+
+
+SAP_CASES = [((8, 8, 8, 8), (4, 4, 4, 4), 12, 3, 4), ((16, 8, 8, 8), (8, 4, 4, 4), 12, 2, 3),
+             ((8, 8, 8, 8), (4, 4, 4, 4), 4, 4, 4), ((8, 8, 4, 8), (4, 4, 2, 4), 6, 2, 2)]
+
+
+@pytest.mark.parametrize("dims,block,L,ncy,nmr", SAP_CASES)
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_tiled_sap_parity(dims, block, L, ncy, nmr, prec):
+    """SAP with the tiled MR kernel (three launches per MR step) against the
+    oracle; the untiled kernels on the same input agree to the same bound."""
+    gu.flush(f"tiled sap {dims} L={L} prec={prec}")
+    V = int(np.prod(dims))
+    U = inputs.gauge_field(dims, 0.3, 430)
+    eta = inputs.gaussian_block(V, L, 431)
+    dom = sap.Domains(dims, block)
+    ref = sap.sap(U, 0.12, gu.PH_AP, dom, eta, ncy, nmr).reshape(12 * V, L)
+    with gu.Lattice(dims, block, U, 0.12) as lat:
+        B.mbbs_lattice_tune(lat.h, B.TUNE_MR_FUSED, 0)
+        ws = torch.empty(B.mbbs_sap_workspace_size(lat.h, L, prec), dtype=torch.uint8, device="cuda")
+        got = {}
+        for on in (1, 0):
+            _set_tile(lat.h, prec, on)
+            assert (B.mbbs_lattice_tile_shape(lat.h, L, prec) != (0, 0, 0, 0)) == bool(on)
+            Yd = torch.empty((12 * V, L), dtype=torch.complex128, device="cuda")
+            B.mbbs_sap_apply(lat.h, L, gu.dev(eta), Yd, ncy, nmr, prec, ws)
+            got[on] = gu.host(Yd)
+    for on in (1, 0):
+        assert np.all(gu.rel_col_err(got[on], ref) <= SAP_TOL[prec]), on
+        assert np.all(gu.max_elem_err(got[on], ref) <= SAP_TOL[prec]), on
+
+
+FP16_FOLDED = pytest.mark.skip(reason="the FP16-storage form of the folded MR update did not finish on its only "
+                                      "GPU run (ncy = nmr = 2); no cause was found in the code, the form is "
+                                      "withdrawn (the knob rejects it) and the case stays off the GPU until a "
+                                      "cause is shown")
+
+
+@pytest.mark.parametrize("ncy,nmr", [(1, 1), (2, 2), (1, 3), (3, 4)])
+@pytest.mark.parametrize("prec", [0, 1, pytest.param(2, marks=FP16_FOLDED)])
+def test_fused_update_sap_bit_identical(ncy, nmr, prec):
+    """MR update folded into the next step (setting 2) against the separate
+    update (setting 1): the same bits, and the oracle's result within the
+    precision's bound."""
+    gu.flush(f"fused-update sap ncy={ncy} nmr={nmr} prec={prec}")
+    dims, block, L = (8, 8, 8, 8), (4, 4, 4, 4), 12
+    V = 4096
+    U = inputs.gauge_field(dims, 0.3, 433)
+    eta = inputs.gaussian_block(V, L, 434)
+    ref = sap.sap(U, 0.12, gu.PH_AP, sap.Domains(dims, block), eta, ncy, nmr).reshape(12 * V, L)
+    with gu.Lattice(dims, block, U, 0.12) as lat:
+        B.mbbs_lattice_tune(lat.h, B.TUNE_MR_FUSED, 0)
+        ws = torch.empty(B.mbbs_sap_workspace_size(lat.h, L, prec), dtype=torch.uint8, device="cuda")
+        got = {}
+        for setting in (2, 1):
+            B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[prec], setting)
+            Yd = torch.empty((12 * V, L), dtype=torch.complex128, device="cuda")
+            B.mbbs_sap_apply(lat.h, L, gu.dev(eta), Yd, ncy, nmr, prec, ws)
+            got[setting] = gu.host(Yd)
+    assert got[2].tobytes() == got[1].tobytes()
+    assert np.all(gu.rel_col_err(got[2], ref) <= SAP_TOL[prec])
+    assert np.all(gu.max_elem_err(got[2], ref) <= SAP_TOL[prec])
+
+
+def test_tiled_sap_point_source():
+    """Point sources: most domains hold an exactly zero residual (the omega = 0
+    branch), in every precision."""
+    dims, block, L = (8, 8, 8, 8), (4, 4, 4, 4), 4
+    V = 4096
+    U = inputs.gauge_field(dims, 0.3, 432)
+    eta = inputs.point_sources(V, L, 0, 0)
+    dom = sap.Domains(dims, block)
+    ref = sap.sap(U, 0.11, gu.PH_AP, dom, eta, 4, 4).reshape(12 * V, L)
+    with gu.Lattice(dims, block, U, 0.11) as lat:
+        B.mbbs_lattice_tune(lat.h, B.TUNE_MR_FUSED, 0)
+        for prec in (0, 1, 2):
+            for setting in (1, 2) if prec != 2 else (1,):
+                B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[prec], setting)
+                ws = torch.empty(B.mbbs_sap_workspace_size(lat.h, L, prec), dtype=torch.uint8, device="cuda")
+                Yd = torch.empty((12 * V, L), dtype=torch.complex128, device="cuda")
+                B.mbbs_sap_apply(lat.h, L, gu.dev(eta), Yd, 4, 4, prec, ws)
+                assert np.all(gu.rel_col_err(gu.host(Yd), ref) <= SAP_TOL[prec]), (prec, setting)
+
+
+@pytest.mark.parametrize("prec,setting", [(0, 1), (0, 2), (1, 1), (1, 2), (2, 1),
+                                          pytest.param(2, 2, marks=FP16_FOLDED)])
+def test_tiled_batch_sap_bit_identical(prec, setting):
+    dims, block, L = (8, 8, 4, 8), (4, 4, 2, 4), 12
+    V = int(np.prod(dims))
+    singles, U_dev, h = _batch(dims, block, 3, 440)
+    try:
+        B.mbbs_lattice_tune(h, B.TUNE_MR_FUSED, 0)
+        B.mbbs_lattice_tune(h, B.TUNE_TILE[prec], setting)
+        etas = [inputs.gaussian_block(V, L, 450 + k) for k in range(3)]
+        ws = torch.empty(B.mbbs_sap_workspace_size(h, L, prec), dtype=torch.uint8, device="cuda")
+        Y = torch.empty((3 * 12 * V, L), dtype=torch.complex128, device="cuda")
+        B.mbbs_sap_apply(h, L, gu.dev(np.concatenate(etas)), Y, 3, 4, prec, ws)
+        Y = gu.host(Y)
+        N = 12 * V
+        for k, (lat, eta) in enumerate(zip(singles, etas)):
+            B.mbbs_lattice_tune(lat.h, B.TUNE_MR_FUSED, 0)
+            B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[prec], 1)
+            ws1 = torch.empty(B.mbbs_sap_workspace_size(lat.h, L, prec), dtype=torch.uint8, device="cuda")
+            R = torch.empty((N, L), dtype=torch.complex128, device="cuda")
+            B.mbbs_sap_apply(lat.h, L, gu.dev(eta), R, 3, 4, prec, ws1)
+            assert Y[k * N:(k + 1) * N].tobytes() == gu.host(R).tobytes(), k
+    finally:
+        for s in singles:
+            s.close()
+        B.mbbs_lattice_destroy(h)
+
+
+@pytest.mark.parametrize("sap_prec", [1, 2])
+def test_tiled_solve_matches_untiled(sap_prec):
+    """Whole solves with every tiled kernel on: converged, true residual
+    within the tolerance, and the solution equal to the untiled solve's within
+    what the two tolerances allow."""
+    dims, block, L = (8, 8, 8, 8), (4, 4, 4, 4), 12
+    V = 4096
+    U = inputs.gauge_field(dims, 0.3, 460)
+    Bm = inputs.gaussian_block(V, L, 461)
+    tol = 1e-10
+    xs = {}
+    with gu.Lattice(dims, block, U, 0.125) as lat:
+        B.mbbs_lattice_tune(lat.h, B.TUNE_MR_FUSED, 0)
+        for on in (2, 0):
+            for p in (0, 1, 2):
+                B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[p], min(on, 1) if p == 2 else on)
+            params = B.mbbs_solve_params_default(tol=tol, maxiter=200, sap_prec=sap_prec)
+            ws = torch.empty(B.mbbs_solve_workspace_size(lat.h, L, params), dtype=torch.uint8, device="cuda")
+            X = torch.zeros((12 * V, L), dtype=torch.complex128, device="cuda")
+            info = B.mbbs_solve(lat.h, L, gu.dev(Bm), X, params, ws)
+            assert info["status"] == 0, info
+            assert np.all(info["true_res"] <= tol), info["true_res"]
+            xs[on] = gu.host(X)
+            res = dirac.apply_D(U, 0.125, gu.PH_AP, xs[on], dims).reshape(12 * V, L) - Bm
+            assert np.all(np.linalg.norm(res, axis=0) <= 1.01 * tol * np.linalg.norm(Bm, axis=0)), on
+    d = np.linalg.norm(xs[2] - xs[0], axis=0) / np.linalg.norm(xs[0], axis=0)
+    assert np.all(d <= 1e-8), d
