@@ -241,7 +241,10 @@ int mbbs_apply_blocked(mbbs_lattice_t lat, int L, const double* X_dev, double* Y
  * by nmr minimal-residual steps from zero (one step size per domain and
  * column).  X_dev, Y_dev: FP64 lexicographic blocks; the preconditioner runs
  * in `prec` in domain-major order; Y is the FP64 image of the result.
- * ws_dev must hold mbbs_sap_workspace_size bytes (caller-owned). */
+ * ws_dev must hold mbbs_sap_workspace_size bytes (caller-owned).  The size
+ * depends on the lattice's MBBS_TUNE_TILE_* setting of `prec` (2: two more
+ * fields); a workspace sized without it still serves (the MR steps then run
+ * unfolded). */
 int mbbs_sap_workspace_size(mbbs_lattice_t lat, int L, int prec, size_t* bytes);
 int mbbs_sap_apply(mbbs_lattice_t lat, int L, const double* X_dev, double* Y_dev,
                    int ncy, int nmr, int prec, void* ws_dev, size_t ws_bytes, void* stream);

@@ -130,10 +130,11 @@ def tune_sap(lat, V, L, prec, op_times, stream=None, ncy=4, nmr=4, reps=2):
     X = torch.zeros((12 * V, L), dtype=torch.complex128, device=dev)
     X[::7] = 1.0
     Y = torch.empty_like(X)
-    ws = torch.empty(B.mbbs_sap_workspace_size(lat, L, prec), dtype=torch.uint8, device=dev)
     times = {}
     for setting in cands:
         apply(lat, prec, setting)
+        # the workspace depends on the setting (the folded MR update needs more)
+        ws = torch.empty(B.mbbs_sap_workspace_size(lat, L, prec), dtype=torch.uint8, device=dev)
         B.mbbs_sap_apply(lat, L, X, Y, ncy, nmr, prec, ws, stream=s)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s)
@@ -142,7 +143,8 @@ def tune_sap(lat, V, L, prec, op_times, stream=None, ncy=4, nmr=4, reps=2):
         e1.record(s)
         e1.synchronize()
         times[setting] = e0.elapsed_time(e1) / reps
+        del ws
     best = min(times, key=times.get)
     apply(lat, prec, best)
-    del X, Y, ws
+    del X, Y
     return best, times

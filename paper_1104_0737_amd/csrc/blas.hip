@@ -42,12 +42,8 @@ __global__ void __launch_bounds__(256) k_gram(int L, size_t N, GramArgs a, doubl
   constexpr int NP = NF + ND;
   const int sys = blockIdx.y;
   if (frozen && frozen[sys * fstride]) return;
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    a.X[p] += (size_t)sys * N * L;
-    a.Y[p] += (size_t)sys * N * L;
-  }
-  partial += (size_t)sys * gridDim.x * GRAM_MAXPAIR * L * L;
+  // the system's rows: [sys N, sys N + N) of the stacked blocks
+  const size_t nbeg = (size_t)sys * N, nend = nbeg + N;
   extern __shared__ double2 sh[];  // [2][GRAM_MAXPAIR][S][L] Y rows, reused for the reduction
   const int j = threadIdx.x, y = threadIdx.y, S = blockDim.y;
   cplx<double> acc[NF > 0 ? NF : 1][LMAX];
@@ -60,7 +56,7 @@ __global__ void __launch_bounds__(256) k_gram(int L, size_t N, GramArgs a, doubl
   for (int p = 0; p < (ND > 0 ? ND : 1); ++p) dacc[p] = cmake(0.0, 0.0);
   const size_t stride = (size_t)gridDim.x * S;
   int buf = 0;   // two row buffers: one barrier per row tile
-  for (size_t n0 = (size_t)blockIdx.x * S; n0 < N; n0 += stride, buf ^= 1) {
+  for (size_t n0 = nbeg + (size_t)blockIdx.x * S; n0 < nend; n0 += stride, buf ^= 1) {
     const size_t n = n0 + y;
     cplx<double> xv[NP];
     double2 yv[NP];
@@ -68,7 +64,7 @@ __global__ void __launch_bounds__(256) k_gram(int L, size_t N, GramArgs a, doubl
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       double2 xe = make_double2(0, 0), ye = make_double2(0, 0);
-      if (n < N) {
+      if (n < nend) {
         xe = a.X[p][n * L + j];
         ye = a.Y[p][n * L + j];
       }
@@ -94,6 +90,7 @@ __global__ void __launch_bounds__(256) k_gram(int L, size_t N, GramArgs a, doubl
     }
   }
   // reduce over y one output column at a time: sh reused as [S][L]
+  partial += (size_t)blockIdx.y * gridDim.x * GRAM_MAXPAIR * L * L;   // the system's partials
 #pragma unroll
   for (int p = 0; p < NF; ++p) {
     double2* out = partial + ((size_t)blockIdx.x * GRAM_MAXPAIR + p) * L * L;
@@ -153,13 +150,11 @@ __global__ void __launch_bounds__(256) k_combo(int L, size_t N, ComboArgs a, dou
   if constexpr (EXACT) L = LMAX;
   const int sys = blockIdx.y;
   if (frozen && frozen[sys * fstride]) return;
-  out += (size_t)sys * N * L;
+  // the system's rows and coefficients: offsets added where the argument
+  // block is read (writing to it would move it to scratch memory)
+  const size_t roff = (size_t)sys * N * L;
+  out += roff;
   if (partial) partial += (size_t)sys * gridDim.x * GRAM_MAXPAIR * L * L;
-  for (int k = 0; k < a.nin; ++k) {
-    a.in[k] += (size_t)sys * N * L;
-    if (a.mode[k] == 1) a.coef[k] += sys;
-    else if (a.mode[k] == 2) a.coef[k] += (size_t)sys * L * L;
-  }
   extern __shared__ double2 sh[];  // [nmat][S][L] rows, then [nmat][L][L] coefficients
   const int j = threadIdx.x, y = threadIdx.y, S = blockDim.y;
   const int tid = y * L + j, nthr = L * S;
@@ -167,7 +162,7 @@ __global__ void __launch_bounds__(256) k_combo(int L, size_t N, ComboArgs a, dou
   double2* mats = sh + (size_t)COMBO_MAXIN * S * L;
   for (int k = 0; k < nin; ++k)
     if (a.mode[k] == 2)
-      for (int e = tid; e < L * L; e += nthr) mats[(size_t)k * L * L + e] = a.coef[k][e];
+      for (int e = tid; e < L * L; e += nthr) mats[(size_t)k * L * L + e] = a.coef[k][(size_t)sys * L * L + e];
   cplx<double> g[LMAX];
 #pragma unroll
   for (int q = 0; q < LMAX; ++q) g[q] = cmake(0.0, 0.0);
@@ -183,11 +178,11 @@ __global__ void __launch_bounds__(256) k_combo(int L, size_t N, ComboArgs a, dou
     cplx<double> acc = cmake(0.0, 0.0);
     for (int k = 0; k < nin; ++k) {
       if (a.mode[k] == 2) {
-        sh[((size_t)k * S + y) * L + j] = n < N ? a.in[k][n * L + j] : make_double2(0, 0);
+        sh[((size_t)k * S + y) * L + j] = n < N ? a.in[k][roff + n * L + j] : make_double2(0, 0);
       } else if (n < N) {
-        double2 v = a.in[k][n * L + j];
+        double2 v = a.in[k][roff + n * L + j];
         if (a.mode[k] == 0) acc = acc + cmake(v.x, v.y);
-        else acc = acc + cmake(a.coef[k][0].x, a.coef[k][0].y) * cmake(v.x, v.y);
+        else acc = acc + cmake(a.coef[k][sys].x, a.coef[k][sys].y) * cmake(v.x, v.y);
       }
     }
     if (anymat) __syncthreads();
@@ -561,9 +556,11 @@ static void launch_gram_l(int L, size_t N, const GramArgs& a, double2* partial, 
   while (nf < a.npair && !a.diag[nf]) ++nf;
   const int nd = a.npair - nf;
   const dim3 grd(nb, sb.n);
+  // two full products with L fixed at compile time need more than 128 VGPRs
+  // (3 waves per SIMD instead of 4): they take the run-time-L form
 #define GL(F, D)                                                                                         \
   do {                                                                                                   \
-    if (L == LMAX)                                                                                       \
+    if (L == LMAX && !(F == 2 && LMAX == 12))                                                            \
       hipLaunchKernelGGL((k_gram<LMAX, F, D, true>), grd, dim3(L, S), shb, st, L, N, a, partial, frozen, sb.fstride); \
     else                                                                                                 \
       hipLaunchKernelGGL((k_gram<LMAX, F, D>), grd, dim3(L, S), shb, st, L, N, a, partial, frozen, sb.fstride);     \

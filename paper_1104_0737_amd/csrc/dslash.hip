@@ -918,7 +918,10 @@ int launch_dslash(const mbbs_lattice_s* lat, int L, int prec_in, int prec_out, i
 }
 
 // ---------------------------------------------------------------- SAP host
-size_t sap_buffer_bytes(const mbbs_lattice_s* lat, int L, int prec, bool ssor) {
+// Whether the MR steps of this precision fold the previous step's update in.
+static bool folded_mr(const mbbs_lattice_s* lat, int prec) { return lat->tile[prec] == 2 && prec != P16; }
+
+static size_t sap_bytes(const mbbs_lattice_s* lat, int L, int prec, bool ssor, bool folded) {
   const size_t V = lat->g.V;
   const size_t elem = prec == P64 ? 16 : prec == P32 ? 8 : 4;
   const size_t field = V * 12 * L * elem;
@@ -927,14 +930,22 @@ size_t sap_buffer_bytes(const mbbs_lattice_s* lat, int L, int prec, bool ssor) {
   const size_t ndc = lat->g.ndom / 2;             // domains per colour
   const size_t nblk = lat->g.Vh;                  // upper bound on blocks per colour
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t nf = ssor ? 4 : 5;   // eta, r, w and x2 (SSOR) or a second r and w (MR)
+  // eta, r, w; x2 (SSOR); a second r and w for the folded MR update (tiled,
+  // setting 2: included only while that setting is on)
+  const size_t nf = ssor ? 4 : (folded ? 5 : 3);
   return al(field) * nf + al(scales) * nf + al(psi) + al(nblk * L * 3 * sizeof(double)) +
          al(ndc * L * 2 * sizeof(double));
 }
 
+size_t sap_buffer_bytes(const mbbs_lattice_s* lat, int L, int prec, bool ssor) {
+  return sap_bytes(lat, L, prec, ssor, !ssor && folded_mr(lat, prec));
+}
+
 int sap_bind(const mbbs_lattice_s* lat, int L, int prec, void* ws, size_t bytes, SapBuffers* b, bool ssor) {
-  const size_t need = sap_buffer_bytes(lat, L, prec, ssor);
-  MBBS_CHECK(ws != nullptr && bytes >= need, "SAP workspace too small");
+  // the folded MR update's buffers are bound only if the workspace holds
+  // them (sized while that setting was on); otherwise the MR steps run unfolded
+  const bool folded = !ssor && folded_mr(lat, prec);
+  MBBS_CHECK(ws != nullptr && bytes >= sap_bytes(lat, L, prec, ssor, false), "SAP workspace too small");
   const size_t V = lat->g.V;
   const size_t elem = prec == P64 ? 16 : prec == P32 ? 8 : 4;
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -958,11 +969,11 @@ int sap_bind(const mbbs_lattice_s* lat, int L, int prec, void* ws, size_t bytes,
   if (ssor) {
     b->x2 = p; p += field;
     b->x2_s = prec == P16 ? (float*)p : nullptr; p += scales;
-  } else {
+  } else if (folded && bytes >= sap_bytes(lat, L, prec, false, true)) {
     b->r2 = p; p += field;
-    b->r2_s = prec == P16 ? (float*)p : nullptr; p += scales;
+    b->r2_s = nullptr; p += scales;
     b->w2 = p; p += field;
-    b->w2_s = prec == P16 ? (float*)p : nullptr; p += scales;
+    b->w2_s = nullptr; p += scales;
   }
   return MBBS_OK;
 }

@@ -150,6 +150,44 @@ __device__ __forceinline__ void pin_regs(T (&s)[NS], U (&l)[NL]) {
   }
 }
 
+// The 9 elements of link (site ls, direction MU) in storage format.  The four
+// links of a site are contiguous and the site's record is 16-byte aligned
+// (288 bytes in FP32, 144 in FP16 storage), so a link is read with 16-byte
+// loads of the aligned window that holds it (5 loads for 72 bytes in FP32, 3
+// for 36 in FP16; FP64 elements are 16 bytes already) instead of one load
+// per element: fewer memory instructions for the same cache lines.
+template <int PL, int MU>
+__device__ __forceinline__ void link_load(const LinkElem<PL>* __restrict__ U, int ls,
+                                          typename RawT<PL>::T* __restrict__ lk) {
+  if constexpr (PL == P32) {
+    constexpr int off = MU & 1;                       // window starts 8 bytes early for odd MU
+    const float4* w = (const float4*)(U + (size_t)ls * 36 + 9 * MU - off);
+    float win[20];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      const float4 v = w[i];
+      win[4 * i] = v.x; win[4 * i + 1] = v.y; win[4 * i + 2] = v.z; win[4 * i + 3] = v.w;
+    }
+#pragma unroll
+    for (int e = 0; e < 18; ++e) lk[e] = win[2 * off + e];
+  } else if constexpr (PL == P16) {
+    constexpr int off = (9 * MU) & 3;                 // window: 12 elements from a 16-byte boundary
+    const uint4* w = (const uint4*)(U + (size_t)ls * 36 + 9 * MU - off);
+    unsigned win[12];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const uint4 v = w[i];
+      win[4 * i] = v.x; win[4 * i + 1] = v.y; win[4 * i + 2] = v.z; win[4 * i + 3] = v.w;
+    }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) lk[e] = win[off + e];
+  } else {
+    const LinkElem<PL>* lp = U + ((size_t)ls * 4 + MU) * 9;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) raw_split<PL>(lp[e], &lk[e * RawT<PL>::per]);
+  }
+}
+
 template <int PIN, int PL, int C>
 struct HopData {
   typename RawT<PIN>::T sp[C * 12 * RawT<PIN>::per];   // column-major: column q at q * 12 * per
@@ -163,9 +201,7 @@ __device__ __forceinline__ void hop_load(int sn, int ls, const typename Store<PI
                                          int L, int col0, HopData<PIN, PL, C>& d) {
   // the link first: loads complete in order, and the arithmetic on the first
   // spinor elements needs the link
-  const LinkElem<PL>* lp = U + ((size_t)ls * 4 + MU) * 9;
-#pragma unroll
-  for (int e = 0; e < 9; ++e) raw_split<PL>(lp[e], &d.lk[e * RawT<PL>::per]);
+  link_load<PL, MU>(U, ls, d.lk);
 #pragma unroll
   for (int q = 0; q < C; ++q) {
     const size_t base = (size_t)sn * 12 * L + col0 + q;

@@ -17,6 +17,11 @@ namespace {
 
 constexpr int TILE_THREADS = 768;   // at most 3 waves per SIMD: 168 VGPRs per lane
 
+// LDS stride of a tile site in elements: the site's 12 L elements and 16
+// bytes of padding, so that the sites a wave reads start in different banks.
+template <typename E>
+__device__ __forceinline__ int tile_ss(int L) { return 12 * L + 16 / (int)sizeof(E); }
+
 // Origin of tile tb inside its domain, and the domain (rank among the
 // launch's domains).  Tiles are walked domain by domain, inside a domain in
 // lexicographic order of the tile grid.
@@ -58,13 +63,19 @@ __device__ __forceinline__ int tile_row_index(const GeomK& k, const TileArgs& T,
 template <int P, int C>
 __device__ __forceinline__ void ld_cols(const typename Store<P>::Elem* p, int e, typename RawT<P>::T* sp) {
   constexpr int per = RawT<P>::per;
-  if constexpr (P == P32 && C == 2) {
-    const float4 v = *(const float4*)p;
-    sp[e * per] = v.x; sp[e * per + 1] = v.y;
-    sp[(12 + e) * per] = v.z; sp[(12 + e) * per + 1] = v.w;
-  } else if constexpr (P == P16 && C == 2) {
-    const uint2 v = *(const uint2*)p;
-    sp[e] = v.x; sp[12 + e] = v.y;
+  if constexpr (P == P32 && C % 2 == 0) {
+#pragma unroll
+    for (int j = 0; j < C / 2; ++j) {
+      const float4 v = *(const float4*)(p + 2 * j);
+      sp[(2 * j * 12 + e) * per] = v.x; sp[(2 * j * 12 + e) * per + 1] = v.y;
+      sp[((2 * j + 1) * 12 + e) * per] = v.z; sp[((2 * j + 1) * 12 + e) * per + 1] = v.w;
+    }
+  } else if constexpr (P == P16 && C % 2 == 0) {
+#pragma unroll
+    for (int j = 0; j < C / 2; ++j) {
+      const uint2 v = *(const uint2*)(p + 2 * j);
+      sp[2 * j * 12 + e] = v.x; sp[(2 * j + 1) * 12 + e] = v.y;
+    }
   } else {
 #pragma unroll
     for (int q = 0; q < C; ++q) raw_split<P>(p[q], &sp[(q * 12 + e) * per]);
@@ -163,11 +174,9 @@ __device__ __forceinline__ void hop_tiled(const GeomK& k, const SiteCtx& c, cons
   // the hop's addresses wait for the previous hop (one hop's data in flight)
   asm volatile("" : "+v"(sn), "+v"(ls), "+v"(tn) : "v"(token));
   HopData<PIN, PL, C> d;
-  const LinkElem<PL>* lp = U + ((size_t)ls * 4 + MU) * 9;
-#pragma unroll
-  for (int e = 0; e < 9; ++e) raw_split<PL>(lp[e], &d.lk[e * RawT<PL>::per]);
+  link_load<PL, MU>(U, ls, d.lk);
   if (inside) {
-    const typename Store<PIN>::Elem* q = lds + (size_t)tn * 12 * L + col0;
+    const typename Store<PIN>::Elem* q = lds + (size_t)tn * tile_ss<typename Store<PIN>::Elem>(L) + col0;
 #pragma unroll
     for (int e = 0; e < 12; ++e) ld_cols<PIN, C>(q + e * L, e, d.sp);
     if constexpr (Store<PIN>::scaled) {
@@ -218,7 +227,8 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
   extern __shared__ float4 tile_lds[];
   __shared__ int row_site[256];
   E* lds = (E*)tile_lds;
-  float* lds_s = (float*)(lds + (size_t)T.ts * 12 * L);
+  const int SS = tile_ss<E>(L);
+  float* lds_s = (float*)(lds + (size_t)T.ts * SS);
   const int tb = xcd_block(blockIdx.x, gridDim.x);
   const TilePos p = tile_pos(k, T, tb);
   const int nrows = T.ts / T.t[0];
@@ -233,12 +243,14 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
     row_site[r] = ORDER == DM ? i : site_ctx_tiled(k, i).s;
   }
   __syncthreads();
-  // stage: each row of t[0] sites is contiguous in the field (all L columns)
+  // stage: each row of t[0] sites is contiguous in the field (all L columns);
+  // LDS holds site ts at ts * SS elements
+  const int site_f4 = 12 * L * (int)sizeof(E) / 16, ss_f4 = SS * (int)sizeof(E) / 16;
   {
-    const int row_f4 = T.t[0] * 12 * L * (int)sizeof(E) / 16;
-    for (int f = threadIdx.x; f < nrows * row_f4; f += blockDim.x) {
-      const int r = f / row_f4, w = f - r * row_f4;
-      tile_lds[f] = ((const float4*)(in + (size_t)row_site[r] * 12 * L))[w];
+    for (int f = threadIdx.x; f < T.ts * site_f4; f += blockDim.x) {
+      const int t = f / site_f4, w = f - t * site_f4;
+      const int r = t / T.t[0], x = t - r * T.t[0];
+      tile_lds[t * ss_f4 + w] = ((const float4*)in)[(size_t)(row_site[r] + x) * site_f4 + w];
     }
     if constexpr (Store<PIN>::scaled) {
       const int row_n = T.t[0] * L;
@@ -274,7 +286,7 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
     for (int q = 0; q < C; ++q) {
       const double* o = mf.omega + ((size_t)p.dom * L + col0 + q) * 2;
       om[q] = cmake<R>((R)o[0], (R)o[1]);
-      const size_t lb = (size_t)ts * 12 * L + col0 + q, ls = (size_t)ts * L + col0 + q;
+      const size_t lb = (size_t)ts * SS + col0 + q, ls = (size_t)ts * L + col0 + q;
       const size_t base = (size_t)s * 12 * L + col0 + q, sidx = (size_t)s * L + col0 + q;
       cplx<R> rv[4][3], wv[4][3];
       load_spinor<PIN, R>(lds, lds_s, lb, L, ls, rv);
@@ -290,11 +302,11 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
       store_spinor<PIN, R>(lds, lds_s, lb, L, ls, rv);
     }
     __syncthreads();
-    // the tile's new r to global memory, row by row
-    const int row_f4 = T.t[0] * 12 * L * (int)sizeof(E) / 16;
-    for (int f = threadIdx.x; f < nrows * row_f4; f += blockDim.x) {
-      const int r = f / row_f4, w = f - r * row_f4;
-      ((float4*)((E*)mf.r_new + (size_t)row_site[r] * 12 * L))[w] = tile_lds[f];
+    // the tile's new r to global memory
+    for (int f = threadIdx.x; f < T.ts * site_f4; f += blockDim.x) {
+      const int t = f / site_f4, w = f - t * site_f4;
+      const int r = t / T.t[0], x = t - r * T.t[0];
+      ((float4*)mf.r_new)[(size_t)(row_site[r] + x) * site_f4 + w] = tile_lds[t * ss_f4 + w];
     }
     if constexpr (Store<PIN>::scaled) {
       const int row_n = T.t[0] * L;
@@ -330,7 +342,7 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
     const size_t base = (size_t)s * 12 * L + col0 + q;
     const size_t sidx = (size_t)s * L + col0 + q;
     cplx<R> v[4][3], wv[4][3];
-    load_spinor<PIN, R>(lds, lds_s, (size_t)ts * 12 * L + col0 + q, L, (size_t)ts * L + col0 + q, v);
+    load_spinor<PIN, R>(lds, lds_s, (size_t)ts * SS + col0 + q, L, (size_t)ts * L + col0 + q, v);
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -388,10 +400,10 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
 // keeps TS * L / C threads within one workgroup (and at least one wave), and
 // whose LDS (the spinors, or the reduction that reuses them) fits 160 KiB.
 bool pick_tile(const mbbs_lattice_s* lat, int L, int prec, TileArgs* out) {
+  const int C = tile_cols(prec);
   static const int cand[][4] = {{4, 4, 4, 4}, {8, 4, 4, 2}, {4, 4, 4, 2}, {8, 4, 2, 2}, {4, 4, 2, 2},
                                 {8, 2, 2, 2}, {4, 2, 2, 2}, {2, 2, 2, 2}, {4, 4, 2, 1}, {2, 2, 2, 1},
                                 {2, 2, 1, 1}};
-  const int C = tile_cols(prec);
   const size_t es = prec == P64 ? 16 : prec == P32 ? 8 : 4;
   const Geom& g = lat->g;
   if (L % C) return false;
@@ -403,12 +415,12 @@ bool pick_tile(const mbbs_lattice_s* lat, int L, int prec, TileArgs* out) {
     const int nthr = ts * (L / C);
     if (nthr > TILE_THREADS || nthr < 64) continue;
     if (ts / t[0] > 256) continue;
-    const size_t spin = (size_t)ts * 12 * L * es + (prec == P16 ? (size_t)ts * L * sizeof(float) : 0);
+    const size_t spin = (size_t)ts * (12 * L * es + 16) + (prec == P16 ? (size_t)ts * L * sizeof(float) : 0);
     const int G = ts >= 16 ? 16 : ts;
     const size_t red = (size_t)3 * (ts + G) * L * sizeof(double);
     const size_t lds = std::max(spin, red);
     if (lds + 256 * sizeof(int) > 160 * 1024) continue;
-    if (((size_t)t[0] * 12 * L * es) % 16) continue;
+    if ((12 * L * es) % 16) continue;
     TileArgs T;
     for (int m = 0; m < 4; ++m) T.t[m] = t[m];
     T.ts = ts;
@@ -455,11 +467,10 @@ int launch_tile_t(const mbbs_lattice_s* lat, int L, const TileArgs& T, const voi
   return MBBS_OK;
 }
 
-template <int P>
+template <int P, int C>
 int dslash_tiled_p(const mbbs_lattice_s* lat, int L, int order, bool blocked, const TileArgs& T, const void* in,
                    const float* in_s, void* out, float* out_s, int s0, int ntiles, const int* frozen,
                    hipStream_t st) {
-  constexpr int C = P == P64 ? 1 : 2;
   const void* U;
   if (order == LEX) U = P == P64 ? (const void*)lat->U64 : P == P32 ? (const void*)lat->U32 : (const void*)lat->U16;
   else U = P == P64 ? (const void*)lat->U64dm : P == P32 ? (const void*)lat->U32dm : (const void*)lat->U16dm;
@@ -483,9 +494,9 @@ int launch_dslash_tiled(const mbbs_lattice_s* lat, int L, int prec, int order, b
                         const int* frozen, hipStream_t st) {
   const int ntiles = n / T.ts;
   if (ntiles <= 0) return MBBS_OK;
-  if (prec == P64) return dslash_tiled_p<P64>(lat, L, order, blocked, T, in, in_s, out, out_s, s0, ntiles, frozen, st);
-  if (prec == P32) return dslash_tiled_p<P32>(lat, L, order, blocked, T, in, in_s, out, out_s, s0, ntiles, frozen, st);
-  return dslash_tiled_p<P16>(lat, L, order, blocked, T, in, in_s, out, out_s, s0, ntiles, frozen, st);
+  if (prec == P64) return dslash_tiled_p<P64, 1>(lat, L, order, blocked, T, in, in_s, out, out_s, s0, ntiles, frozen, st);
+  if (prec == P32) return dslash_tiled_p<P32, 2>(lat, L, order, blocked, T, in, in_s, out, out_s, s0, ntiles, frozen, st);
+  return dslash_tiled_p<P16, 2>(lat, L, order, blocked, T, in, in_s, out, out_s, s0, ntiles, frozen, st);
 }
 
 int launch_mr_dslash_tiled(const mbbs_lattice_s* lat, int L, int prec, const TileArgs& T, const void* r,

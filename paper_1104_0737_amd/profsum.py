@@ -14,6 +14,7 @@ from collections import defaultdict
 
 
 def short(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "")
     name = re.sub(r"\(.*$", "", name)
     name = name.replace("mbbs::", "").replace("void ", "")
     return name if len(name) < 90 else name[:87] + "..."

@@ -201,7 +201,11 @@ def test_fused_update_sap_bit_identical(ncy, nmr, prec):
     ref = sap.sap(U, 0.12, gu.PH_AP, sap.Domains(dims, block), eta, ncy, nmr).reshape(12 * V, L)
     with gu.Lattice(dims, block, U, 0.12) as lat:
         B.mbbs_lattice_tune(lat.h, B.TUNE_MR_FUSED, 0)
+        B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[prec], 2)
+        # sized while the folded update is on: holds its second r and A r
         ws = torch.empty(B.mbbs_sap_workspace_size(lat.h, L, prec), dtype=torch.uint8, device="cuda")
+        B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[prec], 1)
+        assert B.mbbs_sap_workspace_size(lat.h, L, prec) < ws.numel()
         got = {}
         for setting in (2, 1):
             B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[prec], setting)
