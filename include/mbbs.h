@@ -323,7 +323,7 @@ typedef struct {
   int domain_solver;   /* SAP domain solver: 0 = nmr MR steps, 1 = SSOR           */
   int nssor;           /* SSOR correction terms N_SSOR (0 or 1)                   */
   double ssor_omega;   /* SSOR relaxation, 0 < omega < 2                          */
-  const double* rtilde;/* R~ of Alg. 1 ("choose R~"): a device FP64 N x L block
+  const double* rtilde;/* R~ of Alg. 1 (its choice is left open): a device FP64 N x L block
                           (a batch handle: the systems' blocks stacked), read
                           once at the start; NULL: R~ = R_0                       */
 } mbbs_solve_params;
