@@ -161,6 +161,13 @@ int mbbs_lattice_table(mbbs_lattice_t lat, int which, int32_t* out, size_t count
  *      2: as 1, and each MR step also performs the previous step's update of
  *      psi and r (one pass over the fields less per step; same bits as 1);
  *      FP64 and FP32 only (EINVAL for MBBS_TUNE_TILE_FP16S)
+ *  MBBS_TUNE_MR_ONCE_FP64/FP32/FP16S  1: each MR domain solve of up to 4 steps
+ *      forms psi once at its end, psi (+)= c r_0 - sum_j e_j w_j (c = sum_k
+ *      omega_k, e_j = omega_j sum_{k>j} omega_k, the same sum as the step-by-step
+ *      psi += omega_k r_k regrouped), so that between steps only r is updated:
+ *      fewer passes over the fields per domain solve, four more SAP fields in
+ *      the workspace (sized while the setting is on; a smaller workspace runs
+ *      the step-by-step form); 0 (default): psi updated at every step
  *  MBBS_TUNE_LDS_PAD_KB             extra LDS (KiB, 0..64) reserved per stencil
  *      block, which caps the blocks resident on a CU (fewer sites in flight
  *      per XCD, so more of their neighbour data stays in its L2)
@@ -173,7 +180,8 @@ enum { MBBS_TUNE_GROUP_FP64 = 0, MBBS_TUNE_GROUP_FP32 = 1, MBBS_TUNE_GROUP_FP16S
        MBBS_TUNE_NT_STORE_FP16S = 16, MBBS_TUNE_CHUNK_FP64 = 17, MBBS_TUNE_CHUNK_FP32 = 18,
        MBBS_TUNE_CHUNK_FP16S = 19, MBBS_TUNE_BLOCK_THREADS_FP64 = 20,
        MBBS_TUNE_BLOCK_THREADS_FP32 = 21, MBBS_TUNE_BLOCK_THREADS_FP16S = 22,
-       MBBS_TUNE_TILE_FP64 = 23, MBBS_TUNE_TILE_FP32 = 24, MBBS_TUNE_TILE_FP16S = 25 };
+       MBBS_TUNE_TILE_FP64 = 23, MBBS_TUNE_TILE_FP32 = 24, MBBS_TUNE_TILE_FP16S = 25,
+       MBBS_TUNE_MR_ONCE_FP64 = 26, MBBS_TUNE_MR_ONCE_FP32 = 27, MBBS_TUNE_MR_ONCE_FP16S = 28 };
 int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value);
 
 /* The tile shape the LDS-tiled kernels use for L columns in precision prec

@@ -10,7 +10,9 @@ itself.  The split shapes and the number of columns per thread change the
 order in which the hops are summed, and the MR domain sums follow the block
 or tile shape; every other setting leaves the operator's result bits alone.
 
-A setting is (group, threads, split, pair, nt[, columns per thread[, tiled]]).
+A setting is (group, threads, split, pair, nt[, columns per thread[, tiled[,
+psi once]]]); the last element selects the MR domain solve that forms psi
+once per domain solve (a SAP-only choice).
 """
 
 from __future__ import annotations
@@ -59,6 +61,7 @@ def apply(lat, prec, setting):
     g, t, sp, pr, nt = setting[:5]
     ch = setting[5] if len(setting) > 5 else 0
     B.mbbs_lattice_tune(lat, B.TUNE_TILE[prec], setting[6] if _tiled(setting) else 0)
+    B.mbbs_lattice_tune(lat, B.TUNE_MR_ONCE[prec], setting[7] if len(setting) > 7 else 0)
     B.mbbs_lattice_tune(lat, B.TUNE_CHUNK[prec], ch)
     B.mbbs_lattice_tune(lat, B.TUNE_GROUP[prec], g)
     B.mbbs_lattice_tune(lat, B.TUNE_BLOCK_THREADS_PREC[prec], t)
@@ -120,6 +123,9 @@ def tune_sap(lat, V, L, prec, op_times, stream=None, ncy=4, nmr=4, reps=2):
         best = min(classic, key=op_times.get)
         base = tuple(best[:5]) + ((best[5] if len(best) > 5 else 0),)
         cands += [base + (1,)] + ([base + (2,)] if folded else [])
+    # psi formed once per domain solve, on the untiled and tiled candidates
+    pad = lambda c: tuple(c[:5]) + tuple(c[5:7]) + (0,) * (7 - len(c[:7]))
+    cands += [pad(c) + (1,) for c in list(cands) if not (len(c) > 6 and c[6] == 2)]
     if classic and prec != B.FP64:
         # one column per thread: more waves in flight per CU for the domain kernels
         g, t, sp, pr, nt = min(classic, key=op_times.get)[:5]

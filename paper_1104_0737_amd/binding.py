@@ -199,6 +199,7 @@ TUNE_LDS_PAD_KB = 4
 TUNE_SPLIT = {0: 5, 1: 6, 2: 7}      # precision -> knob
 TUNE_PERSIST_BLOCKS = 8
 TUNE_MR_FUSED = 9
+TUNE_MR_ONCE = {0: 26, 1: 27, 2: 28}    # precision -> knob
 TUNE_NT_STORE = {0: 14, 1: 15, 2: 16}   # precision -> knob
 TUNE_CHUNK = {0: 17, 1: 18, 2: 19}      # precision -> knob
 TUNE_HOP_PAIR = {0: 11, 1: 12, 2: 13}   # precision -> knob

@@ -433,6 +433,162 @@ __global__ void __launch_bounds__(256) k_mr_update_flat(GeomK k, int L, int s0, 
   r[g] = make_float4(rv.x - m0.re, rv.y - m0.im, rv.z - m1.re, rv.w - m1.im);
 }
 
+// MR with psi formed once per domain solve (the MR steps of Sec. 2.2, with
+// the sum psi = sum_k omega_k r_k regrouped).  Since r_k = r_0 - sum_{j<k}
+// omega_j w_j,  sum_{k<n} omega_k r_k = c r_0 - sum_{j<n-1} e_j w_j  with
+// c = sum_k omega_k and e_j = omega_j sum_{k>j} omega_k.  Between steps only
+// r_{k+1} = r_k - omega_k w_k is formed; psi is read and written once, from r_0
+// and the kept w_j, instead of at every step.
+constexpr int MR_ONCE_MAX = 4;   // MR steps per domain solve in that form
+
+struct MrOnceArgs {
+  const void* r0;
+  const float* r0_s;
+  const void* w[MR_ONCE_MAX - 1];
+  const float* w_s[MR_ONCE_MAX - 1];
+};
+
+// c and e_j of one domain and column from the steps' omega (stride apart).
+__device__ __forceinline__ void mr_once_coefs(const double* omega, size_t stride, size_t idx, int nmr,
+                                              cplx<double>& c, cplx<double> (&e)[MR_ONCE_MAX - 1]) {
+  cplx<double> om[MR_ONCE_MAX];
+#pragma unroll
+  for (int k = 0; k < MR_ONCE_MAX; ++k)
+    om[k] = k < nmr ? cmake(omega[k * stride + idx], omega[k * stride + idx + 1]) : cmake(0.0, 0.0);
+  c = cmake(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < MR_ONCE_MAX; ++k) c = c + om[k];
+  cplx<double> tail = cmake(0.0, 0.0);
+#pragma unroll
+  for (int j = MR_ONCE_MAX - 2; j >= 0; --j) {
+    tail = tail + om[j + 1];
+    e[j] = om[j] * tail;
+  }
+}
+
+// r_out = r_in - omega w on one colour (r_out may be r_in).
+template <int PR>
+__global__ void __launch_bounds__(256) k_mr_rstep(GeomK k, int L, int s0, int n,
+                                                  const typename Store<PR>::Elem* r_in, const float* r_in_s,
+                                                  const typename Store<PR>::Elem* __restrict__ w,
+                                                  const float* __restrict__ w_s, typename Store<PR>::Elem* r_out,
+                                                  float* r_out_s, const double* __restrict__ omega,
+                                                  const int* __restrict__ frozen) {
+  using R = typename Store<PR>::Real;
+  const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * blockDim.y + threadIdx.y;
+  if (s >= s0 + n) return;
+  const int col = threadIdx.x;
+  const int dom = (s - (s >= k.g.Vh ? k.g.Vh : 0)) / k.g.Vb;
+  if (sys_frozen(k, frozen, sys_of_domain(k, dom))) return;
+  const cplx<R> om = cmake<R>((R)omega[((size_t)dom * L + col) * 2], (R)omega[((size_t)dom * L + col) * 2 + 1]);
+  const size_t base = (size_t)s * 12 * L + col;
+  const size_t sidx = (size_t)s * L + col;
+  cplx<R> rv[4][3], wv[4][3];
+  load_spinor<PR, R>(r_in, r_in_s, base, L, sidx, rv);
+  load_spinor<PR, R>(w, w_s, base, L, sidx, wv);
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) rv[sp][a] = rv[sp][a] - mr_mul(om, wv[sp][a]);
+  store_spinor<PR, R>(r_out, r_out_s, base, L, sidx, rv);
+}
+
+// The same for FP32 storage as a flat stream of float4 (two columns).
+__global__ void __launch_bounds__(256) k_mr_rstep_flat(GeomK k, int L, int s0, int n, const float4* r_in,
+                                                       const float4* __restrict__ w, float4* r_out,
+                                                       const double* __restrict__ omega,
+                                                       const int* __restrict__ frozen) {
+  const size_t npair = (size_t)n * 6 * L;
+  const size_t q = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (q >= npair) return;
+  const size_t e0 = 2 * q;
+  const int col = (int)(e0 % L);
+  const int s = (int)(e0 / (12 * (size_t)L));
+  const int dom = s / k.g.Vb;
+  if (sys_frozen(k, frozen, sys_of_domain(k, dom))) return;
+  const double* om = omega + ((size_t)dom * L + col) * 2;
+  const cplx<float> o0 = cmake((float)om[0], (float)om[1]), o1 = cmake((float)om[2], (float)om[3]);
+  const size_t g = (size_t)s0 * 6 * L + q;
+  const float4 rv = r_in[g], wv = w[g];
+  const cplx<float> m0 = mr_mul(o0, cmake(wv.x, wv.y)), m1 = mr_mul(o1, cmake(wv.z, wv.w));
+  r_out[g] = make_float4(rv.x - m0.re, rv.y - m0.im, rv.z - m1.re, rv.w - m1.im);
+}
+
+// psi (+)= c r_0 - sum_{j<nmr-1} e_j w_j on one colour (assign: =).
+template <int PR, int PPSI>
+__global__ void __launch_bounds__(256) k_mr_psi_once(GeomK k, int L, int s0, int n, MrOnceArgs a,
+                                                     typename Store<PPSI>::Elem* __restrict__ psi,
+                                                     const double* __restrict__ omega, size_t ostride, int nmr,
+                                                     int assign, const int* __restrict__ frozen) {
+  using R = typename Store<PR>::Real;
+  using E = typename Store<PR>::Elem;
+  const int s = s0 + xcd_block(blockIdx.x, gridDim.x) * blockDim.y + threadIdx.y;
+  if (s >= s0 + n) return;
+  const int col = threadIdx.x;
+  const int dom = (s - (s >= k.g.Vh ? k.g.Vh : 0)) / k.g.Vb;
+  if (sys_frozen(k, frozen, sys_of_domain(k, dom))) return;
+  cplx<double> cd, ed[MR_ONCE_MAX - 1];
+  mr_once_coefs(omega, ostride, ((size_t)dom * L + col) * 2, nmr, cd, ed);
+  const size_t base = (size_t)s * 12 * L + col;
+  const size_t sidx = (size_t)s * L + col;
+  cplx<R> v[4][3], acc[4][3];
+  load_spinor<PR, R>((const E*)a.r0, a.r0_s, base, L, sidx, v);
+  const cplx<R> c = cmake<R>((R)cd.re, (R)cd.im);
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc[sp][q] = mr_mul(c, v[sp][q]);
+#pragma unroll
+  for (int j = 0; j < MR_ONCE_MAX - 1; ++j) {
+    if (j >= nmr - 1) break;
+    const cplx<R> e = cmake<R>((R)ed[j].re, (R)ed[j].im);
+    load_spinor<PR, R>((const E*)a.w[j], a.w_s[j], base, L, sidx, v);
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) acc[sp][q] = acc[sp][q] - mr_mul(e, v[sp][q]);
+  }
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) mr_psi_update<PPSI, R>(psi, base + (size_t)(3 * sp + q) * L, acc[sp][q], assign);
+}
+
+// The same for FP32 storage and FP32 psi as a flat stream of float4.
+__global__ void __launch_bounds__(256) k_mr_psi_once_flat(GeomK k, int L, int s0, int n, MrOnceArgs a,
+                                                          float4* __restrict__ psi, const double* __restrict__ omega,
+                                                          size_t ostride, int nmr, int assign,
+                                                          const int* __restrict__ frozen) {
+  const size_t npair = (size_t)n * 6 * L;
+  const size_t q = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (q >= npair) return;
+  const size_t e0 = 2 * q;
+  const int col = (int)(e0 % L);
+  const int s = (int)(e0 / (12 * (size_t)L));
+  const int dom = s / k.g.Vb;
+  if (sys_frozen(k, frozen, sys_of_domain(k, dom))) return;
+  cplx<double> cd0, cd1, ed0[MR_ONCE_MAX - 1], ed1[MR_ONCE_MAX - 1];
+  mr_once_coefs(omega, ostride, ((size_t)dom * L + col) * 2, nmr, cd0, ed0);
+  mr_once_coefs(omega, ostride, ((size_t)dom * L + col + 1) * 2, nmr, cd1, ed1);
+  const size_t g = (size_t)s0 * 6 * L + q;
+  const float4 r0 = ((const float4*)a.r0)[g];
+  cplx<float> d0 = mr_mul(cmake((float)cd0.re, (float)cd0.im), cmake(r0.x, r0.y));
+  cplx<float> d1 = mr_mul(cmake((float)cd1.re, (float)cd1.im), cmake(r0.z, r0.w));
+#pragma unroll
+  for (int j = 0; j < MR_ONCE_MAX - 1; ++j) {
+    if (j >= nmr - 1) break;
+    const float4 wv = ((const float4*)a.w[j])[g];
+    d0 = d0 - mr_mul(cmake((float)ed0[j].re, (float)ed0[j].im), cmake(wv.x, wv.y));
+    d1 = d1 - mr_mul(cmake((float)ed1[j].re, (float)ed1[j].im), cmake(wv.z, wv.w));
+  }
+  if (assign) {
+    psi[g] = make_float4(d0.re, d0.im, d1.re, d1.im);
+  } else {
+    const float4 p = psi[g];
+    psi[g] = make_float4(p.x + d0.re, p.y + d0.im, p.z + d1.re, p.w + d1.im);
+  }
+}
+
 // ---------------------------------------------------------------- split-wave kernels
 // Block = (IPB items) x (P hop groups); item = (site, column), IPB = S * L is a
 // multiple of the wave size so every wave belongs to one hop group.  Group h
@@ -921,7 +1077,10 @@ int launch_dslash(const mbbs_lattice_s* lat, int L, int prec_in, int prec_out, i
 // Whether the MR steps of this precision fold the previous step's update in.
 static bool folded_mr(const mbbs_lattice_s* lat, int prec) { return lat->tile[prec] == 2 && prec != P16; }
 
-static size_t sap_bytes(const mbbs_lattice_s* lat, int L, int prec, bool ssor, bool folded) {
+// Whether MR domain solves form psi once (needs a second r and three more w).
+static bool once_mr(const mbbs_lattice_s* lat, int prec) { return lat->mr_once[prec] == 1; }
+
+static size_t sap_bytes(const mbbs_lattice_s* lat, int L, int prec, bool ssor, bool folded, bool once = false) {
   const size_t V = lat->g.V;
   const size_t elem = prec == P64 ? 16 : prec == P32 ? 8 : 4;
   const size_t field = V * 12 * L * elem;
@@ -932,13 +1091,14 @@ static size_t sap_bytes(const mbbs_lattice_s* lat, int L, int prec, bool ssor, b
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   // eta, r, w; x2 (SSOR); a second r and w for the folded MR update (tiled,
   // setting 2: included only while that setting is on)
-  const size_t nf = ssor ? 4 : (folded ? 5 : 3);
+  // psi once: a second r (r2) and w2 plus wx[0], wx[1]
+  const size_t nf = ssor ? 4 : (once ? 7 : (folded ? 5 : 3));
   return al(field) * nf + al(scales) * nf + al(psi) + al(nblk * L * 3 * sizeof(double)) +
-         al(ndc * L * 2 * sizeof(double));
+         al(ndc * L * 2 * sizeof(double) * MR_ONCE_MAX);
 }
 
 size_t sap_buffer_bytes(const mbbs_lattice_s* lat, int L, int prec, bool ssor) {
-  return sap_bytes(lat, L, prec, ssor, !ssor && folded_mr(lat, prec));
+  return sap_bytes(lat, L, prec, ssor, !ssor && folded_mr(lat, prec), !ssor && once_mr(lat, prec));
 }
 
 int sap_bind(const mbbs_lattice_s* lat, int L, int prec, void* ws, size_t bytes, SapBuffers* b, bool ssor) {
@@ -962,13 +1122,22 @@ int sap_bind(const mbbs_lattice_s* lat, int L, int prec, void* ws, size_t bytes,
   b->w_s = prec == P16 ? (float*)p : nullptr; p += scales;
   b->psi = p; p += al(V * 12 * L * (prec == P64 ? 16 : 8));
   b->partial = (double*)p; p += al((size_t)lat->g.Vh * L * 3 * sizeof(double));
-  b->omega = (double*)p; p += al((size_t)(lat->g.ndom / 2) * L * 2 * sizeof(double));
+  b->omega = (double*)p; p += al((size_t)(lat->g.ndom / 2) * L * 2 * sizeof(double) * MR_ONCE_MAX);
   b->ssor = ssor ? 1 : 0;
   b->x2 = nullptr;
   b->x2_s = nullptr;
   if (ssor) {
     b->x2 = p; p += field;
     b->x2_s = prec == P16 ? (float*)p : nullptr; p += scales;
+  } else if (once_mr(lat, prec) && bytes >= sap_bytes(lat, L, prec, false, false, true)) {
+    b->r2 = p; p += field;
+    b->r2_s = prec == P16 ? (float*)p : nullptr; p += scales;
+    b->w2 = p; p += field;
+    b->w2_s = prec == P16 ? (float*)p : nullptr; p += scales;
+    for (int j = 0; j < 2; ++j) {
+      b->wx[j] = p; p += field;
+      b->wx_s[j] = prec == P16 ? (float*)p : nullptr; p += scales;
+    }
   } else if (folded && bytes >= sap_bytes(lat, L, prec, false, true)) {
     b->r2 = p; p += field;
     b->r2_s = nullptr; p += scales;
@@ -1078,6 +1247,114 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
       }
       TileArgs T;
       const bool tiled = ((uintptr_t)b.r & 15) == 0 && ((uintptr_t)b.w & 15) == 0 && tile_plan(lat, L, PL, &T);
+      const size_t ostride = (size_t)(g.ndom / 2) * L * 2;   // doubles per step's omega
+      // one MR stencil step w = A_DD r on this colour, then its omega (per domain and column) into om
+      auto stencil_step = [&](const void* rr, const float* rr_s, void* ww, float* ww_s, double* om) -> int {
+        int nblk_dom = g.Vb / S;
+        if (tiled) {
+          nblk_dom = T.tpd;
+          MBBS_TRY(launch_mr_dslash_tiled(lat, L, PL, T, rr, rr_s, ww, ww_s, s0, n, b.partial, frozen, st));
+        } else if (SS > 0) {
+          nblk_dom = g.Vb / SS;
+          const size_t smem = split_smem_bytes(PL, P, SS, L);
+          if (P == 4) {
+            auto fn = k_mr_dslash_split<PR, PL, 4>;
+            allow_lds((const void*)fn);
+            hipLaunchKernelGGL(fn, dim3(split_grid(lat, PL, 4, SS, L, n / SS)), dim3(SS * L, 4), smem, st, lat->gk,
+                               lat->kappa, L, s0, n, (const ER*)rr, rr_s, (ER*)ww, ww_s, U, b.partial, SS, frozen);
+          } else {
+            auto fn = k_mr_dslash_split<PR, PL, 2>;
+            allow_lds((const void*)fn);
+            hipLaunchKernelGGL(fn, dim3(split_grid(lat, PL, 2, SS, L, n / SS)), dim3(SS * L, 2), smem, st, lat->gk,
+                               lat->kappa, L, s0, n, (const ER*)rr, rr_s, (ER*)ww, ww_s, U, b.partial, SS, frozen);
+          }
+        } else {
+#define MRD(CC, PV)                                                                                   \
+  if (L == 12)                                                                                        \
+    hipLaunchKernelGGL((k_mr_dslash<PR, PL, CC, PV, 12>), dim3(pl.nblocks), dim3(pl.nchunk, S),             \
+                       red_bytes + (size_t)lat->lds_pad_kb * 1024, st, lat->gk,                              \
+                       lat->kappa, L, s0, n, (const ER*)rr, rr_s, (ER*)ww, ww_s, U, b.partial, pl.bpt,      \
+                       pl.ngroups, frozen);                                                                \
+  else                                                                                                \
+  hipLaunchKernelGGL((k_mr_dslash<PR, PL, CC, PV>), dim3(pl.nblocks), dim3(pl.nchunk, S),                   \
+                     red_bytes + (size_t)lat->lds_pad_kb * 1024, st, lat->gk,                                \
+                     lat->kappa, L, s0, n, (const ER*)rr, rr_s, (ER*)ww, ww_s, U, b.partial, pl.bpt,        \
+                     pl.ngroups, frozen)
+          const bool pr = lat->hop_pair[PL] != 0;
+          switch (C) {
+            case 4: hipLaunchKernelGGL((k_mr_dslash<PR, PL, 4>), dim3(pl.nblocks), dim3(pl.nchunk, S),
+                                       red_bytes + (size_t)lat->lds_pad_kb * 1024, st, lat->gk, lat->kappa, L, s0,
+                                       n, (const ER*)rr, rr_s, (ER*)ww, ww_s, U, b.partial, pl.bpt, pl.ngroups,
+                                       frozen); break;
+            case 3: hipLaunchKernelGGL((k_mr_dslash<PR, PL, 3>), dim3(pl.nblocks), dim3(pl.nchunk, S),
+                                       red_bytes + (size_t)lat->lds_pad_kb * 1024, st, lat->gk, lat->kappa, L, s0,
+                                       n, (const ER*)rr, rr_s, (ER*)ww, ww_s, U, b.partial, pl.bpt, pl.ngroups,
+                                       frozen); break;
+            case 2: if (pr) MRD(2, true); else MRD(2, false); break;
+            default: if (pr) MRD(1, true); else MRD(1, false);
+          }
+#undef MRD
+        }
+        MBBS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_mr_omega, dim3(g.ndom / 2), dim3(256), 0, st, lat->gk, L, nblk_dom,
+                           (const double*)b.partial, om, frozen);
+        MBBS_HIP(hipGetLastError());
+        return MBBS_OK;
+      };
+      if (lat->mr_once[PL] && nmr <= MR_ONCE_MAX && b.r2 && b.w2 && b.wx[0] && b.wx[1]) {
+        // psi formed once: r_0 stays in b.r, r_1, r_2, ... overwrite r2, the
+        // steps' A r are kept (w_0 .. w_{nmr-1}), each step's omega kept
+        void* wb[MR_ONCE_MAX] = {b.w, b.w2, b.wx[0], b.wx[1]};
+        float* wbs[MR_ONCE_MAX] = {b.w_s, b.w2_s, b.wx_s[0], b.wx_s[1]};
+        for (int it = 0; it < nmr; ++it) {
+          const void* rin = it == 0 ? b.r : b.r2;
+          float* rin_s = it == 0 ? b.r_s : b.r2_s;
+          if (prof) prof->begin(MBBS_K_MR_DSLASH);
+          MBBS_TRY(stencil_step(rin, rin_s, wb[it], wbs[it], b.omega + it * ostride));
+          if (prof) prof->end();
+          if (it + 1 == nmr) break;
+          if (prof) prof->begin(MBBS_K_MR_UPDATE);
+          if constexpr (PR == P32) {
+            if (L % 2 == 0) {
+              const size_t npair = (size_t)n * 6 * L;
+              hipLaunchKernelGGL(k_mr_rstep_flat, dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st, lat->gk,
+                                 L, s0, n, (const float4*)rin, (const float4*)wb[it], (float4*)b.r2,
+                                 b.omega + it * ostride, frozen);
+            } else {
+              hipLaunchKernelGGL((k_mr_rstep<PR>), dim3(ceil_div(n, Su)), dim3(L, Su), 0, st, lat->gk, L, s0, n,
+                                 (const ER*)rin, rin_s, (const ER*)wb[it], wbs[it], (ER*)b.r2, b.r2_s,
+                                 b.omega + it * ostride, frozen);
+            }
+          } else {
+            hipLaunchKernelGGL((k_mr_rstep<PR>), dim3(ceil_div(n, Su)), dim3(L, Su), 0, st, lat->gk, L, s0, n,
+                               (const ER*)rin, rin_s, (const ER*)wb[it], wbs[it], (ER*)b.r2, b.r2_s,
+                               b.omega + it * ostride, frozen);
+          }
+          if (prof) prof->end();
+          MBBS_HIP(hipGetLastError());
+        }
+        MrOnceArgs oa{};
+        oa.r0 = b.r; oa.r0_s = b.r_s;
+        for (int j = 0; j < MR_ONCE_MAX - 1; ++j) { oa.w[j] = wb[j]; oa.w_s[j] = wbs[j]; }
+        if (prof) prof->begin(MBBS_K_MR_UPDATE);
+        if constexpr (PR == P32 && PPSI == P32) {
+          if (L % 2 == 0) {
+            const size_t npair = (size_t)n * 6 * L;
+            hipLaunchKernelGGL(k_mr_psi_once_flat, dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st, lat->gk,
+                               L, s0, n, oa, (float4*)b.psi, (const double*)b.omega, ostride, nmr, (int)(cy == 0),
+                               frozen);
+          } else {
+            hipLaunchKernelGGL((k_mr_psi_once<PR, PPSI>), dim3(ceil_div(n, Su)), dim3(L, Su), 0, st, lat->gk, L, s0,
+                               n, oa, (EP*)b.psi, (const double*)b.omega, ostride, nmr, (int)(cy == 0), frozen);
+          }
+        } else {
+          hipLaunchKernelGGL((k_mr_psi_once<PR, PPSI>), dim3(ceil_div(n, Su)), dim3(L, Su), 0, st, lat->gk, L, s0,
+                             n, oa, (EP*)b.psi, (const double*)b.omega, ostride, nmr, (int)(cy == 0), frozen);
+        }
+        if (prof) prof->end();
+        MBBS_HIP(hipGetLastError());
+        continue;
+      }
       if (tiled && lat->tile[PL] == 2 && PL != P16 && b.r2 && b.w2) {
         // each step folds the previous step's update in; the steps alternate
         // between two residual / A r buffers; psi's last update follows
@@ -1116,58 +1393,8 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
       }
       for (int it = 0; it < nmr; ++it) {
         if (prof) prof->begin(MBBS_K_MR_DSLASH);
-        int nblk_dom = g.Vb / S;
-        if (tiled) {
-          nblk_dom = T.tpd;
-          MBBS_TRY(launch_mr_dslash_tiled(lat, L, PL, T, b.r, b.r_s, b.w, b.w_s, s0, n, b.partial, frozen, st));
-        } else if (SS > 0) {
-          nblk_dom = g.Vb / SS;
-          const size_t smem = split_smem_bytes(PL, P, SS, L);
-          if (P == 4) {
-            auto fn = k_mr_dslash_split<PR, PL, 4>;
-            allow_lds((const void*)fn);
-            hipLaunchKernelGGL(fn, dim3(split_grid(lat, PL, 4, SS, L, n / SS)), dim3(SS * L, 4), smem, st, lat->gk,
-                               lat->kappa, L, s0, n,
-                               (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial, SS, frozen);
-          } else {
-            auto fn = k_mr_dslash_split<PR, PL, 2>;
-            allow_lds((const void*)fn);
-            hipLaunchKernelGGL(fn, dim3(split_grid(lat, PL, 2, SS, L, n / SS)), dim3(SS * L, 2), smem, st, lat->gk,
-                               lat->kappa, L, s0, n,
-                               (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial, SS, frozen);
-          }
-        } else {
-#define MRD(CC, PV)                                                                                   \
-  if (L == 12)                                                                                        \
-    hipLaunchKernelGGL((k_mr_dslash<PR, PL, CC, PV, 12>), dim3(pl.nblocks), dim3(pl.nchunk, S),             \
-                       red_bytes + (size_t)lat->lds_pad_kb * 1024, st, lat->gk,                              \
-                       lat->kappa, L, s0, n, (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial, pl.bpt, \
-                       pl.ngroups, frozen);                                                                \
-  else                                                                                                \
-  hipLaunchKernelGGL((k_mr_dslash<PR, PL, CC, PV>), dim3(pl.nblocks), dim3(pl.nchunk, S),                   \
-                     red_bytes + (size_t)lat->lds_pad_kb * 1024, st, lat->gk,                                \
-                     lat->kappa, L, s0, n, (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial, pl.bpt,   \
-                     pl.ngroups, frozen)
-        const bool pr = lat->hop_pair[PL] != 0;
-        switch (C) {
-          case 4: hipLaunchKernelGGL((k_mr_dslash<PR, PL, 4>), dim3(pl.nblocks), dim3(pl.nchunk, S),
-                                     red_bytes + (size_t)lat->lds_pad_kb * 1024, st, lat->gk, lat->kappa, L, s0,
-                                     n, (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial, pl.bpt, pl.ngroups,
-                                     frozen); break;
-          case 3: hipLaunchKernelGGL((k_mr_dslash<PR, PL, 3>), dim3(pl.nblocks), dim3(pl.nchunk, S),
-                                     red_bytes + (size_t)lat->lds_pad_kb * 1024, st, lat->gk, lat->kappa, L, s0,
-                                     n, (const ER*)b.r, b.r_s, (ER*)b.w, b.w_s, U, b.partial, pl.bpt, pl.ngroups,
-                                     frozen); break;
-          case 2: if (pr) MRD(2, true); else MRD(2, false); break;
-          default: if (pr) MRD(1, true); else MRD(1, false);
-        }
-#undef MRD
-        }
-        MBBS_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_mr_omega, dim3(g.ndom / 2), dim3(256), 0, st, lat->gk, L, nblk_dom,
-                           (const double*)b.partial, b.omega, frozen);
+        MBBS_TRY(stencil_step(b.r, b.r_s, b.w, b.w_s, b.omega));
         if (prof) prof->end();
-        MBBS_HIP(hipGetLastError());
         if (prof) prof->begin(MBBS_K_MR_UPDATE);
         if constexpr (PR == P32 && PPSI == P32) {
           if (L % 2 == 0) {

@@ -127,6 +127,7 @@ struct mbbs_lattice_s {
   int nt_store[3] = {0, 0, 0};  // operator: nontemporal output stores
   int chunk[3] = {0, 0, 0};     // columns per thread of the stencil kernels (0: automatic)
   int tile[3] = {0, 0, 0};      // LDS-tiled operator and MR kernels: 0 off, 1 on, 2 on with the MR update fused
+  int mr_once[3] = {0, 0, 0};   // MR domain solves form psi once from r_0 and the steps' A r (1) or step by step (0)
   // SSOR wavefront order inside a domain: local indices sorted by the
   // hyperplane h = l_0 + l_1 + l_2 + l_3 (then by local index); hyperplane h
   // holds entries hp_off[h] .. hp_off[h+1]-1 (device arrays)
@@ -168,9 +169,12 @@ struct SapBuffers {
   double ssor_omega = 1.0;
   void* x2 = nullptr; float* x2_s = nullptr;
   // MR with the update folded into the next step (tiled kernels): second
-  // residual and A r buffers, the steps alternate between the two
+  // residual and A r buffers, the steps alternate between the two.  MR with
+  // psi formed once per domain solve: r2 holds r_1, r_2, ... and w, w2,
+  // wx[0], wx[1] keep the steps' A r
   void* r2 = nullptr; float* r2_s = nullptr;
   void* w2 = nullptr; float* w2_s = nullptr;
+  void* wx[2] = {nullptr, nullptr}; float* wx_s[2] = {nullptr, nullptr};
 };
 size_t sap_buffer_bytes(const mbbs_lattice_s* lat, int L, int prec, bool ssor = false);
 int sap_bind(const mbbs_lattice_s* lat, int L, int prec, void* ws, size_t bytes, SapBuffers* b, bool ssor = false);

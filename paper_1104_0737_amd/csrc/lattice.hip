@@ -369,6 +369,12 @@ extern "C" int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value) {
       MBBS_CHECK(!(value == 2 && knob == MBBS_TUNE_TILE_FP16S), "folded MR update not available for FP16 storage");
       lat->tile[knob - MBBS_TUNE_TILE_FP64] = value;
       return MBBS_OK;
+    case MBBS_TUNE_MR_ONCE_FP64:
+    case MBBS_TUNE_MR_ONCE_FP32:
+    case MBBS_TUNE_MR_ONCE_FP16S:
+      MBBS_CHECK(value == 0 || value == 1, "psi-once MR must be 0 or 1");
+      lat->mr_once[knob - MBBS_TUNE_MR_ONCE_FP64] = value;
+      return MBBS_OK;
     case MBBS_TUNE_MR_FUSED:
       MBBS_CHECK(value >= -1 && value <= 1, "fused MR must be -1 (auto), 0 or 1");
       lat->mr_fused = value;

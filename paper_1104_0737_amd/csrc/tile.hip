@@ -351,6 +351,7 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
       if (k.nt_store) store_spinor<PIN, R, true>(out, out_s, base, L, sidx, wv);
       else store_spinor<PIN, R>(out, out_s, base, L, sidx, wv);
     } else {
+      // plain stores: nontemporal ones (measured) made the step slower
       store_spinor<PIN, R>(out, out_s, base, L, sidx, wv);
       // the update must see the stored (rounded) w
       if constexpr (Store<PIN>::scaled) load_spinor<PIN, R>(out, out_s, base, L, sidx, wv);

@@ -102,14 +102,16 @@ def test_binding_constants_match_header_enums():
     assert e["MBBS_K_COUNT"] == len(binding.KERNEL_CLASSES)
     per_prec = {"GROUP": binding.TUNE_GROUP, "SPLIT": binding.TUNE_SPLIT, "HOP_PAIR": binding.TUNE_HOP_PAIR,
                 "NT_STORE": binding.TUNE_NT_STORE, "CHUNK": binding.TUNE_CHUNK,
-                "BLOCK_THREADS": binding.TUNE_BLOCK_THREADS_PREC, "TILE": binding.TUNE_TILE}
+                "BLOCK_THREADS": binding.TUNE_BLOCK_THREADS_PREC, "TILE": binding.TUNE_TILE,
+                "MR_ONCE": binding.TUNE_MR_ONCE}
     for knob, m in per_prec.items():
         for prec, suffix in ((binding.FP64, "FP64"), (binding.FP32, "FP32"), (binding.FP16S, "FP16S")):
             assert e[f"MBBS_TUNE_{knob}_{suffix}"] == m[prec], (knob, suffix)
-    for knob in ("BLOCK_THREADS", "LDS_PAD_KB", "PERSIST_BLOCKS", "MR_FUSED"):
+    single = ("BLOCK_THREADS", "LDS_PAD_KB", "PERSIST_BLOCKS", "MR_FUSED")
+    for knob in single:
         assert e["MBBS_TUNE_" + knob] == getattr(binding, "TUNE_" + knob), knob
     tune = {k for k in e if k.startswith("MBBS_TUNE_")}
-    assert len(tune) == 4 + 3 * len(per_prec)      # every knob of the header is mapped above
+    assert len(tune) == len(single) + 3 * len(per_prec)      # every knob of the header is mapped above
 
 
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):
