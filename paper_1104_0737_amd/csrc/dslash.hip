@@ -1191,7 +1191,12 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
       const int P = lat->nsys == 1 ? lat->split[PL] : 0;   // the split kernels serve single systems only
       const int SS = ((P == 2 || P == 4) && !lat->gk.clov) ? split_sites(lat, L, PL, P) : 0;
       if (prof) prof->begin(MBBS_K_SAP_RES);
-      if (SS > 0) {
+      TileArgs TR;
+      const bool tres = cy > 0 && ((uintptr_t)b.psi & 15) == 0 && tile_plan_resid(lat, L, PL, &TR);
+      if (tres) {
+        // general case with psi staged per tile in LDS
+        MBBS_TRY(launch_resid_tiled(lat, L, PL, TR, b.eta, b.eta_s, b.psi, b.r, b.r_s, s0, n, frozen, st));
+      } else if (SS > 0) {
         const size_t smem = split_smem_bytes(PL, P, SS, L);
         const int mode = cy > 0 ? 2 : col;
         if (P == 4) {
@@ -1309,8 +1314,11 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
         for (int it = 0; it < nmr; ++it) {
           const void* rin = it == 0 ? b.r : b.r2;
           float* rin_s = it == 0 ? b.r_s : b.r2_s;
+          // the last step's A r only feeds its omega: the tiled step need not store it
+          const bool keep = it + 1 < nmr || !tiled;
           if (prof) prof->begin(MBBS_K_MR_DSLASH);
-          MBBS_TRY(stencil_step(rin, rin_s, wb[it], wbs[it], b.omega + it * ostride));
+          MBBS_TRY(stencil_step(rin, rin_s, keep ? wb[it] : nullptr, keep ? wbs[it] : nullptr,
+                                b.omega + it * ostride));
           if (prof) prof->end();
           if (it + 1 == nmr) break;
           if (prof) prof->begin(MBBS_K_MR_UPDATE);

@@ -37,6 +37,15 @@ int launch_mr_dslash_tiled(const mbbs_lattice_s* lat, int L, int prec, const Til
                            const float* r_s, void* w, float* w_s, int s0, int n, double* partial, const int* frozen,
                            hipStream_t st);
 
+// The SAP residual on one colour's domains (domain-major sites [s0, s0 + n)),
+// general case: r = eta - psi + kappa H psi over all hops (with the clover
+// step when set), psi staged in LDS.  prec is the SAP storage precision of
+// eta and r; psi is FP64 for FP64 and FP32 otherwise.
+bool tile_plan_resid(const mbbs_lattice_s* lat, int L, int prec, TileArgs* out);
+int launch_resid_tiled(const mbbs_lattice_s* lat, int L, int prec, const TileArgs& T, const void* eta,
+                       const float* eta_s, const void* psi, void* r, float* r_s, int s0, int n, const int* frozen,
+                       hipStream_t st);
+
 // MR step with the previous step's update folded in, on one colour's domains:
 // psi (+)= omega r_old (assign: =), r_new = r_old - omega w_old, then
 // w_new = A_DD r_new and the partials as launch_mr_dslash_tiled.  omega holds

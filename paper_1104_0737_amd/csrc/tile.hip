@@ -142,8 +142,9 @@ __device__ __forceinline__ void mr_residual_cols(const typename Store<P>::Elem* 
   }
 }
 
-// Arguments of the MR step with the previous step's update folded in.
-struct MrfArgs {
+// Further arguments: of the MR step with the previous step's update folded
+// in, and of the SAP residual.
+struct TileExtra {
   const void* w_old;     // A r of the previous step
   const float* w_old_s;
   void* r_new;           // receives r - omega w
@@ -151,6 +152,8 @@ struct MrfArgs {
   void* psi;             // psi (+)= omega r (previous step's r and omega)
   const double* omega;   // previous step's omega per domain and column
   int assign;
+  const void* eta;       // SAP residual: eta (the output's precision)
+  const float* eta_s;
 };
 
 // One hop for the C columns of a thread: the neighbour's spinor from LDS when
@@ -162,7 +165,7 @@ __device__ __forceinline__ void hop_tiled(const GeomK& k, const SiteCtx& c, cons
                                           int ts, const typename Store<PIN>::Elem* __restrict__ in,
                                           const float* __restrict__ in_s, const typename Store<PIN>::Elem* lds,
                                           const float* lds_s, const LinkElem<PL>* __restrict__ U, int L, int col0,
-                                          const MrfArgs& mf, const cplx<R> (&om)[C],
+                                          const TileExtra& mf, const cplx<R> (&om)[C],
                                           cplx<R> (&acc)[4][3][C], R& token) {
   if (hop_skipped<ORDER, HOPS, MU, FWD>(k, c)) return;
   const bool inside = FWD ? lt[MU] < T.t[MU] - 1 : lt[MU] > 0;
@@ -202,7 +205,7 @@ __device__ __forceinline__ void hop_tiled(const GeomK& k, const SiteCtx& c, cons
   hop_settle(acc, token);
 }
 
-enum { OP_DSLASH = 0, OP_MR = 1, OP_MRF = 2 };
+enum { OP_DSLASH = 0, OP_MR = 1, OP_MRF = 2, OP_RESID = 3 };
 
 // OP_DSLASH: out = in - kappa H in (HOPS: all hops or in-domain hops).
 // OP_MR: w = r - kappa H_DD r on one colour's domains (in = r, out = w), plus
@@ -211,16 +214,18 @@ enum { OP_DSLASH = 0, OP_MR = 1, OP_MRF = 2 };
 // previous A r, omega and psi): psi (+)= omega r, r <- r - omega w (written to
 // mf.r_new), then OP_MR on the new r.  The new r of the tile is formed once,
 // in LDS; neighbours outside the tile form theirs from the previous r and A r.
+// OP_RESID: the SAP residual on one colour's sites, r = eta - psi + kappa H psi
+// over all hops (in = psi, out = r of precision PO, mf.eta).
 // Launch: one workgroup per tile, T.ts * L / C threads, T.lds bytes of LDS.
-template <int PIN, int PL, int C, int ORDER, int HOPS, int OP, int LT, int PPSI = PIN>
+template <int PIN, int PL, int C, int ORDER, int HOPS, int OP, int LT, int PPSI = PIN, int PO = PIN>
 __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, int L, TileArgs T,
                                                        const typename Store<PIN>::Elem* __restrict__ in,
                                                        const float* __restrict__ in_s,
-                                                       typename Store<PIN>::Elem* __restrict__ out,
+                                                       typename Store<PO>::Elem* __restrict__ out,
                                                        float* __restrict__ out_s,
                                                        const LinkElem<PL>* __restrict__ U, int s0,
                                                        double* __restrict__ partial,
-                                                       const int* __restrict__ frozen, MrfArgs mf) {
+                                                       const int* __restrict__ frozen, TileExtra mf) {
   if constexpr (LT > 0) L = LT;
   using E = typename Store<PIN>::Elem;
   using R = typename Store<PL>::Real;
@@ -343,6 +348,15 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
     const size_t sidx = (size_t)s * L + col0 + q;
     cplx<R> v[4][3], wv[4][3];
     load_spinor<PIN, R>(lds, lds_s, (size_t)ts * SS + col0 + q, L, (size_t)ts * L + col0 + q, v);
+    if constexpr (OP == OP_RESID) {
+      // r = eta - psi + kappa H psi, in the residual kernel's order
+      load_spinor<PO, R>((const typename Store<PO>::Elem*)mf.eta, mf.eta_s, base, L, sidx, wv);
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) wv[sp][a] = wv[sp][a] - v[sp][a] + kap * acc[sp][a][q];
+      store_spinor<PO, R>(out, out_s, base, L, sidx, wv);
+    } else {
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -350,11 +364,14 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
     if constexpr (OP == OP_DSLASH) {
       if (k.nt_store) store_spinor<PIN, R, true>(out, out_s, base, L, sidx, wv);
       else store_spinor<PIN, R>(out, out_s, base, L, sidx, wv);
-    } else {
+    } else if (out) {
       // plain stores: nontemporal ones (measured) made the step slower
       store_spinor<PIN, R>(out, out_s, base, L, sidx, wv);
       // the update must see the stored (rounded) w
       if constexpr (Store<PIN>::scaled) load_spinor<PIN, R>(out, out_s, base, L, sidx, wv);
+    }
+    }
+    if constexpr (OP == OP_MR || OP == OP_MRF) {
       R a_re = 0, a_im = 0, a_ww = 0;
 #pragma unroll
       for (int sp = 0; sp < 4; ++sp)
@@ -368,7 +385,7 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
       sums[q][0] = a_re; sums[q][1] = a_im; sums[q][2] = a_ww;
     }
   }
-  if constexpr (OP != OP_DSLASH) {
+  if constexpr (OP == OP_MR || OP == OP_MRF) {
     // per-column sums over the tile's sites in a fixed order, in two stages
     // (G interleaved groups of sites, then the groups), through the LDS the
     // tile's spinors no longer need
@@ -400,12 +417,11 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
 // Largest tile shape (of a fixed candidate list) that divides the SAP block,
 // keeps TS * L / C threads within one workgroup (and at least one wave), and
 // whose LDS (the spinors, or the reduction that reuses them) fits 160 KiB.
-bool pick_tile(const mbbs_lattice_s* lat, int L, int prec, TileArgs* out) {
-  const int C = tile_cols(prec);
+// es: bytes per staged element; C columns per thread; scaled: FP16 storage.
+bool pick_tile(const mbbs_lattice_s* lat, int L, size_t es, int C, bool scaled, TileArgs* out) {
   static const int cand[][4] = {{4, 4, 4, 4}, {8, 4, 4, 2}, {4, 4, 4, 2}, {8, 4, 2, 2}, {4, 4, 2, 2},
                                 {8, 2, 2, 2}, {4, 2, 2, 2}, {2, 2, 2, 2}, {4, 4, 2, 1}, {2, 2, 2, 1},
                                 {2, 2, 1, 1}};
-  const size_t es = prec == P64 ? 16 : prec == P32 ? 8 : 4;
   const Geom& g = lat->g;
   if (L % C) return false;
   for (const auto& t : cand) {
@@ -416,7 +432,7 @@ bool pick_tile(const mbbs_lattice_s* lat, int L, int prec, TileArgs* out) {
     const int nthr = ts * (L / C);
     if (nthr > TILE_THREADS || nthr < 64) continue;
     if (ts / t[0] > 256) continue;
-    const size_t spin = (size_t)ts * (12 * L * es + 16) + (prec == P16 ? (size_t)ts * L * sizeof(float) : 0);
+    const size_t spin = (size_t)ts * (12 * L * es + 16) + (scaled ? (size_t)ts * L * sizeof(float) : 0);
     const int G = ts >= 16 ? 16 : ts;
     const size_t red = (size_t)3 * (ts + G) * L * sizeof(double);
     const size_t lds = std::max(spin, red);
@@ -444,24 +460,25 @@ void allow_tile_lds(const void* fn) {
   if (nseen < 64) seen[nseen++] = fn;
 }
 
-template <int P, int C, int ORDER, int HOPS, int OP, int PPSI = P>
+template <int P, int C, int ORDER, int HOPS, int OP, int PPSI = P, int PL = P, int PO = P>
 int launch_tile_t(const mbbs_lattice_s* lat, int L, const TileArgs& T, const void* in, const float* in_s,
                   void* out, float* out_s, const void* U, int s0, int ntiles, double* partial, const int* frozen,
-                  hipStream_t st, const MrfArgs& mf = MrfArgs{}) {
+                  hipStream_t st, const TileExtra& mf = TileExtra{}) {
   using E = typename Store<P>::Elem;
-  using EL = LinkElem<P>;
+  using EO = typename Store<PO>::Elem;
+  using EL = LinkElem<PL>;
   GeomK gk = lat->gk;
-  gk.nt_store = lat->nt_store[P];
+  gk.nt_store = lat->nt_store[PL];
   const dim3 blk(T.ts * (L / C)), grd(ntiles);
   if (L == 12) {
-    auto fn = k_tile<P, P, C, ORDER, HOPS, OP, 12, PPSI>;
+    auto fn = k_tile<P, PL, C, ORDER, HOPS, OP, 12, PPSI, PO>;
     allow_tile_lds((const void*)fn);
-    hipLaunchKernelGGL(fn, grd, blk, T.lds, st, gk, lat->kappa, L, T, (const E*)in, in_s, (E*)out, out_s,
+    hipLaunchKernelGGL(fn, grd, blk, T.lds, st, gk, lat->kappa, L, T, (const E*)in, in_s, (EO*)out, out_s,
                        (const EL*)U, s0, partial, frozen, mf);
   } else {
-    auto fn = k_tile<P, P, C, ORDER, HOPS, OP, 0, PPSI>;
+    auto fn = k_tile<P, PL, C, ORDER, HOPS, OP, 0, PPSI, PO>;
     allow_tile_lds((const void*)fn);
-    hipLaunchKernelGGL(fn, grd, blk, T.lds, st, gk, lat->kappa, L, T, (const E*)in, in_s, (E*)out, out_s,
+    hipLaunchKernelGGL(fn, grd, blk, T.lds, st, gk, lat->kappa, L, T, (const E*)in, in_s, (EO*)out, out_s,
                        (const EL*)U, s0, partial, frozen, mf);
   }
   MBBS_HIP(hipGetLastError());
@@ -485,9 +502,17 @@ int dslash_tiled_p(const mbbs_lattice_s* lat, int L, int order, bool blocked, co
 
 }  // namespace
 
+static size_t elem_bytes(int prec) { return prec == P64 ? 16 : prec == P32 ? 8 : 4; }
+
 bool tile_plan(const mbbs_lattice_s* lat, int L, int prec, TileArgs* out) {
   if (lat->tile[prec] < 1) return false;
-  return pick_tile(lat, L, prec, out);
+  return pick_tile(lat, L, elem_bytes(prec), tile_cols(prec), prec == P16, out);
+}
+
+bool tile_plan_resid(const mbbs_lattice_s* lat, int L, int prec, TileArgs* out) {
+  if (lat->tile[prec] < 1) return false;
+  // the staged field is psi: FP64 in FP64 SAP, FP32 otherwise
+  return pick_tile(lat, L, prec == P64 ? 16 : 8, tile_cols(prec), false, out);
 }
 
 int launch_dslash_tiled(const mbbs_lattice_s* lat, int L, int prec, int order, bool blocked, const TileArgs& T,
@@ -518,7 +543,7 @@ int launch_mr_fused_tiled(const mbbs_lattice_s* lat, int L, int prec, const Tile
                           double* partial, const int* frozen, hipStream_t st) {
   const int ntiles = n / T.ts;
   if (ntiles <= 0) return MBBS_OK;
-  MrfArgs mf;
+  TileExtra mf;
   mf.w_old = w_old; mf.w_old_s = w_old_s; mf.r_new = r_new; mf.r_new_s = r_new_s;
   mf.psi = psi; mf.omega = omega; mf.assign = assign ? 1 : 0;
   if (prec == P64)
@@ -530,6 +555,24 @@ int launch_mr_fused_tiled(const mbbs_lattice_s* lat, int L, int prec, const Tile
   // FP16 storage: withdrawn (its only run did not finish; no cause found)
   set_error("folded MR update not available for FP16 storage");
   return MBBS_EINVAL;
+}
+
+int launch_resid_tiled(const mbbs_lattice_s* lat, int L, int prec, const TileArgs& T, const void* eta,
+                       const float* eta_s, const void* psi, void* r, float* r_s, int s0, int n, const int* frozen,
+                       hipStream_t st) {
+  const int ntiles = n / T.ts;
+  if (ntiles <= 0) return MBBS_OK;
+  TileExtra ex{};
+  ex.eta = eta;
+  ex.eta_s = eta_s;
+  if (prec == P64)
+    return launch_tile_t<P64, 1, DM, ALL, OP_RESID>(lat, L, T, psi, nullptr, r, r_s, lat->U64dm, s0, ntiles, nullptr,
+                                                   frozen, st, ex);
+  if (prec == P32)
+    return launch_tile_t<P32, 2, DM, ALL, OP_RESID>(lat, L, T, psi, nullptr, r, r_s, lat->U32dm, s0, ntiles, nullptr,
+                                                   frozen, st, ex);
+  return launch_tile_t<P32, 2, DM, ALL, OP_RESID, P32, P16, P16>(lat, L, T, psi, nullptr, r, r_s, lat->U16dm, s0,
+                                                                 ntiles, nullptr, frozen, st, ex);
 }
 
 }  // namespace mbbs
