@@ -56,22 +56,33 @@ __global__ void __launch_bounds__(256) k_gram(int L, size_t N, GramArgs a, doubl
   for (int p = 0; p < (ND > 0 ? ND : 1); ++p) dacc[p] = cmake(0.0, 0.0);
   const size_t stride = (size_t)gridDim.x * S;
   int buf = 0;   // two row buffers: one barrier per row tile
-  for (size_t n0 = nbeg + (size_t)blockIdx.x * S; n0 < nend; n0 += stride, buf ^= 1) {
-    const size_t n = n0 + y;
-    cplx<double> xv[NP];
-    double2 yv[NP];
-    double2* rows = sh + (size_t)buf * GRAM_MAXPAIR * S * L;
+  // the next row tile's values are loaded while the current one is summed
+  // (twice the bytes in flight per wave: the pass is bound by memory latency)
+  double2 xn[NP], yn[NP];
+  auto fetch = [&](size_t n) {
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-      double2 xe = make_double2(0, 0), ye = make_double2(0, 0);
+      xn[p] = make_double2(0, 0);
+      yn[p] = make_double2(0, 0);
       if (n < nend) {
-        xe = a.X[p][n * L + j];
-        ye = a.Y[p][n * L + j];
+        xn[p] = a.X[p][n * L + j];
+        yn[p] = a.Y[p][n * L + j];
       }
-      xv[p] = cmake(xe.x, xe.y);
-      yv[p] = ye;
-      if (p < NF) rows[((size_t)p * S + y) * L + j] = ye;
     }
+  };
+  fetch(nbeg + (size_t)blockIdx.x * S + y);
+  for (size_t n0 = nbeg + (size_t)blockIdx.x * S; n0 < nend; n0 += stride, buf ^= 1) {
+    cplx<double> xv[NP];
+    double2 yv[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      xv[p] = cmake(xn[p].x, xn[p].y);
+      yv[p] = yn[p];
+    }
+    fetch(n0 + stride + y);
+    double2* rows = sh + (size_t)buf * GRAM_MAXPAIR * S * L;
+#pragma unroll
+    for (int p = 0; p < NF; ++p) rows[((size_t)p * S + y) * L + j] = yv[p];
 #pragma unroll
     for (int p = NF; p < NP; ++p) dacc[p - NF] = dacc[p - NF] + cdot(xv[p], cmake(yv[p].x, yv[p].y));
     if constexpr (NF > 0) {
@@ -172,15 +183,32 @@ __global__ void __launch_bounds__(256) k_combo(int L, size_t N, ComboArgs a, dou
   for (int k = 0; k < nin; ++k) anymat = anymat || a.mode[k] == 2;
   const bool staged = anymat || GM == 2;
   const size_t stride = (size_t)gridDim.x * S;
+  // the next row tile's inputs are loaded while the current one is combined
+  // (more bytes in flight per wave: the pass is bound by memory latency)
+  double2 vn[COMBO_MAXIN];
+  auto fetch = [&](size_t n) {
+#pragma unroll
+    for (int k = 0; k < COMBO_MAXIN; ++k) {
+      vn[k] = make_double2(0, 0);
+      if (k < nin && n < N) vn[k] = a.in[k][roff + n * L + j];
+    }
+  };
+  fetch((size_t)blockIdx.x * S + y);
   for (size_t n0 = (size_t)blockIdx.x * S; n0 < N; n0 += stride) {
     const size_t n = n0 + y;
+    double2 vc[COMBO_MAXIN];
+#pragma unroll
+    for (int k = 0; k < COMBO_MAXIN; ++k) vc[k] = vn[k];
+    fetch(n0 + stride + y);
     if (staged) __syncthreads();
     cplx<double> acc = cmake(0.0, 0.0);
-    for (int k = 0; k < nin; ++k) {
+#pragma unroll
+    for (int k = 0; k < COMBO_MAXIN; ++k) {
+      if (k >= nin) break;
       if (a.mode[k] == 2) {
-        sh[((size_t)k * S + y) * L + j] = n < N ? a.in[k][roff + n * L + j] : make_double2(0, 0);
+        sh[((size_t)k * S + y) * L + j] = vc[k];   // zero past the last row
       } else if (n < N) {
-        double2 v = a.in[k][roff + n * L + j];
+        const double2 v = vc[k];
         if (a.mode[k] == 0) acc = acc + cmake(v.x, v.y);
         else acc = acc + cmake(a.coef[k][sys].x, a.coef[k][sys].y) * cmake(v.x, v.y);
       }
@@ -556,11 +584,9 @@ static void launch_gram_l(int L, size_t N, const GramArgs& a, double2* partial, 
   while (nf < a.npair && !a.diag[nf]) ++nf;
   const int nd = a.npair - nf;
   const dim3 grd(nb, sb.n);
-  // two full products with L fixed at compile time need more than 128 VGPRs
-  // (3 waves per SIMD instead of 4): they take the run-time-L form
 #define GL(F, D)                                                                                         \
   do {                                                                                                   \
-    if (L == LMAX && !(F == 2 && LMAX == 12))                                                            \
+    if (L == LMAX)                                                                                       \
       hipLaunchKernelGGL((k_gram<LMAX, F, D, true>), grd, dim3(L, S), shb, st, L, N, a, partial, frozen, sb.fstride); \
     else                                                                                                 \
       hipLaunchKernelGGL((k_gram<LMAX, F, D>), grd, dim3(L, S), shb, st, L, N, a, partial, frozen, sb.fstride);     \
