@@ -68,7 +68,8 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(cls, L, dims, block, ncy, nmr, sap_prec="fp32", nssor=1, clover=False):
+def algorithmic_bytes(cls, L, dims, block, ncy, nmr, sap_prec="fp32", nssor=1, clover=False, once=False,
+                      tiled=False):
     """Compulsory HBM bytes of one launch of a kernel class, averaged over the
     launches of one SAP application where they differ.  SAP storage: FP32
     8-byte complex and 72-byte link, or FP16 storage 4-byte complex plus one
@@ -80,6 +81,11 @@ def algorithmic_bytes(cls, L, dims, block, ncy, nmr, sap_prec="fp32", nssor=1, c
     mr_update  one colour: read r and psi, write psi; while r is still
                needed also read w and write r; the first step of the first
                cycle assigns psi (no psi read).
+    With psi formed once per domain solve (once=True) the MR steps only
+    carry the residual: mr_update is then nmr - 1 residual steps (read r and
+    w, write the next r) and one psi pass (read r_0 and the first nmr - 1 A r,
+    read psi except in the first cycle, write psi); the last MR step of the
+    tiled stencil (tiled=True) stores no A r, since only its omega is used.
     sap_resid  one colour: read eta, write r; except on the first half-sweep
                also read psi on the colour and on the other colour's sites
                that touch it (a fraction f of them), and 4 links per site.
@@ -100,7 +106,14 @@ def algorithmic_bytes(cls, L, dims, block, ncy, nmr, sap_prec="fp32", nssor=1, c
     if cls == "dslash64":
         return V * ((48 * L + 72) * 8 + (576 if clover else 0))
     if cls == "mr_dslash":
+        if once and tiled:
+            return Vh * (sp + 4 * lk + cl) + Vh * sp * (nmr - 1) / nmr
         return Vh * (2 * sp + 4 * lk + cl)
+    if cls == "mr_update" and once:
+        tot = 0
+        for cy in range(ncy):
+            tot += (nmr - 1) * 3 * sp + nmr * sp + (ps if cy == 0 else 2 * ps)
+        return Vh * tot / (ncy * nmr)
     if cls == "mr_update":
         tot = 0
         for cy in range(ncy):
@@ -389,8 +402,12 @@ def main():
     dominant = max(("dslash64", "mr_dslash", "mr_update", "sap_resid", "ssor"), key=lambda c: km[c])
     roof = None
     if args.profile and kl[dominant] > 0:
+        # the SAP setting in force: tiled MR stencil, psi formed once
+        sset = tuning.get(args.sap_prec, {}).get("sap", {}).get("setting", [])
+        once = len(sset) > 7 and sset[7] == 1
+        tiled = len(sset) > 6 and sset[6] >= 1
         byl = algorithmic_bytes(dominant, L, dims, cfg.block, cfg.ncy, cfg.nmr, args.sap_prec, args.nssor,
-                                bool(args.csw))
+                                bool(args.csw), once, tiled)
         avg_ms = km[dominant] / kl[dominant]
         ach = byl / (avg_ms * 1e-3) / 1e9
         traffic = measured_traffic(dominant, dims, L, args.sap_prec, bool(args.csw))
@@ -398,6 +415,7 @@ def main():
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_over_algorithmic": round(traffic / byl, 3) if traffic else None,
                 "bytes_per_launch": byl, "avg_launch_ms": avg_ms, "launches": kl[dominant],
+                "sap_tiled": tiled, "sap_psi_once": once,
                 "class_ms": {k: round(v, 3) for k, v in km.items()}}
 
     cpu = None

@@ -160,7 +160,16 @@ int mbbs_lattice_table(mbbs_lattice_t lat, int which, int32_t* out, size_t count
  *      output bits are unchanged, the MR sums follow the sub-block shape);
  *      2: as 1, and each MR step also performs the previous step's update of
  *      psi and r (one pass over the fields less per step; same bits as 1);
- *      FP64 and FP32 only (EINVAL for MBBS_TUNE_TILE_FP16S)
+ *      FP64 and FP32 only (EINVAL for MBBS_TUNE_TILE_FP16S); 3: as 1 with
+ *      tiles of at most half the LDS, so two workgroups share a CU (one stages
+ *      its tile while the other computes; more hops leave the smaller tile)
+ *  MBBS_TUNE_TILE_COLS_FP64/FP32/FP16S  columns per workgroup of the tiled
+ *      kernels (0..256; 0, the default: all L): with a value that divides L
+ *      into the kernel's column pairs (FP32 / FP16 storage: even) the columns
+ *      of a tile are split over L / value adjacent workgroups, each staging
+ *      only its columns, so that a larger tile fits the LDS (fewer hops leave
+ *      it; its links are read once per workgroup); other values or L act as
+ *      0.  Results are the same bits as with 0 for the same tile shape
  *  MBBS_TUNE_MR_ONCE_FP64/FP32/FP16S  1: each MR domain solve of up to 4 steps
  *      forms psi once at its end, psi (+)= c r_0 - sum_j e_j w_j (c = sum_k
  *      omega_k, e_j = omega_j sum_{k>j} omega_k, the same sum as the step-by-step
@@ -181,7 +190,8 @@ enum { MBBS_TUNE_GROUP_FP64 = 0, MBBS_TUNE_GROUP_FP32 = 1, MBBS_TUNE_GROUP_FP16S
        MBBS_TUNE_CHUNK_FP16S = 19, MBBS_TUNE_BLOCK_THREADS_FP64 = 20,
        MBBS_TUNE_BLOCK_THREADS_FP32 = 21, MBBS_TUNE_BLOCK_THREADS_FP16S = 22,
        MBBS_TUNE_TILE_FP64 = 23, MBBS_TUNE_TILE_FP32 = 24, MBBS_TUNE_TILE_FP16S = 25,
-       MBBS_TUNE_MR_ONCE_FP64 = 26, MBBS_TUNE_MR_ONCE_FP32 = 27, MBBS_TUNE_MR_ONCE_FP16S = 28 };
+       MBBS_TUNE_MR_ONCE_FP64 = 26, MBBS_TUNE_MR_ONCE_FP32 = 27, MBBS_TUNE_MR_ONCE_FP16S = 28,
+       MBBS_TUNE_TILE_COLS_FP64 = 29, MBBS_TUNE_TILE_COLS_FP32 = 30, MBBS_TUNE_TILE_COLS_FP16S = 31 };
 int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value);
 
 /* The tile shape the LDS-tiled kernels use for L columns in precision prec

@@ -11,8 +11,8 @@ order in which the hops are summed, and the MR domain sums follow the block
 or tile shape; every other setting leaves the operator's result bits alone.
 
 A setting is (group, threads, split, pair, nt[, columns per thread[, tiled[,
-psi once]]]); the last element selects the MR domain solve that forms psi
-once per domain solve (a SAP-only choice).
+psi once[, columns per tiled workgroup]]]]); psi once selects the MR domain
+solve that forms psi once per domain solve (a SAP-only choice).
 """
 
 from __future__ import annotations
@@ -49,8 +49,17 @@ def operator_candidates(L, prec):
     if L % other == 0:
         out += [(L, t, 0, 0, nt, other) for t in (128, 256) for nt in (0, 1)]
     out += [(L, 256, sp, 0, nt) for sp in (2, 4) for nt in (0, 1)]
-    # the LDS-tiled kernels (where a tile shape fits)
-    return out + [(L, 256, 0, 0, nt, 0, 1) for nt in (0, 1)]
+    # the LDS-tiled kernels (where a tile shape fits), whole-LDS and half-LDS
+    # tiles, all columns or half of them per workgroup
+    out += [(L, 256, 0, 0, nt, 0, tl) for tl in (1, 3) for nt in (0, 1)]
+    if L % (2 * c) == 0:
+        out += [(L, 256, 0, 0, nt, 0, tl, 0, L // 2) for tl in (1, 3) for nt in (0, 1)]
+    return out
+
+
+def _full(setting):
+    """The setting with every optional element present (defaults 0)."""
+    return tuple(setting) + (0,) * (9 - len(setting))
 
 
 def _tiled(setting):
@@ -62,6 +71,7 @@ def apply(lat, prec, setting):
     ch = setting[5] if len(setting) > 5 else 0
     B.mbbs_lattice_tune(lat, B.TUNE_TILE[prec], setting[6] if _tiled(setting) else 0)
     B.mbbs_lattice_tune(lat, B.TUNE_MR_ONCE[prec], setting[7] if len(setting) > 7 else 0)
+    B.mbbs_lattice_tune(lat, B.TUNE_TILE_COLS[prec], setting[8] if len(setting) > 8 else 0)
     B.mbbs_lattice_tune(lat, B.TUNE_CHUNK[prec], ch)
     B.mbbs_lattice_tune(lat, B.TUNE_GROUP[prec], g)
     B.mbbs_lattice_tune(lat, B.TUNE_BLOCK_THREADS_PREC[prec], t)
@@ -102,14 +112,13 @@ def tune_operator(lat, V, L, prec, stream=None, reps=3):
     return best, times
 
 
-def tune_sap(lat, V, L, prec, op_times, stream=None, ncy=4, nmr=4, reps=2):
-    """Among the fastest split, one-thread-per-site and tiled operator
-    settings (from tune_operator's timings), one column per thread for FP32 /
-    FP16 storage, and the fastest one-thread-per-site shape with the tiled MR
-    kernel (with and without the MR update folded in), keep the one under
-    which the SAP preconditioner itself runs faster.  Returns (setting,
-    {setting: ms})."""
-    import torch
+def sap_candidates(L, prec, op_times):
+    """The SAP settings tune_sap times, from tune_operator's timings: the
+    fastest split, one-thread-per-site and tiled operator settings, the tiled
+    one with the MR update folded in (FP64 / FP32), with the other tile sizes
+    (whole or half LDS, all or half the columns per workgroup), the tiled MR
+    step under the fastest one-thread-per-site shape, each of these with psi
+    formed once, and one column per thread (FP32 / FP16 storage)."""
     split = [k for k in op_times if k[2] in (2, 4)]
     classic = [k for k in op_times if k[2] not in (2, 4) and not _tiled(k)]
     tiled = [k for k in op_times if _tiled(k)]
@@ -118,19 +127,40 @@ def tune_sap(lat, V, L, prec, op_times, stream=None, ncy=4, nmr=4, reps=2):
     if tiled and folded:
         # the MR update folded into the next MR step
         cands.append(tuple(min(tiled, key=op_times.get)[:6]) + (2,))
+    if tiled:
+        # the other tile sizes than the operator's fastest: whole or half LDS,
+        # all columns or half of them per workgroup
+        bt = min(tiled, key=op_times.get)
+        c = next(c for c in range(_cmax(prec), 0, -1) if L % c == 0)
+        halves = [L // 2] if L % (2 * c) == 0 else []
+        seen = {_full(x) for x in cands}
+        for tl in (1, 3):
+            for lg in [0] + halves:
+                v = tuple(bt[:6]) + (tl, 0) + ((lg,) if lg else ())
+                if _full(v) not in seen:
+                    cands.append(v)
+                    seen.add(_full(v))
     if classic and tiled:
         # the SAP residual kernel in the best classic shape, the MR step tiled
         best = min(classic, key=op_times.get)
         base = tuple(best[:5]) + ((best[5] if len(best) > 5 else 0),)
-        cands += [base + (1,)] + ([base + (2,)] if folded else [])
+        cands += [base + (1,), base + (3,)] + ([base + (2,)] if folded else [])
     # psi formed once per domain solve, on the untiled and tiled candidates
     pad = lambda c: tuple(c[:5]) + tuple(c[5:7]) + (0,) * (7 - len(c[:7]))
-    cands += [pad(c) + (1,) for c in list(cands) if not (len(c) > 6 and c[6] == 2)]
+    cands += [pad(c) + (1,) + tuple(c[8:9]) for c in list(cands) if not (len(c) > 6 and c[6] == 2)]
     if classic and prec != B.FP64:
         # one column per thread: more waves in flight per CU for the domain kernels
         g, t, sp, pr, nt = min(classic, key=op_times.get)[:5]
         cands += [(L, tt, 0, pv, nt, 1) for tt in (128, 256) for pv in (0, 1)]
         cands += [(L, 256, 0, 1, nt, 0)]
+    return cands
+
+
+def tune_sap(lat, V, L, prec, op_times, stream=None, ncy=4, nmr=4, reps=2):
+    """Of sap_candidates' settings keep the one under which the SAP
+    preconditioner itself runs faster.  Returns (setting, {setting: ms})."""
+    import torch
+    cands = sap_candidates(L, prec, op_times)
     dev = torch.device("cuda")
     s = stream or torch.cuda.current_stream()
     X = torch.zeros((12 * V, L), dtype=torch.complex128, device=dev)

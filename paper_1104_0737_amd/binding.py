@@ -204,6 +204,7 @@ TUNE_NT_STORE = {0: 14, 1: 15, 2: 16}   # precision -> knob
 TUNE_CHUNK = {0: 17, 1: 18, 2: 19}      # precision -> knob
 TUNE_HOP_PAIR = {0: 11, 1: 12, 2: 13}   # precision -> knob
 TUNE_TILE = {0: 23, 1: 24, 2: 25}       # precision -> knob
+TUNE_TILE_COLS = {0: 29, 1: 30, 2: 31}  # precision -> knob
 
 
 def mbbs_lattice_tune(lat, knob, value):

@@ -126,7 +126,9 @@ struct mbbs_lattice_s {
   int hop_pair[3] = {0, 0, 0};  // operator: both hops of a direction in flight at once
   int nt_store[3] = {0, 0, 0};  // operator: nontemporal output stores
   int chunk[3] = {0, 0, 0};     // columns per thread of the stencil kernels (0: automatic)
-  int tile[3] = {0, 0, 0};      // LDS-tiled operator and MR kernels: 0 off, 1 on, 2 on with the MR update fused
+  int tile[3] = {0, 0, 0};      // LDS-tiled operator and MR kernels: 0 off, 1 on, 2 on with the MR update fused,
+                                // 3 on with tiles of at most half the LDS
+  int tile_lg[3] = {0, 0, 0};   // columns per tiled workgroup (0: all L)
   int mr_once[3] = {0, 0, 0};   // MR domain solves form psi once from r_0 and the steps' A r (1) or step by step (0)
   // SSOR wavefront order inside a domain: local indices sorted by the
   // hyperplane h = l_0 + l_1 + l_2 + l_3 (then by local index); hyperplane h

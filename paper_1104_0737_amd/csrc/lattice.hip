@@ -364,10 +364,16 @@ extern "C" int mbbs_lattice_tune(mbbs_lattice_t lat, int knob, int value) {
     case MBBS_TUNE_TILE_FP64:
     case MBBS_TUNE_TILE_FP32:
     case MBBS_TUNE_TILE_FP16S:
-      MBBS_CHECK(value >= 0 && value <= 2, "tiled stencil setting must be 0, 1 or 2");
+      MBBS_CHECK(value >= 0 && value <= 3, "tiled stencil setting must be 0, 1, 2 or 3");
       // the folded MR update is withdrawn for FP16 storage: its only run did not finish
       MBBS_CHECK(!(value == 2 && knob == MBBS_TUNE_TILE_FP16S), "folded MR update not available for FP16 storage");
       lat->tile[knob - MBBS_TUNE_TILE_FP64] = value;
+      return MBBS_OK;
+    case MBBS_TUNE_TILE_COLS_FP64:
+    case MBBS_TUNE_TILE_COLS_FP32:
+    case MBBS_TUNE_TILE_COLS_FP16S:
+      MBBS_CHECK(value >= 0 && value <= 256, "columns per tiled workgroup must be in 0..256");
+      lat->tile_lg[knob - MBBS_TUNE_TILE_COLS_FP64] = value;
       return MBBS_OK;
     case MBBS_TUNE_MR_ONCE_FP64:
     case MBBS_TUNE_MR_ONCE_FP32:

@@ -1,6 +1,7 @@
 // LDS-tiled stencil launches: a workgroup owns one tile (a sub-block of a SAP
-// domain) and all L columns, stages the tile's input spinors in LDS, and
-// reads from global memory only the neighbours outside the tile.
+// domain) and all L columns or a group of them, stages the tile's input
+// spinors in LDS, and reads from global memory only the neighbours outside
+// the tile.
 #pragma once
 
 #include "internal.h"
@@ -12,6 +13,8 @@ struct TileArgs {
   int tstr[4];     // strides of the tile-local lexicographic index
   int ts;          // sites per tile
   int tpd;         // tiles per domain
+  int lg;          // columns per workgroup (a divisor of L)
+  int ng;          // workgroups per tile: L / lg
   unsigned lds;    // dynamic LDS bytes per workgroup
 };
 

@@ -1,7 +1,8 @@
 // LDS-tiled stencil kernels (Sec. 2.1, block hopping-term equation; Sec. 2.2,
 // the Dirichlet operator A_DD of the MR domain solve).  A workgroup owns one
-// tile of sites (a sub-block of a SAP domain) and all L columns: it copies
-// the tile's input spinors into LDS with full-width coalesced loads, then
+// tile of sites (a sub-block of a SAP domain) and all L columns, or a group
+// of lg of them (then L / lg adjacent workgroups share a tile and its links):
+// it copies the tile's input spinors into LDS with coalesced loads, then
 // every hop whose neighbour lies in the tile reads it from LDS and only the
 // hops that leave the tile read global memory.  Each spinor of the tile thus
 // passes the L1/L2 path once instead of once per neighbour.  A thread owns
@@ -55,6 +56,45 @@ __device__ __forceinline__ int tile_row_index(const GeomK& k, const TileArgs& T,
   const int l3 = p.base[3] + r2 / T.t[2];
   const int loc = p.base[0] + k.g.b[0] * (l1 + k.g.b[1] * (l2 + k.g.b[2] * l3));
   return s0 + p.dom * k.g.Vb + loc;
+}
+
+// Copy the tile's columns [cb, cb + Lg) between the field (12 L elements per
+// site) and LDS (SS elements per site, element e of a site at e Lg), in units
+// of U.  With Lg = L a site's elements are one contiguous row.
+template <typename U, bool TO_LDS, typename E>
+__device__ __forceinline__ void tile_copy_u(E* g, E* lds, const int* row_site, int ts, int t0, int L, int Lg, int SS,
+                                            int cb) {
+  const int nrow = Lg == L ? 1 : 12, rlen = Lg == L ? 12 * L : Lg;
+  const int ru = rlen * (int)sizeof(E) / (int)sizeof(U), su = nrow * ru;
+  for (int f = threadIdx.x; f < ts * su; f += blockDim.x) {
+    const int t = f / su, rem = f - t * su, e = rem / ru, w = rem - e * ru;
+    const int r = t / t0, x = t - r * t0;
+    U* gp = (U*)(g + ((size_t)(row_site[r] + x) * 12 + e) * L + cb) + w;
+    U* lp = (U*)(lds + (size_t)t * SS + e * Lg) + w;
+    if constexpr (TO_LDS) *lp = *gp;
+    else *gp = *lp;
+  }
+}
+
+template <bool TO_LDS, typename E>
+__device__ __forceinline__ void tile_copy(E* g, E* lds, const int* row_site, int ts, int t0, int L, int Lg, int SS,
+                                          int cb) {
+  const int rlen = Lg == L ? 12 * L : Lg;
+  if ((rlen * (int)sizeof(E)) % 16 == 0) tile_copy_u<float4, TO_LDS>(g, lds, row_site, ts, t0, L, Lg, SS, cb);
+  else tile_copy_u<uint2, TO_LDS>(g, lds, row_site, ts, t0, L, Lg, SS, cb);
+}
+
+// The per-(site, column) scales of FP16 storage, likewise.
+template <bool TO_LDS>
+__device__ __forceinline__ void tile_copy_scales(float* g, float* lds_s, const int* row_site, int ts, int t0, int L,
+                                                 int Lg, int cb) {
+  for (int f = threadIdx.x; f < ts * Lg; f += blockDim.x) {
+    const int t = f / Lg, w = f - t * Lg;
+    const int r = t / t0, x = t - r * t0;
+    float* gp = g + (size_t)(row_site[r] + x) * L + cb + w;
+    if constexpr (TO_LDS) lds_s[f] = *gp;
+    else *gp = lds_s[f];
+  }
 }
 
 // C consecutive columns of element e of a spinor into the hop's registers
@@ -165,7 +205,7 @@ __device__ __forceinline__ void hop_tiled(const GeomK& k, const SiteCtx& c, cons
                                           int ts, const typename Store<PIN>::Elem* __restrict__ in,
                                           const float* __restrict__ in_s, const typename Store<PIN>::Elem* lds,
                                           const float* lds_s, const LinkElem<PL>* __restrict__ U, int L, int col0,
-                                          const TileExtra& mf, const cplx<R> (&om)[C],
+                                          int Lg, int cl0, const TileExtra& mf, const cplx<R> (&om)[C],
                                           cplx<R> (&acc)[4][3][C], R& token) {
   if (hop_skipped<ORDER, HOPS, MU, FWD>(k, c)) return;
   const bool inside = FWD ? lt[MU] < T.t[MU] - 1 : lt[MU] > 0;
@@ -179,12 +219,12 @@ __device__ __forceinline__ void hop_tiled(const GeomK& k, const SiteCtx& c, cons
   HopData<PIN, PL, C> d;
   link_load<PL, MU>(U, ls, d.lk);
   if (inside) {
-    const typename Store<PIN>::Elem* q = lds + (size_t)tn * tile_ss<typename Store<PIN>::Elem>(L) + col0;
+    const typename Store<PIN>::Elem* q = lds + (size_t)tn * tile_ss<typename Store<PIN>::Elem>(Lg) + cl0;
 #pragma unroll
-    for (int e = 0; e < 12; ++e) ld_cols<PIN, C>(q + e * L, e, d.sp);
+    for (int e = 0; e < 12; ++e) ld_cols<PIN, C>(q + e * Lg, e, d.sp);
     if constexpr (Store<PIN>::scaled) {
 #pragma unroll
-      for (int qq = 0; qq < C; ++qq) d.sc[qq] = lds_s[tn * L + col0 + qq];
+      for (int qq = 0; qq < C; ++qq) d.sc[qq] = lds_s[tn * Lg + cl0 + qq];
     }
   } else if constexpr (HALO == 1) {
     using E = typename Store<PIN>::Elem;
@@ -216,8 +256,10 @@ enum { OP_DSLASH = 0, OP_MR = 1, OP_MRF = 2, OP_RESID = 3 };
 // in LDS; neighbours outside the tile form theirs from the previous r and A r.
 // OP_RESID: the SAP residual on one colour's sites, r = eta - psi + kappa H psi
 // over all hops (in = psi, out = r of precision PO, mf.eta).
-// Launch: one workgroup per tile, T.ts * L / C threads, T.lds bytes of LDS.
-template <int PIN, int PL, int C, int ORDER, int HOPS, int OP, int LT, int PPSI = PIN, int PO = PIN>
+// Launch: T.ng workgroups per tile (adjacent blocks; column group g holds
+// columns [g lg, (g + 1) lg)), T.ts * lg / C threads, T.lds bytes of LDS.
+// LT / LGT: L and lg fixed at compile time (0: taken from L and T.lg).
+template <int PIN, int PL, int C, int ORDER, int HOPS, int OP, int LT, int LGT, int PPSI = PIN, int PO = PIN>
 __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, int L, TileArgs T,
                                                        const typename Store<PIN>::Elem* __restrict__ in,
                                                        const float* __restrict__ in_s,
@@ -227,14 +269,18 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
                                                        double* __restrict__ partial,
                                                        const int* __restrict__ frozen, TileExtra mf) {
   if constexpr (LT > 0) L = LT;
+  const int Lg = LGT > 0 ? LGT : T.lg;
+  const int ng = LT > 0 && LGT > 0 ? LT / LGT : T.ng;
   using E = typename Store<PIN>::Elem;
   using R = typename Store<PL>::Real;
   extern __shared__ float4 tile_lds[];
   __shared__ int row_site[256];
   E* lds = (E*)tile_lds;
-  const int SS = tile_ss<E>(L);
+  const int SS = tile_ss<E>(Lg);
   float* lds_s = (float*)(lds + (size_t)T.ts * SS);
-  const int tb = xcd_block(blockIdx.x, gridDim.x);
+  const int tg = xcd_block(blockIdx.x, gridDim.x);
+  const int tb = tg / ng;                 // the tile
+  const int cb = (tg - tb * ng) * Lg;     // the workgroup's first column
   const TilePos p = tile_pos(k, T, tb);
   const int nrows = T.ts / T.t[0];
   // a tile lies in one domain, hence one system: the flag test is block-uniform
@@ -248,27 +294,15 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
     row_site[r] = ORDER == DM ? i : site_ctx_tiled(k, i).s;
   }
   __syncthreads();
-  // stage: each row of t[0] sites is contiguous in the field (all L columns);
-  // LDS holds site ts at ts * SS elements
-  const int site_f4 = 12 * L * (int)sizeof(E) / 16, ss_f4 = SS * (int)sizeof(E) / 16;
-  {
-    for (int f = threadIdx.x; f < T.ts * site_f4; f += blockDim.x) {
-      const int t = f / site_f4, w = f - t * site_f4;
-      const int r = t / T.t[0], x = t - r * T.t[0];
-      tile_lds[t * ss_f4 + w] = ((const float4*)in)[(size_t)(row_site[r] + x) * site_f4 + w];
-    }
-    if constexpr (Store<PIN>::scaled) {
-      const int row_n = T.t[0] * L;
-      for (int f = threadIdx.x; f < nrows * row_n; f += blockDim.x) {
-        const int r = f / row_n, w = f - r * row_n;
-        lds_s[f] = in_s[(size_t)row_site[r] * L + w];
-      }
-    }
-  }
+  // stage the tile's columns [cb, cb + Lg); LDS holds site ts at ts * SS elements
+  tile_copy<true>(const_cast<E*>(in), lds, row_site, T.ts, T.t[0], L, Lg, SS, cb);
+  if constexpr (Store<PIN>::scaled)
+    tile_copy_scales<true>(const_cast<float*>(in_s), lds_s, row_site, T.ts, T.t[0], L, Lg, cb);
   __syncthreads();
-  const int nchunk = L / C;
+  const int nchunk = Lg / C;
   const int ts = threadIdx.x / nchunk;
-  const int col0 = (threadIdx.x - ts * nchunk) * C;
+  const int cl0 = (threadIdx.x - ts * nchunk) * C;   // first column of the thread: in LDS
+  const int col0 = cb + cl0;                          // and in the field
   int lt[4];
   {
     int q = ts;
@@ -291,10 +325,10 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
     for (int q = 0; q < C; ++q) {
       const double* o = mf.omega + ((size_t)p.dom * L + col0 + q) * 2;
       om[q] = cmake<R>((R)o[0], (R)o[1]);
-      const size_t lb = (size_t)ts * SS + col0 + q, ls = (size_t)ts * L + col0 + q;
+      const size_t lb = (size_t)ts * SS + cl0 + q, ls = (size_t)ts * Lg + cl0 + q;
       const size_t base = (size_t)s * 12 * L + col0 + q, sidx = (size_t)s * L + col0 + q;
       cplx<R> rv[4][3], wv[4][3];
-      load_spinor<PIN, R>(lds, lds_s, lb, L, ls, rv);
+      load_spinor<PIN, R>(lds, lds_s, lb, Lg, ls, rv);
       load_spinor<PIN, R>((const E*)mf.w_old, mf.w_old_s, base, L, sidx, wv);
 #pragma unroll
       for (int sp = 0; sp < 4; ++sp)
@@ -304,22 +338,12 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
                                  mr_mul(om[q], rv[sp][a]), mf.assign);
           rv[sp][a] = rv[sp][a] - mr_mul(om[q], wv[sp][a]);
         }
-      store_spinor<PIN, R>(lds, lds_s, lb, L, ls, rv);
+      store_spinor<PIN, R>(lds, lds_s, lb, Lg, ls, rv);
     }
     __syncthreads();
     // the tile's new r to global memory
-    for (int f = threadIdx.x; f < T.ts * site_f4; f += blockDim.x) {
-      const int t = f / site_f4, w = f - t * site_f4;
-      const int r = t / T.t[0], x = t - r * T.t[0];
-      ((float4*)mf.r_new)[(size_t)(row_site[r] + x) * site_f4 + w] = tile_lds[t * ss_f4 + w];
-    }
-    if constexpr (Store<PIN>::scaled) {
-      const int row_n = T.t[0] * L;
-      for (int f = threadIdx.x; f < nrows * row_n; f += blockDim.x) {
-        const int r = f / row_n, w = f - r * row_n;
-        mf.r_new_s[(size_t)row_site[r] * L + w] = lds_s[f];
-      }
-    }
+    tile_copy<false>((E*)mf.r_new, lds, row_site, T.ts, T.t[0], L, Lg, SS, cb);
+    if constexpr (Store<PIN>::scaled) tile_copy_scales<false>(mf.r_new_s, lds_s, row_site, T.ts, T.t[0], L, Lg, cb);
   }
   constexpr int HALO = OP == OP_MRF ? 1 : 0;
   cplx<R> acc[4][3][C];
@@ -331,14 +355,14 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
       for (int q = 0; q < C; ++q) acc[sp][a][q] = cmake<R>(0, 0);
   // the hops in the order of the one-thread-per-site kernels
   R token = 0;
-  hop_tiled<PIN, PL, C, ORDER, HOPS, 0, 1, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, mf, om, acc, token);
-  hop_tiled<PIN, PL, C, ORDER, HOPS, 0, 0, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, mf, om, acc, token);
-  hop_tiled<PIN, PL, C, ORDER, HOPS, 1, 1, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, mf, om, acc, token);
-  hop_tiled<PIN, PL, C, ORDER, HOPS, 1, 0, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, mf, om, acc, token);
-  hop_tiled<PIN, PL, C, ORDER, HOPS, 2, 1, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, mf, om, acc, token);
-  hop_tiled<PIN, PL, C, ORDER, HOPS, 2, 0, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, mf, om, acc, token);
-  hop_tiled<PIN, PL, C, ORDER, HOPS, 3, 1, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, mf, om, acc, token);
-  hop_tiled<PIN, PL, C, ORDER, HOPS, 3, 0, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, mf, om, acc, token);
+  hop_tiled<PIN, PL, C, ORDER, HOPS, 0, 1, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, Lg, cl0, mf, om, acc, token);
+  hop_tiled<PIN, PL, C, ORDER, HOPS, 0, 0, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, Lg, cl0, mf, om, acc, token);
+  hop_tiled<PIN, PL, C, ORDER, HOPS, 1, 1, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, Lg, cl0, mf, om, acc, token);
+  hop_tiled<PIN, PL, C, ORDER, HOPS, 1, 0, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, Lg, cl0, mf, om, acc, token);
+  hop_tiled<PIN, PL, C, ORDER, HOPS, 2, 1, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, Lg, cl0, mf, om, acc, token);
+  hop_tiled<PIN, PL, C, ORDER, HOPS, 2, 0, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, Lg, cl0, mf, om, acc, token);
+  hop_tiled<PIN, PL, C, ORDER, HOPS, 3, 1, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, Lg, cl0, mf, om, acc, token);
+  hop_tiled<PIN, PL, C, ORDER, HOPS, 3, 0, HALO, R>(k, c, T, lt, ts, in, in_s, lds, lds_s, U, L, col0, Lg, cl0, mf, om, acc, token);
   if (k.clov) clover_apply<ORDER, C, R>(k, s, acc);
   const R kap = (R)kappa_of(k, c, kappa);
   double sums[C][3];
@@ -347,7 +371,7 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
     const size_t base = (size_t)s * 12 * L + col0 + q;
     const size_t sidx = (size_t)s * L + col0 + q;
     cplx<R> v[4][3], wv[4][3];
-    load_spinor<PIN, R>(lds, lds_s, (size_t)ts * SS + col0 + q, L, (size_t)ts * L + col0 + q, v);
+    load_spinor<PIN, R>(lds, lds_s, (size_t)ts * SS + cl0 + q, Lg, (size_t)ts * Lg + cl0 + q, v);
     if constexpr (OP == OP_RESID) {
       // r = eta - psi + kappa H psi, in the residual kernel's order
       load_spinor<PO, R>((const typename Store<PO>::Elem*)mf.eta, mf.eta_s, base, L, sidx, wv);
@@ -390,26 +414,26 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
     // (G interleaved groups of sites, then the groups), through the LDS the
     // tile's spinors no longer need
     __syncthreads();
-    double* red = (double*)tile_lds;                 // [3][ts][L]
-    double* red2 = red + (size_t)3 * T.ts * L;       // [3][G][L]
+    double* red = (double*)tile_lds;                 // [3][ts][Lg]
+    double* red2 = red + (size_t)3 * T.ts * Lg;      // [3][G][Lg]
 #pragma unroll
     for (int q = 0; q < C; ++q)
 #pragma unroll
-      for (int m = 0; m < 3; ++m) red[((size_t)m * T.ts + ts) * L + col0 + q] = sums[q][m];
+      for (int m = 0; m < 3; ++m) red[((size_t)m * T.ts + ts) * Lg + cl0 + q] = sums[q][m];
     __syncthreads();
     const int G = T.ts >= 16 ? 16 : T.ts;
-    for (int e = threadIdx.x; e < 3 * G * L; e += blockDim.x) {
-      const int m = e / (G * L), rem = e - m * G * L, g = rem / L, col = rem - g * L;
+    for (int e = threadIdx.x; e < 3 * G * Lg; e += blockDim.x) {
+      const int m = e / (G * Lg), rem = e - m * G * Lg, g = rem / Lg, col = rem - g * Lg;
       double a = 0;
-      for (int y = g; y < T.ts; y += G) a += red[((size_t)m * T.ts + y) * L + col];
-      red2[((size_t)m * G + g) * L + col] = a;
+      for (int y = g; y < T.ts; y += G) a += red[((size_t)m * T.ts + y) * Lg + col];
+      red2[((size_t)m * G + g) * Lg + col] = a;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 3 * L; e += blockDim.x) {
-      const int m = e / L, col = e - m * L;
+    for (int e = threadIdx.x; e < 3 * Lg; e += blockDim.x) {
+      const int m = e / Lg, col = e - m * Lg;
       double a = 0;
-      for (int g = 0; g < G; ++g) a += red2[((size_t)m * G + g) * L + col];
-      partial[((size_t)tb * L + col) * 3 + m] = a;
+      for (int g = 0; g < G; ++g) a += red2[((size_t)m * G + g) * Lg + col];
+      partial[((size_t)tb * L + cb + col) * 3 + m] = a;
     }
   }
 }
@@ -418,27 +442,36 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
 // keeps TS * L / C threads within one workgroup (and at least one wave), and
 // whose LDS (the spinors, or the reduction that reuses them) fits 160 KiB.
 // es: bytes per staged element; C columns per thread; scaled: FP16 storage.
-bool pick_tile(const mbbs_lattice_s* lat, int L, size_t es, int C, bool scaled, TileArgs* out) {
+// The first candidate shape whose workgroup (tile sites x lg / C threads) and
+// LDS (staged spinors, or the MR sums' scratch, plus the row table) fit:
+// within the whole 160 KiB for cap = 1, within half of it for cap = 2 (two
+// workgroups resident per CU, one staging while the other computes).  lg:
+// columns per workgroup when it divides L into whole column pairs of the
+// kernel and aligned rows, else all L.
+bool pick_tile(const mbbs_lattice_s* lat, int L, size_t es, int C, bool scaled, int cap, int lg, TileArgs* out) {
   static const int cand[][4] = {{4, 4, 4, 4}, {8, 4, 4, 2}, {4, 4, 4, 2}, {8, 4, 2, 2}, {4, 4, 2, 2},
                                 {8, 2, 2, 2}, {4, 2, 2, 2}, {2, 2, 2, 2}, {4, 4, 2, 1}, {2, 2, 2, 1},
                                 {2, 2, 1, 1}};
   const Geom& g = lat->g;
   if (L % C) return false;
+  if (lg <= 0 || lg >= L || L % lg || lg % C || (lg * es) % 8 || (12 * lg * es) % 16) lg = L;
   for (const auto& t : cand) {
     bool ok = true;
     for (int m = 0; m < 4; ++m) ok = ok && g.b[m] % t[m] == 0;
     if (!ok) continue;
     const int ts = t[0] * t[1] * t[2] * t[3];
-    const int nthr = ts * (L / C);
+    const int nthr = ts * (lg / C);
     if (nthr > TILE_THREADS || nthr < 64) continue;
     if (ts / t[0] > 256) continue;
-    const size_t spin = (size_t)ts * (12 * L * es + 16) + (scaled ? (size_t)ts * L * sizeof(float) : 0);
+    const size_t spin = (size_t)ts * (12 * lg * es + 16) + (scaled ? (size_t)ts * lg * sizeof(float) : 0);
     const int G = ts >= 16 ? 16 : ts;
-    const size_t red = (size_t)3 * (ts + G) * L * sizeof(double);
+    const size_t red = (size_t)3 * (ts + G) * lg * sizeof(double);
     const size_t lds = std::max(spin, red);
-    if (lds + 256 * sizeof(int) > 160 * 1024) continue;
+    if (lds + 256 * sizeof(int) > 160 * 1024 / (size_t)cap) continue;
     if ((12 * L * es) % 16) continue;
     TileArgs T;
+    T.lg = lg;
+    T.ng = L / lg;
     for (int m = 0; m < 4; ++m) T.t[m] = t[m];
     T.ts = ts;
     T.tstr[0] = 1;
@@ -469,14 +502,19 @@ int launch_tile_t(const mbbs_lattice_s* lat, int L, const TileArgs& T, const voi
   using EL = LinkElem<PL>;
   GeomK gk = lat->gk;
   gk.nt_store = lat->nt_store[PL];
-  const dim3 blk(T.ts * (L / C)), grd(ntiles);
-  if (L == 12) {
-    auto fn = k_tile<P, PL, C, ORDER, HOPS, OP, 12, PPSI, PO>;
+  const dim3 blk(T.ts * (T.lg / C)), grd(ntiles * T.ng);
+  if (L == 12 && T.lg == 12) {
+    auto fn = k_tile<P, PL, C, ORDER, HOPS, OP, 12, 12, PPSI, PO>;
+    allow_tile_lds((const void*)fn);
+    hipLaunchKernelGGL(fn, grd, blk, T.lds, st, gk, lat->kappa, L, T, (const E*)in, in_s, (EO*)out, out_s,
+                       (const EL*)U, s0, partial, frozen, mf);
+  } else if (L == 12 && T.lg == 6) {
+    auto fn = k_tile<P, PL, C, ORDER, HOPS, OP, 12, 6, PPSI, PO>;
     allow_tile_lds((const void*)fn);
     hipLaunchKernelGGL(fn, grd, blk, T.lds, st, gk, lat->kappa, L, T, (const E*)in, in_s, (EO*)out, out_s,
                        (const EL*)U, s0, partial, frozen, mf);
   } else {
-    auto fn = k_tile<P, PL, C, ORDER, HOPS, OP, 0, PPSI, PO>;
+    auto fn = k_tile<P, PL, C, ORDER, HOPS, OP, 0, 0, PPSI, PO>;
     allow_tile_lds((const void*)fn);
     hipLaunchKernelGGL(fn, grd, blk, T.lds, st, gk, lat->kappa, L, T, (const E*)in, in_s, (EO*)out, out_s,
                        (const EL*)U, s0, partial, frozen, mf);
@@ -504,15 +542,20 @@ int dslash_tiled_p(const mbbs_lattice_s* lat, int L, int order, bool blocked, co
 
 static size_t elem_bytes(int prec) { return prec == P64 ? 16 : prec == P32 ? 8 : 4; }
 
+// setting 3 asks for tiles of at most half the LDS
+static int tile_cap(const mbbs_lattice_s* lat, int prec) { return lat->tile[prec] == 3 ? 2 : 1; }
+
 bool tile_plan(const mbbs_lattice_s* lat, int L, int prec, TileArgs* out) {
   if (lat->tile[prec] < 1) return false;
-  return pick_tile(lat, L, elem_bytes(prec), tile_cols(prec), prec == P16, out);
+  return pick_tile(lat, L, elem_bytes(prec), tile_cols(prec), prec == P16, tile_cap(lat, prec), lat->tile_lg[prec],
+                   out);
 }
 
 bool tile_plan_resid(const mbbs_lattice_s* lat, int L, int prec, TileArgs* out) {
   if (lat->tile[prec] < 1) return false;
   // the staged field is psi: FP64 in FP64 SAP, FP32 otherwise
-  return pick_tile(lat, L, prec == P64 ? 16 : 8, tile_cols(prec), false, out);
+  return pick_tile(lat, L, prec == P64 ? 16 : 8, tile_cols(prec), false, tile_cap(lat, prec), lat->tile_lg[prec],
+                   out);
 }
 
 int launch_dslash_tiled(const mbbs_lattice_s* lat, int L, int prec, int order, bool blocked, const TileArgs& T,

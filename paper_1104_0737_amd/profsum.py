@@ -39,23 +39,35 @@ def traffic(fetch_db, write_db, cfetch_db, cwrite_db, classes, copy_bytes=4 << 3
     """HBM bytes per launch of the named kernels from a FETCH_SIZE and a
     WRITE_SIZE run (KiB per dispatch), each scaled by what the same counter
     reads for a plain device copy of `copy_bytes` bytes.  classes maps a
-    kernel class to its kernel name.  Returns a JSON-ready dict that also
-    records the hash of the sources the counters were taken with."""
+    kernel class to its kernel name, or to several names joined by '+' (the
+    class's figure is then the mean over all their dispatches).  Returns a
+    JSON-ready dict that also records the hash of the sources the counters
+    were taken with."""
     from .build import source_hash
 
     def avg(db, cname, kname):
-        vals = [v for k, c, n, v in counters(db) if c == cname and k == kname]
-        return vals[0] if vals else None
+        vals = [(n, v) for k, c, n, v in counters(db) if c == cname and k == kname]
+        return vals[0] if vals else (0, None)
     copy = "__amd_rocclr_copyBuffer"
-    rs = copy_bytes / 1024 / avg(cfetch_db, "FETCH_SIZE", copy)
-    ws = copy_bytes / 1024 / avg(cwrite_db, "WRITE_SIZE", copy)
+    rs = copy_bytes / 1024 / avg(cfetch_db, "FETCH_SIZE", copy)[1]
+    ws = copy_bytes / 1024 / avg(cwrite_db, "WRITE_SIZE", copy)[1]
     out = {"source_hash": source_hash(), "read_scale": rs, "write_scale": ws, "classes": {}}
-    for cls, kname in classes.items():
-        f, w = avg(fetch_db, "FETCH_SIZE", kname), avg(write_db, "WRITE_SIZE", kname)
-        if f is None or w is None:
+    for cls, knames in classes.items():
+        parts, nf, nw, fs, wsum = [], 0, 0, 0.0, 0.0
+        for kname in knames.split("+"):
+            (n1, f), (n2, w) = avg(fetch_db, "FETCH_SIZE", kname), avg(write_db, "WRITE_SIZE", kname)
+            if f is None or w is None:
+                parts = None
+                break
+            parts.append({"kernel": kname, "dispatches": n1, "fetch_kib": f, "write_kib": w})
+            nf, nw, fs, wsum = nf + n1, nw + n2, fs + n1 * f, wsum + n2 * w
+        if not parts:
             continue
-        out["classes"][cls] = {"kernel": kname, "fetch_kib": f, "write_kib": w,
+        f, w = fs / nf, wsum / nw
+        out["classes"][cls] = {"kernel": knames, "fetch_kib": f, "write_kib": w,
                                "bytes": f * 1024 * rs + w * 1024 * ws}
+        if len(parts) > 1:
+            out["classes"][cls]["parts"] = parts
     return out
 
 

@@ -103,7 +103,7 @@ def test_binding_constants_match_header_enums():
     per_prec = {"GROUP": binding.TUNE_GROUP, "SPLIT": binding.TUNE_SPLIT, "HOP_PAIR": binding.TUNE_HOP_PAIR,
                 "NT_STORE": binding.TUNE_NT_STORE, "CHUNK": binding.TUNE_CHUNK,
                 "BLOCK_THREADS": binding.TUNE_BLOCK_THREADS_PREC, "TILE": binding.TUNE_TILE,
-                "MR_ONCE": binding.TUNE_MR_ONCE}
+                "MR_ONCE": binding.TUNE_MR_ONCE, "TILE_COLS": binding.TUNE_TILE_COLS}
     for knob, m in per_prec.items():
         for prec, suffix in ((binding.FP64, "FP64"), (binding.FP32, "FP32"), (binding.FP16S, "FP16S")):
             assert e[f"MBBS_TUNE_{knob}_{suffix}"] == m[prec], (knob, suffix)

@@ -51,6 +51,24 @@ def test_mr_update(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp16s"])
+@pytest.mark.parametrize("tiled", [False, True])
+def test_psi_once(prec, tiled):
+    """psi formed once per domain solve: the MR steps carry only r; the
+    tiled stencil's last step stores no A r."""
+    sp, lk = _store(prec)
+    steps = [2 * sp + 4 * lk] * (NMR - 1) + [(sp if tiled else 2 * sp) + 4 * lk]
+    got = bench.algorithmic_bytes("mr_dslash", L, DIMS, BLOCK, NCY, NMR, prec, once=True, tiled=tiled)
+    assert got == pytest.approx(VH * sum(steps) / NMR, rel=1e-12)
+    # per colour and cycle: NMR - 1 steps r' = r - omega w, then psi (+)= c r_0 - sum_j e_j w_j
+    launches = []
+    for cy in range(NCY):
+        launches += [3 * sp] * (NMR - 1)
+        launches.append(NMR * sp + (PS if cy == 0 else 2 * PS))
+    got = bench.algorithmic_bytes("mr_update", L, DIMS, BLOCK, NCY, NMR, prec, once=True, tiled=tiled)
+    assert got == pytest.approx(VH * sum(launches) / len(launches), rel=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16s"])
 def test_sap_residual(prec):
     sp, lk = _store(prec)
     launches = [2 * sp,                                 # first cycle, colour 0: psi = 0

@@ -69,8 +69,10 @@ def test_sap_parity(dims, block, L, nmr, prec):
     with gu.Lattice(dims, block, U, 0.12) as lat:
         B.mbbs_lattice_tune(lat.h, B.TUNE_MR_FUSED, 0)
         B.mbbs_lattice_tune(lat.h, B.TUNE_MR_ONCE[prec], 1)
-        for tile in (0, 1):
-            B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[prec], tile)
+        for tile in (0, 1, 3, 11):
+            # 11: tiled with half the columns per workgroup (where L splits so)
+            B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[prec], tile % 10)
+            B.mbbs_lattice_tune(lat.h, B.TUNE_TILE_COLS[prec], L // 2 if tile == 11 else 0)
             Y = _sap(lat, L, eta, ncy, nmr, prec, V)
             assert np.all(gu.rel_col_err(Y, ref) <= SAP_TOL[prec]), tile
             assert np.all(gu.max_elem_err(Y, ref) <= SAP_TOL[prec]), tile

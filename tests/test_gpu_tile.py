@@ -6,7 +6,8 @@ every precision, on the full and the Dirichlet operator, with a clover term
 and on a batch handle.  The tiled MR kernel sums <w, r> and <w, w> over
 tiles instead of thread blocks (another summation order), so SAP and whole
 solves with it are checked against the oracle at the usual tolerances, and a
-batch handle against its single handles bit for bit (both tiled).  With the
+batch handle against its single handles bit for bit (both tiled).  Setting
+3 (tiles of at most half the LDS) is held to the same bars as setting 1.  With the
 MR update folded into the next step (setting 2) every value is computed as
 with the separate update (setting 1), so SAP must match it bit for bit.
 """
@@ -27,8 +28,15 @@ TOL = {B.FP64: 1e-14, B.FP32: 1e-6, B.FP16S: 2e-3}
 SAP_TOL = {B.FP64: 1e-12, B.FP32: 3e-5, B.FP16S: 1e-2}
 
 
-def _set_tile(h, prec, on):
+def _set_tile(h, prec, on, cols=0):
     B.mbbs_lattice_tune(h, B.TUNE_TILE[prec], int(on))
+    B.mbbs_lattice_tune(h, B.TUNE_TILE_COLS[prec], cols)
+
+
+def _half(L, prec):
+    """Columns per workgroup for the split-column runs: half of L, or one
+    column (FP64, odd L); FP32 / FP16 storage with odd L have no tiled form."""
+    return L // 2 if L % 2 == 0 else 1
 
 
 def test_tile_knob_and_shapes():
@@ -37,7 +45,7 @@ def test_tile_knob_and_shapes():
     with gu.Lattice(dims, block, U, 0.12) as lat:
         for prec in (0, 1, 2):
             with pytest.raises(B.MbbsError) as e:
-                B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[prec], 3)
+                B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[prec], 4)
             assert e.value.code == B.EINVAL
         with pytest.raises(B.MbbsError) as e:
             B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[2], 2)      # folded update: FP64 and FP32 only
@@ -53,6 +61,35 @@ def test_tile_knob_and_shapes():
         assert B.mbbs_lattice_tile_shape(lat.h, 12, 1) == (4, 4, 4, 2)
         assert B.mbbs_lattice_tile_shape(lat.h, 12, 2) == (4, 4, 4, 2)
         assert B.mbbs_lattice_tile_shape(lat.h, 12, 0) == (4, 4, 2, 2)
+        # setting 3: tiles of at most half the LDS
+        for prec in (0, 1, 2):
+            _set_tile(lat.h, prec, 3)
+        assert B.mbbs_lattice_tile_shape(lat.h, 12, 1) == (4, 4, 2, 2)
+        assert B.mbbs_lattice_tile_shape(lat.h, 12, 2) == (4, 4, 2, 2)
+        assert B.mbbs_lattice_tile_shape(lat.h, 12, 0) == (4, 2, 2, 2)
+        assert B.mbbs_lattice_tile_shape(lat.h, 5, 1) == (0, 0, 0, 0)
+        # columns per workgroup: half of L lets larger tiles fit
+        for prec in (0, 1, 2):
+            for bad in (-1, 257):
+                with pytest.raises(B.MbbsError) as e:
+                    B.mbbs_lattice_tune(lat.h, B.TUNE_TILE_COLS[prec], bad)
+                assert e.value.code == B.EINVAL
+            _set_tile(lat.h, prec, 1, 6)
+        assert B.mbbs_lattice_tile_shape(lat.h, 12, 1) == (4, 4, 4, 4)
+        assert B.mbbs_lattice_tile_shape(lat.h, 12, 2) == (4, 4, 4, 4)
+        assert B.mbbs_lattice_tile_shape(lat.h, 12, 0) == (4, 4, 4, 2)
+        for prec in (0, 1, 2):
+            _set_tile(lat.h, prec, 3, 6)
+        assert B.mbbs_lattice_tile_shape(lat.h, 12, 1) == (4, 4, 4, 2)
+        assert B.mbbs_lattice_tile_shape(lat.h, 12, 2) == (4, 4, 4, 2)
+        assert B.mbbs_lattice_tile_shape(lat.h, 12, 0) == (4, 4, 2, 2)
+        # a value that does not split L into the kernel's column pairs acts as all L
+        _set_tile(lat.h, 1, 1, 5)
+        assert B.mbbs_lattice_tile_shape(lat.h, 12, 1) == (4, 4, 4, 2)
+        _set_tile(lat.h, 1, 1, 3)
+        assert B.mbbs_lattice_tile_shape(lat.h, 12, 1) == (4, 4, 4, 2)
+        _set_tile(lat.h, 1, 1, 4)
+        assert B.mbbs_lattice_tile_shape(lat.h, 12, 1) == (4, 4, 4, 4)
         for L in (1, 4, 12, 16, 64):
             for prec in (0, 1, 2):
                 t = B.mbbs_lattice_tile_shape(lat.h, L, prec)
@@ -75,19 +112,21 @@ def test_tiled_operator_bit_identical(dims, block, L, prec):
     with gu.Lattice(dims, block, U, 0.1235, PH_TWIST) as lat:
         Xd = gu.dev(X)
         outs = {}
-        for on in (0, 1):
-            _set_tile(lat.h, prec, on)
+        settings = [(0, 0), (1, 0), (3, 0), (1, _half(L, prec)), (3, _half(L, prec))]
+        for on, cols in settings:
+            _set_tile(lat.h, prec, on, cols)
             Y = torch.empty_like(Xd)
             Yb = torch.empty_like(Xd)
             B.mbbs_apply_dirac(lat.h, L, Xd, Y, prec)
             B.mbbs_apply_blocked(lat.h, L, Xd, Yb, prec)
-            outs[on] = (gu.host(Y), gu.host(Yb))
+            outs[on, cols] = (gu.host(Y), gu.host(Yb))
         tiled = B.mbbs_lattice_tile_shape(lat.h, L, prec) != (0, 0, 0, 0)
     assert tiled == (L % 2 == 0 or prec == 0)
-    assert outs[1][0].tobytes() == outs[0][0].tobytes()
-    assert outs[1][1].tobytes() == outs[0][1].tobytes()
-    assert np.all(gu.rel_col_err(outs[1][0], ref) <= TOL[prec])
-    assert np.all(gu.max_elem_err(outs[1][0], ref) <= TOL[prec])
+    for st in settings[1:]:
+        assert outs[st][0].tobytes() == outs[0, 0][0].tobytes(), st
+        assert outs[st][1].tobytes() == outs[0, 0][1].tobytes(), st
+    assert np.all(gu.rel_col_err(outs[1, 0][0], ref) <= TOL[prec])
+    assert np.all(gu.max_elem_err(outs[1, 0][0], ref) <= TOL[prec])
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
@@ -99,14 +138,14 @@ def test_tiled_operator_clover_bit_identical(prec):
     with gu.Lattice(dims, block, U, 0.12) as lat:
         B.mbbs_lattice_set_clover(lat.h, 1.3)
         outs = []
-        for on in (0, 1):
-            _set_tile(lat.h, prec, on)
+        for on, cols in ((0, 0), (1, 0), (3, 0), (1, 6)):
+            _set_tile(lat.h, prec, on, cols)
             Y = torch.empty_like(X)
             B.mbbs_apply_dirac(lat.h, L, X, Y, prec)
             Yb = torch.empty_like(X)
             B.mbbs_apply_blocked(lat.h, L, X, Yb, prec)
             outs.append((gu.host(Y).tobytes(), gu.host(Yb).tobytes()))
-    assert outs[0] == outs[1]
+    assert all(o == outs[0] for o in outs)
 
 
 def _batch(dims, block, n, seed):
@@ -118,15 +157,16 @@ def _batch(dims, block, n, seed):
     return singles, U_dev, h
 
 
+@pytest.mark.parametrize("cols", [0, 6])
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_tiled_batch_operator_bit_identical(prec):
+def test_tiled_batch_operator_bit_identical(prec, cols):
     """Tiled batch handle (three systems stacked along t) against untiled
     single handles: the same bits."""
     dims, block, L = (8, 8, 4, 8), (4, 4, 2, 4), 12
     V = int(np.prod(dims))
     singles, U_dev, h = _batch(dims, block, 3, 410)
     try:
-        _set_tile(h, prec, 1)
+        _set_tile(h, prec, 1, cols)
         assert B.mbbs_lattice_tile_shape(h, L, prec) != (0, 0, 0, 0)
         Xs = [inputs.gaussian_block(V, L, 420 + k) for k in range(3)]
         Xst = gu.dev(np.concatenate(Xs))
@@ -169,16 +209,23 @@ def test_tiled_sap_parity(dims, block, L, ncy, nmr, prec):
     with gu.Lattice(dims, block, U, 0.12) as lat:
         B.mbbs_lattice_tune(lat.h, B.TUNE_MR_FUSED, 0)
         ws = torch.empty(B.mbbs_sap_workspace_size(lat.h, L, prec), dtype=torch.uint8, device="cuda")
-        got = {}
-        for on in (1, 0):
-            _set_tile(lat.h, prec, on)
-            assert (B.mbbs_lattice_tile_shape(lat.h, L, prec) != (0, 0, 0, 0)) == bool(on)
+        got, shape = {}, {}
+        settings = [(1, 0), (3, 0), (1, _half(L, prec)), (3, _half(L, prec)), (0, 0)]
+        for on, cols in settings:
+            _set_tile(lat.h, prec, on, cols)
+            shape[on, cols] = B.mbbs_lattice_tile_shape(lat.h, L, prec)
+            assert (shape[on, cols] != (0, 0, 0, 0)) == bool(on)
             Yd = torch.empty((12 * V, L), dtype=torch.complex128, device="cuda")
             B.mbbs_sap_apply(lat.h, L, gu.dev(eta), Yd, ncy, nmr, prec, ws)
-            got[on] = gu.host(Yd)
-    for on in (1, 0):
-        assert np.all(gu.rel_col_err(got[on], ref) <= SAP_TOL[prec]), on
-        assert np.all(gu.max_elem_err(got[on], ref) <= SAP_TOL[prec]), on
+            got[on, cols] = gu.host(Yd)
+    for st in settings:
+        assert np.all(gu.rel_col_err(got[st], ref) <= SAP_TOL[prec]), st
+        assert np.all(gu.max_elem_err(got[st], ref) <= SAP_TOL[prec]), st
+    # the MR sums follow the tile shape only: split columns on the same shape give the same bits
+    for a in settings[:4]:
+        for b in settings[:4]:
+            if shape[a] == shape[b]:
+                assert got[a].tobytes() == got[b].tobytes(), (a, b)
 
 
 FP16_FOLDED = pytest.mark.skip(reason="the FP16-storage form of the folded MR update did not finish on its only "
@@ -276,14 +323,18 @@ def test_tiled_sap_point_source():
 
 
 @pytest.mark.parametrize("prec,setting", [(0, 1), (0, 2), (1, 1), (1, 2), (2, 1),
-                                          pytest.param(2, 2, marks=FP16_FOLDED)])
+                                          pytest.param(2, 2, marks=FP16_FOLDED), (0, 16), (1, 16), (2, 16)])
 def test_tiled_batch_sap_bit_identical(prec, setting):
+    """Batch SAP against its single handles (setting 1) bit for bit; setting
+    16 stands for tiled with 6 of the 12 columns per workgroup (the same tile
+    shape on this lattice)."""
     dims, block, L = (8, 8, 4, 8), (4, 4, 2, 4), 12
     V = int(np.prod(dims))
     singles, U_dev, h = _batch(dims, block, 3, 440)
     try:
         B.mbbs_lattice_tune(h, B.TUNE_MR_FUSED, 0)
-        B.mbbs_lattice_tune(h, B.TUNE_TILE[prec], setting)
+        B.mbbs_lattice_tune(h, B.TUNE_TILE[prec], 1 if setting == 16 else setting)
+        B.mbbs_lattice_tune(h, B.TUNE_TILE_COLS[prec], 6 if setting == 16 else 0)
         etas = [inputs.gaussian_block(V, L, 450 + k) for k in range(3)]
         ws = torch.empty(B.mbbs_sap_workspace_size(h, L, prec), dtype=torch.uint8, device="cuda")
         Y = torch.empty((3 * 12 * V, L), dtype=torch.complex128, device="cuda")
@@ -316,9 +367,11 @@ def test_tiled_solve_matches_untiled(sap_prec):
     xs = {}
     with gu.Lattice(dims, block, U, 0.125) as lat:
         B.mbbs_lattice_tune(lat.h, B.TUNE_MR_FUSED, 0)
-        for on in (2, 0):
+        for on in (2, 16, 0):
+            # 16: tiled with 6 of the 12 columns per workgroup
             for p in (0, 1, 2):
-                B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[p], min(on, 1) if p == 2 else on)
+                B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[p], 1 if on == 16 or (on == 2 and p == 2) else on)
+                B.mbbs_lattice_tune(lat.h, B.TUNE_TILE_COLS[p], 6 if on == 16 else 0)
             params = B.mbbs_solve_params_default(tol=tol, maxiter=200, sap_prec=sap_prec)
             ws = torch.empty(B.mbbs_solve_workspace_size(lat.h, L, params), dtype=torch.uint8, device="cuda")
             X = torch.zeros((12 * V, L), dtype=torch.complex128, device="cuda")
@@ -328,5 +381,6 @@ def test_tiled_solve_matches_untiled(sap_prec):
             xs[on] = gu.host(X)
             res = dirac.apply_D(U, 0.125, gu.PH_AP, xs[on], dims).reshape(12 * V, L) - Bm
             assert np.all(np.linalg.norm(res, axis=0) <= 1.01 * tol * np.linalg.norm(Bm, axis=0)), on
-    d = np.linalg.norm(xs[2] - xs[0], axis=0) / np.linalg.norm(xs[0], axis=0)
-    assert np.all(d <= 1e-8), d
+    for on in (2, 16):
+        d = np.linalg.norm(xs[on] - xs[0], axis=0) / np.linalg.norm(xs[0], axis=0)
+        assert np.all(d <= 1e-8), (on, d)
