@@ -1438,39 +1438,57 @@ __global__ void __launch_bounds__(256) k_to_sap(GeomK k, int L, const double2* _
                                                 float* __restrict__ out_s, const int* __restrict__ frozen) {
   if constexpr (LT > 0) L = LT;
   using R = typename Store<PR>::Real;
+  // with gamma: [L][L] gamma, then the block's sites' 12 L input values
+  // ([site][12][L], staged once: every column of a row reads all of it)
   extern __shared__ double2 gsh[];
+  __shared__ int lsh[256];
   // a block never straddles two systems (its site count divides a system's
   // half volume), so the system, its flag and its gamma are block-uniform
   const int sys = site_ctx<DM>(k, min((int)(blockIdx.x * blockDim.y), k.g.V - 1)).sys;
   if (sys_frozen(k, frozen, sys)) return;
-  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x, nthr = blockDim.x * blockDim.y;
+  const int s = blockIdx.x * blockDim.y + threadIdx.y;  // domain-major index
+  double2* ish = gsh + L * L;
   if (gam) {
-    for (int e = tid; e < L * L; e += blockDim.x * blockDim.y) gsh[e] = gam[(size_t)sys * L * L + e];
+    for (int e = tid; e < L * L; e += nthr) gsh[e] = gam[(size_t)sys * L * L + e];
+    for (int y = tid; y < (int)blockDim.y; y += nthr) {
+      const int sy = blockIdx.x * blockDim.y + y;
+      lsh[y] = sy < k.g.V ? lex_of(k, site_ctx<DM>(k, sy)) : -1;
+    }
+    __syncthreads();
+    const int row = 12 * L;
+    for (int f = tid; f < (int)blockDim.y * row; f += nthr) {
+      const int y = f / row, w = f - y * row;
+      if (lsh[y] >= 0) ish[f] = in[(size_t)lsh[y] * row + w];
+    }
     __syncthreads();
   }
-  const int s = blockIdx.x * blockDim.y + threadIdx.y;  // domain-major index
   if (s >= k.g.V) return;
   const int j = threadIdx.x;
-  const SiteCtx c = site_ctx<DM>(k, s);
-  const int ls = lex_of(k, c);
   cplx<double> v[4][3];
+  if (gam) {
+    const double2* xr = ish + (size_t)threadIdx.y * 12 * L;
 #pragma unroll
-  for (int sp = 0; sp < 4; ++sp)
+    for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const size_t row = ((size_t)ls * 12 + 3 * sp + a) * L;
-      if (gam) {
+      for (int a = 0; a < 3; ++a) {
         cplx<double> acc = cmake(0.0, 0.0);
         for (int m = 0; m < L; ++m) {
-          double2 e = in[row + m], gg = gsh[m * L + j];
+          double2 e = xr[(3 * sp + a) * L + m], gg = gsh[m * L + j];
           acc = acc + cmake(e.x, e.y) * cmake(gg.x, gg.y);
         }
         v[sp][a] = acc;
-      } else {
-        double2 e = in[row + j];
+      }
+  } else {
+    const int ls = lex_of(k, site_ctx<DM>(k, s));
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        double2 e = in[((size_t)ls * 12 + 3 * sp + a) * L + j];
         v[sp][a] = cmake(e.x, e.y);
       }
-    }
+  }
   cplx<R> vr[4][3];
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
@@ -1502,7 +1520,7 @@ int sap_to(const mbbs_lattice_s* lat, const SapBuffers& b, const double2* in, co
   const Geom& g = lat->g;
   // a batch: blocks stay inside one system's half volume (per-system gamma)
   const int S = sites_per_block(L, lat->nsys > 1 ? g.V / (2 * lat->nsys) : g.V);
-  const size_t gsh = gam ? (size_t)L * L * sizeof(double2) : 0;
+  const size_t gsh = gam ? ((size_t)L * L + (size_t)S * 12 * L) * sizeof(double2) : 0;
   const bool l12 = L == 12;   // compile-time row offsets for the common block width
   switch (b.prec) {
     case P64:
