@@ -1,5 +1,7 @@
 """Helpers shared by the GPU tests: device tensors and lattice handles."""
 
+import os
+
 import numpy as np
 import pytest
 
@@ -56,3 +58,22 @@ class Lattice:
 
 def flush(msg):
     print(msg, flush=True)
+
+
+def apply_benchmark_tuning(h):
+    """The launch settings the benchmark's tuning chose at this size (its
+    recorded JSON line): each precision's operator setting, then its SAP
+    setting (tiled MR stencil and residual, psi formed once, ...)."""
+    import json
+    from paper_1104_0737_amd import autotune
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
+                        "tuning_32x32x32x64_L12.txt")
+    with open(path) as f:
+        tun = json.loads(f.read().strip().splitlines()[-1])["tuning"]
+    for prec, name in ((binding.FP64, "fp64"), (binding.FP32, "fp32"), (binding.FP16S, "fp16s")):
+        t = tun[name]
+        autotune.apply(h, prec, (t["group_cols"], t["block_threads"], t["split"], t["hop_pair"], t["nt_store"],
+                                 t.get("chunk", 0), t.get("tile", 0)))
+        if "sap" in t:
+            autotune.apply(h, prec, tuple(t["sap"]["setting"]))
+    flush(f"  tuned settings: fp32 SAP {tun['fp32']['sap']['setting']}, fp16s SAP {tun['fp16s']['sap']['setting']}")

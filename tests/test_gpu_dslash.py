@@ -104,7 +104,9 @@ def _sample_sites(dims, n, seed):
 
 @pytest.mark.slow
 def test_dslash_full_size_sampled():
-    """32^3 x 64, L = 12, FP64, FP32 and FP16 storage, as the benchmark runs them."""
+    """32^3 x 64, L = 12, FP64, FP32 and FP16 storage, in the default launch
+    settings and in those the benchmark's tuning chose (its recorded JSON
+    line), at sampled sites; FP64 also on two whole columns."""
     cfg = configs.c4()
     dims, L = cfg.dims, 12
     V = cfg.V
@@ -119,41 +121,48 @@ def test_dslash_full_size_sampled():
         ref = dirac.apply_D_sites(U, cfg.kappa, cfg.phases, X.reshape(V, 4, 3, L), dims, sites)
         idx = torch.from_numpy((12 * sites[:, None] + np.arange(12)[None, :]).ravel()).cuda()
         Yd = torch.empty_like(Xd)
-        gu.flush("full-size: FP64")
-        B.mbbs_apply_dirac(lat.h, L, Xd, Yd, B.FP64)
-        got = gu.host(Yd.index_select(0, idx))
-        err = gu.rel_col_err(got, ref.reshape(-1, L))
-        assert np.all(err <= 1e-14), err
-        # two columns over the whole lattice, every element
-        gu.flush("full-size: FP64, columns 0 and 7 over the whole lattice")
-        cols = [0, 7]
-        Xc = np.ascontiguousarray(X[:, cols])
-        refc = dirac.apply_D(U, cfg.kappa, cfg.phases, Xc, dims).reshape(12 * V, 2)
-        Yc = gu.host(Yd)[:, cols]
-        assert np.all(gu.rel_col_err(Yc, refc) <= 1e-14)
-        assert np.all(gu.max_elem_err(Yc, refc) <= 1e-14)
-        del refc, Yc, Xc
-        gu.flush("full-size: FP32 storage")
-        X32 = torch.empty((12 * V, L, 2), dtype=torch.float32, device="cuda")
-        Y32 = torch.empty_like(X32)
-        B.mbbs_convert_to(B.FP32, V, L, Xd, X32)
-        B.mbbs_apply_dirac_raw(lat.h, L, B.FP32, X32, None, Y32, None)
-        B.mbbs_convert_from(B.FP32, V, L, Y32, None, Yd)
-        got = gu.host(Yd.index_select(0, idx))
-        err = gu.rel_col_err(got, ref.reshape(-1, L))
-        assert np.all(err <= 1e-6), err
-        gu.flush("full-size: FP16 storage")
-        X16 = torch.empty((12 * V, L, 2), dtype=torch.float16, device="cuda")
-        Y16 = torch.empty_like(X16)
-        X16s = torch.empty((V, L), dtype=torch.float32, device="cuda")
-        Y16s = torch.empty_like(X16s)
-        B.mbbs_convert_to(B.FP16S, V, L, Xd, X16, X16s)
-        B.mbbs_apply_dirac_raw(lat.h, L, B.FP16S, X16, X16s, Y16, Y16s)
-        B.mbbs_convert_from(B.FP16S, V, L, Y16, Y16s, Yd)
-        got = gu.host(Yd.index_select(0, idx))
-        err = gu.rel_col_err(got, ref.reshape(-1, L))
-        assert np.all(err <= 2e-3), err
-        assert np.all(gu.max_elem_err(got, ref.reshape(-1, L)) <= 2e-3)
+        for tuned in (False, True):
+            tag = "tuned settings" if tuned else "default settings"
+            if tuned:
+                gu.apply_benchmark_tuning(lat.h)
+            gu.flush(f"full-size: FP64, {tag}")
+            B.mbbs_apply_dirac(lat.h, L, Xd, Yd, B.FP64)
+            got = gu.host(Yd.index_select(0, idx))
+            err = gu.rel_col_err(got, ref.reshape(-1, L))
+            assert np.all(err <= 1e-14), (tag, err)
+            if not tuned:
+                # two columns over the whole lattice, every element
+                gu.flush("full-size: FP64, columns 0 and 7 over the whole lattice")
+                cols = [0, 7]
+                Xc = np.ascontiguousarray(X[:, cols])
+                refc = dirac.apply_D(U, cfg.kappa, cfg.phases, Xc, dims).reshape(12 * V, 2)
+                Yc = gu.host(Yd)[:, cols]
+                assert np.all(gu.rel_col_err(Yc, refc) <= 1e-14)
+                assert np.all(gu.max_elem_err(Yc, refc) <= 1e-14)
+                del refc, Yc, Xc
+            gu.flush(f"full-size: FP32 storage, {tag}")
+            X32 = torch.empty((12 * V, L, 2), dtype=torch.float32, device="cuda")
+            Y32 = torch.empty_like(X32)
+            B.mbbs_convert_to(B.FP32, V, L, Xd, X32)
+            B.mbbs_apply_dirac_raw(lat.h, L, B.FP32, X32, None, Y32, None)
+            B.mbbs_convert_from(B.FP32, V, L, Y32, None, Yd)
+            got = gu.host(Yd.index_select(0, idx))
+            err = gu.rel_col_err(got, ref.reshape(-1, L))
+            assert np.all(err <= 1e-6), (tag, err)
+            del X32, Y32
+            gu.flush(f"full-size: FP16 storage, {tag}")
+            X16 = torch.empty((12 * V, L, 2), dtype=torch.float16, device="cuda")
+            Y16 = torch.empty_like(X16)
+            X16s = torch.empty((V, L), dtype=torch.float32, device="cuda")
+            Y16s = torch.empty_like(X16s)
+            B.mbbs_convert_to(B.FP16S, V, L, Xd, X16, X16s)
+            B.mbbs_apply_dirac_raw(lat.h, L, B.FP16S, X16, X16s, Y16, Y16s)
+            B.mbbs_convert_from(B.FP16S, V, L, Y16, Y16s, Yd)
+            got = gu.host(Yd.index_select(0, idx))
+            err = gu.rel_col_err(got, ref.reshape(-1, L))
+            assert np.all(err <= 2e-3), (tag, err)
+            assert np.all(gu.max_elem_err(got, ref.reshape(-1, L)) <= 2e-3), tag
+            del X16, Y16, X16s, Y16s
 
 
 def test_tuning_is_bit_identical():

@@ -313,13 +313,14 @@ def test_batched_mixed_solvers_clover_and_a_bad_system():
             l.close()
 
 
-def _c4_check(cfg, tag, sap_prec=B.FP32, full=False, **kw):
+def _c4_check(cfg, tag, sap_prec=B.FP32, full=False, tune=None, **kw):
     """Solve a 32^3 x 64 system to 1e-10 (FP32 SAP on 8^4 domains); form the
     residual B - D X of the GPU solution on the GPU in FP64 and compare it
     with the oracle's at sampled sites (the source site and its 8 neighbours
     among them), so the norms the solver reports rest on checked values.
     full: also the oracle's own true residual of the GPU solution over the
-    whole lattice (its operator applied to X, four columns at a time)."""
+    whole lattice (its operator applied to X, four columns at a time).
+    tune: called with the lattice handle before the solve (launch settings)."""
     V, L, dims = cfg.V, cfg.L, cfg.dims
     gu.flush(f"c4 {tag}: links")
     U = cfg.gauge()
@@ -334,6 +335,8 @@ def _c4_check(cfg, tag, sap_prec=B.FP32, full=False, **kw):
             sites.append(int(np.ravel_multi_index(tuple(n[::-1]), dims[::-1])))
     sites = np.array(sites + np.random.default_rng(4006).integers(0, V, 200).tolist())
     with gu.Lattice(dims, cfg.block, U, cfg.kappa) as lat:
+        if tune is not None:
+            tune(lat.h)
         gu.flush(f"c4 {tag}: solve")
         X, info = _solve(lat, L, Bh, tol=1e-10, sap_prec=sap_prec, ncy=cfg.ncy, nmr=cfg.nmr, **kw)
         gu.flush(f"  iterations {info['iterations']} restarts {info['restarts']} {info['seconds']:.2f}s")
@@ -373,14 +376,21 @@ def test_c4_mixed_full_size(domain_solver):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("variant", ["alg2", "fp16s"])
+@pytest.mark.parametrize("variant", ["alg2", "fp16s", "tuned", "tuned_fp16s"])
 def test_c4_variants_full_size(variant):
-    """The benchmark's system solved with the memory-saving Alg. 2, or with
-    FP16-storage SAP, to 1e-10, checked against the oracle."""
+    """The benchmark's system solved with the memory-saving Alg. 2, with
+    FP16-storage SAP, or in the launch settings the benchmark times (its
+    recorded tuning: tiled MR stencil and SAP residual, psi formed once) with
+    FP32 and FP16-storage SAP, to 1e-10, checked against the oracle (over the
+    whole lattice for all but Alg. 2)."""
     if variant == "alg2":
         _c4_check(configs.c4(), "Alg. 2", memsave=1)
-    else:
+    elif variant == "fp16s":
         _c4_check(configs.c4(), "FP16S SAP", sap_prec=B.FP16S, full=True)
+    elif variant == "tuned":
+        _c4_check(configs.c4(), "tuned, FP32 SAP", full=True, tune=gu.apply_benchmark_tuning)
+    else:
+        _c4_check(configs.c4(), "tuned, FP16S SAP", sap_prec=B.FP16S, full=True, tune=gu.apply_benchmark_tuning)
 
 
 @pytest.mark.slow
