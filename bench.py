@@ -251,7 +251,7 @@ def main():
         for prec, name in ((B.FP64, "fp64"), (B.FP32, "fp32"), (B.FP16S, "fp16s")):
             t = prev[name]
             op = (t["group_cols"], t["block_threads"], t["split"], t["hop_pair"], t["nt_store"], t.get("chunk", 0),
-                  t.get("tile", 0))
+                  t.get("tile", 0), 0, t.get("tile_cols", 0))
             autotune.apply(lat, prec, op)
             if not args.skip_dslash:
                 dslash[name] = time_dslash(prec)
@@ -268,6 +268,7 @@ def main():
             tuning[name] = {"group_cols": best[0], "block_threads": best[1], "split": best[2],
                             "hop_pair": best[3], "nt_store": best[4], "chunk": best[5] if len(best) > 5 else 0,
                             "tile": best[6] if len(best) > 6 else 0,
+                            "tile_cols": best[8] if len(best) > 8 else 0,
                             "ms": round(times[best], 4), "worst_ms": round(max(times.values()), 4),
                             "classic_best_ms": round(min(v for k, v in times.items()
                                                          if k[2] == 0 and not (len(k) > 6 and k[6])), 4)}

@@ -9,6 +9,8 @@
 // one site and C columns and applies each link to all of them.  The per-site
 // arithmetic, hop order included, is that of the one-thread-per-site kernels,
 // so the operator's output bits are the same.
+#include <type_traits>
+
 #include "stencil.h"
 #include "tile.h"
 
@@ -61,38 +63,40 @@ __device__ __forceinline__ int tile_row_index(const GeomK& k, const TileArgs& T,
 // Copy the tile's columns [cb, cb + Lg) between the field (12 L elements per
 // site) and LDS (SS elements per site, element e of a site at e Lg), in units
 // of U.  With Lg = L a site's elements are one contiguous row.
-template <typename U, bool TO_LDS, typename E>
-__device__ __forceinline__ void tile_copy_u(E* g, E* lds, const int* row_site, int ts, int t0, int L, int Lg, int SS,
+// GE is E when copying out of LDS and const E when staging into it.
+template <typename U, typename GE, typename E>
+__device__ __forceinline__ void tile_copy_u(GE* g, E* lds, const int* row_site, int ts, int t0, int L, int Lg, int SS,
                                             int cb) {
+  constexpr bool TO_LDS = std::is_const<GE>::value;
   const int nrow = Lg == L ? 1 : 12, rlen = Lg == L ? 12 * L : Lg;
   const int ru = rlen * (int)sizeof(E) / (int)sizeof(U), su = nrow * ru;
   for (int f = threadIdx.x; f < ts * su; f += blockDim.x) {
     const int t = f / su, rem = f - t * su, e = rem / ru, w = rem - e * ru;
     const int r = t / t0, x = t - r * t0;
-    U* gp = (U*)(g + ((size_t)(row_site[r] + x) * 12 + e) * L + cb) + w;
+    const size_t go = ((size_t)(row_site[r] + x) * 12 + e) * L + cb;
     U* lp = (U*)(lds + (size_t)t * SS + e * Lg) + w;
-    if constexpr (TO_LDS) *lp = *gp;
-    else *gp = *lp;
+    if constexpr (TO_LDS) *lp = ((const U*)(g + go))[w];
+    else ((U*)(g + go))[w] = *lp;
   }
 }
 
-template <bool TO_LDS, typename E>
-__device__ __forceinline__ void tile_copy(E* g, E* lds, const int* row_site, int ts, int t0, int L, int Lg, int SS,
+template <typename GE, typename E>
+__device__ __forceinline__ void tile_copy(GE* g, E* lds, const int* row_site, int ts, int t0, int L, int Lg, int SS,
                                           int cb) {
   const int rlen = Lg == L ? 12 * L : Lg;
-  if ((rlen * (int)sizeof(E)) % 16 == 0) tile_copy_u<float4, TO_LDS>(g, lds, row_site, ts, t0, L, Lg, SS, cb);
-  else tile_copy_u<uint2, TO_LDS>(g, lds, row_site, ts, t0, L, Lg, SS, cb);
+  if ((rlen * (int)sizeof(E)) % 16 == 0) tile_copy_u<float4>(g, lds, row_site, ts, t0, L, Lg, SS, cb);
+  else tile_copy_u<uint2>(g, lds, row_site, ts, t0, L, Lg, SS, cb);
 }
 
 // The per-(site, column) scales of FP16 storage, likewise.
-template <bool TO_LDS>
-__device__ __forceinline__ void tile_copy_scales(float* g, float* lds_s, const int* row_site, int ts, int t0, int L,
+template <typename GF>
+__device__ __forceinline__ void tile_copy_scales(GF* g, float* lds_s, const int* row_site, int ts, int t0, int L,
                                                  int Lg, int cb) {
   for (int f = threadIdx.x; f < ts * Lg; f += blockDim.x) {
     const int t = f / Lg, w = f - t * Lg;
     const int r = t / t0, x = t - r * t0;
-    float* gp = g + (size_t)(row_site[r] + x) * L + cb + w;
-    if constexpr (TO_LDS) lds_s[f] = *gp;
+    GF* gp = g + (size_t)(row_site[r] + x) * L + cb + w;
+    if constexpr (std::is_const<GF>::value) lds_s[f] = *gp;
     else *gp = lds_s[f];
   }
 }
@@ -295,9 +299,8 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
   }
   __syncthreads();
   // stage the tile's columns [cb, cb + Lg); LDS holds site ts at ts * SS elements
-  tile_copy<true>(const_cast<E*>(in), lds, row_site, T.ts, T.t[0], L, Lg, SS, cb);
-  if constexpr (Store<PIN>::scaled)
-    tile_copy_scales<true>(const_cast<float*>(in_s), lds_s, row_site, T.ts, T.t[0], L, Lg, cb);
+  tile_copy(in, lds, row_site, T.ts, T.t[0], L, Lg, SS, cb);
+  if constexpr (Store<PIN>::scaled) tile_copy_scales(in_s, lds_s, row_site, T.ts, T.t[0], L, Lg, cb);
   __syncthreads();
   const int nchunk = Lg / C;
   const int ts = threadIdx.x / nchunk;
@@ -342,8 +345,8 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
     }
     __syncthreads();
     // the tile's new r to global memory
-    tile_copy<false>((E*)mf.r_new, lds, row_site, T.ts, T.t[0], L, Lg, SS, cb);
-    if constexpr (Store<PIN>::scaled) tile_copy_scales<false>(mf.r_new_s, lds_s, row_site, T.ts, T.t[0], L, Lg, cb);
+    tile_copy((E*)mf.r_new, lds, row_site, T.ts, T.t[0], L, Lg, SS, cb);
+    if constexpr (Store<PIN>::scaled) tile_copy_scales(mf.r_new_s, lds_s, row_site, T.ts, T.t[0], L, Lg, cb);
   }
   constexpr int HALO = OP == OP_MRF ? 1 : 0;
   cplx<R> acc[4][3][C];

@@ -73,7 +73,7 @@ def apply_benchmark_tuning(h):
     for prec, name in ((binding.FP64, "fp64"), (binding.FP32, "fp32"), (binding.FP16S, "fp16s")):
         t = tun[name]
         autotune.apply(h, prec, (t["group_cols"], t["block_threads"], t["split"], t["hop_pair"], t["nt_store"],
-                                 t.get("chunk", 0), t.get("tile", 0)))
+                                 t.get("chunk", 0), t.get("tile", 0), 0, t.get("tile_cols", 0)))
         if "sap" in t:
             autotune.apply(h, prec, tuple(t["sap"]["setting"]))
     flush(f"  tuned settings: fp32 SAP {tun['fp32']['sap']['setting']}, fp16s SAP {tun['fp16s']['sap']['setting']}")

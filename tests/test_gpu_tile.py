@@ -234,13 +234,15 @@ FP16_FOLDED = pytest.mark.skip(reason="the FP16-storage form of the folded MR up
                                       "cause is shown")
 
 
+@pytest.mark.parametrize("cols", [0, 6])
 @pytest.mark.parametrize("ncy,nmr", [(1, 1), (2, 2), (1, 3), (3, 4)])
 @pytest.mark.parametrize("prec", [0, 1, pytest.param(2, marks=FP16_FOLDED)])
-def test_fused_update_sap_bit_identical(ncy, nmr, prec):
+def test_fused_update_sap_bit_identical(ncy, nmr, prec, cols):
     """MR update folded into the next step (setting 2) against the separate
     update (setting 1): the same bits, and the oracle's result within the
-    precision's bound."""
-    gu.flush(f"fused-update sap ncy={ncy} nmr={nmr} prec={prec}")
+    precision's bound; with all 12 columns or 6 per workgroup (the same
+    tile shape in both settings)."""
+    gu.flush(f"fused-update sap ncy={ncy} nmr={nmr} prec={prec} cols={cols}")
     dims, block, L = (8, 8, 8, 8), (4, 4, 4, 4), 12
     V = 4096
     U = inputs.gauge_field(dims, 0.3, 433)
@@ -248,6 +250,7 @@ def test_fused_update_sap_bit_identical(ncy, nmr, prec):
     ref = sap.sap(U, 0.12, gu.PH_AP, sap.Domains(dims, block), eta, ncy, nmr).reshape(12 * V, L)
     with gu.Lattice(dims, block, U, 0.12) as lat:
         B.mbbs_lattice_tune(lat.h, B.TUNE_MR_FUSED, 0)
+        B.mbbs_lattice_tune(lat.h, B.TUNE_TILE_COLS[prec], cols)
         B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[prec], 2)
         # sized while the folded update is on: holds its second r and A r
         ws = torch.empty(B.mbbs_sap_workspace_size(lat.h, L, prec), dtype=torch.uint8, device="cuda")
