@@ -37,13 +37,54 @@ def source_hash() -> str:
     return h.hexdigest()
 
 
-def _compile(unit: str) -> str:
-    obj = os.path.join(BUILD, unit.replace(".hip", ".o"))
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(SRC, unit), "-o", obj]
+# The host-checked build: the address and undefined-behaviour sanitizers on
+# the host pass only (device code as in the product build).  It serves the
+# CPU tests of the C ABI's host paths (argument checks, sizes, defaults);
+# its users preload the sanitizer runtime.  A stamp holds the source hash it
+# was built from, so an unchanged tree is not rebuilt.
+SAN_BUILD = os.path.join(HERE, "_build_san")
+SAN_OUT = os.path.join(SAN_BUILD, "libmbbs_san.so")
+SAN_FLAGS = ["-Xarch_host", "-O1", "-Xarch_host", "-g", "-Xarch_host", "-fno-omit-frame-pointer",
+             "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
+
+
+def _compile(unit: str, out_dir: str = BUILD, extra=()) -> str:
+    obj = os.path.join(out_dir, unit.replace(".hip", ".o"))
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(SRC, unit), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {unit}:\n{r.stderr[-6000:]}")
     return obj
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """Build the host-checked library (SAN_FLAGS) at SAN_OUT, unless it was
+    built from the present sources."""
+    stamp = SAN_OUT + ".srchash"
+    if os.path.exists(SAN_OUT) and os.path.exists(stamp) and open(stamp).read().strip() == source_hash():
+        return SAN_OUT
+    os.makedirs(SAN_BUILD, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=min(len(UNITS), 7)) as ex:
+        objs = list(ex.map(lambda u: _compile(u, SAN_BUILD, SAN_FLAGS), UNITS))
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined", *objs, "-o", SAN_OUT]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr[-6000:]}")
+    with open(stamp, "w") as f:
+        f.write(source_hash() + "\n")
+    if verbose:
+        print("built", SAN_OUT)
+    return SAN_OUT
+
+
+def sanitizer_runtime() -> str:
+    """Path of the address-sanitizer runtime of hipcc's clang (to preload)."""
+    clang = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "lib", "llvm", "bin", "clang++")
+    if not os.path.exists(clang):
+        clang = "/opt/rocm/llvm/bin/clang++"
+    r = subprocess.run([clang, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    return r.stdout.strip()
 
 
 def build(verbose: bool = False) -> str:
@@ -62,5 +103,8 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    if "--sanitized" in sys.argv[1:]:
+        build_sanitized(verbose=True)
+    else:
+        build(verbose=True)
     sys.exit(0)
