@@ -81,7 +81,8 @@ def algorithmic_bytes(cls, L, dims, block, ncy, nmr, sap_prec="fp32", nssor=1, c
     mr_update  one colour: read r and psi, write psi; while r is still
                needed also read w and write r; the first step of the first
                cycle assigns psi (no psi read).
-    With psi formed once per domain solve (once=True) the MR steps only
+    With psi formed once per domain solve (once=True) sap_resid has no pass
+    on the first colour of the first cycle, and the MR steps only
     carry the residual: mr_update is then nmr - 1 residual steps (read r and
     w, write the next r) and one psi pass (read r_0 and the first nmr - 1 A r,
     read psi except in the first cycle, write psi); the last MR step of the
@@ -124,11 +125,13 @@ def algorithmic_bytes(cls, L, dims, block, ncy, nmr, sap_prec="fp32", nssor=1, c
     if cls == "sap_resid":
         inner = int(np.prod([b - 2 for b in block]))
         f = 1 - inner / int(np.prod(block))  # sites of a domain that touch another domain
-        tot = 2 * (2 * Vh * sp)                          # first cycle, colour 0 and 1: eta, r
+        # with psi formed once, the first colour of the first cycle has no
+        # residual pass (its domain solves read eta)
+        tot = (1 if once else 2) * (2 * Vh * sp)         # first cycle, colour 0 and 1: eta, r
         tot += Vh * (f * ps + 4 * lk)                    # first cycle, colour 1: psi of colour 0
         tot += 2 * (ncy - 1) * Vh * (2 * sp + (1 + f) * ps + 4 * lk)
         tot += (2 * ncy - 1) * Vh * cl                   # every half-sweep but the first
-        return tot / (2 * ncy)
+        return tot / (2 * ncy - (1 if once else 0))
     if cls == "ssor":
         # the SAP residual is formed inside the first sweep
         inner = int(np.prod([b - 2 for b in block]))

@@ -1190,6 +1190,14 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
       }
       const int P = lat->nsys == 1 ? lat->split[PL] : 0;   // the split kernels serve single systems only
       const int SS = ((P == 2 || P == 4) && !lat->gk.clov) ? split_sites(lat, L, PL, P) : 0;
+      // psi formed once: r_0 is only read, so on the first colour of the first
+      // cycle (psi = 0, r_0 = eta) the domain solve reads eta itself
+      const bool once_form = !use_mr_fused(lat, L) && lat->mr_once[PL] && nmr <= MR_ONCE_MAX && b.r2 && b.w2 &&
+                             b.wx[0] && b.wx[1];
+      const bool r_is_eta = once_form && cy == 0 && col == 0;
+      void* r0 = r_is_eta ? b.eta : b.r;
+      float* r0_s = r_is_eta ? b.eta_s : b.r_s;
+      if (!r_is_eta) {
       if (prof) prof->begin(MBBS_K_SAP_RES);
       TileArgs TR;
       const bool tres = cy > 0 && ((uintptr_t)b.psi & 15) == 0 && tile_plan_resid(lat, L, PL, &TR);
@@ -1239,6 +1247,7 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
       }
       if (prof) prof->end();
       MBBS_HIP(hipGetLastError());
+      }
 
       if (use_mr_fused(lat, L)) {
         const int spb = mr_fused_spb(g.Vb, L, mr_fused_threads<PR>());
@@ -1306,14 +1315,14 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
         MBBS_HIP(hipGetLastError());
         return MBBS_OK;
       };
-      if (lat->mr_once[PL] && nmr <= MR_ONCE_MAX && b.r2 && b.w2 && b.wx[0] && b.wx[1]) {
-        // psi formed once: r_0 stays in b.r, r_1, r_2, ... overwrite r2, the
-        // steps' A r are kept (w_0 .. w_{nmr-1}), each step's omega kept
+      if (once_form) {
+        // psi formed once: r_0 stays in b.r (or is eta), r_1, r_2, ... overwrite
+        // r2, the steps' A r are kept (w_0 .. w_{nmr-1}), each step's omega kept
         void* wb[MR_ONCE_MAX] = {b.w, b.w2, b.wx[0], b.wx[1]};
         float* wbs[MR_ONCE_MAX] = {b.w_s, b.w2_s, b.wx_s[0], b.wx_s[1]};
         for (int it = 0; it < nmr; ++it) {
-          const void* rin = it == 0 ? b.r : b.r2;
-          float* rin_s = it == 0 ? b.r_s : b.r2_s;
+          const void* rin = it == 0 ? r0 : b.r2;
+          float* rin_s = it == 0 ? r0_s : b.r2_s;
           // the last step's A r only feeds its omega: the tiled step need not store it
           const bool keep = it + 1 < nmr || !tiled;
           if (prof) prof->begin(MBBS_K_MR_DSLASH);
@@ -1342,7 +1351,7 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
           MBBS_HIP(hipGetLastError());
         }
         MrOnceArgs oa{};
-        oa.r0 = b.r; oa.r0_s = b.r_s;
+        oa.r0 = r0; oa.r0_s = r0_s;
         for (int j = 0; j < MR_ONCE_MAX - 1; ++j) { oa.w[j] = wb[j]; oa.w_s[j] = wbs[j]; }
         if (prof) prof->begin(MBBS_K_MR_UPDATE);
         if constexpr (PR == P32 && PPSI == P32) {

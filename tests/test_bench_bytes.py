@@ -66,6 +66,10 @@ def test_psi_once(prec, tiled):
         launches.append(NMR * sp + (PS if cy == 0 else 2 * PS))
     got = bench.algorithmic_bytes("mr_update", L, DIMS, BLOCK, NCY, NMR, prec, once=True, tiled=tiled)
     assert got == pytest.approx(VH * sum(launches) / len(launches), rel=1e-12)
+    # the SAP residual: no pass on the first colour of the first cycle
+    res = [2 * sp + F * PS + 4 * lk] + [2 * sp + (1 + F) * PS + 4 * lk] * (2 * (NCY - 1))
+    got = bench.algorithmic_bytes("sap_resid", L, DIMS, BLOCK, NCY, NMR, prec, once=True, tiled=tiled)
+    assert got == pytest.approx(VH * sum(res) / len(res), rel=1e-12)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp16s"])

@@ -448,27 +448,31 @@ def test_c5_batched_48_systems():
             B.mbbs_lattice_destroy(h)
 
 
-@pytest.mark.parametrize("tile", [0, 2])
-def test_launch_counts_per_iteration(c1, tile):
+@pytest.mark.parametrize("tile,once", [(0, 0), (2, 0), (1, 1), (0, 1)])
+def test_launch_counts_per_iteration(c1, tile, once):
     """Kernel launches of a solve, counted by the profiler: per iteration two
     preconditioner applications, each ncy cycles x 2 colours x (one SAP
     residual, nmr MR stencil steps and nmr updates -- one per domain solve when
-    the update is folded into the next step), two outer operators; one more
-    outer operator for the closing true residual, and nothing for an
+    the update is folded into the next step; with psi formed once, nmr - 1
+    residual steps and one psi pass, and no residual pass on the first colour
+    of the first cycle, whose domain solves read eta), two outer operators;
+    one more outer operator for the closing true residual, and nothing for an
     iteration after convergence (the loop test follows step 4.10)."""
     cfg, U, Bh, ref, lat = c1
-    gu.flush(f"launch counts tile={tile}")
+    gu.flush(f"launch counts tile={tile} once={once}")
     B.mbbs_lattice_tune(lat.h, B.TUNE_MR_FUSED, 0)          # the three-launch MR path
     B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[B.FP32], tile)
+    B.mbbs_lattice_tune(lat.h, B.TUNE_MR_ONCE[B.FP32], once)
     try:
         X, info = _solve(lat, cfg.L, Bh, tol=1e-10, sap_prec=B.FP32, profile=1, ncy=4, nmr=4)
     finally:
         B.mbbs_lattice_tune(lat.h, B.TUNE_MR_FUSED, -1)
         B.mbbs_lattice_tune(lat.h, B.TUNE_TILE[B.FP32], 0)
+        B.mbbs_lattice_tune(lat.h, B.TUNE_MR_ONCE[B.FP32], 0)
     assert info["status"] == B.OK and info["restarts"] == 0
     it, n = info["iterations"], info["kernel_launches"]
     per_sap = 4 * 2                                           # cycles x colours
-    assert n["sap_resid"] == 2 * it * per_sap
+    assert n["sap_resid"] == 2 * it * (per_sap - once)
     assert n["mr_dslash"] == 2 * it * per_sap * 4
     assert n["mr_update"] == 2 * it * per_sap * (1 if tile == 2 else 4)
     assert n["dslash64"] == 2 * it + 1
