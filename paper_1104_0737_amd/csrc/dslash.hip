@@ -1477,17 +1477,36 @@ __global__ void __launch_bounds__(256) k_to_sap(GeomK k, int L, const double2* _
   cplx<double> v[4][3];
   if (gam) {
     const double2* xr = ish + (size_t)threadIdx.y * 12 * L;
+    if constexpr (LT > 0) {
+      // column j of gamma in registers: only the rows come from LDS
+      cplx<double> gc[LT];
 #pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
+      for (int m = 0; m < LT; ++m) gc[m] = cmake(gsh[m * L + j].x, gsh[m * L + j].y);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        cplx<double> acc = cmake(0.0, 0.0);
-        for (int m = 0; m < L; ++m) {
-          double2 e = xr[(3 * sp + a) * L + m], gg = gsh[m * L + j];
-          acc = acc + cmake(e.x, e.y) * cmake(gg.x, gg.y);
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          cplx<double> acc = cmake(0.0, 0.0);
+#pragma unroll
+          for (int m = 0; m < LT; ++m) {
+            const double2 e = xr[(3 * sp + a) * L + m];
+            acc = acc + cmake(e.x, e.y) * gc[m];
+          }
+          v[sp][a] = acc;
         }
-        v[sp][a] = acc;
-      }
+    } else {
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          cplx<double> acc = cmake(0.0, 0.0);
+          for (int m = 0; m < L; ++m) {
+            double2 e = xr[(3 * sp + a) * L + m], gg = gsh[m * L + j];
+            acc = acc + cmake(e.x, e.y) * cmake(gg.x, gg.y);
+          }
+          v[sp][a] = acc;
+        }
+    }
   } else {
     const int ls = lex_of(k, site_ctx<DM>(k, s));
 #pragma unroll
@@ -1520,6 +1539,36 @@ __global__ void __launch_bounds__(256) k_from_sap(GeomK k, int L, const typename
   for (int e = 0; e < 12; ++e) {
     auto v = Store<PPSI>::ld(in, ((size_t)s * 12 + e) * L + j);
     out[((size_t)ls * 12 + e) * L + j] = make_double2((double)v.re, (double)v.im);
+  }
+}
+
+// FP32 psi to the FP64 block, even L: a block takes FROM_SITES consecutive
+// domain-major sites, finds their lexicographic rows once, then streams each
+// site's 12 L values as 16-byte loads (two complex) and 32-byte stores.
+constexpr int FROM_SITES = 16;
+__global__ void __launch_bounds__(256) k_from_sap_flat(GeomK k, int L, const float4* __restrict__ in,
+                                                       double2* __restrict__ out, const int* __restrict__ frozen) {
+  __shared__ int lsh[FROM_SITES];
+  const int s0 = blockIdx.x * FROM_SITES;
+  if (threadIdx.x < FROM_SITES) {
+    const int s = s0 + threadIdx.x;
+    int ls = -1;
+    if (s < k.g.V) {
+      const SiteCtx c = site_ctx<DM>(k, s);
+      if (!sys_frozen(k, frozen, c.sys)) ls = lex_of(k, c);
+    }
+    lsh[threadIdx.x] = ls;
+  }
+  __syncthreads();
+  const int per = 6 * L;   // float4 units per site
+  for (int u = threadIdx.x; u < FROM_SITES * per; u += blockDim.x) {
+    const int y = u / per, w = u - y * per;
+    const int ls = lsh[y];
+    if (ls < 0) continue;
+    const float4 v = in[(size_t)(s0 + y) * per + w];
+    double2* o = out + (size_t)ls * 12 * L + 2 * w;
+    o[0] = make_double2((double)v.x, (double)v.y);
+    o[1] = make_double2((double)v.z, (double)v.w);
   }
 }
 
@@ -1556,6 +1605,9 @@ int sap_from(const mbbs_lattice_s* lat, const SapBuffers& b, double2* out, const
   if (b.prec == P64) {
     if (L == 12) hipLaunchKernelGGL((k_from_sap<P64, 12>), dim3(ceil_div(g.V, S)), dim3(L, S), 0, st, lat->gk, L, (const double2*)b.psi, out, frozen);
     else hipLaunchKernelGGL((k_from_sap<P64>), dim3(ceil_div(g.V, S)), dim3(L, S), 0, st, lat->gk, L, (const double2*)b.psi, out, frozen);
+  } else if (L % 2 == 0 && ((uintptr_t)b.psi & 15) == 0 && ((uintptr_t)out & 15) == 0) {
+    hipLaunchKernelGGL(k_from_sap_flat, dim3(ceil_div(g.V, FROM_SITES)), dim3(256), 0, st, lat->gk, L,
+                       (const float4*)b.psi, out, frozen);
   } else {
     if (L == 12) hipLaunchKernelGGL((k_from_sap<P32, 12>), dim3(ceil_div(g.V, S)), dim3(L, S), 0, st, lat->gk, L, (const float2*)b.psi, out, frozen);
     else hipLaunchKernelGGL((k_from_sap<P32>), dim3(ceil_div(g.V, S)), dim3(L, S), 0, st, lat->gk, L, (const float2*)b.psi, out, frozen);
