@@ -8,7 +8,8 @@
   reported;
 * config 2 (16^3 x 32, L = 12, all FP64): true residual by the oracle;
 * Alg. 2, no preconditioner, CholQR2, graph capture, restart from a guess;
-* failure handling: zero column, duplicate columns, iteration cap,
+* failure handling: zero or non-finite column, duplicate columns, a
+  singular R~^H V (R~ with a zero column), iteration cap,
   workspace too small;
 * batched solves equal independent solves.
 """
@@ -217,6 +218,20 @@ def test_failures():
         with pytest.raises(B.MbbsError) as e:
             _solve(lat, L, D, tol=1e-12)
         assert e.value.code == B.EBREAKDOWN
+        # a non-finite column of B is rejected like a zero one
+        Nn = Bh.copy()
+        Nn[5, 0] = np.nan
+        with pytest.raises(B.MbbsError) as e:
+            _solve(lat, L, Nn)
+        assert e.value.code == B.EINVAL
+        # a caller-chosen R~ with a zero column: R~^H V is singular at the first LU
+        Rt = Bh.copy()
+        Rt[:, 2] = 0
+        Rtd = gu.dev(Rt)
+        with pytest.raises(B.MbbsError) as e:
+            _solve(lat, L, Bh, tol=1e-12, rtilde=Rtd)
+        assert e.value.code == B.EBREAKDOWN
+        assert B.mbbs_last_error()
         X, info = _solve(lat, L, Bh, tol=1e-14, maxiter=1)
         assert info["status"] == B.NOT_CONVERGED and info["iterations"] == 1
         assert np.all(info["true_res"] > 1e-14) and np.all(np.isfinite(info["rec_res"]))
