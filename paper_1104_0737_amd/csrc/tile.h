@@ -9,7 +9,8 @@
 namespace mbbs {
 
 struct TileArgs {
-  int t[4];        // tile extents (each divides the SAP block extent)
+  int t[4];        // tile extents (each divides the SAP block extent; powers of two)
+  int lt[4];       // their base-2 logarithms
   int tstr[4];     // strides of the tile-local lexicographic index
   int ts;          // sites per tile
   int tpd;         // tiles per domain

@@ -52,10 +52,10 @@ __device__ __forceinline__ TilePos tile_pos(const GeomK& k, const TileArgs& T, i
 // (LEX: domains in lexicographic order of the domain grid, then local
 // lexicographic order).
 __device__ __forceinline__ int tile_row_index(const GeomK& k, const TileArgs& T, const TilePos& p, int s0, int r) {
-  const int l1 = p.base[1] + r % T.t[1];
-  const int r2 = r / T.t[1];
-  const int l2 = p.base[2] + r2 % T.t[2];
-  const int l3 = p.base[3] + r2 / T.t[2];
+  const int l1 = p.base[1] + (r & (T.t[1] - 1));
+  const int r2 = r >> T.lt[1];
+  const int l2 = p.base[2] + (r2 & (T.t[2] - 1));
+  const int l3 = p.base[3] + (r2 >> T.lt[2]);
   const int loc = p.base[0] + k.g.b[0] * (l1 + k.g.b[1] * (l2 + k.g.b[2] * l3));
   return s0 + p.dom * k.g.Vb + loc;
 }
@@ -65,14 +65,47 @@ __device__ __forceinline__ int tile_row_index(const GeomK& k, const TileArgs& T,
 // of U.  With Lg = L a site's elements are one contiguous row.
 // GE is E when copying out of LDS and const E when staging into it.
 template <typename U, typename GE, typename E>
-__device__ __forceinline__ void tile_copy_u(GE* g, E* lds, const int* row_site, int ts, int t0, int L, int Lg, int SS,
-                                            int cb) {
+__device__ __forceinline__ void tile_copy_u(GE* g, E* lds, const int* row_site, int ts, int lt0, int L, int Lg,
+                                            int SS, int cb) {
   constexpr bool TO_LDS = std::is_const<GE>::value;
   const int nrow = Lg == L ? 1 : 12, rlen = Lg == L ? 12 * L : Lg;
   const int ru = rlen * (int)sizeof(E) / (int)sizeof(U), su = nrow * ru;
+  const int spi = (int)blockDim.x / su;   // whole sites per pass
+  if (spi > 0) {
+    // thread -> (unit u of a site, first site); then whole sites per pass
+    const int t1 = threadIdx.x / su, u = threadIdx.x - t1 * su;
+    if (t1 >= spi) return;
+    const int e = u / ru, w = u - e * ru;
+    if constexpr (TO_LDS) {
+      // NB loads of a thread are issued before its first LDS write, so they
+      // are in flight together instead of one at a time.  Past the tile's
+      // end a slot repeats the last site: it loads and writes the same bytes
+      // as that site's own thread (no branch, so nothing moves a load next
+      // to its write)
+      constexpr int NB = 8;
+      for (int tc = t1; tc < ts; tc += NB * spi) {
+        U buf[NB];
+        int tt[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          tt[j] = min(tc + j * spi, ts - 1);
+          const int r = tt[j] >> lt0, x = tt[j] & ((1 << lt0) - 1);
+          buf[j] = ((const U*)(g + ((size_t)(row_site[r] + x) * 12 + e) * L + cb))[w];
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) ((U*)(lds + (size_t)tt[j] * SS + e * Lg))[w] = buf[j];
+      }
+    } else {
+      for (int t = t1; t < ts; t += spi) {
+        const int r = t >> lt0, x = t & ((1 << lt0) - 1);
+        ((U*)(g + ((size_t)(row_site[r] + x) * 12 + e) * L + cb))[w] = ((const U*)(lds + (size_t)t * SS + e * Lg))[w];
+      }
+    }
+    return;
+  }
   for (int f = threadIdx.x; f < ts * su; f += blockDim.x) {
     const int t = f / su, rem = f - t * su, e = rem / ru, w = rem - e * ru;
-    const int r = t / t0, x = t - r * t0;
+    const int r = t >> lt0, x = t & ((1 << lt0) - 1);
     const size_t go = ((size_t)(row_site[r] + x) * 12 + e) * L + cb;
     U* lp = (U*)(lds + (size_t)t * SS + e * Lg) + w;
     if constexpr (TO_LDS) *lp = ((const U*)(g + go))[w];
@@ -81,20 +114,20 @@ __device__ __forceinline__ void tile_copy_u(GE* g, E* lds, const int* row_site, 
 }
 
 template <typename GE, typename E>
-__device__ __forceinline__ void tile_copy(GE* g, E* lds, const int* row_site, int ts, int t0, int L, int Lg, int SS,
+__device__ __forceinline__ void tile_copy(GE* g, E* lds, const int* row_site, int ts, int lt0, int L, int Lg, int SS,
                                           int cb) {
   const int rlen = Lg == L ? 12 * L : Lg;
-  if ((rlen * (int)sizeof(E)) % 16 == 0) tile_copy_u<float4>(g, lds, row_site, ts, t0, L, Lg, SS, cb);
-  else tile_copy_u<uint2>(g, lds, row_site, ts, t0, L, Lg, SS, cb);
+  if ((rlen * (int)sizeof(E)) % 16 == 0) tile_copy_u<float4>(g, lds, row_site, ts, lt0, L, Lg, SS, cb);
+  else tile_copy_u<uint2>(g, lds, row_site, ts, lt0, L, Lg, SS, cb);
 }
 
 // The per-(site, column) scales of FP16 storage, likewise.
 template <typename GF>
-__device__ __forceinline__ void tile_copy_scales(GF* g, float* lds_s, const int* row_site, int ts, int t0, int L,
+__device__ __forceinline__ void tile_copy_scales(GF* g, float* lds_s, const int* row_site, int ts, int lt0, int L,
                                                  int Lg, int cb) {
   for (int f = threadIdx.x; f < ts * Lg; f += blockDim.x) {
     const int t = f / Lg, w = f - t * Lg;
-    const int r = t / t0, x = t - r * t0;
+    const int r = t >> lt0, x = t & ((1 << lt0) - 1);
     GF* gp = g + (size_t)(row_site[r] + x) * L + cb + w;
     if constexpr (std::is_const<GF>::value) lds_s[f] = *gp;
     else *gp = lds_s[f];
@@ -286,7 +319,7 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
   const int tb = tg / ng;                 // the tile
   const int cb = (tg - tb * ng) * Lg;     // the workgroup's first column
   const TilePos p = tile_pos(k, T, tb);
-  const int nrows = T.ts / T.t[0];
+  const int nrows = T.ts >> T.lt[0];
   // a tile lies in one domain, hence one system: the flag test is block-uniform
   {
     const int i0 = tile_row_index(k, T, p, s0, 0);
@@ -299,8 +332,8 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
   }
   __syncthreads();
   // stage the tile's columns [cb, cb + Lg); LDS holds site ts at ts * SS elements
-  tile_copy(in, lds, row_site, T.ts, T.t[0], L, Lg, SS, cb);
-  if constexpr (Store<PIN>::scaled) tile_copy_scales(in_s, lds_s, row_site, T.ts, T.t[0], L, Lg, cb);
+  tile_copy(in, lds, row_site, T.ts, T.lt[0], L, Lg, SS, cb);
+  if constexpr (Store<PIN>::scaled) tile_copy_scales(in_s, lds_s, row_site, T.ts, T.lt[0], L, Lg, cb);
   __syncthreads();
   const int nchunk = Lg / C;
   const int ts = threadIdx.x / nchunk;
@@ -311,13 +344,13 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
     int q = ts;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      const int r = q / T.t[m];
-      lt[m] = q - r * T.t[m];
+      const int r = q >> T.lt[m];
+      lt[m] = q & (T.t[m] - 1);
       q = r;
     }
     lt[3] = q;
   }
-  const int row = ts / T.t[0];
+  const int row = ts >> T.lt[0];
   const SiteCtx c = ORDER == DM ? site_ctx<DM>(k, row_site[row] + lt[0])
                                 : site_ctx_tiled(k, tile_row_index(k, T, p, s0, row) + lt[0]);
   const int s = c.s;
@@ -345,8 +378,8 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
     }
     __syncthreads();
     // the tile's new r to global memory
-    tile_copy((E*)mf.r_new, lds, row_site, T.ts, T.t[0], L, Lg, SS, cb);
-    if constexpr (Store<PIN>::scaled) tile_copy_scales(mf.r_new_s, lds_s, row_site, T.ts, T.t[0], L, Lg, cb);
+    tile_copy((E*)mf.r_new, lds, row_site, T.ts, T.lt[0], L, Lg, SS, cb);
+    if constexpr (Store<PIN>::scaled) tile_copy_scales(mf.r_new_s, lds_s, row_site, T.ts, T.lt[0], L, Lg, cb);
   }
   constexpr int HALO = OP == OP_MRF ? 1 : 0;
   cplx<R> acc[4][3][C];
@@ -475,7 +508,11 @@ bool pick_tile(const mbbs_lattice_s* lat, int L, size_t es, int C, bool scaled, 
     TileArgs T;
     T.lg = lg;
     T.ng = L / lg;
-    for (int m = 0; m < 4; ++m) T.t[m] = t[m];
+    for (int m = 0; m < 4; ++m) {
+      T.t[m] = t[m];
+      T.lt[m] = 0;
+      while ((1 << T.lt[m]) < t[m]) ++T.lt[m];
+    }
     T.ts = ts;
     T.tstr[0] = 1;
     for (int m = 1; m < 4; ++m) T.tstr[m] = T.tstr[m - 1] * t[m - 1];
