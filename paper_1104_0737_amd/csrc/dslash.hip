@@ -1465,10 +1465,21 @@ __global__ void __launch_bounds__(256) k_to_sap(GeomK k, int L, const double2* _
       lsh[y] = sy < k.g.V ? lex_of(k, site_ctx<DM>(k, sy)) : -1;
     }
     __syncthreads();
-    const int row = 12 * L;
-    for (int f = tid; f < (int)blockDim.y * row; f += nthr) {
-      const int y = f / row, w = f - y * row;
-      if (lsh[y] >= 0) ish[f] = in[(size_t)lsh[y] * row + w];
+    const int row = 12 * L, tot = (int)blockDim.y * row;
+    // NB loads of a thread are in flight before its LDS writes; past the end
+    // a slot repeats the last element (same bytes, same place)
+    constexpr int NB = 8;
+    for (int f0 = tid; f0 < tot; f0 += NB * nthr) {
+      double2 buf[NB];
+      int ff[NB];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        ff[q] = min(f0 + q * nthr, tot - 1);
+        const int y = ff[q] / row, w = ff[q] - y * row;
+        buf[q] = in[(size_t)max(lsh[y], 0) * row + w];
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q) ish[ff[q]] = buf[q];
     }
     __syncthreads();
   }
@@ -1561,14 +1572,27 @@ __global__ void __launch_bounds__(256) k_from_sap_flat(GeomK k, int L, const flo
   }
   __syncthreads();
   const int per = 6 * L;   // float4 units per site
-  for (int u = threadIdx.x; u < FROM_SITES * per; u += blockDim.x) {
-    const int y = u / per, w = u - y * per;
-    const int ls = lsh[y];
-    if (ls < 0) continue;
-    const float4 v = in[(size_t)(s0 + y) * per + w];
-    double2* o = out + (size_t)ls * 12 * L + 2 * w;
-    o[0] = make_double2((double)v.x, (double)v.y);
-    o[1] = make_double2((double)v.z, (double)v.w);
+  const int tot = min(FROM_SITES, k.g.V - s0) * per;
+  // a thread's loads are in flight together before its stores (past the end
+  // a slot reloads the last unit and stores nothing)
+  constexpr int NB = 6;
+  for (int u0 = threadIdx.x; u0 < tot; u0 += NB * blockDim.x) {
+    float4 v[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int u = min(u0 + q * (int)blockDim.x, tot - 1);
+      v[q] = in[(size_t)s0 * per + u];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int u = u0 + q * (int)blockDim.x;
+      if (u >= tot) continue;
+      const int y = u / per, w = u - y * per;
+      if (lsh[y] < 0) continue;
+      double2* o = out + (size_t)lsh[y] * 12 * L + 2 * w;
+      o[0] = make_double2((double)v[q].x, (double)v[q].y);
+      o[1] = make_double2((double)v[q].z, (double)v[q].w);
+    }
   }
 }
 
