@@ -82,7 +82,7 @@ __device__ __forceinline__ void tile_copy_u(GE* g, E* lds, const int* row_site, 
       // end a slot repeats the last site: it loads and writes the same bytes
       // as that site's own thread (no branch, so nothing moves a load next
       // to its write)
-      constexpr int NB = 8;
+      constexpr int NB = 13;
       for (int tc = t1; tc < ts; tc += NB * spi) {
         U buf[NB];
         int tt[NB];
