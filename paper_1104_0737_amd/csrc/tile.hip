@@ -402,8 +402,55 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
   if (k.clov) clover_apply<ORDER, C, R>(k, s, acc);
   const R kap = (R)kappa_of(k, c, kappa);
   double sums[C][3];
+  // FP32 storage, two columns per thread: both columns of an element move as
+  // one 16-byte access (LDS read, eta read, store); the same values and sums
+  // as the column-by-column form below
+  constexpr bool PAIRED = PIN == P32 && C == 2 && OP != OP_MRF && (OP != OP_RESID || PO == P32);
+  if constexpr (PAIRED) {
+    const float* lrow = (const float*)(lds + (size_t)ts * SS + cl0);
+    const size_t base0 = (size_t)s * 12 * L + col0;
+    R s_re[2] = {0, 0}, s_im[2] = {0, 0}, s_ww[2] = {0, 0};
 #pragma unroll
-  for (int q = 0; q < C; ++q) {
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int e = 3 * sp + a;
+        const float4 vv = *(const float4*)(lrow + 2 * e * Lg);
+        const cplx<R> v[2] = {cmake<R>(vv.x, vv.y), cmake<R>(vv.z, vv.w)};
+        cplx<R> w[2];
+        if constexpr (OP == OP_RESID) {
+          const float4 ee = *(const float4*)((const float*)mf.eta + 2 * (base0 + (size_t)e * L));
+          const cplx<R> et[2] = {cmake<R>(ee.x, ee.y), cmake<R>(ee.z, ee.w)};
+#pragma unroll
+          for (int q = 0; q < 2; ++q) w[q] = et[q] - v[q] + kap * acc[sp][a][q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) w[q] = v[q] - kap * acc[sp][a][q];
+        }
+        typedef float v4 __attribute__((ext_vector_type(4)));
+        v4* o = (v4*)((float*)out + 2 * (base0 + (size_t)e * L));
+        const v4 wo = {w[0].re, w[0].im, w[1].re, w[1].im};
+        if constexpr (OP == OP_DSLASH) {
+          if (k.nt_store) __builtin_nontemporal_store(wo, o);
+          else *o = wo;
+        } else if (OP == OP_RESID || out) {
+          *o = wo;
+        }
+        if constexpr (OP == OP_MR) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const cplx<R> x = w[q], y = v[q];
+            s_re[q] = fmar(x.re, y.re, fmar(x.im, y.im, s_re[q]));
+            s_im[q] = fmar(x.re, y.im, fmar(-x.im, y.re, s_im[q]));
+            s_ww[q] = fmar(x.re, x.re, fmar(x.im, x.im, s_ww[q]));
+          }
+        }
+      }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) { sums[q][0] = s_re[q]; sums[q][1] = s_im[q]; sums[q][2] = s_ww[q]; }
+  }
+#pragma unroll
+  for (int q = 0; q < (PAIRED ? 0 : C); ++q) {
     const size_t base = (size_t)s * 12 * L + col0 + q;
     const size_t sidx = (size_t)s * L + col0 + q;
     cplx<R> v[4][3], wv[4][3];
