@@ -1038,7 +1038,10 @@ static int dslash_dispatch_c(const mbbs_lattice_s* lat, int L, int order, bool b
   if constexpr (PIN == POUT && PIN == PL) {
     TileArgs T;
     const bool whole = order == LEX ? (s0 == 0 && n == lat->g.V) : (s0 % lat->g.Vb == 0 && n % lat->g.Vb == 0);
-    if (whole && ((uintptr_t)in & 15) == 0 && tile_plan(lat, L, PL, &T))
+    // the tiled kernels move two FP32 columns as one 16-byte access: both
+    // fields 16-byte aligned, else the column-by-column kernel below
+    const bool al = (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
+    if (whole && al && tile_plan(lat, L, PL, &T))
       return launch_dslash_tiled(lat, L, PL, order, blocked, T, in, in_s, out, out_s, s0, n, frozen, st);
   }
   const int P = lat->nsys == 1 ? lat->split[PL] : 0;   // the split kernels serve single systems only
@@ -1200,7 +1203,8 @@ static int sap_cycles(const mbbs_lattice_s* lat, const SapBuffers& b, int ncy, i
       if (!r_is_eta) {
       if (prof) prof->begin(MBBS_K_SAP_RES);
       TileArgs TR;
-      const bool tres = cy > 0 && ((uintptr_t)b.psi & 15) == 0 && tile_plan_resid(lat, L, PL, &TR);
+      const bool tres = cy > 0 && (((uintptr_t)b.psi | (uintptr_t)b.r | (uintptr_t)b.eta) & 15) == 0 &&
+                        tile_plan_resid(lat, L, PL, &TR);
       if (tres) {
         // general case with psi staged per tile in LDS
         MBBS_TRY(launch_resid_tiled(lat, L, PL, TR, b.eta, b.eta_s, b.psi, b.r, b.r_s, s0, n, frozen, st));

@@ -521,16 +521,15 @@ __global__ void __launch_bounds__(TILE_THREADS) k_tile(GeomK k, double kappa, in
   }
 }
 
-// Largest tile shape (of a fixed candidate list) that divides the SAP block,
-// keeps TS * L / C threads within one workgroup (and at least one wave), and
-// whose LDS (the spinors, or the reduction that reuses them) fits 160 KiB.
-// es: bytes per staged element; C columns per thread; scaled: FP16 storage.
-// The first candidate shape whose workgroup (tile sites x lg / C threads) and
-// LDS (staged spinors, or the MR sums' scratch, plus the row table) fit:
-// within the whole 160 KiB for cap = 1, within half of it for cap = 2 (two
-// workgroups resident per CU, one staging while the other computes).  lg:
-// columns per workgroup when it divides L into whole column pairs of the
-// kernel and aligned rows, else all L.
+// The first shape of a fixed candidate list (largest first) that divides the
+// SAP block and whose workgroup (tile sites x lg / C threads, at least one
+// wave) and LDS (staged spinors, or the MR sums' scratch that reuses them,
+// plus the row table) fit: within the whole 160 KiB for cap = 1, within half
+// of it for cap = 2 (two workgroups resident per CU, one staging while the
+// other computes).  es: bytes per staged element; C: columns per thread;
+// scaled: FP16 storage; lg: columns per workgroup when it divides L into whole
+// column pairs of the kernel and aligned rows, else all L.  The caller checks
+// that the fields are 16-byte aligned.
 bool pick_tile(const mbbs_lattice_s* lat, int L, size_t es, int C, bool scaled, int cap, int lg, TileArgs* out) {
   static const int cand[][4] = {{4, 4, 4, 4}, {8, 4, 4, 2}, {4, 4, 4, 2}, {8, 4, 2, 2}, {4, 4, 2, 2},
                                 {8, 2, 2, 2}, {4, 2, 2, 2}, {2, 2, 2, 2}, {4, 4, 2, 1}, {2, 2, 2, 1},
