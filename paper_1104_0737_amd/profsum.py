@@ -1,6 +1,7 @@
 """Summarise rocprofv3 SQLite output (kernel trace and PMC counters) as text.
 
 usage: python -m paper_1104_0737_amd.profsum DB [DB ...] [--match SUBSTR]
+       python -m paper_1104_0737_amd.profsum --bench JSON   (a bench.py --sweep or --batched line)
 Kernel-trace databases print calls and average/total duration per kernel;
 counter databases print the average counter value per dispatch per kernel.
 """
@@ -71,6 +72,36 @@ def traffic(fetch_db, write_db, cfetch_db, cwrite_db, classes, copy_bytes=4 << 3
     return out
 
 
+def bench_table(line: dict) -> str:
+    """Text table of a bench.py --sweep line (per L: operator times and solve
+    times) or of a --batched line (fused, separate-handle and sequential
+    times, iterations per lattice)."""
+    out = []
+    if "sweep" in line:
+        out.append(f"# {line['workload']}")
+        out.append(f"{'L':>3s} {'blocks':>6s} {'op FP64 ms':>10s} {'FP64 GB/s':>9s} {'op FP32 ms':>10s} "
+                   f"{'op FP16S ms':>11s} {'mixed MR s':>10s} {'FP64 MR s':>9s} {'mixed SSOR s':>12s} "
+                   f"{'it MR':>6s} {'it SSOR':>7s} {'gain MR / FP64 / SSOR vs L=1':>28s}")
+        for r in line["sweep"]:
+            d, g = r["dslash"], r["gain_vs_L1"]
+            it = lambda k: f"{min(r[k]['iterations'])}-{max(r[k]['iterations'])}"
+            out.append(f"{r['L']:3d} {r['blocks']:6d} {d['fp64']['ms']:10.3f} {d['fp64']['algo_GBps']:9.0f} "
+                       f"{d['fp32']['ms']:10.3f} {d['fp16s']['ms']:11.3f} {r['mixed_mr']['seconds']:10.3f} "
+                       f"{r['fp64_mr']['seconds']:9.3f} {r['mixed_ssor']['seconds']:12.3f} {it('mixed_mr'):>6s} "
+                       f"{it('mixed_ssor'):>7s} {g['mixed_mr']:10.2f} {g['fp64_mr']:6.2f} {g['mixed_ssor']:6.2f}")
+    else:
+        out.append(f"# {line['metric']}: {line['config']['workload']}")
+        out.append(f"fused batched solve   {line['ms_per_step'] / 1e3:.3f} s per step ({line['steps']} steps), "
+                   f"{line['value']:.1f} {line['unit']}, all converged: {line['converged']}, "
+                   f"max true residual {line['max_true_res']:.2e}")
+        out.append(f"separate handles      {line['separate_handles_s']:.3f} s (one batched call)")
+        out.append(f"one system at a time  {line['sequential_s']:.3f} s")
+        out.append(f"fused / sequential    {line['fused_over_sequential']:.3f}x")
+        for k, v in line["iterations"].items():
+            out.append(f"iterations {k}: {v[0]}-{v[1]}")
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("db", nargs="*")
@@ -78,7 +109,13 @@ def main():
     ap.add_argument("--traffic", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
                     help="print per-launch HBM traffic of --kernel CLASS=NAME pairs as JSON")
     ap.add_argument("--kernel", action="append", default=[])
+    ap.add_argument("--bench", default=None, help="print a table of a bench.py --sweep / --batched JSON line")
     a = ap.parse_args()
+    if a.bench:
+        import json
+        with open(a.bench) as f:
+            print(bench_table(json.loads(f.read().strip().splitlines()[-1])))
+        return
     if a.traffic:
         import json
         classes = dict(kv.split("=", 1) for kv in a.kernel)
