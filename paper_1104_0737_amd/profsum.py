@@ -1,7 +1,7 @@
 """Summarise rocprofv3 SQLite output (kernel trace and PMC counters) as text.
 
 usage: python -m paper_1104_0737_amd.profsum DB [DB ...] [--match SUBSTR]
-       python -m paper_1104_0737_amd.profsum --bench JSON   (a bench.py --sweep or --batched line)
+       python -m paper_1104_0737_amd.profsum --bench JSON   (a bench.py line: benchmark, --sweep or --batched)
 Kernel-trace databases print calls and average/total duration per kernel;
 counter databases print the average counter value per dispatch per kernel.
 """
@@ -74,8 +74,8 @@ def traffic(fetch_db, write_db, cfetch_db, cwrite_db, classes, copy_bytes=4 << 3
 
 def bench_table(line: dict) -> str:
     """Text table of a bench.py --sweep line (per L: operator times and solve
-    times) or of a --batched line (fused, separate-handle and sequential
-    times, iterations per lattice)."""
+    times), of a --batched line (fused, separate-handle and sequential times,
+    iterations per lattice) or of a benchmark line (solves and operators)."""
     out = []
     if "sweep" in line:
         out.append(f"# {line['workload']}")
@@ -89,6 +89,34 @@ def bench_table(line: dict) -> str:
                        f"{d['fp32']['ms']:10.3f} {d['fp16s']['ms']:11.3f} {r['mixed_mr']['seconds']:10.3f} "
                        f"{r['fp64_mr']['seconds']:9.3f} {r['mixed_ssor']['seconds']:12.3f} {it('mixed_mr'):>6s} "
                        f"{it('mixed_ssor'):>7s} {g['mixed_mr']:10.2f} {g['fp64_mr']:6.2f} {g['mixed_ssor']:6.2f}")
+    elif "dslash" in line:
+        out.append(f"# {line['config']['workload']}")
+        out.append(f"mixed solve           {line['ms_per_step'] / 1e3:.3f} s per step ({line['steps']} steps), "
+                   f"{line['iterations']} iterations, max true residual {line['max_true_res']:.2e}; "
+                   f"{line['value']:.3e} {line['unit']}")
+        t = line.get("tts_per_rhs_s") or {}
+        if "fp64" in t:
+            out.append(f"per RHS               mixed {t['mixed']:.4f} s, all-FP64 {t['fp64']:.4f} s "
+                       f"({t['fp64_over_mixed']:.2f}x)")
+        for key, name in (("other_sap_prec_solve", "other SAP storage"), ("ssor_domain_solve", "SSOR domains")):
+            o = line.get(key)
+            if o:
+                tag = f" ({o['sap_prec']})" if "sap_prec" in o else ""
+                out.append(f"{name + tag:21s} {o['seconds']:.3f} s, {o['iterations']} iterations, "
+                           f"max true residual {o['max_true_res']:.2e}")
+        for prec, d in line["dslash"].items():
+            out.append(f"operator {prec:12s} {d['ms']:.3f} ms, {d['algo_GBps']:.0f} GB/s algorithmic "
+                       f"({100 * d['frac_hbm_peak']:.0f} % of HBM peak)")
+        r = line.get("roofline")
+        if r:
+            tr = (f", counter traffic {r['traffic'] / 1e9:.3f} GB ({r['traffic_over_algorithmic']:.2f}x)"
+                  if r.get("traffic") else ", counter traffic null")
+            out.append(f"roofline {r['kernel']}: {r['launches']} launches of {r['avg_launch_ms']:.3f} ms, "
+                       f"{r['bytes_per_launch'] / 1e9:.3f} GB algorithmic each, {r['achieved']:.0f} {r['unit']} "
+                       f"= {r['frac']:.3f} of {r['peak']:.0f}{tr}")
+        c = line.get("cpu_baseline")
+        if c:
+            out.append(f"cpu baseline ({c['kind']}, {c['cores']} core): {c['value']:.3e} {c['unit']}; {c['sample']}")
     else:
         out.append(f"# {line['metric']}: {line['config']['workload']}")
         out.append(f"fused batched solve   {line['ms_per_step'] / 1e3:.3f} s per step ({line['steps']} steps), "
@@ -109,7 +137,7 @@ def main():
     ap.add_argument("--traffic", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
                     help="print per-launch HBM traffic of --kernel CLASS=NAME pairs as JSON")
     ap.add_argument("--kernel", action="append", default=[])
-    ap.add_argument("--bench", default=None, help="print a table of a bench.py --sweep / --batched JSON line")
+    ap.add_argument("--bench", default=None, help="print a table of a bench.py JSON line (benchmark, --sweep or --batched)")
     a = ap.parse_args()
     if a.bench:
         import json
